@@ -1,0 +1,58 @@
+"""KXRCF troubled-cell indicator (Section 3.1, eq. troubledCellIndicator).
+
+R_j = | int_{dI-} (U_j - U_nb) ds | / ( h^{(N+1)/2} |dI-| ||U_j|| ),
+troubled when R_j > C_K with C_K = 1 and h the circumradius.
+
+Readings: the inflow part dI- is taken point by point at the edge Gauss
+points (v.n < 0 strictly, v from the interior trace: (u, u) for Burgers,
+the velocity for Euler); |dI-| is the same quadrature of 1 over those
+points; U is u for Burgers and the density for Euler; ||U_j|| is the
+literal L2 norm (int U^2 dA)^(1/2) = (J sum_n U_n^2)^(1/2); R = 0 when
+|dI-| = 0 or ||U|| = 0; on a transmissive boundary U_nb = U_j.
+
+Parity status: pinned by tests/test_oracle_kxrcf.py (zero on global
+polynomials, closed-form value for a piecewise-constant jump).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .dg import DG
+from .physics import EQ_BURGERS
+
+
+def indicator(dg: DG, u, elems=None, c_k=1.0):
+    """Returns (R [len], troubled bool [len])."""
+    M = dg.mesh
+    E = np.arange(M.K) if elems is None else np.asarray(elems)
+    ue = u[E]
+    PFrev = dg.PF[:, ::-1, :]
+    fprime = M.neighbour_face()
+    bnd = M.boundary_mask()
+    num = np.zeros(len(E))
+    length = np.zeros(len(E))
+    for f in range(3):
+        um = np.einsum("gn,kcn->kgc", dg.PF[f], ue)
+        nb = M.nbr[E, f]
+        isb = bnd[E, f]
+        nb_safe = np.where(isb, E, nb)
+        sel = PFrev[fprime[E, f]]
+        up = np.einsum("kgn,kn->kg", sel, u[nb_safe, 0, :])
+        Um = um[..., 0]
+        Up = np.where(isb[:, None], Um, up)
+        if dg.eq == EQ_BURGERS:
+            vx = vy = Um
+        else:
+            vx = um[..., 1] / um[..., 0]
+            vy = um[..., 2] / um[..., 0]
+        vn = vx * M.nx[E, f][:, None] + vy * M.ny[E, f][:, None]
+        inflow = vn < 0.0
+        ds = 0.5 * M.L[E, f][:, None] * dg.ew[None, :]
+        num += np.sum(np.where(inflow, ds * (Um - Up), 0.0), axis=1)
+        length += np.sum(np.where(inflow, ds, 0.0), axis=1)
+    norm = np.sqrt(M.J[E] * np.sum(ue[:, 0, :] ** 2, axis=1))
+    h = M.circumradius[E]
+    denom = h ** ((dg.N + 1) / 2.0) * length * norm
+    ok = (length > 0.0) & (norm > 0.0)
+    R = np.where(ok, np.abs(num) / np.where(ok, denom, 1.0), 0.0)
+    return R, R > c_k

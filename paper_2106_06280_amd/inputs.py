@@ -1,0 +1,249 @@
+"""Seeded synthetic inputs: jittered triangle meshes and initial/exact states.
+
+This module is the only code shared by the GPU path's callers and by the
+CPU oracle.  It produces *data* (vertex coordinates, triangle lists and
+pointwise initial states of the conservation law); it contains none of the
+discontinuous Galerkin or limiter arithmetic.
+
+Stand-ins for the paper's inputs (Section 4): the paper meshes its domains
+with an unstructured generator whose meshes are not available, so every
+workload here uses a structured n x n grid of squares, each split along its
+(i,j)->(i+1,j+1) diagonal, with interior vertices jittered by a seeded
+uniform perturbation of +-0.1 h.  Boundary vertices stay on the uniform grid
+so that periodic partners match exactly.
+
+Random numbers come from numpy's PCG64 generator seeded explicitly.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA_GAS = 1.4  # ratio of specific heats used for every Euler example (Section 4)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def jittered_mesh(n: int, x0: float = 0.0, x1: float = 1.0, y0: float = 0.0,
+                  y1: float = 1.0, jitter: float = 0.1, seed: int = 0,
+                  ny: int | None = None):
+    """Jittered structured triangulation of [x0,x1] x [y0,y1].
+
+    Returns (vxy, tri): vxy float64 [(n+1)*(ny+1), 2], tri int32 [2*n*ny, 3].
+    Vertex (i, j) has id j*(n+1)+i.  Square (i, j) gives the two CCW triangles
+    [(i,j),(i+1,j),(i+1,j+1)] and [(i,j),(i+1,j+1),(i,j+1)] with element ids
+    2*(j*n+i) and 2*(j*n+i)+1.  Interior vertices move by iid U(-jitter*hx,
+    jitter*hx) in x and U(-jitter*hy, jitter*hy) in y.
+    """
+    if ny is None:
+        ny = n
+    if n < 1 or ny < 1:
+        raise ValueError("mesh needs at least one square per side")
+    rng = _rng(seed)
+    i = np.arange(n + 1, dtype=np.float64)
+    j = np.arange(ny + 1, dtype=np.float64)
+    xs = x0 + (x1 - x0) * (i / n)
+    ys = y0 + (y1 - y0) * (j / ny)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")  # [ny+1, n+1]
+    d = rng.uniform(-1.0, 1.0, size=(ny + 1, n + 1, 2))
+    hx = (x1 - x0) / n
+    hy = (y1 - y0) / ny
+    interior = np.zeros((ny + 1, n + 1), dtype=bool)
+    interior[1:ny, 1:n] = True
+    X = np.where(interior, X + jitter * hx * d[..., 0], X)
+    Y = np.where(interior, Y + jitter * hy * d[..., 1], Y)
+    vxy = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
+
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(n), indexing="ij")
+    a = (jj * (n + 1) + ii).ravel()
+    b = a + 1
+    c = a + (n + 1) + 1
+    dd = a + (n + 1)
+    tri = np.empty((2 * n * ny, 3), dtype=np.int32)
+    tri[0::2, 0], tri[0::2, 1], tri[0::2, 2] = a, b, c
+    tri[1::2, 0], tri[1::2, 1], tri[1::2, 2] = a, c, dd
+    return vxy, tri
+
+
+def n_for_target(k_target: int) -> int:
+    """Squares per side so that 2 n^2 is closest to the requested triangle count."""
+    return int(round(math.sqrt(k_target / 2.0)))
+
+
+# ----------------------------------------------------------------------------
+# Pointwise states.  Scalar problems return an array shaped like x; Euler
+# problems return conservative variables stacked on a trailing axis of 4:
+# (rho, rho*u, rho*v, E) with E = p/(gamma-1) + rho*(u^2+v^2)/2 (Section 4,
+# Euler equations of Example 2).
+# ----------------------------------------------------------------------------
+
+def primitive_to_conservative(rho, u, v, p, gamma=GAMMA_GAS):
+    rho, u, v, p = np.broadcast_arrays(*(np.asarray(t, dtype=np.float64) for t in (rho, u, v, p)))
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack([rho, rho * u, rho * v, E], axis=-1)
+
+
+class BurgersSine:
+    """u0 = a + b sin(k (x + y)); with u0 = F(x+y) the exact solution follows
+    the characteristics of u_t + 2 u u_xi = 0 in xi = x + y until they cross
+    (Example 1 uses a = 0.5, b = 1, k = pi/2 on [-2,2]^2)."""
+
+    def __init__(self, a=0.5, b=1.0, k=math.pi / 2):
+        self.a, self.b, self.k = a, b, k
+
+    def __call__(self, x, y):
+        return self.a + self.b * np.sin(self.k * (np.asarray(x) + np.asarray(y)))
+
+    def breaking_time(self):
+        return 1.0 / (2.0 * self.b * self.k)
+
+    def exact(self, x, y, t, iters=60):
+        """Solution at time t by fixed-point/Newton on xi0 + 2 t F(xi0) = xi."""
+        xi = np.asarray(x, dtype=np.float64) + np.asarray(y, dtype=np.float64)
+        z = xi.copy()
+        for _ in range(iters):
+            F = self.a + self.b * np.sin(self.k * z)
+            dF = self.b * self.k * np.cos(self.k * z)
+            g = z + 2.0 * t * F - xi
+            z = z - g / (1.0 + 2.0 * t * dF)
+        return self.a + self.b * np.sin(self.k * z)
+
+
+class EntropyWave:
+    """Example 2: rho = 1 + 0.2 sin(pi (x + y - t)), u = 0.7, v = 0.3, p = 1.
+
+    The paper prints the exact density with x + y - t; the state is advected
+    by (0.7, 0.3), for which x + y moves at speed 1, so both agree."""
+
+    def __init__(self, amp=0.2, k=math.pi, u=0.7, v=0.3, p=1.0):
+        self.amp, self.k, self.u, self.v, self.p = amp, k, u, v, p
+
+    def exact(self, x, y, t):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        rho = 1.0 + self.amp * np.sin(self.k * (x + y - (self.u + self.v) * t))
+        return primitive_to_conservative(rho, self.u + 0 * rho, self.v + 0 * rho, self.p + 0 * rho)
+
+    def __call__(self, x, y):
+        return self.exact(x, y, 0.0)
+
+
+class IsentropicVortex:
+    """Example 3: isentropic vortex of strength beta centred at (x0, y0),
+    advected with unit x-velocity; p = rho^gamma.  With period_x the
+    vortex is wrapped so that the periodic extension is used."""
+
+    def __init__(self, beta=5.0, x0=5.0, y0=0.0, gamma=GAMMA_GAS, period_x=None, period_y=None):
+        self.beta, self.x0, self.y0, self.gamma = beta, x0, y0, gamma
+        self.px, self.py = period_x, period_y
+
+    def primitive(self, x, y, t):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        g, b = self.gamma, self.beta
+        dx = x - self.x0 - t
+        dy = y - self.y0
+        if self.px:
+            dx = dx - self.px * np.round(dx / self.px)
+        if self.py:
+            dy = dy - self.py * np.round(dy / self.py)
+        r2 = dx * dx + dy * dy
+        e = np.exp(1.0 - r2)
+        T = 1.0 - (g - 1.0) / (16.0 * g * math.pi ** 2) * b * b * e * e
+        rho = T ** (1.0 / (g - 1.0))
+        u = 1.0 - b * e * dy / (2.0 * math.pi)
+        v = b * e * dx / (2.0 * math.pi)
+        p = rho ** g
+        return rho, u, v, p
+
+    def exact(self, x, y, t):
+        return primitive_to_conservative(*self.primitive(x, y, t), gamma=self.gamma)
+
+    def __call__(self, x, y):
+        return self.exact(x, y, 0.0)
+
+
+class FourQuadrant:
+    """Piecewise-constant Riemann data with four quadrants split at (xc, yc),
+    following the layout of the paper's two-dimensional Riemann problems
+    (Example 7).  States are drawn from the seed unless given explicitly as
+    a [4, 4] array of primitive (rho, u, v, p) per quadrant, ordered
+    (x>=xc,y>=yc), (x<xc,y>=yc), (x<xc,y<yc), otherwise."""
+
+    def __init__(self, seed=None, states=None, xc=0.5, yc=0.5,
+                 rho_range=(0.1, 1.5), p_range=(0.03, 1.5), vel_range=(-1.0, 1.0)):
+        if states is None:
+            rng = _rng(seed)
+            st = np.empty((4, 4))
+            st[:, 0] = rng.uniform(*rho_range, size=4)
+            st[:, 3] = rng.uniform(*p_range, size=4)
+            st[:, 1] = rng.uniform(*vel_range, size=4)
+            st[:, 2] = rng.uniform(*vel_range, size=4)
+            states = st
+        self.states = np.asarray(states, dtype=np.float64)
+        self.xc, self.yc = xc, yc
+
+    def quadrant(self, x, y):
+        x = np.asarray(x)
+        y = np.asarray(y)
+        right = x >= self.xc
+        top = y >= self.yc
+        return np.where(top, np.where(right, 0, 1), np.where(right, 3, 2))
+
+    def __call__(self, x, y):
+        q = self.quadrant(x, y)
+        s = self.states[q]
+        return primitive_to_conservative(s[..., 0], s[..., 1], s[..., 2], s[..., 3])
+
+
+# Printed initial states of the paper's Example 7 (configurations 3 and 12),
+# quadrant order as in FourQuadrant: (rho, u, v, p).
+RIEMANN_CONFIG3 = np.array([
+    [1.5, 0.0, 0.0, 1.5],
+    [0.5323, 1.206, 0.0, 0.3],
+    [0.138, 1.206, 1.206, 0.029],
+    [0.5323, 0.0, 1.206, 0.3],
+])
+RIEMANN_CONFIG12 = np.array([
+    [0.5313, 0.0, 0.0, 0.4],
+    [1.0, 0.7276, 0.0, 1.0],
+    [0.8, 0.0, 0.0, 1.0],
+    [1.0, 0.0, 0.7276, 1.0],
+])
+
+
+class VortexCircles:
+    """Periodic isentropic vortex plus seeded circular jumps: inside each of
+    n_circles circles (centres uniform in the domain, radii U[r_lo, r_hi],
+    periodic distance) density and pressure are multiplied by a factor
+    U[f_lo, f_hi]; overlapping circles multiply."""
+
+    def __init__(self, seed, x0=0.0, x1=10.0, y0=-5.0, y1=5.0, n_circles=8,
+                 r_range=(1.0, 2.0), f_range=(2.0, 5.0), beta=5.0):
+        rng = _rng(seed)
+        self.Lx, self.Ly = x1 - x0, y1 - y0
+        self.cx = rng.uniform(x0, x1, size=n_circles)
+        self.cy = rng.uniform(y0, y1, size=n_circles)
+        self.r = rng.uniform(*r_range, size=n_circles)
+        self.f = rng.uniform(*f_range, size=n_circles)
+        self.vortex = IsentropicVortex(beta=beta, x0=0.5 * (x0 + x1), y0=0.5 * (y0 + y1),
+                                       period_x=self.Lx, period_y=self.Ly)
+
+    def __call__(self, x, y):
+        rho, u, v, p = self.vortex.primitive(x, y, 0.0)
+        fac = np.ones_like(rho)
+        for k in range(len(self.r)):
+            dx = np.asarray(x) - self.cx[k]
+            dy = np.asarray(y) - self.cy[k]
+            dx = dx - self.Lx * np.round(dx / self.Lx)
+            dy = dy - self.Ly * np.round(dy / self.Ly)
+            fac = np.where(dx * dx + dy * dy < self.r[k] ** 2, fac * self.f[k], fac)
+        return primitive_to_conservative(rho * fac, u, v, p * fac)
+
+
+def random_coefficients(shape, seed, scale=1.0):
+    """Seeded normal draws (used as raw modal coefficients in parity tests)."""
+    return scale * _rng(seed).standard_normal(size=shape)

@@ -1,0 +1,237 @@
+"""Pins for the CSWENO limiter oracle (Section 3.2)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle_runs
+from oracle import csweno
+from oracle.dg import DG
+from oracle.mesh import BC_PERIODIC, BC_TRANSMISSIVE, INFO_BOUNDARY, Mesh, connectivity_bruteforce
+from paper_2106_06280_amd import inputs
+
+
+def _mesh(n=6, bc=BC_TRANSMISSIVE, seed=11):
+    v, t = inputs.jittered_mesh(n, seed=seed)
+    return Mesh(v, t, bc, (1.0, 1.0))
+
+
+def _interior(M):
+    """Cells whose three neighbours are real elements that are themselves
+    not across a periodic seam."""
+    return np.nonzero(~np.any((M.info & (INFO_BOUNDARY | 0x3C)) != 0, axis=1))[0]
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_pieces_tile_neighbours(N):
+    M = _mesh()
+    d = DG(M, N, 0)
+    E = np.arange(M.K)
+    W, fp, nid, shift = csweno.neighbour_frames(d, E)
+    pcs, nbad = csweno.pieces(W, fp, N)
+    assert nbad == 0
+    A = csweno.tri_area(W)
+    for nm in ("S1", "S2", "S3"):
+        assert np.all(csweno.tri_area(pcs[nm]) > 0)
+        assert np.allclose(csweno.tri_area(pcs[nm]), A / 3.0, rtol=1e-13)
+    if N >= 2:
+        a = {nm: csweno.tri_area(pcs[nm]) for nm in pcs}
+        assert np.all(np.stack([a[k] for k in ("S2p", "S21", "S3p", "S31")]) > 0)
+        assert np.allclose(a["S2p"] + a["S21"], a["S2"], rtol=1e-13)
+        assert np.allclose(a["S3p"] + a["S31"], a["S3"], rtol=1e-13)
+        # the cut is the perpendicular from G to the outer side
+        G = pcs["S2p"][..., 0, :]
+        wb, F2, wc = pcs["S2p"][..., 1, :], pcs["S2p"][..., 2, :], pcs["S21"][..., 2, :]
+        dot = np.sum((F2 - G) * (wc - wb), axis=-1)
+        assert np.abs(dot).max() < 1e-14
+        # Delta_i1 shares the edge with Delta0
+        V0 = M.V[E]
+        for f in range(3):
+            s1 = pcs["S1"][:, f]
+            assert np.allclose(s1[:, 1], V0[:, (f + 1) % 3]) and np.allclose(s1[:, 2], V0[:, f])
+
+
+def test_mirror_ghost_is_reflection():
+    M = _mesh(3)
+    d = DG(M, 1, 0)
+    E = np.arange(M.K)
+    W, fp, nid, shift = csweno.neighbour_frames(d, E)
+    for e in range(M.K):
+        for f in range(3):
+            if M.info[e, f] & INFO_BOUNDARY:
+                assert nid[e, f] == -1
+                assert math.isclose(csweno.tri_area(W[e, f]), M.area[e], rel_tol=1e-13)
+                P, Q = M.V[e, f], M.V[e, (f + 1) % 3]
+                mid = 0.5 * (W[e, f, 2] + M.V[e, (f + 2) % 3])
+                dvec = Q - P
+                assert abs((mid - P)[0] * dvec[1] - (mid - P)[1] * dvec[0]) < 1e-14
+
+
+def test_stencil_list_against_bruteforce():
+    for n in (2, 3):
+        v, t = inputs.jittered_mesh(n, seed=n)
+        for bc in (BC_PERIODIC, BC_TRANSMISSIVE):
+            M = Mesh(v, t, bc, (1.0, 1.0))
+            _, nbr, info = connectivity_bruteforce(v, t, bc, (1.0, 1.0))
+            for e in range(M.K):
+                exp = []
+                for f in range(3):
+                    if info[e, f] & INFO_BOUNDARY:
+                        exp += [-1, 0, 0, 0]
+                    else:
+                        exp += [nbr[e, f], info[e, f] & 3, (info[e, f] >> 2) & 3, (info[e, f] >> 4) & 3]
+                assert csweno.stencil_list(M, e) == exp
+
+
+def test_linear_weights():
+    g = csweno.linear_weights(np.array([0.5, 2.0]), 3)
+    assert np.allclose(g[0], [1 / 7, 2 / 7, 4 / 7], rtol=1e-15)
+    assert np.allclose(g[1], [4 / 7, 2 / 7, 1 / 7], rtol=1e-15)
+    for t in (2, 3, 4):
+        gg = csweno.linear_weights(np.array([0.013, 0.7, 3.1]), t)
+        assert np.allclose(gg.sum(-1), 1.0, rtol=0, atol=1e-15)
+        assert np.all(gg > 0)
+
+
+def test_beta_closed_form():
+    """On the unit right triangle (area 1/2): q linear with gradient g gives
+    beta = |g|^2/2; q = x^2 gives 4 int x^2 + |D0| 4 |D0| = 1/3 + 1 = 4/3."""
+    V0 = np.array([[[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]])
+    x0 = np.array([1 / 3])
+    y0 = np.array([1 / 3])
+    h0 = np.array([(2 + math.sqrt(2)) / 3])
+    area = np.array([0.5])
+    B = csweno._beta_matrix(V0, x0, y0, h0, area, 2)[0]
+    g = np.array([0.3, -0.8])
+    c = np.array([g[0] * h0[0], g[1] * h0[0], 0, 0, 0])
+    assert math.isclose(c @ B @ c, (g @ g) / 2, rel_tol=1e-13)
+    # x = x0 + h0 xi: x^2 = const + 2 x0 h0 xi + h0^2 xi^2
+    c = np.array([2 * x0[0] * h0[0], 0, h0[0] ** 2, 0, 0])
+    assert math.isclose(c @ B @ c, 4.0 / 3.0, rel_tol=1e-13)
+
+
+@pytest.mark.parametrize("N,deg", [(1, 1), (2, 2), (3, 3)])
+def test_least_squares_levels_reproduce_polynomials(N, deg):
+    M = _mesh(7)
+    d = DG(M, N, 0)
+    coef = {1: (0.2, 0.5, -0.3, 0, 0, 0), 2: (0.2, 0.5, -0.3, 0.4, -0.2, 0.3),
+            3: (0.2, 0.5, -0.3, 0.4, -0.2, 0.3)}[deg]
+
+    def u(x, y):
+        val = coef[0] + coef[1] * x + coef[2] * y + coef[3] * x * x + coef[4] * x * y + coef[5] * y * y
+        if deg == 3:
+            val = val + 0.25 * x ** 3 - 0.1 * x * y * y
+        return val
+
+    U = d.project(u)
+    E = _interior(M)
+    out, info = csweno.reconstruct(d, U, E, linear_only=True, return_info=True)
+    # the top level (degree >= data degree) reproduces the data exactly, and
+    # with omega = gamma the reconstruction telescopes to it
+    assert np.abs(out - U[E]).max() < 1e-11
+    # telescoping identity sum_l gamma_{l,top} p_l = q_top
+    tel = sum(info["gamma"][:, l, None, None] * info["ps"][l] for l in range(len(info["ps"])))
+    assert np.abs(tel - info["qs"][-1]).max() < 1e-10
+    # lower levels reproduce data of their own degree
+    if deg == 1:
+        for l in (1, 2):
+            assert np.abs(info["qs"][l] - info["qs"][-1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("eq", [0, 1])
+def test_linear_data_reproduced_by_nonlinear_weights(N, eq):
+    """Linear data: all smoothness indicators coincide, tau = 0, omega =
+    gamma and the reconstruction returns the data (the identity on linear
+    states is what fixes beta to be taken of q_l)."""
+    M = _mesh(6)
+    d = DG(M, N, eq)
+    if eq == 0:
+        U = d.project(lambda x, y: 0.4 + 0.7 * x - 0.5 * y)
+    else:
+        U = d.project(lambda x, y: np.stack([1.0 + 0.2 * x - 0.1 * y, 0.3 + 0.1 * x, -0.2 + 0.05 * y,
+                                             2.5 + 0.1 * x + 0.2 * y], -1))
+    E = _interior(M)
+    out, info = csweno.reconstruct(d, U, E, return_info=True)
+    assert np.abs(out - U[E]).max() < 1e-11
+    om = np.stack(info["omega"], 1)
+    assert np.allclose(om.sum(1), 1.0, atol=1e-15)
+    assert np.allclose(om, info["gamma"][:, :, None], atol=1e-9)
+
+
+def test_quadratic_data_changes_nonlinear_weights():
+    """Property of the method: for quadratic data the linear level q_2 is an
+    inexact least-squares fit, so beta_2 differs from the top beta, tau > 0
+    and omega differs from gamma."""
+    M = _mesh(6)
+    d = DG(M, 2, 0)
+    U = d.project(lambda x, y: 0.4 + 0.7 * x - 0.5 * y + 2.0 * x * x)
+    E = _interior(M)
+    out, info = csweno.reconstruct(d, U, E, return_info=True)
+    assert np.all(info["tau"] > 0)
+    om = np.stack(info["omega"], 1)
+    assert np.allclose(om.sum(1), 1.0, atol=1e-15)
+
+
+def test_mean_retained_and_untroubled_cells_untouched():
+    M = _mesh(6, BC_PERIODIC)
+    for eq in (0, 1):
+        d = DG(M, 2, eq)
+        ic = inputs.BurgersSine(k=2 * math.pi) if eq == 0 else inputs.FourQuadrant(seed=3)
+        U = d.project(ic)
+        mask = np.zeros(M.K, bool)
+        mask[::3] = True
+        out = csweno.limit(d, U, mask)
+        assert np.array_equal(out[:, :, 0], U[:, :, 0])
+        assert np.array_equal(out[~mask], U[~mask])
+        assert not np.array_equal(out[mask], U[mask])
+
+
+@pytest.mark.parametrize("N,ns", [(1, (16, 32)), (2, (32, 64)), (3, (32, 64))])
+def test_single_application_keeps_design_order(N, ns):
+    """Smooth data, every cell troubled: the limited field stays within
+    O(h^{N+1}) of the exact solution (the accuracy claim of Section 4.1)."""
+    ic = inputs.BurgersSine()
+    errs = []
+    for n in ns:
+        v, t = inputs.jittered_mesh(n, -2, 2, -2, 2, seed=7)
+        M = Mesh(v, t, BC_PERIODIC, (4.0, 4.0))
+        d = DG(M, N, 0)
+        U = d.project(ic)
+        out = csweno.limit(d, U, np.ones(M.K, bool))
+        errs.append(d.errors(out, ic)[0])
+    order = math.log2(errs[0] / errs[1])
+    assert order > N + 1 - 0.3, (errs, order)
+
+
+def test_burgers_p1_convergence_with_limiter():
+    orders = oracle_runs.load_orders()
+    _, o = oracle_runs.convergence("burgers", 1, [16, 32], 0.1, True)
+    assert abs(o[-1] - orders[(1, 1)][1]) < 0.45, o
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_mirror_ghost_reproduces_tangential_linear_data(N):
+    """u = a + b y is even under reflection across the vertical walls x = 0
+    and x = 1, so the mirror ghosts there carry the same linear function and
+    cells touching only those walls are reproduced exactly."""
+    M = _mesh(6)
+    d = DG(M, N, 0)
+    U = d.project(lambda x, y: 0.3 + 0.8 * y)
+    bnd = (M.info & INFO_BOUNDARY) != 0
+    c = M.centroid
+    sel = []
+    for e in range(M.K):
+        faces = np.nonzero(bnd[e])[0]
+        if len(faces) == 0:
+            continue
+        vertical = all(abs(M.nx[e, f]) == 1.0 for f in faces)
+        # the neighbours' own boundary faces must be vertical too
+        nb_ok = all(np.all(np.abs(M.nx[M.nbr[e, f]][bnd[M.nbr[e, f]]]) == 1.0)
+                    for f in range(3) if not bnd[e, f])
+        if vertical and nb_ok and 0.2 < c[e, 1] < 0.8:
+            sel.append(e)
+    sel = np.array(sel)
+    assert len(sel) > 4
+    out = csweno.reconstruct(d, U, sel)
+    assert np.abs(out - U[sel]).max() < 1e-11
