@@ -1,0 +1,196 @@
+/*
+ * cswdg.h -- C ABI of the MI355X (gfx950) library for one SSP-RK3 stage of
+ * the Runge-Kutta discontinuous Galerkin operator on unstructured
+ * triangles followed by the compact subcell WENO (CSWENO) limiter
+ * (Kochi & Ramakrishna, "A compact subcell WENO limiting strategy using
+ * immediate neighbors for Runge-Kutta discontinuous Galerkin methods for
+ * unstructured meshes").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns 0 (CSWDG_OK) or a negative CSWDG_E* code;
+ * cswdg_last_error() gives a message.  No C++ exception crosses the ABI.
+ *
+ * Coefficients: modal coefficients in the orthonormal basis of Section 2
+ * (eq. triangleBasis; Jacobi polynomials L2-normalised, 1-based index
+ * m = j + (N+1) i + 1 - i(i-1)/2 stored at position m-1), on each
+ * triangle's affine map x(r,s) = v0 + (1+r)/2 (v1-v0) + (1+s)/2 (v2-v0)
+ * from the reference triangle {r,s >= -1, r+s <= 0}, using the vertex order
+ * after the counter-clockwise fix of cswdg_mesh_upload.  The cell mean is
+ * coefficient 0 divided by sqrt(2).
+ *
+ * State layout (device memory, caller-owned): [m][Np][K] contiguous, element
+ * index fastest; m = 1 (Burgers) or 4 (Euler: rho, rho u, rho v, E);
+ * Np = (N+1)(N+2)/2; element type double (precision 0) or float
+ * (precision 1, "FP32-bulk": state in float, limiter arithmetic in double).
+ *
+ * Streams: every call that takes device pointers is enqueued on the
+ * solver's HIP stream (given at creation; NULL = default stream) and
+ * returns without waiting, except the calls marked "synchronous".
+ *
+ * Mesh conventions: a triangle whose signed area is negative has its local
+ * vertices 1 and 2 swapped (reported through cswdg_mesh_info, not an error);
+ * a zero-area triangle, an edge shared by more than two triangles, two
+ * neighbours traversing their shared edge in the same direction, and (for
+ * periodic meshes) a boundary edge without exactly one partner one period
+ * away are errors (CSWDG_EBADMESH).  Local face f joins local vertices f and
+ * f+1 (mod 3).  Connectivity info byte: bits 0-1 the neighbour's local face,
+ * bits 2-3 / 4-5 the x / y shift code (0 none, 1 add +period, 2 add -period
+ * to the neighbour's coordinates to place it next to the element), bit 6 set
+ * on a transmissive boundary face (neighbour id -1).
+ */
+#ifndef CSWDG_H
+#define CSWDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSWDG_OK 0
+#define CSWDG_EINVAL (-1)   /* bad argument (null pointer, size, enum value) */
+#define CSWDG_EBADMESH (-2) /* mesh rejected by validation */
+#define CSWDG_ERANK (-3)    /* a stencil least-squares system is rank deficient */
+#define CSWDG_EHIP (-4)     /* a HIP runtime call failed */
+#define CSWDG_ESTATE (-5)   /* call out of order (e.g. no mesh uploaded yet) */
+#define CSWDG_ENOMEM (-6)   /* device allocation failed */
+
+#define CSWDG_EQ_BURGERS 0
+#define CSWDG_EQ_EULER 1
+
+#define CSWDG_BC_PERIODIC 0
+#define CSWDG_BC_TRANSMISSIVE 1
+
+#define CSWDG_LIMIT_KXRCF 0 /* limit the cells the KXRCF indicator flags (Section 3.1) */
+#define CSWDG_LIMIT_ALL 1   /* mark every cell troubled (the accuracy tests of Section 4.1) */
+#define CSWDG_LIMIT_NONE 2  /* no limiter */
+
+#define CSWDG_STATUS_NONFINITE 0x1u /* a NaN/Inf coefficient was produced */
+#define CSWDG_STATUS_NEGATIVE 0x2u  /* a non-positive Euler cell-mean density or pressure */
+#define CSWDG_STATUS_RANK 0x4u      /* a stencil least-squares system was rank deficient */
+#define CSWDG_STATUS_FOOT 0x8u      /* a perpendicular foot fell outside its side (midpoint used) */
+
+typedef struct cswdg_solver cswdg_solver;
+
+/* Parameters.  Zero-initialise and set what you need; a zero/negative value
+ * selects the default shown. */
+typedef struct cswdg_params {
+    int equation;     /* CSWDG_EQ_BURGERS (eq. 2dBurgers) or CSWDG_EQ_EULER (eq. 2dEulerEquations) */
+    int degree;       /* N = 1, 2 or 3 (Section 2, eq. modalForm2D) */
+    int precision;    /* 0 FP64 everywhere; 1 FP32 state/residual/indicator, FP64 limiter */
+    int limiter_mode; /* CSWDG_LIMIT_* used by cswdg_ssprk3_step (default KXRCF) */
+    double gas_gamma; /* ratio of specific heats, default 1.4 (Section 4) */
+    double cfl;       /* default 0.3/(2N+1) */
+    double c_k;       /* KXRCF threshold C_K, default 1 (Section 3.1) */
+    double eps_weno;  /* epsilon of the nonlinear weights, default 1e-10 (Section 3.2) */
+} cswdg_params;
+
+/* Create a solver bound to the current HIP device and to hip_stream
+ * (a hipStream_t; NULL = default stream).  *out receives the handle. */
+int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** out);
+int cswdg_destroy(cswdg_solver* s);
+/* Message of the last error on s (or of the last failed cswdg_create /
+ * host-only call when s is NULL).  Valid until the next call on s. */
+const char* cswdg_last_error(const cswdg_solver* s);
+
+/* Upload a triangulation (Section 2, eq. triangulation): host arrays
+ * vxy [nv][2] (double) and tri [nt][3] (int32 vertex ids), read
+ * synchronously and not retained.  bc = CSWDG_BC_*; period_x/period_y are
+ * the domain periods for periodic meshes (ignored otherwise).  Builds the
+ * connectivity on the host, the element geometry and the per-element
+ * stencil operators of the limiter on the device.  Synchronous. */
+int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt,
+                      const int32_t* tri, int bc, double period_x, double period_y);
+
+/* Number of elements, number of triangles re-oriented by the CCW fix. */
+int cswdg_mesh_info(const cswdg_solver* s, int64_t* n_elements, int64_t* n_flipped);
+
+/* Host-only connectivity builder (no device needed): tri_ccw [nt][3]
+ * receives the re-oriented triangles, nbr [nt][3] and info [nt][3] the
+ * tables described above.  Same rules as cswdg_mesh_upload. */
+int cswdg_host_connectivity(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc,
+                            double period_x, double period_y, int32_t* tri_ccw, int32_t* nbr,
+                            uint8_t* info);
+
+/* Copy the uploaded connectivity to host arrays nbr [nt][3], info [nt][3].
+ * Synchronous. */
+int cswdg_connectivity(const cswdg_solver* s, int32_t* nbr, uint8_t* info);
+
+/* Limiter stencil of element elem (Section 3.2, Fig. 1): for faces f = 0..2
+ * the 4 ints (neighbour id or -1 for the mirror ghost of a transmissive
+ * face, neighbour's shared face, x shift code, y shift code); *n = 12.
+ * Subcell order per neighbour: Delta_i1 (touching the element), Delta_i2,
+ * Delta_i3 in counter-clockwise order; for N >= 2 Delta_i2 and Delta_i3 are
+ * cut at the foot of the perpendicular from the neighbour's centroid.
+ * ids is a host array of at least 12 ints.  Synchronous. */
+int cswdg_stencil(const cswdg_solver* s, int32_t elem, int32_t* ids, int32_t* n);
+
+/* Physical coordinates of the projection quadrature points: xy is a device
+ * array [2][nq][K] (double); *nq receives nq.  With xy = NULL only *nq is
+ * set.  Used with cswdg_project to load initial data. */
+int cswdg_ic_points(cswdg_solver* s, double* xy, int32_t* nq);
+/* L2 projection (Section 2, eq. modalForm2D with eq. massMatrix2D) of point
+ * values vals [m][nq][K] (device, double) at the cswdg_ic_points onto the
+ * basis: u (device, state layout). */
+int cswdg_project(cswdg_solver* s, const double* vals, void* u);
+
+/* r = L(u) (Section 2, eq. weakFormScheme2D read as the triangle weak form:
+ * volume quadrature of grad psi . F(u_h), edge quadrature of the local
+ * Lax-Friedrichs flux, times the inverse mass matrix 1/J).  u, r: device,
+ * state layout, distinct buffers. */
+int cswdg_dg_residual(cswdg_solver* s, const void* u, void* r);
+
+/* *dt_dev (device double) = CFL * min_e(2 r_e) / max_e a(ubar_e) with r_e the
+ * inradius and a the cell-mean wave speed (Burgers sqrt(2)|u|, Euler
+ * |v| + c). */
+int cswdg_max_dt(cswdg_solver* s, const void* u, double* dt_dev);
+
+/* KXRCF indicator (Section 3.1, eq. troubledCellIndicator): flags [K]
+ * (device uint8, 1 = troubled, R > C_K) and optionally R [K] (device double,
+ * may be NULL). */
+int cswdg_kxrcf(cswdg_solver* s, const void* u, uint8_t* flags, double* R);
+
+/* CSWENO limiter (Section 3.2).  Reads u_in, writes u_out (distinct
+ * buffers; every troubled cell reads the pre-limit field).  Troubled cells:
+ * mask_in (device uint8 [K], nonzero = troubled) when not NULL, otherwise
+ * the KXRCF flags.  Cell means are copied bitwise; untroubled cells are
+ * copied.  flags_out (device uint8 [K]) receives the mask used; may be NULL. */
+int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* flags_out,
+                       const uint8_t* mask_in);
+
+/* One stage of the table:tvd third-order RK (end of Section 3) followed by
+ * the limiter: out = a u_n + b (u_prev + dt L(u_prev)) with
+ * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 1, 2, 3, then limited
+ * in place according to params.limiter_mode.  dt_dev: device double.  out
+ * must not alias u_prev; out may alias u_n (stage 3 of an in-place step). */
+int cswdg_rk_stage(cswdg_solver* s, int stage, const void* u_n, const void* u_prev, void* out,
+                   const double* dt_dev);
+
+/* One full SSP-RK3 step in place on u (device, state layout), limiter after
+ * every stage.  dt_dev: device double, or NULL to compute it with
+ * cswdg_max_dt from u at the start of the step (kept in the solver; see
+ * cswdg_last_dt). */
+int cswdg_ssprk3_step(cswdg_solver* s, void* u, const double* dt_dev);
+/* Device pointer to the solver's last computed dt (valid for its lifetime). */
+int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
+
+/* Troubled-cell count of the last limiter call (host int, synchronous). */
+int cswdg_troubled_count(cswdg_solver* s, int64_t* count);
+/* Accumulated status bits CSWDG_STATUS_* since the last call (synchronous;
+ * clears them). */
+int cswdg_status(cswdg_solver* s, uint32_t* flags);
+
+/* Kernel timing with HIP events recorded around every launch on the
+ * solver's stream.  enable = 1 starts (and clears) recording.
+ * cswdg_kernel_times fills up to cap entries: names (static strings),
+ * total milliseconds and launch counts; *n receives the number of kernel
+ * classes.  Synchronous. */
+int cswdg_profile(cswdg_solver* s, int enable);
+int cswdg_kernel_times(cswdg_solver* s, const char** names, double* total_ms, int64_t* counts,
+                       int cap, int* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

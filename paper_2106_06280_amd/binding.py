@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libcswdg.so (include/cswdg.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+stream; every step of the computation runs in the library's kernels.  The
+binding raises if the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcswdg.so")
+
+EQ_BURGERS, EQ_EULER = 0, 1
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+LIMIT_KXRCF, LIMIT_ALL, LIMIT_NONE = 0, 1, 2
+STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_RANK, STATUS_FOOT = 1, 2, 4, 8
+
+_lib = None
+
+
+class CswdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cswdg error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("equation", ctypes.c_int), ("degree", ctypes.c_int), ("precision", ctypes.c_int),
+                ("limiter_mode", ctypes.c_int), ("gas_gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("c_k", ctypes.c_double), ("eps_weno", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SIGS = {
+    "cswdg_create": (ctypes.c_int, [ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
+    "cswdg_destroy": (ctypes.c_int, [_P]),
+    "cswdg_last_error": (ctypes.c_char_p, [_P]),
+    "cswdg_mesh_upload": (ctypes.c_int, [_P, _I64, _P, _I64, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    "cswdg_mesh_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "cswdg_host_connectivity": (ctypes.c_int, [_I64, _P, _I64, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "cswdg_connectivity": (ctypes.c_int, [_P, _P, _P]),
+    "cswdg_stencil": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "cswdg_ic_points": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "cswdg_project": (ctypes.c_int, [_P, _P, _P]),
+    "cswdg_dg_residual": (ctypes.c_int, [_P, _P, _P]),
+    "cswdg_max_dt": (ctypes.c_int, [_P, _P, _P]),
+    "cswdg_kxrcf": (ctypes.c_int, [_P, _P, _P, _P]),
+    "cswdg_csweno_limit": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "cswdg_rk_stage": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
+    "cswdg_ssprk3_step": (ctypes.c_int, [_P, _P, _P]),
+    "cswdg_last_dt": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "cswdg_troubled_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "cswdg_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
+    "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python paper_2106_06280_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, handle=None):
+    if rc != 0:
+        msg = lib().cswdg_last_error(handle)
+        raise CswdgError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def host_connectivity(vxy, tri, bc, period=(0.0, 0.0)):
+    """Host-only connectivity builder: (tri_ccw, nbr, info) as numpy arrays."""
+    vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    K = tri.shape[0]
+    tc = np.zeros((K, 3), np.int32)
+    nbr = np.zeros((K, 3), np.int32)
+    info = np.zeros((K, 3), np.uint8)
+    rc = lib().cswdg_host_connectivity(vxy.shape[0], vxy.ctypes.data, K, tri.ctypes.data, bc,
+                                       float(period[0]), float(period[1]), tc.ctypes.data,
+                                       nbr.ctypes.data, info.ctypes.data)
+    _check(rc, None)
+    return tc, nbr, info
+
+
+class Solver:
+    """One solver = one equation, degree and mesh on the current GPU."""
+
+    def __init__(self, equation, degree, limiter_mode=LIMIT_KXRCF, precision=0, gamma=1.4, cfl=0.0,
+                 c_k=0.0, eps=0.0, stream=None):
+        import torch
+        self.torch = torch
+        p = Params(equation, degree, precision, limiter_mode, gamma, cfl, c_k, eps)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().cswdg_create(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None)
+        self.h = h
+        self.equation, self.degree = equation, degree
+        self.m = 1 if equation == EQ_BURGERS else 4
+        self.Np = (degree + 1) * (degree + 2) // 2
+        self.K = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().cswdg_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _c(self, rc):
+        _check(rc, self.h)
+
+    # -- mesh ------------------------------------------------------------
+    def mesh_upload(self, vxy, tri, bc, period=(0.0, 0.0)):
+        vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self._c(lib().cswdg_mesh_upload(self.h, vxy.shape[0], vxy.ctypes.data, tri.shape[0], tri.ctypes.data,
+                                        bc, float(period[0]), float(period[1])))
+        self.K = tri.shape[0]
+
+    def mesh_info(self):
+        k, f = _I64(), _I64()
+        self._c(lib().cswdg_mesh_info(self.h, ctypes.byref(k), ctypes.byref(f)))
+        return k.value, f.value
+
+    def connectivity(self):
+        nbr = np.zeros((self.K, 3), np.int32)
+        info = np.zeros((self.K, 3), np.uint8)
+        self._c(lib().cswdg_connectivity(self.h, nbr.ctypes.data, info.ctypes.data))
+        return nbr, info
+
+    def stencil(self, e):
+        ids = np.zeros(12, np.int32)
+        n = ctypes.c_int32()
+        self._c(lib().cswdg_stencil(self.h, int(e), ids.ctypes.data, ctypes.byref(n)))
+        return ids[: n.value].tolist()
+
+    # -- state helpers ----------------------------------------------------
+    def empty_state(self):
+        return self.torch.empty((self.m, self.Np, self.K), dtype=self.torch.float64, device="cuda")
+
+    def to_device(self, u_kmn):
+        """Oracle layout [K, m, Np] (numpy) -> device layout [m, Np, K]."""
+        a = np.ascontiguousarray(np.transpose(np.asarray(u_kmn, dtype=np.float64), (1, 2, 0)))
+        return self.torch.from_numpy(a).to("cuda")
+
+    @staticmethod
+    def to_host(u):
+        """Device layout [m, Np, K] -> numpy [K, m, Np]."""
+        return np.ascontiguousarray(np.transpose(u.detach().cpu().numpy(), (2, 0, 1)))
+
+    def ic_points(self):
+        nq = ctypes.c_int32()
+        self._c(lib().cswdg_ic_points(self.h, None, ctypes.byref(nq)))
+        xy = self.torch.empty((2, nq.value, self.K), dtype=self.torch.float64, device="cuda")
+        self._c(lib().cswdg_ic_points(self.h, _ptr(xy), ctypes.byref(nq)))
+        return xy
+
+    def project(self, vals):
+        """vals [m, nq, K] device double -> coefficients."""
+        vals = vals.contiguous()
+        u = self.empty_state()
+        self._c(lib().cswdg_project(self.h, _ptr(vals), _ptr(u)))
+        return u
+
+    def project_fn(self, fn):
+        """Evaluate fn(x, y) (numpy, pointwise) at the projection points and project."""
+        xy = self.ic_points().cpu().numpy()
+        v = np.asarray(fn(xy[0], xy[1]), dtype=np.float64)
+        if v.ndim == 2:
+            v = v[None]
+        else:
+            v = np.moveaxis(v, -1, 0)
+        return self.project(self.torch.from_numpy(np.ascontiguousarray(v)).to("cuda"))
+
+    # -- operators --------------------------------------------------------
+    def dg_residual(self, u, r=None):
+        if r is None:
+            r = self.empty_state()
+        self._c(lib().cswdg_dg_residual(self.h, _ptr(u), _ptr(r)))
+        return r
+
+    def max_dt(self, u, dt=None):
+        if dt is None:
+            dt = self.torch.zeros(1, dtype=self.torch.float64, device="cuda")
+        self._c(lib().cswdg_max_dt(self.h, _ptr(u), _ptr(dt)))
+        return dt
+
+    def kxrcf(self, u, want_R=True):
+        flags = self.torch.zeros(self.K, dtype=self.torch.uint8, device="cuda")
+        R = self.torch.zeros(self.K, dtype=self.torch.float64, device="cuda") if want_R else None
+        self._c(lib().cswdg_kxrcf(self.h, _ptr(u), _ptr(flags), _ptr(R)))
+        return flags, R
+
+    def csweno_limit(self, u_in, u_out=None, mask=None):
+        if u_out is None:
+            u_out = self.empty_state()
+        flags = self.torch.zeros(self.K, dtype=self.torch.uint8, device="cuda")
+        m = None
+        if mask is not None:
+            m = mask.to(device="cuda", dtype=self.torch.uint8).contiguous()
+        self._c(lib().cswdg_csweno_limit(self.h, _ptr(u_in), _ptr(u_out), _ptr(flags), _ptr(m)))
+        return u_out, flags
+
+    def rk_stage(self, stage, u_n, u_prev, out, dt):
+        self._c(lib().cswdg_rk_stage(self.h, int(stage), _ptr(u_n), _ptr(u_prev), _ptr(out), _ptr(dt)))
+        return out
+
+    def ssprk3_step(self, u, dt=None):
+        self._c(lib().cswdg_ssprk3_step(self.h, _ptr(u), _ptr(dt)))
+        return u
+
+    def last_dt_ptr(self):
+        p = ctypes.c_void_p()
+        self._c(lib().cswdg_last_dt(self.h, ctypes.byref(p)))
+        return p.value
+
+    def troubled_count(self):
+        c = _I64()
+        self._c(lib().cswdg_troubled_count(self.h, ctypes.byref(c)))
+        return c.value
+
+    def status(self):
+        v = ctypes.c_uint32()
+        self._c(lib().cswdg_status(self.h, ctypes.byref(v)))
+        return v.value
+
+    def profile(self, enable=True):
+        self._c(lib().cswdg_profile(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        cap = 16
+        names = (ctypes.c_char_p * cap)()
+        tot = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        n = ctypes.c_int()
+        self._c(lib().cswdg_kernel_times(self.h, names, tot, cnt, cap, ctypes.byref(n)))
+        return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(n.value, cap))}

@@ -1,0 +1,483 @@
+// C ABI of the library (declared in include/cswdg.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace cswdg;
+
+namespace {
+
+thread_local std::string g_err;
+
+const char* kKernelNames[] = {"residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero", "project"};
+enum KernelId { KID_RESIDUAL = 0, KID_DT, KID_KXRCF, KID_COMPACT, KID_LIMITER, KID_SCATTER, KID_COPY, KID_ZERO, KID_PROJECT, KID_COUNT };
+
+std::mutex g_dev_mutex;
+std::vector<int> g_dev_tables;  // devices whose constant tables are uploaded
+
+}  // namespace
+
+struct cswdg_solver {
+    cswdg_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    LaunchCtx ctx{};
+    bool has_mesh = false;
+    HostMesh mesh;
+    DevMesh dm{};
+    int M = 1, NP = 3;
+    size_t state_elems = 0;
+    double* d_vx = nullptr;
+    double* d_vy = nullptr;
+    int32_t* d_nbr = nullptr;
+    uint32_t* d_info = nullptr;
+    double* d_ops = nullptr;
+    uint8_t* d_flags = nullptr;
+    int32_t* d_list = nullptr;
+    uint32_t* d_count = nullptr;   // [0] troubled count
+    uint32_t* d_status = nullptr;
+    double* d_compact = nullptr;
+    double* d_partial = nullptr;
+    double* d_dt = nullptr;
+    void* d_T1 = nullptr;
+    void* d_T2 = nullptr;
+    int dt_blocks = 1024;
+    int64_t n_rank = 0, n_foot = 0;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> recs;  // kernel id, event index of the start
+};
+
+namespace {
+
+int fail(cswdg_solver* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    g_err = msg;
+    return code;
+}
+
+int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
+    return fail(s, CSWDG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void free_mesh(cswdg_solver* s) {
+    void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
+                    s->d_status, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    s->d_vx = s->d_vy = nullptr;
+    s->d_nbr = nullptr;
+    s->d_info = nullptr;
+    s->d_ops = nullptr;
+    s->d_flags = nullptr;
+    s->d_list = nullptr;
+    s->d_count = s->d_status = nullptr;
+    s->d_compact = s->d_partial = s->d_dt = nullptr;
+    s->d_T1 = s->d_T2 = nullptr;
+    s->has_mesh = false;
+}
+
+template <class F>
+hipError_t timed(cswdg_solver* s, int kid, F&& f) {
+    if (!s->prof || s->ev_used + 2 > s->ev_pool.size()) return f();
+    size_t i = s->ev_used;
+    s->ev_used += 2;
+    (void)hipEventRecord(s->ev_pool[i], s->stream);
+    hipError_t r = f();
+    (void)hipEventRecord(s->ev_pool[i + 1], s->stream);
+    s->recs.push_back({kid, i});
+    return r;
+}
+
+int check_ready(cswdg_solver* s) {
+    if (!s) return fail(nullptr, CSWDG_EINVAL, "null solver");
+    if (!s->has_mesh) return fail(s, CSWDG_ESTATE, "no mesh uploaded");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(s, CSWDG_EHIP, "hipSetDevice failed");
+    return CSWDG_OK;
+}
+
+// limit `buf` in place: troubled list from mask or KXRCF, limiter reading
+// `src` (the pre-limit field), scatter into buf
+int limit_into(cswdg_solver* s, const void* src, void* buf, uint8_t* flags_out, const uint8_t* mask,
+               int mode, bool count_zeroed) {
+    hipError_t e;
+    const int K = (int)s->mesh.K;
+    if (mode == CSWDG_LIMIT_NONE) return CSWDG_OK;
+    uint8_t* flags = flags_out ? flags_out : s->d_flags;
+    if (!count_zeroed) {
+        e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, 1); });
+        if (e != hipSuccess) return hipfail(s, e, "zero");
+    }
+    if (mask || mode == CSWDG_LIMIT_ALL) {
+        e = timed(s, KID_COMPACT, [&] { return launch_compact_mask(s->ctx, K, mask, flags, s->d_list, s->d_count); });
+    } else {
+        e = timed(s, KID_KXRCF, [&] { return launch_kxrcf(s->ctx, s->dm, src, flags, nullptr, s->d_list, s->d_count); });
+    }
+    if (e != hipSuccess) return hipfail(s, e, "troubled-cell list");
+    e = timed(s, KID_LIMITER, [&] {
+        return launch_limiter(s->ctx, s->dm, src, s->d_ops, s->d_list, s->d_count, s->d_compact, s->d_status, K);
+    });
+    if (e != hipSuccess) return hipfail(s, e, "limiter");
+    e = timed(s, KID_SCATTER, [&] { return launch_scatter(s->ctx, K, buf, s->d_list, s->d_count, s->d_compact, K); });
+    if (e != hipSuccess) return hipfail(s, e, "scatter");
+    return CSWDG_OK;
+}
+
+int rk_stage_impl(cswdg_solver* s, int stage, const void* u_n, const void* u_prev, void* out, const double* dt) {
+    hipError_t e = timed(s, KID_RESIDUAL, [&] {
+        return launch_residual_reset(s->ctx, s->dm, stage, u_prev, u_n, out, dt, s->d_count);
+    });
+    if (e != hipSuccess) return hipfail(s, e, "residual");
+    return limit_into(s, out, out, nullptr, nullptr, s->p.limiter_mode, true);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** out) {
+    if (!params || !out) return fail(nullptr, CSWDG_EINVAL, "null argument");
+    *out = nullptr;
+    cswdg_params p = *params;
+    if (p.equation != CSWDG_EQ_BURGERS && p.equation != CSWDG_EQ_EULER)
+        return fail(nullptr, CSWDG_EINVAL, "equation must be CSWDG_EQ_BURGERS or CSWDG_EQ_EULER");
+    if (p.degree < 1 || p.degree > 3) return fail(nullptr, CSWDG_EINVAL, "degree must be 1, 2 or 3");
+    if (p.precision != 0) return fail(nullptr, CSWDG_EINVAL, "only precision 0 (FP64) is implemented");
+    if (p.limiter_mode < 0 || p.limiter_mode > 2) return fail(nullptr, CSWDG_EINVAL, "bad limiter_mode");
+    if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
+    if (!(p.cfl > 0)) p.cfl = 0.3 / (2 * p.degree + 1);
+    if (!(p.c_k > 0)) p.c_k = 1.0;
+    if (!(p.eps_weno > 0)) p.eps_weno = 1e-10;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, CSWDG_EHIP, "hipGetDevice failed (no GPU?)");
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mutex);
+        if (std::find(g_dev_tables.begin(), g_dev_tables.end(), dev) == g_dev_tables.end()) {
+            int rc = upload_tables_device();
+            if (rc != CSWDG_OK) return fail(nullptr, rc, "constant table upload failed");
+            g_dev_tables.push_back(dev);
+        }
+    }
+    cswdg_solver* s = new (std::nothrow) cswdg_solver();
+    if (!s) return fail(nullptr, CSWDG_ENOMEM, "out of host memory");
+    s->p = p;
+    s->stream = (hipStream_t)hip_stream;
+    s->device = dev;
+    s->M = p.equation == CSWDG_EQ_EULER ? 4 : 1;
+    s->NP = n_modes(p.degree);
+    s->ctx.stream = s->stream;
+    s->ctx.eq = p.equation;
+    s->ctx.N = p.degree;
+    s->ctx.precision = p.precision;
+    s->ctx.gamma = p.gas_gamma;
+    s->ctx.cfl = p.cfl;
+    s->ctx.c_k = p.c_k;
+    s->ctx.eps = p.eps_weno;
+    *out = s;
+    return CSWDG_OK;
+}
+
+int cswdg_destroy(cswdg_solver* s) {
+    if (!s) return CSWDG_OK;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    free_mesh(s);
+    for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
+    delete s;
+    return CSWDG_OK;
+}
+
+const char* cswdg_last_error(const cswdg_solver* s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+int cswdg_host_connectivity(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc, double px,
+                            double py, int32_t* tri_ccw, int32_t* nbr, uint8_t* info) {
+    if (!tri_ccw || !nbr || !info) return fail(nullptr, CSWDG_EINVAL, "null output");
+    HostMesh m;
+    std::string msg;
+    int rc = build_mesh(nv, vxy, nt, tri, bc, px, py, m, msg);
+    if (rc != CSWDG_OK) return fail(nullptr, rc, msg);
+    std::memcpy(tri_ccw, m.tri.data(), sizeof(int32_t) * 3 * nt);
+    std::memcpy(nbr, m.nbr.data(), sizeof(int32_t) * 3 * nt);
+    std::memcpy(info, m.info.data(), 3 * nt);
+    return CSWDG_OK;
+}
+
+int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc,
+                      double px, double py) {
+    if (!s) return fail(nullptr, CSWDG_EINVAL, "null solver");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(s, CSWDG_EHIP, "hipSetDevice failed");
+    (void)hipStreamSynchronize(s->stream);
+    free_mesh(s);
+    std::string msg;
+    int rc = build_mesh(nv, vxy, nt, tri, bc, px, py, s->mesh, msg);
+    if (rc != CSWDG_OK) return fail(s, rc, msg);
+    const int64_t K = s->mesh.K;
+    std::vector<double> ops;
+    rc = build_limiter_ops(s->mesh, s->p.degree, ops, s->n_rank, s->n_foot);
+    if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
+    std::vector<int32_t> nbrT(3 * K);
+    std::vector<uint32_t> info4(K);
+    for (int64_t e = 0; e < K; ++e) {
+        uint32_t w = 0;
+        for (int f = 0; f < 3; ++f) {
+            nbrT[f * K + e] = s->mesh.nbr[3 * e + f];
+            w |= (uint32_t)s->mesh.info[3 * e + f] << (8 * f);
+        }
+        info4[e] = w;
+    }
+    const size_t NPM = (size_t)s->M * s->NP;
+    s->state_elems = NPM * K;
+    struct A {
+        void** p;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&s->d_vx, sizeof(double) * 3 * K},
+        {(void**)&s->d_vy, sizeof(double) * 3 * K},
+        {(void**)&s->d_nbr, sizeof(int32_t) * 3 * K},
+        {(void**)&s->d_info, sizeof(uint32_t) * K},
+        {(void**)&s->d_ops, sizeof(double) * ops.size()},
+        {(void**)&s->d_flags, (size_t)K},
+        {(void**)&s->d_list, sizeof(int32_t) * K},
+        {(void**)&s->d_count, sizeof(uint32_t) * 4},
+        {(void**)&s->d_status, sizeof(uint32_t) * 4},
+        {(void**)&s->d_compact, sizeof(double) * NPM * K},
+        {(void**)&s->d_partial, sizeof(double) * s->dt_blocks},
+        {(void**)&s->d_dt, sizeof(double) * 2},
+        {(void**)&s->d_T1, sizeof(double) * NPM * K},
+        {(void**)&s->d_T2, sizeof(double) * NPM * K},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            free_mesh(s);
+            return fail(s, CSWDG_ENOMEM, "device allocation failed");
+        }
+    }
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* d, const void* h, size_t b) {
+        if (e == hipSuccess) e = hipMemcpy(d, h, b, hipMemcpyHostToDevice);
+    };
+    cp(s->d_vx, s->mesh.vx.data(), sizeof(double) * 3 * K);
+    cp(s->d_vy, s->mesh.vy.data(), sizeof(double) * 3 * K);
+    cp(s->d_nbr, nbrT.data(), sizeof(int32_t) * 3 * K);
+    cp(s->d_info, info4.data(), sizeof(uint32_t) * K);
+    cp(s->d_ops, ops.data(), sizeof(double) * ops.size());
+    uint32_t zeros[4] = {0, 0, 0, 0};
+    cp(s->d_count, zeros, sizeof(zeros));
+    cp(s->d_status, zeros, sizeof(zeros));
+    if (e != hipSuccess) {
+        free_mesh(s);
+        return hipfail(s, e, "mesh upload");
+    }
+    s->dm.K = (int)K;
+    s->dm.vx = s->d_vx;
+    s->dm.vy = s->d_vy;
+    s->dm.nbr = s->d_nbr;
+    s->dm.info = s->d_info;
+    s->has_mesh = true;
+    return CSWDG_OK;
+}
+
+int cswdg_mesh_info(const cswdg_solver* s, int64_t* n_elements, int64_t* n_flipped) {
+    if (!s || !s->has_mesh) return fail(const_cast<cswdg_solver*>(s), CSWDG_ESTATE, "no mesh uploaded");
+    if (n_elements) *n_elements = s->mesh.K;
+    if (n_flipped) *n_flipped = s->mesh.n_flipped;
+    return CSWDG_OK;
+}
+
+int cswdg_connectivity(const cswdg_solver* s, int32_t* nbr, uint8_t* info) {
+    if (!s || !s->has_mesh) return fail(const_cast<cswdg_solver*>(s), CSWDG_ESTATE, "no mesh uploaded");
+    if (!nbr || !info) return fail(const_cast<cswdg_solver*>(s), CSWDG_EINVAL, "null output");
+    std::memcpy(nbr, s->mesh.nbr.data(), sizeof(int32_t) * 3 * s->mesh.K);
+    std::memcpy(info, s->mesh.info.data(), 3 * s->mesh.K);
+    return CSWDG_OK;
+}
+
+int cswdg_stencil(const cswdg_solver* s, int32_t elem, int32_t* ids, int32_t* n) {
+    if (!s || !s->has_mesh) return fail(const_cast<cswdg_solver*>(s), CSWDG_ESTATE, "no mesh uploaded");
+    if (!ids || !n || elem < 0 || elem >= s->mesh.K) return fail(const_cast<cswdg_solver*>(s), CSWDG_EINVAL, "bad element");
+    for (int f = 0; f < 3; ++f) {
+        uint8_t inf = s->mesh.info[3 * elem + f];
+        if (inf & 0x40) {
+            ids[4 * f] = -1;
+            ids[4 * f + 1] = ids[4 * f + 2] = ids[4 * f + 3] = 0;
+        } else {
+            ids[4 * f] = s->mesh.nbr[3 * elem + f];
+            ids[4 * f + 1] = inf & 3;
+            ids[4 * f + 2] = (inf >> 2) & 3;
+            ids[4 * f + 3] = (inf >> 4) & 3;
+        }
+    }
+    *n = 12;
+    return CSWDG_OK;
+}
+
+int cswdg_ic_points(cswdg_solver* s, double* xy, int32_t* nq) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!nq) return fail(s, CSWDG_EINVAL, "null nq");
+    *nq = ic_points_per_element(s->p.degree);
+    if (!xy) return CSWDG_OK;
+    hipError_t e = launch_ic_points(s->ctx, s->dm, xy);
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "ic_points");
+}
+
+int cswdg_project(cswdg_solver* s, const double* vals, void* u) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!vals || !u) return fail(s, CSWDG_EINVAL, "null pointer");
+    hipError_t e = timed(s, KID_PROJECT, [&] { return launch_project(s->ctx, s->dm, vals, u); });
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "project");
+}
+
+int cswdg_dg_residual(cswdg_solver* s, const void* u, void* r) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u || !r || u == r) return fail(s, CSWDG_EINVAL, "u and r must be distinct non-null buffers");
+    hipError_t e = timed(s, KID_RESIDUAL, [&] { return launch_residual_reset(s->ctx, s->dm, 0, u, nullptr, r, nullptr, nullptr); });
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "residual");
+}
+
+int cswdg_max_dt(cswdg_solver* s, const void* u, double* dt_dev) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u || !dt_dev) return fail(s, CSWDG_EINVAL, "null pointer");
+    int nb = std::min(s->dt_blocks, (int)((s->mesh.K + 255) / 256));
+    if (nb < 1) nb = 1;
+    hipError_t e = timed(s, KID_DT, [&] {
+        return launch_max_dt(s->ctx, s->dm, u, s->mesh.hmin, dt_dev, s->d_partial, nullptr, s->d_status, nb);
+    });
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "max_dt");
+}
+
+int cswdg_kxrcf(cswdg_solver* s, const void* u, uint8_t* flags, double* R) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u || !flags) return fail(s, CSWDG_EINVAL, "null pointer");
+    hipError_t e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, 1); });
+    if (e == hipSuccess)
+        e = timed(s, KID_KXRCF, [&] { return launch_kxrcf(s->ctx, s->dm, u, flags, R, s->d_list, s->d_count); });
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "kxrcf");
+}
+
+int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* flags_out, const uint8_t* mask_in) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u_in || !u_out || u_in == u_out) return fail(s, CSWDG_EINVAL, "u_in and u_out must be distinct non-null buffers");
+    const size_t bytes = sizeof(double) * s->state_elems;
+    hipError_t e = timed(s, KID_COPY, [&] { return hipMemcpyAsync(u_out, u_in, bytes, hipMemcpyDeviceToDevice, s->stream); });
+    if (e != hipSuccess) return hipfail(s, e, "copy");
+    int mode = mask_in ? CSWDG_LIMIT_KXRCF : (s->p.limiter_mode == CSWDG_LIMIT_ALL ? CSWDG_LIMIT_ALL : CSWDG_LIMIT_KXRCF);
+    return limit_into(s, u_in, u_out, flags_out, mask_in, mode, false);
+}
+
+int cswdg_rk_stage(cswdg_solver* s, int stage, const void* u_n, const void* u_prev, void* out, const double* dt_dev) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (stage < 1 || stage > 3) return fail(s, CSWDG_EINVAL, "stage must be 1, 2 or 3");
+    if (!u_prev || !out || !dt_dev || (stage > 1 && !u_n)) return fail(s, CSWDG_EINVAL, "null pointer");
+    if (out == u_prev) return fail(s, CSWDG_EINVAL, "out must not alias u_prev");
+    return rk_stage_impl(s, stage, u_n, u_prev, out, dt_dev);
+}
+
+int cswdg_ssprk3_step(cswdg_solver* s, void* u, const double* dt_dev) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u) return fail(s, CSWDG_EINVAL, "null state");
+    const double* dt = dt_dev;
+    if (!dt) {
+        rc = cswdg_max_dt(s, u, s->d_dt);
+        if (rc) return rc;
+        dt = s->d_dt;
+    }
+    rc = rk_stage_impl(s, 1, nullptr, u, s->d_T1, dt);
+    if (rc) return rc;
+    rc = rk_stage_impl(s, 2, u, s->d_T1, s->d_T2, dt);
+    if (rc) return rc;
+    return rk_stage_impl(s, 3, u, s->d_T2, u, dt);
+}
+
+int cswdg_last_dt(cswdg_solver* s, double** dt_dev) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!dt_dev) return fail(s, CSWDG_EINVAL, "null pointer");
+    *dt_dev = s->d_dt;
+    return CSWDG_OK;
+}
+
+int cswdg_troubled_count(cswdg_solver* s, int64_t* count) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!count) return fail(s, CSWDG_EINVAL, "null pointer");
+    uint32_t c = 0;
+    hipError_t e = hipMemcpyAsync(&c, s->d_count, sizeof(c), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hipfail(s, e, "troubled_count");
+    *count = c;
+    return CSWDG_OK;
+}
+
+int cswdg_status(cswdg_solver* s, uint32_t* flags) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!flags) return fail(s, CSWDG_EINVAL, "null pointer");
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, s->d_status, sizeof(v), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = launch_zero_u32(s->ctx, s->d_status, 1);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hipfail(s, e, "status");
+    if (s->n_foot > 0) v |= CSWDG_STATUS_FOOT;
+    *flags = v;
+    return CSWDG_OK;
+}
+
+int cswdg_profile(cswdg_solver* s, int enable) {
+    if (!s) return fail(nullptr, CSWDG_EINVAL, "null solver");
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    if (enable && s->ev_pool.empty()) {
+        s->ev_pool.resize(1 << 15);
+        for (auto& ev : s->ev_pool)
+            if (hipEventCreate(&ev) != hipSuccess) return fail(s, CSWDG_EHIP, "hipEventCreate failed");
+    }
+    s->prof = enable != 0;
+    if (enable) {
+        s->ev_used = 0;
+        s->recs.clear();
+    }
+    return CSWDG_OK;
+}
+
+int cswdg_kernel_times(cswdg_solver* s, const char** names, double* total_ms, int64_t* counts, int cap, int* n) {
+    if (!s || !n) return fail(s, CSWDG_EINVAL, "null argument");
+    (void)hipSetDevice(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hipfail(s, e, "kernel_times");
+    double tot[KID_COUNT] = {0};
+    int64_t cnt[KID_COUNT] = {0};
+    for (auto& r : s->recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, s->ev_pool[r.second], s->ev_pool[r.second + 1]) == hipSuccess) {
+            tot[r.first] += ms;
+            cnt[r.first] += 1;
+        }
+    }
+    *n = KID_COUNT;
+    for (int k = 0; k < KID_COUNT && k < cap; ++k) {
+        if (names) names[k] = kKernelNames[k];
+        if (total_ms) total_ms[k] = tot[k];
+        if (counts) counts[k] = cnt[k];
+    }
+    return CSWDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Host triangulation checks and connectivity (Section 2, eq. triangulation;
+// the neighbour 'across the boundary' of Section 3.1 and the immediate
+// neighbours of Section 3.2).
+//
+// Interior edges are paired by sorting the 3K half-edges on their
+// (min vertex id, max vertex id) key.  Periodic boundary edges are paired
+// by coordinates: half-edge q is the partner of p when q's start plus a
+// period vector equals p's end and q's end plus the same vector equals p's
+// start, within 1e-9 times the larger period.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace cswdg {
+
+namespace {
+
+int shift_code(double s) { return s == 0.0 ? 0 : (s > 0.0 ? 1 : 2); }
+
+}  // namespace
+
+int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri_in, int bc, double px,
+               double py, HostMesh& m, std::string& msg) {
+    if (nv <= 0 || nt <= 0 || !vxy || !tri_in) {
+        msg = "mesh: empty or null arrays";
+        return CSWDG_EINVAL;
+    }
+    if (bc != CSWDG_BC_PERIODIC && bc != CSWDG_BC_TRANSMISSIVE) {
+        msg = "mesh: unknown boundary condition";
+        return CSWDG_EINVAL;
+    }
+    if (nt > (int64_t)0x3fffffff) {
+        msg = "mesh: too many triangles for int32 ids";
+        return CSWDG_EINVAL;
+    }
+    const int64_t K = nt;
+    m = HostMesh();
+    m.K = K;
+    m.bc = bc;
+    m.px = px;
+    m.py = py;
+    m.tri.assign(tri_in, tri_in + 3 * K);
+    for (int64_t i = 0; i < 3 * K; ++i)
+        if (m.tri[i] < 0 || m.tri[i] >= nv) {
+            msg = "mesh: vertex id out of range";
+            return CSWDG_EBADMESH;
+        }
+    // counter-clockwise fix
+    for (int64_t e = 0; e < K; ++e) {
+        int32_t* t = &m.tri[3 * e];
+        double x0 = vxy[2 * t[0]], y0 = vxy[2 * t[0] + 1];
+        double x1 = vxy[2 * t[1]], y1 = vxy[2 * t[1] + 1];
+        double x2 = vxy[2 * t[2]], y2 = vxy[2 * t[2] + 1];
+        double a2 = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+        if (a2 == 0.0) {
+            msg = "mesh: zero-area triangle " + std::to_string(e);
+            return CSWDG_EBADMESH;
+        }
+        if (a2 < 0.0) {
+            std::swap(t[1], t[2]);
+            ++m.n_flipped;
+        }
+    }
+    // interior edges by sorted vertex-pair keys
+    std::vector<int64_t> key(3 * K);
+    std::vector<int64_t> order(3 * K);
+    for (int64_t e = 0; e < K; ++e)
+        for (int f = 0; f < 3; ++f) {
+            int64_t a = m.tri[3 * e + f], b = m.tri[3 * e + (f + 1) % 3];
+            int64_t lo = std::min(a, b), hi = std::max(a, b);
+            key[3 * e + f] = lo * nv + hi;
+        }
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+    m.nbr.assign(3 * K, -1);
+    m.info.assign(3 * K, 0);
+    std::vector<int64_t> boundary;
+    for (int64_t i = 0; i < 3 * K;) {
+        int64_t j = i;
+        while (j < 3 * K && key[order[j]] == key[order[i]]) ++j;
+        int64_t cnt = j - i;
+        if (cnt > 2) {
+            msg = "mesh: non-manifold edge";
+            return CSWDG_EBADMESH;
+        }
+        if (cnt == 2) {
+            int64_t h0 = order[i], h1 = order[i + 1];
+            int64_t e0 = h0 / 3, f0 = h0 % 3, e1 = h1 / 3, f1 = h1 % 3;
+            if (m.tri[3 * e0 + f0] == m.tri[3 * e1 + f1]) {
+                msg = "mesh: neighbours traverse their shared edge in the same direction";
+                return CSWDG_EBADMESH;
+            }
+            m.nbr[h0] = (int32_t)e1;
+            m.nbr[h1] = (int32_t)e0;
+            m.info[h0] = (uint8_t)f1;
+            m.info[h1] = (uint8_t)f0;
+        } else {
+            boundary.push_back(order[i]);
+        }
+        i = j;
+    }
+    if (bc == CSWDG_BC_TRANSMISSIVE) {
+        for (int64_t h : boundary) m.info[h] = 0x40;
+    } else if (!boundary.empty()) {
+        double tol = 1e-9 * std::max(std::fabs(px), std::fabs(py));
+        if (!(tol > 0.0)) {
+            msg = "mesh: periodic boundary needs positive periods";
+            return CSWDG_EINVAL;
+        }
+        const int64_t B = (int64_t)boundary.size();
+        std::vector<double> ax(B), ay(B), bx(B), by(B);
+        for (int64_t p = 0; p < B; ++p) {
+            int64_t h = boundary[p], e = h / 3, f = h % 3;
+            int64_t a = m.tri[3 * e + f], b = m.tri[3 * e + (f + 1) % 3];
+            ax[p] = vxy[2 * a];
+            ay[p] = vxy[2 * a + 1];
+            bx[p] = vxy[2 * b];
+            by[p] = vxy[2 * b + 1];
+        }
+        // index boundary half-edges by their start x (then y) for range queries
+        std::vector<int64_t> idx(B);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+            return ax[x] < ax[y] || (ax[x] == ax[y] && ay[x] < ay[y]);
+        });
+        std::vector<double> sax(B);
+        for (int64_t k = 0; k < B; ++k) sax[k] = ax[idx[k]];
+        const double sh[4][2] = {{px, 0.0}, {-px, 0.0}, {0.0, py}, {0.0, -py}};
+        for (int64_t p = 0; p < B; ++p) {
+            int matches = 0;
+            int64_t q_found = -1;
+            int s_found = -1;
+            for (int si = 0; si < 4; ++si) {
+                if (sh[si][0] == 0.0 && sh[si][1] == 0.0) continue;
+                // candidate q: ax[q] + sx == bx[p]
+                double target = bx[p] - sh[si][0];
+                auto lo = std::lower_bound(sax.begin(), sax.end(), target - 2 * tol);
+                for (auto it = lo; it != sax.end() && *it <= target + 2 * tol; ++it) {
+                    int64_t q = idx[it - sax.begin()];
+                    bool c1 = std::fabs(ax[q] + sh[si][0] - bx[p]) <= tol && std::fabs(ay[q] + sh[si][1] - by[p]) <= tol;
+                    bool c2 = std::fabs(bx[q] + sh[si][0] - ax[p]) <= tol && std::fabs(by[q] + sh[si][1] - ay[p]) <= tol;
+                    if (c1 && c2) {
+                        ++matches;
+                        q_found = q;
+                        s_found = si;
+                    }
+                }
+            }
+            if (matches != 1) {
+                msg = "mesh: unmatched or ambiguous periodic boundary edge";
+                return CSWDG_EBADMESH;
+            }
+            int64_t hp = boundary[p], hq = boundary[q_found];
+            m.nbr[hp] = (int32_t)(hq / 3);
+            m.info[hp] = (uint8_t)((hq % 3) | (shift_code(sh[s_found][0]) << 2) | (shift_code(sh[s_found][1]) << 4));
+        }
+    }
+    // element vertices (SoA) and the time-step length scale
+    m.vx.resize(3 * K);
+    m.vy.resize(3 * K);
+    double hmin = INFINITY;
+    for (int64_t e = 0; e < K; ++e) {
+        for (int k = 0; k < 3; ++k) {
+            m.vx[k * K + e] = vxy[2 * m.tri[3 * e + k]];
+            m.vy[k * K + e] = vxy[2 * m.tri[3 * e + k] + 1];
+        }
+        double x0 = m.vx[e], x1 = m.vx[K + e], x2 = m.vx[2 * K + e];
+        double y0 = m.vy[e], y1 = m.vy[K + e], y2 = m.vy[2 * K + e];
+        double area = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+        double a = std::hypot(x1 - x0, y1 - y0), b = std::hypot(x2 - x1, y2 - y1), c = std::hypot(x0 - x2, y0 - y2);
+        double twor = 4.0 * area / (a + b + c);
+        hmin = std::min(hmin, twor);
+    }
+    m.hmin = hmin;
+    return CSWDG_OK;
+}
+
+}  // namespace cswdg

@@ -1,0 +1,410 @@
+// Per-element operators of the CSWENO limiter (Section 3.2).  Everything
+// here depends on the mesh only, so it is built once per mesh; the
+// per-stage kernel applies these operators to the current coefficients.
+//
+// For element e (= Delta0) and its faces f = 0, 1, 2 (neighbours
+// Delta_{f+1}; a periodic neighbour is translated next to e, a
+// transmissive face gets the mirror image of e):
+//   AVG[f][p][n]  average over piece p of the source element's psi_n, so a
+//                 piece average is AVG . (source coefficients).  Pieces:
+//                 S1 = (G, w_f', w_f'+1) touching e, S2 = (G, w_f'+1, w_f'+2),
+//                 S3 = (G, w_f'+2, w_f'); for N >= 2 also S2' = (G, w_f'+1, F2),
+//                 S21 = (G, F2, w_f'+2), S3' = (G, w_f'+2, F3), S31 = (G, F3, w_f')
+//                 with F2, F3 the feet of the perpendiculars from the
+//                 neighbour's centroid G to its outer sides (Fig. 2).
+//   X2, X3, X5    least-squares pseudo-inverses (Householder QR) of the
+//                 constrained fits q_2 (linear, rows S1 x 3 faces), q_3
+//                 (quadratic, rows S1, S2, S3 x 3) and q_5 (quartic, rows
+//                 S1, S2', S21, S3', S31 x 3) in the scaled monomials
+//                 ((x-x0)/h0)^a ((y-y0)/h0)^b, 1 <= a+b, minus their mean
+//                 over e; the right-hand side is (piece average - mean of e).
+//   BP            the smoothness-indicator matrix of eq. smoothnessIndicator:
+//                 c^T B c = sum_{1<=|alpha|<=DTOP} |e|^{|alpha|-1} int_e (D^alpha q)^2
+//                 for q = sum c_j phi_j (physical derivatives); lower-degree
+//                 levels use its leading block (higher derivatives vanish).
+//   MINV          per face, the inverse of the centroid differences of
+//                 S2 - S1 and S3 - S1, giving the gradient of the linear
+//                 functions of eq. sigmaEqn.
+//   PM            (1/J) int_e phi_j psi_i for i >= 1: the L2 projection of
+//                 the reconstruction onto the basis.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "internal.h"
+
+namespace cswdg {
+
+namespace {
+
+struct P2d {
+    double x, y;
+};
+
+inline P2d operator+(P2d a, P2d b) { return {a.x + b.x, a.y + b.y}; }
+inline P2d operator-(P2d a, P2d b) { return {a.x - b.x, a.y - b.y}; }
+inline P2d operator*(double s, P2d a) { return {s * a.x, s * a.y}; }
+inline double dot(P2d a, P2d b) { return a.x * b.x + a.y * b.y; }
+inline double tri_area(P2d a, P2d b, P2d c) {
+    return 0.5 * ((b.x - a.x) * (c.y - a.y) - (c.x - a.x) * (b.y - a.y));
+}
+
+struct Frame {  // maps placed coordinates to the source element's physical frame
+    bool mirror;
+    P2d shift;  // subtract (real neighbour)
+    P2d P, Q;   // mirror line (ghost)
+    P2d apply(P2d x) const {
+        if (!mirror) return x - shift;
+        P2d d = Q - P;
+        double t = dot(x - P, d) / dot(d, d);
+        P2d F = P + t * d;
+        return 2.0 * F - x;
+    }
+};
+
+// Householder QR pseudo-inverse X (c x r) of A (r x c), long double.
+bool pinv(int r, int c, const double* A, double* X) {
+    long double R[16][16], QT[16][16];
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < c; ++j) R[i][j] = A[i * c + j];
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) QT[i][j] = (i == j) ? 1.0L : 0.0L;
+    for (int k = 0; k < c; ++k) {
+        long double nrm = 0;
+        for (int i = k; i < r; ++i) nrm += R[i][k] * R[i][k];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0) continue;
+        long double alpha = R[k][k] > 0 ? -nrm : nrm;
+        long double v[16];
+        for (int i = 0; i < r; ++i) v[i] = 0;
+        for (int i = k; i < r; ++i) v[i] = R[i][k];
+        v[k] -= alpha;
+        long double vv = 0;
+        for (int i = k; i < r; ++i) vv += v[i] * v[i];
+        if (vv == 0) continue;
+        for (int j = 0; j < c; ++j) {
+            long double s = 0;
+            for (int i = k; i < r; ++i) s += v[i] * R[i][j];
+            s = 2 * s / vv;
+            for (int i = k; i < r; ++i) R[i][j] -= s * v[i];
+        }
+        for (int j = 0; j < r; ++j) {
+            long double s = 0;
+            for (int i = k; i < r; ++i) s += v[i] * QT[i][j];
+            s = 2 * s / vv;
+            for (int i = k; i < r; ++i) QT[i][j] -= s * v[i];
+        }
+    }
+    long double dmax = 0, dmin = INFINITY;
+    for (int k = 0; k < c; ++k) {
+        dmax = std::max(dmax, std::fabs(R[k][k]));
+        dmin = std::min(dmin, std::fabs(R[k][k]));
+    }
+    if (!(dmin > 1e-12L * dmax)) return false;
+    // X = R^{-1} QT[0:c, :]
+    for (int col = 0; col < r; ++col) {
+        long double y[16];
+        for (int i = c - 1; i >= 0; --i) {
+            long double s = QT[i][col];
+            for (int j = i + 1; j < c; ++j) s -= R[i][j] * y[j];
+            y[i] = s / R[i][i];
+        }
+        for (int i = 0; i < c; ++i) X[i * r + col] = (double)y[i];
+    }
+    return true;
+}
+
+struct MonoList {
+    int a[14], b[14], n;
+    explicit MonoList(int d) : n(0) {
+        for (int s = 1; s <= d; ++s)
+            for (int bb = 0; bb <= s; ++bb) {
+                a[n] = s - bb;
+                b[n] = bb;
+                ++n;
+            }
+    }
+};
+
+template <int N>
+struct OpBuilder {
+    using D = Dims<N>;
+    using L = OpLayout<N>;
+    const HostMesh& m;
+    std::vector<double> C;  // basis monomial form [NP][NP]
+    Rule2D rN, rTop, rBeta, rProj;
+    std::vector<double> psiProj;  // [q][NP] on rProj
+    MonoList mono{D::DTOP};
+
+    explicit OpBuilder(const HostMesh& mm) : m(mm) {
+        basis_monomial_form(N, C);
+        rN = triangle_rule((N + 2) / 2);
+        rTop = triangle_rule((D::DTOP + 2) / 2);
+        rBeta = triangle_rule(D::DTOP);
+        rProj = triangle_rule((D::DTOP + N + 2) / 2);
+        psiProj.resize(rProj.w.size() * D::NP);
+        for (size_t q = 0; q < rProj.w.size(); ++q) basis_eval(N, rProj.r[q], rProj.s[q], &psiProj[q * D::NP]);
+    }
+
+    P2d vert(int64_t e, int k) const { return {m.vx[k * m.K + e], m.vy[k * m.K + e]}; }
+
+    void psi_mono(double r, double s, double* psi) const {
+        double pw[D::NP];
+        int k = 0;
+        for (int d = 0; d <= N; ++d)
+            for (int bb = 0; bb <= d; ++bb) {
+                int aa = d - bb;
+                double v = 1.0;
+                for (int t = 0; t < aa; ++t) v *= r;
+                for (int t = 0; t < bb; ++t) v *= s;
+                pw[k++] = v;
+            }
+        for (int n = 0; n < D::NP; ++n) {
+            double acc = 0;
+            for (int kk = 0; kk < D::NP; ++kk) acc += C[n * D::NP + kk] * pw[kk];
+            psi[n] = acc;
+        }
+    }
+
+    // reference coordinates of physical point x in element src
+    void to_ref(int64_t src, P2d x, double& r, double& s) const {
+        P2d v0 = vert(src, 0), v1 = vert(src, 1), v2 = vert(src, 2);
+        double xr = 0.5 * (v1.x - v0.x), xs = 0.5 * (v2.x - v0.x);
+        double yr = 0.5 * (v1.y - v0.y), ys = 0.5 * (v2.y - v0.y);
+        double J = xr * ys - xs * yr;
+        double dx = x.x - v0.x, dy = x.y - v0.y;
+        r = -1.0 + (ys * dx - xs * dy) / J;
+        s = -1.0 + (-yr * dx + xr * dy) / J;
+    }
+
+    static P2d map_tri(const P2d* T, double r, double s) {
+        return T[0] + (0.5 * (1.0 + r)) * (T[1] - T[0]) + (0.5 * (1.0 + s)) * (T[2] - T[0]);
+    }
+
+    void mono_eval(P2d x, P2d c0, double h0, double* out) const {
+        double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
+        for (int j = 0; j < mono.n; ++j) {
+            double v = 1.0;
+            for (int t = 0; t < mono.a[j]; ++t) v *= xi;
+            for (int t = 0; t < mono.b[j]; ++t) v *= eta;
+            out[j] = v;
+        }
+    }
+
+    // returns valid flag; counts feet outside their side
+    bool build(int64_t e, double* op, int64_t& nfoot) const {
+        for (int i = 0; i < L::LEN; ++i) op[i] = 0.0;
+        P2d V0[3] = {vert(e, 0), vert(e, 1), vert(e, 2)};
+        P2d c0 = (1.0 / 3.0) * (V0[0] + V0[1] + V0[2]);
+        double la = std::sqrt(dot(V0[1] - V0[0], V0[1] - V0[0]));
+        double lb = std::sqrt(dot(V0[2] - V0[1], V0[2] - V0[1]));
+        double lc = std::sqrt(dot(V0[0] - V0[2], V0[0] - V0[2]));
+        double h0 = (la + lb + lc) / 3.0;
+        double area0 = tri_area(V0[0], V0[1], V0[2]);
+        double J0 = 0.5 * area0;
+
+        // monomial means over e
+        double mavg0[14] = {0};
+        {
+            double tmp[14];
+            double wsum = 0;
+            for (size_t q = 0; q < rTop.w.size(); ++q) {
+                mono_eval(map_tri(V0, rTop.r[q], rTop.s[q]), c0, h0, tmp);
+                for (int j = 0; j < mono.n; ++j) mavg0[j] += rTop.w[q] * tmp[j];
+                wsum += rTop.w[q];
+            }
+            for (int j = 0; j < mono.n; ++j) mavg0[j] /= wsum;
+        }
+
+        double mavg[3][7][14];
+        P2d cen[3][3];
+        for (int f = 0; f < 3; ++f) {
+            uint8_t inf = m.info[3 * e + f];
+            Frame fr;
+            P2d W[3];
+            int fp;
+            int64_t src;
+            if (inf & 0x40) {
+                fr.mirror = true;
+                fr.P = V0[f];
+                fr.Q = V0[(f + 1) % 3];
+                P2d R = fr.apply(V0[(f + 2) % 3]);
+                W[0] = V0[(f + 1) % 3];
+                W[1] = V0[f];
+                W[2] = R;
+                fp = 0;
+                src = e;
+            } else {
+                int cx = (inf >> 2) & 3, cy = (inf >> 4) & 3;
+                double sx = cx == 1 ? m.px : (cx == 2 ? -m.px : 0.0);
+                double sy = cy == 1 ? m.py : (cy == 2 ? -m.py : 0.0);
+                fr.mirror = false;
+                fr.shift = {sx, sy};
+                src = m.nbr[3 * e + f];
+                for (int k = 0; k < 3; ++k) W[k] = vert(src, k) + fr.shift;
+                fp = inf & 3;
+            }
+            P2d G = (1.0 / 3.0) * (W[0] + W[1] + W[2]);
+            P2d wa = W[fp], wb = W[(fp + 1) % 3], wc = W[(fp + 2) % 3];
+            P2d pcs[7][3] = {{G, wa, wb}, {G, wb, wc}, {G, wc, wa}};
+            if (N >= 2) {
+                auto foot = [&](P2d p, P2d q) {
+                    P2d d = q - p;
+                    double t = dot(G - p, d) / dot(d, d);
+                    if (!(t > 0.0 && t < 1.0)) {
+                        t = 0.5;
+                        ++nfoot;
+                    }
+                    return p + t * d;
+                };
+                P2d F2 = foot(wb, wc), F3 = foot(wc, wa);
+                P2d extra[4][3] = {{G, wb, F2}, {G, F2, wc}, {G, wc, F3}, {G, F3, wa}};
+                for (int p = 0; p < 4; ++p)
+                    for (int k = 0; k < 3; ++k) pcs[3 + p][k] = extra[p][k];
+            }
+            for (int p = 0; p < 3; ++p) cen[f][p] = (1.0 / 3.0) * (pcs[p][0] + pcs[p][1] + pcs[p][2]);
+            for (int p = 0; p < D::NPIECE; ++p) {
+                // average of psi_n of the source element
+                double acc[D::NP] = {0};
+                double wsum = 0, psi[D::NP];
+                for (size_t q = 0; q < rN.w.size(); ++q) {
+                    P2d x = fr.apply(map_tri(pcs[p], rN.r[q], rN.s[q]));
+                    double r, s;
+                    to_ref(src, x, r, s);
+                    psi_mono(r, s, psi);
+                    for (int n = 0; n < D::NP; ++n) acc[n] += rN.w[q] * psi[n];
+                    wsum += rN.w[q];
+                }
+                for (int n = 0; n < D::NP; ++n) op[L::AVG + (f * D::NPIECE + p) * D::NP + n] = acc[n] / wsum;
+                // scaled-monomial averages
+                double ma[14] = {0}, tmp[14];
+                wsum = 0;
+                for (size_t q = 0; q < rTop.w.size(); ++q) {
+                    mono_eval(map_tri(pcs[p], rTop.r[q], rTop.s[q]), c0, h0, tmp);
+                    for (int j = 0; j < mono.n; ++j) ma[j] += rTop.w[q] * tmp[j];
+                    wsum += rTop.w[q];
+                }
+                for (int j = 0; j < mono.n; ++j) mavg[f][p][j] = ma[j] / wsum - mavg0[j];
+            }
+            // gradient of the linear function through the centroid subcells
+            double m00 = cen[f][1].x - cen[f][0].x, m01 = cen[f][1].y - cen[f][0].y;
+            double m10 = cen[f][2].x - cen[f][0].x, m11 = cen[f][2].y - cen[f][0].y;
+            double det = m00 * m11 - m01 * m10;
+            double* mi = op + L::MINV + 4 * f;
+            mi[0] = m11 / det;
+            mi[1] = -m01 / det;
+            mi[2] = -m10 / det;
+            mi[3] = m00 / det;
+        }
+
+        bool valid = true;
+        // linear level: rows S1 of faces 0..2, columns monomials of degree 1
+        {
+            double A[3 * 2];
+            for (int f = 0; f < 3; ++f)
+                for (int j = 0; j < 2; ++j) A[f * 2 + j] = mavg[f][0][j];
+            valid &= pinv(3, 2, A, op + L::X2);
+        }
+        // quadratic level: rows S1 f0..2, S2 f0..2, S3 f0..2
+        {
+            double A[9 * 5];
+            for (int p = 0; p < 3; ++p)
+                for (int f = 0; f < 3; ++f)
+                    for (int j = 0; j < 5; ++j) A[(p * 3 + f) * 5 + j] = mavg[f][p][j];
+            valid &= pinv(9, 5, A, op + L::X3);
+        }
+        if (N >= 2) {
+            // quartic level: rows S1, S2', S21, S3', S31 (pieces 0, 3, 4, 5, 6) x faces
+            const int pl[5] = {0, 3, 4, 5, 6};
+            double A[15 * 14];
+            for (int k = 0; k < 5; ++k)
+                for (int f = 0; f < 3; ++f)
+                    for (int j = 0; j < 14; ++j) A[(k * 3 + f) * 14 + j] = mavg[f][pl[k]][j];
+            valid &= pinv(15, 14, A, op + L::X5);
+        }
+
+        // smoothness-indicator matrix
+        {
+            const int nm = mono.n;
+            double B[14][14] = {{0}};
+            for (size_t q = 0; q < rBeta.w.size(); ++q) {
+                P2d x = map_tri(V0, rBeta.r[q], rBeta.s[q]);
+                double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
+                double wq = J0 * rBeta.w[q];
+                for (int s = 1; s <= D::DTOP; ++s)
+                    for (int a1 = 0; a1 <= s; ++a1) {
+                        int a2 = s - a1;
+                        double Dv[14];
+                        for (int j = 0; j < nm; ++j) {
+                            int a = mono.a[j], b = mono.b[j];
+                            if (a < a1 || b < a2) {
+                                Dv[j] = 0;
+                                continue;
+                            }
+                            double coef = 1.0;
+                            for (int t = 0; t < a1; ++t) coef *= (a - t);
+                            for (int t = 0; t < a2; ++t) coef *= (b - t);
+                            double v = coef / std::pow(h0, s);
+                            for (int t = 0; t < a - a1; ++t) v *= xi;
+                            for (int t = 0; t < b - a2; ++t) v *= eta;
+                            Dv[j] = v;
+                        }
+                        double sc = std::pow(area0, s - 1) * wq;
+                        for (int i = 0; i < nm; ++i)
+                            for (int j = 0; j < nm; ++j) B[i][j] += sc * Dv[i] * Dv[j];
+                    }
+            }
+            int k = 0;
+            for (int i = 0; i < nm; ++i)
+                for (int j = i; j < nm; ++j) op[L::BP + k++] = B[i][j];
+        }
+        // projection onto psi_1..psi_{NP-1}
+        {
+            double tmp[14];
+            for (size_t q = 0; q < rProj.w.size(); ++q) {
+                mono_eval(map_tri(V0, rProj.r[q], rProj.s[q]), c0, h0, tmp);
+                for (int i = 1; i < D::NP; ++i)
+                    for (int j = 0; j < mono.n; ++j)
+                        op[L::PM + (i - 1) * D::NMONO + j] += rProj.w[q] * tmp[j] * psiProj[q * D::NP + i];
+            }
+        }
+        op[L::H0] = h0;
+        op[L::AREA0] = area0;
+        op[L::VALID] = valid ? 1.0 : 0.0;
+        return valid;
+    }
+};
+
+template <int N>
+int build_ops_n(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank, int64_t& n_foot) {
+    using L = OpLayout<N>;
+    OpBuilder<N> b(m);
+    ops.assign((size_t)m.K * L::LEN, 0.0);
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<int64_t> rank(nt, 0), foot(nt, 0);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int64_t e = t; e < m.K; e += nt)
+                if (!b.build(e, &ops[(size_t)e * L::LEN], foot[t])) ++rank[t];
+        });
+    for (auto& x : th) x.join();
+    n_rank = n_foot = 0;
+    for (unsigned t = 0; t < nt; ++t) {
+        n_rank += rank[t];
+        n_foot += foot[t];
+    }
+    return CSWDG_OK;
+}
+
+}  // namespace
+
+int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank,
+                      int64_t& n_foot) {
+    if (N == 1) return build_ops_n<1>(m, ops, n_rank, n_foot);
+    if (N == 2) return build_ops_n<2>(m, ops, n_rank, n_foot);
+    if (N == 3) return build_ops_n<3>(m, ops, n_rank, n_foot);
+    return CSWDG_EINVAL;
+}
+
+}  // namespace cswdg

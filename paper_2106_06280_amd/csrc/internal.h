@@ -1,0 +1,107 @@
+// Internal declarations shared by the host sources and the kernel source.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cswdg.h"
+#include "tables.h"
+
+namespace cswdg {
+
+constexpr double kPsi0 = 0.70710678118654752440;  // constant mode 1/sqrt(2)
+
+// ----------------------------------------------------------------------------
+// host: basis and quadrature (host_tables.cpp)
+// ----------------------------------------------------------------------------
+struct Rule1D {
+    std::vector<long double> x, w;
+};
+Rule1D gauss_jacobi(int n, double alpha);  // weight (1-x)^alpha on [-1,1]
+struct Rule2D {
+    std::vector<double> r, s, w;  // reference triangle, sum w = 2
+};
+Rule2D triangle_rule(int n);
+int n_modes(int N);
+// psi_n(r,s), dpsi/dr, dpsi/ds for n = 0..Np-1 (orthonormal basis)
+void basis_eval(int N, double r, double s, double* psi, double* dr = nullptr, double* ds = nullptr);
+// monomial-form coefficients of the basis: psi_n = sum_k C[n][k] r^a_k s^b_k
+// with (a_k, b_k) enumerated by total degree, k < Np
+void basis_monomial_form(int N, std::vector<double>& C);
+
+template <int N>
+void fill_tables(Tab<N>& t);
+
+// ----------------------------------------------------------------------------
+// host: mesh (host_mesh.cpp)
+// ----------------------------------------------------------------------------
+struct HostMesh {
+    int64_t K = 0;
+    int bc = 0;
+    double px = 0, py = 0;
+    std::vector<int32_t> tri;   // [K][3] after the CCW fix
+    std::vector<int32_t> nbr;   // [K][3]
+    std::vector<uint8_t> info;  // [K][3]
+    std::vector<double> vx, vy; // [3][K] SoA element vertices
+    int64_t n_flipped = 0;
+    double hmin = 0;            // min over elements of 2 * inradius
+};
+
+// returns CSWDG_OK or an error code with msg filled
+int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc, double px,
+               double py, HostMesh& m, std::string& msg);
+
+// per-element limiter operators (host_ops.cpp); returns number of
+// rank-deficient elements and perpendicular feet that fell outside
+int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank,
+                      int64_t& n_foot);
+
+// ----------------------------------------------------------------------------
+// device views and launchers (kernels.hip)
+// ----------------------------------------------------------------------------
+struct DevMesh {
+    int K;
+    const double* vx;      // [3][K]
+    const double* vy;      // [3][K]
+    const int32_t* nbr;    // [3][K]
+    const uint32_t* info;  // [K], face f in byte f
+};
+
+struct LaunchCtx {
+    hipStream_t stream;
+    int eq, N, precision;
+    double gamma, cfl, c_k, eps;
+};
+
+int upload_tables_device();  // once per device
+
+// residual (mode 0) or RK stage 1..3; dt read from device; reset (may be
+// null) is a counter set to zero by the kernel
+hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode, const void* u,
+                                 const void* un, void* out, const double* dt, uint32_t* reset);
+// wave-speed reduction, dt = cfl * hmin / amax and state checks
+hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, double hmin,
+                         double* dt, double* partial, uint32_t* counter, uint32_t* status,
+                         int nblocks);
+// KXRCF flags (+ optional R) and the compacted list of troubled cells
+hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags,
+                        double* R, int32_t* list, uint32_t* count);
+// compact a mask (or all cells when mask == nullptr) into the list
+hipError_t launch_compact_mask(const LaunchCtx& c, int K, const uint8_t* mask, uint8_t* flags,
+                               int32_t* list, uint32_t* count);
+hipError_t launch_zero_u32(const LaunchCtx& c, uint32_t* p, int n);
+// limiter over the list; results to the compact buffer
+hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, const double* ops,
+                          const int32_t* list, const uint32_t* count, double* compact,
+                          uint32_t* status, int max_cells);
+// write the compact results into u (modes >= 1)
+hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* list,
+                          const uint32_t* count, const double* compact, int max_cells);
+hipError_t launch_ic_points(const LaunchCtx& c, const DevMesh& m, double* xy);
+hipError_t launch_project(const LaunchCtx& c, const DevMesh& m, const double* vals, void* u);
+int ic_points_per_element(int N);
+
+}  // namespace cswdg

@@ -1,0 +1,902 @@
+// gfx950 kernels of one SSP-RK3 stage with the CSWENO limiter.
+//
+// Layout: state [m][Np][K] (element index fastest, so a wave of 64
+// consecutive elements reads each coefficient with one coalesced access);
+// element vertices [3][K] for x and y; neighbours [3][K]; face info packed
+// as one uint32 per element (byte f = info of face f).
+//
+// Kernels
+//   k_residual  one thread per element: volume quadrature of
+//               grad(psi).F(u_h), traces of the element and of its three
+//               neighbours at the edge Gauss points, local Lax-Friedrichs
+//               flux, lift, inverse mass matrix (1/J) and the RK combine.
+//   k_dt_*      cell-mean wave speeds -> dt (two-pass reduction).
+//   k_kxrcf     one thread per element: KXRCF indicator, then a wave ballot
+//               and one atomic per wave to append troubled cells to a list.
+//   k_limiter   one thread per troubled cell: subcell averages, the three
+//               (four) least-squares levels, smoothness indicators, WENO-Z
+//               weights and the projection, per characteristic field for
+//               Euler; results to a compact buffer (every cell reads the
+//               pre-limit field).
+//   k_scatter   compact results -> state (modes >= 1).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "internal.h"
+
+namespace cswdg {
+
+namespace {
+
+template <int N>
+struct TabIC {
+    double r[Dims<N>::NQI], s[Dims<N>::NQI];
+    double wV[Dims<N>::NQI][Dims<N>::NP];
+};
+
+__constant__ Tab<1> c_tab1;
+__constant__ Tab<2> c_tab2;
+__constant__ Tab<3> c_tab3;
+__constant__ TabIC<1> c_ic1;
+__constant__ TabIC<2> c_ic2;
+__constant__ TabIC<3> c_ic3;
+
+template <int N>
+__device__ __forceinline__ const Tab<N>& tab();
+template <>
+__device__ __forceinline__ const Tab<1>& tab<1>() { return c_tab1; }
+template <>
+__device__ __forceinline__ const Tab<2>& tab<2>() { return c_tab2; }
+template <>
+__device__ __forceinline__ const Tab<3>& tab<3>() { return c_tab3; }
+template <int N>
+__device__ __forceinline__ const TabIC<N>& tabic();
+template <>
+__device__ __forceinline__ const TabIC<1>& tabic<1>() { return c_ic1; }
+template <>
+__device__ __forceinline__ const TabIC<2>& tabic<2>() { return c_ic2; }
+template <>
+__device__ __forceinline__ const TabIC<3>& tabic<3>() { return c_ic3; }
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
+// contiguous range of element tiles so that neighbour gathers stay in its L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Physics: fluxes and wave speeds (Section 4 eqs. 2dBurgers, 2dEulerEquations)
+// ---------------------------------------------------------------------------
+template <int EQ>
+struct Phys;
+
+template <>
+struct Phys<0> {
+    static constexpr int M = 1;
+    __device__ static __forceinline__ void normal_flux(const double* u, double nx, double ny, double,
+                                                       double* Fn, double& lam) {
+        double h = 0.5 * u[0] * u[0];
+        Fn[0] = h * nx + h * ny;
+        lam = fabs(u[0] * (nx + ny));
+    }
+    __device__ static __forceinline__ void flux(const double* u, double, double* F, double* G) {
+        F[0] = 0.5 * u[0] * u[0];
+        G[0] = F[0];
+    }
+};
+
+template <>
+struct Phys<1> {
+    static constexpr int M = 4;
+    __device__ static __forceinline__ void flux(const double* U, double g, double* F, double* G) {
+        double rho = U[0], mu = U[1], mv = U[2], E = U[3];
+        double u = mu / rho, v = mv / rho;
+        double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+        F[0] = mu;
+        F[1] = mu * u + p;
+        F[2] = mv * u;
+        F[3] = (E + p) * u;
+        G[0] = mv;
+        G[1] = mu * v;
+        G[2] = mv * v + p;
+        G[3] = (E + p) * v;
+    }
+    __device__ static __forceinline__ void normal_flux(const double* U, double nx, double ny, double g,
+                                                       double* Fn, double& lam) {
+        double rho = U[0], mu = U[1], mv = U[2], E = U[3];
+        double u = mu / rho, v = mv / rho;
+        double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+        double un = u * nx + v * ny;
+        Fn[0] = mu * nx + mv * ny;
+        Fn[1] = (mu * u + p) * nx + (mu * v) * ny;
+        Fn[2] = (mv * u) * nx + (mv * v + p) * ny;
+        Fn[3] = ((E + p) * u) * nx + ((E + p) * v) * ny;
+        lam = fabs(un) + sqrt(g * p / rho);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Residual and RK stage
+// ---------------------------------------------------------------------------
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __restrict__ u,
+                                                  const double* __restrict__ un,
+                                                  double* __restrict__ out,
+                                                  const double* __restrict__ dtp, double gamma,
+                                                  uint32_t* __restrict__ cnt_reset) {
+    using D = Dims<N>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
+    const int K = msh.K;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
+    if (e >= K) return;
+    const Tab<N>& T = tab<N>();
+
+    double U[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) U[c][n] = u[(size_t)(c * NP + n) * K + e];
+
+    const double X[3] = {msh.vx[e], msh.vx[K + e], msh.vx[2 * K + e]};
+    const double Y[3] = {msh.vy[e], msh.vy[K + e], msh.vy[2 * K + e]};
+    const double xr = 0.5 * (X[1] - X[0]), xs = 0.5 * (X[2] - X[0]);
+    const double yr = 0.5 * (Y[1] - Y[0]), ys = 0.5 * (Y[2] - Y[0]);
+    const double J = xr * ys - xs * yr;
+    const double iJ = 1.0 / J;
+    const double rx = ys * iJ, ry = -xs * iJ, sx = -yr * iJ, sy = xr * iJ;
+
+    double acc[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) acc[c][n] = 0.0;
+
+    // volume term: sum_q w_q (dpsi/dr (r_x f + r_y g) + dpsi/ds (s_x f + s_y g))
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double uq[M], F[M], G[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < NP; ++n) s += T.V[q][n] * U[c][n];
+            uq[c] = s;
+        }
+        Phys<EQ>::flux(uq, gamma, F, G);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const double fr = rx * F[c] + ry * G[c];
+            const double fs = sx * F[c] + sy * G[c];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) acc[c][i] += T.wDr[q][i] * fr + T.wDs[q][i] * fs;
+        }
+    }
+
+    // surface term
+    const uint32_t info4 = msh.info[e];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int f1 = (f + 1) % 3;
+        const double ex = X[f1] - X[f], ey = Y[f1] - Y[f];
+        const double L = sqrt(ex * ex + ey * ey);
+        const double nx = ey / L, ny = -ex / L;
+        const double sf = 0.5 * L * iJ;
+        const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+        const bool bnd = (inf & 0x40u) != 0u;
+        const int fp = (int)(inf & 3u);
+        const int nb = bnd ? e : msh.nbr[f * K + e];
+        double Un[M][NP];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int n = 0; n < NP; ++n) Un[c][n] = u[(size_t)(c * NP + n) * K + nb];
+#pragma unroll
+        for (int g = 0; g < NE; ++g) {
+            double um[M], up[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double a = 0.0, b = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) {
+                    a += T.PF[f][g][n] * U[c][n];
+                    b += T.PF[fp][NE - 1 - g][n] * Un[c][n];
+                }
+                um[c] = a;
+                up[c] = bnd ? a : b;
+            }
+            double Fm[M], Fp[M], lm, lp;
+            Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
+            Phys<EQ>::normal_flux(up, nx, ny, gamma, Fp, lp);
+            const double alpha = fmax(lm, lp);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (up[c] - um[c]);
+                const double sFs = sf * Fs;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] -= T.wPF[f][g][i] * sFs;
+            }
+        }
+    }
+
+    double dt = 0.0;
+    if (MODE != 0) dt = *dtp;
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const size_t idx = (size_t)(c * NP + i) * K + e;
+            double v;
+            if (MODE == 0) {
+                v = acc[c][i];
+            } else if (MODE == 1) {
+                v = U[c][i] + dt * acc[c][i];
+            } else if (MODE == 2) {
+                v = 0.75 * un[idx] + 0.25 * (U[c][i] + dt * acc[c][i]);
+            } else {
+                v = (1.0 / 3.0) * un[idx] + (2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
+            }
+            out[idx] = v;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Time step: cell-mean wave speeds (block maxima, then one block)
+// ---------------------------------------------------------------------------
+template <int EQ, int N>
+__global__ __launch_bounds__(256) void k_dt_partial(int K, const double* __restrict__ u,
+                                                    double gamma, double* __restrict__ partial,
+                                                    uint32_t* __restrict__ status) {
+    constexpr int NP = Dims<N>::NP, M = Phys<EQ>::M;
+    double amax = 0.0;
+    uint32_t st = 0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < K; e += gridDim.x * blockDim.x) {
+        double ub[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) ub[c] = u[(size_t)(c * NP) * K + e] * kPsi0;
+        double s;
+        if constexpr (EQ == 0) {
+            s = 1.41421356237309504880 * fabs(ub[0]);
+        } else {
+            double rho = ub[0], vx = ub[1] / rho, vy = ub[2] / rho;
+            double p = (gamma - 1.0) * (ub[3] - 0.5 * rho * (vx * vx + vy * vy));
+            if (!(rho > 0.0) || !(p > 0.0)) st |= CSWDG_STATUS_NEGATIVE;
+            s = sqrt(vx * vx + vy * vy) + sqrt(gamma * p / rho);
+        }
+        if (!isfinite(s)) st |= CSWDG_STATUS_NONFINITE;
+        amax = fmax(amax, s);
+    }
+    __shared__ double red[4];
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = fmax(b, red[i]);
+        partial[blockIdx.x] = b;
+    }
+    if (st) atomicOr(status, st);
+}
+
+__global__ __launch_bounds__(256) void k_dt_final(int nblocks, const double* __restrict__ partial,
+                                                  double cfl, double hmin, double* __restrict__ dt) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) a = fmax(a, partial[i]);
+    for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = fmax(b, red[i]);
+        *dt = cfl * hmin / b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// KXRCF indicator + compaction (Section 3.1)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void append_list(bool tr, int e, int32_t* list, uint32_t* count, int cap) {
+    const unsigned long long mask = __ballot(tr ? 1 : 0);
+    const int lane = threadIdx.x & 63;
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    const int total = __popcll(mask);
+    uint32_t base = 0;
+    if (lane == 0 && total > 0) base = atomicAdd(count, (uint32_t)total);
+    base = __shfl(base, 0);
+    if (tr && base + (uint32_t)before < (uint32_t)cap) list[base + before] = e;
+}
+
+template <int EQ, int N>
+__global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const double* __restrict__ u,
+                                               uint8_t* __restrict__ flags, double* __restrict__ Rout,
+                                               int32_t* __restrict__ list,
+                                               uint32_t* __restrict__ count, double ck) {
+    using D = Dims<N>;
+    constexpr int NP = D::NP, NE = D::NE;
+    const int K = msh.K;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    bool tr = false;
+    if (e < K) {
+        const Tab<N>& T = tab<N>();
+        double U0[NP], U1[NP], U2[NP];
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+            U0[n] = u[(size_t)n * K + e];
+            if constexpr (EQ == 1) {
+                U1[n] = u[(size_t)(NP + n) * K + e];
+                U2[n] = u[(size_t)(2 * NP + n) * K + e];
+            }
+        }
+        const double X[3] = {msh.vx[e], msh.vx[K + e], msh.vx[2 * K + e]};
+        const double Y[3] = {msh.vy[e], msh.vy[K + e], msh.vy[2 * K + e]};
+        const double J = 0.25 * ((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]));
+        const uint32_t info4 = msh.info[e];
+        double num = 0.0, len = 0.0, Ls[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const int f1 = (f + 1) % 3;
+            const double ex = X[f1] - X[f], ey = Y[f1] - Y[f];
+            const double L = sqrt(ex * ex + ey * ey);
+            Ls[f] = L;
+            const double nx = ey / L, ny = -ex / L;
+            const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+            const bool bnd = (inf & 0x40u) != 0u;
+            const int fp = (int)(inf & 3u);
+            const int nb = bnd ? e : msh.nbr[f * K + e];
+            double Un[NP];
+#pragma unroll
+            for (int n = 0; n < NP; ++n) Un[n] = u[(size_t)n * K + nb];
+#pragma unroll
+            for (int g = 0; g < NE; ++g) {
+                double um = 0.0, mu = 0.0, mv = 0.0, upv = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) {
+                    um += T.PF[f][g][n] * U0[n];
+                    if constexpr (EQ == 1) {
+                        mu += T.PF[f][g][n] * U1[n];
+                        mv += T.PF[f][g][n] * U2[n];
+                    }
+                    upv += T.PF[fp][NE - 1 - g][n] * Un[n];
+                }
+                double vx, vy;
+                if constexpr (EQ == 1) {
+                    vx = mu / um;
+                    vy = mv / um;
+                } else {
+                    vx = um;
+                    vy = um;
+                }
+                const double vn = vx * nx + vy * ny;
+                if (vn < 0.0) {
+                    const double up = bnd ? um : upv;
+                    const double ds = 0.5 * L * T.we[g];
+                    num += ds * (um - up);
+                    len += ds;
+                }
+            }
+        }
+        double ss = 0.0;
+#pragma unroll
+        for (int n = 0; n < NP; ++n) ss += U0[n] * U0[n];
+        const double norm = sqrt(J * ss);
+        const double h = Ls[0] * Ls[1] * Ls[2] / (4.0 * (2.0 * J));
+        const double hp = (N == 1) ? h : ((N == 2) ? h * sqrt(h) : h * h);
+        double R = 0.0;
+        if (len > 0.0 && norm > 0.0) R = fabs(num) / (hp * len * norm);
+        tr = R > ck;
+        flags[e] = tr ? 1 : 0;
+        if (Rout) Rout[e] = R;
+    }
+    append_list(tr, e, list, count, K);
+}
+
+__global__ __launch_bounds__(256) void k_compact_mask(int K, const uint8_t* __restrict__ mask,
+                                                      uint8_t* __restrict__ flags,
+                                                      int32_t* __restrict__ list,
+                                                      uint32_t* __restrict__ count) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    bool tr = false;
+    if (e < K) {
+        tr = mask ? (mask[e] != 0) : true;
+        if (flags) flags[e] = tr ? 1 : 0;
+    }
+    append_list(tr, e, list, count, K);
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// CSWENO limiter (Section 3.2)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void euler_eigen(const double* U, double nx, double ny, double g,
+                                            double L[4][4], double R[4][4]) {
+    const double rho = U[0], u = U[1] / rho, v = U[2] / rho, E = U[3];
+    const double q2 = u * u + v * v;
+    const double p = (g - 1.0) * (E - 0.5 * rho * q2);
+    const double c = sqrt(g * p / rho);
+    const double H = (E + p) / rho;
+    const double un = u * nx + v * ny;
+    // right eigenvectors (columns): u_n - c, u_n (entropy), u_n (shear), u_n + c
+    R[0][0] = 1.0;            R[0][1] = 1.0;      R[0][2] = 0.0;              R[0][3] = 1.0;
+    R[1][0] = u - c * nx;     R[1][1] = u;        R[1][2] = -ny;              R[1][3] = u + c * nx;
+    R[2][0] = v - c * ny;     R[2][1] = v;        R[2][2] = nx;               R[2][3] = v + c * ny;
+    R[3][0] = H - c * un;     R[3][1] = 0.5 * q2; R[3][2] = -ny * u + nx * v; R[3][3] = H + c * un;
+    // closed-form inverse
+    const double b1 = (g - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+    L[0][0] = 0.5 * (b2 + un / c); L[0][1] = 0.5 * (-b1 * u - nx / c); L[0][2] = 0.5 * (-b1 * v - ny / c); L[0][3] = 0.5 * b1;
+    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;                   L[1][2] = b1 * v;                   L[1][3] = -b1;
+    L[2][0] = ny * u - nx * v;     L[2][1] = -ny;                      L[2][2] = nx;                       L[2][3] = 0.0;
+    L[3][0] = 0.5 * (b2 - un / c); L[3][1] = 0.5 * (-b1 * u + nx / c); L[3][2] = 0.5 * (-b1 * v + ny / c); L[3][3] = 0.5 * b1;
+}
+
+// c^T B c over the leading k x k block of the packed upper triangle of an
+// nm x nm matrix
+template <int NM, int KK>
+__device__ __forceinline__ double quad_form(const double* __restrict__ bp, const double* c) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < KK; ++i) {
+        const int row = i * NM - (i * (i - 1)) / 2;
+        double t = bp[row] * c[i];
+#pragma unroll
+        for (int j = i + 1; j < KK; ++j) t += 2.0 * bp[row + (j - i)] * c[j];
+        s += c[i] * t;
+    }
+    return s;
+}
+
+template <int EQ, int N>
+__global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __restrict__ u,
+                                                const double* __restrict__ ops,
+                                                const int32_t* __restrict__ list,
+                                                const uint32_t* __restrict__ count,
+                                                double* __restrict__ compact,
+                                                uint32_t* __restrict__ status, double gamma,
+                                                double eps) {
+    using D = Dims<N>;
+    using LO = OpLayout<N>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = D::NPIECE, NM = D::NMONO;
+    constexpr int ND = (EQ == 1) ? 2 : 1;
+    const int K = msh.K;
+    const uint32_t ncell = min(*count, (uint32_t)K);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ncell; t += gridDim.x * blockDim.x) {
+        const int e = list[t];
+        const double* __restrict__ op = ops + (size_t)e * LO::LEN;
+        double U0[M][NP];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int n = 0; n < NP; ++n) U0[c][n] = u[(size_t)(c * NP + n) * K + e];
+        double* outp = compact + (size_t)t * (M * NP);
+        if (op[LO::VALID] == 0.0) {
+            atomicOr(status, CSWDG_STATUS_RANK);
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+#pragma unroll
+                for (int n = 0; n < NP; ++n) outp[c * NP + n] = U0[c][n];
+            continue;
+        }
+        // subcell averages of the source polynomials
+        const uint32_t info4 = msh.info[e];
+        double av[3][NPC][M];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+            const int src = (inf & 0x40u) ? e : msh.nbr[f * K + e];
+            double Us[M][NP];
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+#pragma unroll
+                for (int n = 0; n < NP; ++n) Us[c][n] = u[(size_t)(c * NP + n) * K + src];
+#pragma unroll
+            for (int p = 0; p < NPC; ++p) {
+                const double* a = op + LO::AVG + (f * NPC + p) * NP;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int n = 0; n < NP; ++n) s += a[n] * Us[c][n];
+                    av[f][p][c] = s;
+                }
+            }
+        }
+        double ub0[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) ub0[c] = U0[c][0] * kPsi0;
+
+        const double h0 = op[LO::H0], area0 = op[LO::AREA0];
+        // linear weights gamma_{l,t} = h^{-(l-1)} / sum (Section 3.2, Step 2)
+        const double ih = 1.0 / h0;
+        double g2[2], g3[3], g5[4];
+        {
+            double s2 = 1.0 + ih;
+            g2[0] = 1.0 / s2;
+            g2[1] = ih / s2;
+            double s3 = 1.0 + ih + ih * ih;
+            g3[0] = 1.0 / s3;
+            g3[1] = ih / s3;
+            g3[2] = ih * ih / s3;
+            double s5 = 1.0 + ih + ih * ih + ih * ih * ih;
+            g5[0] = 1.0 / s5;
+            g5[1] = ih / s5;
+            g5[2] = ih * ih / s5;
+            g5[3] = ih * ih * ih / s5;
+        }
+
+        double res[M][NP - 1];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int i = 0; i < NP - 1; ++i) res[c][i] = 0.0;
+
+#pragma unroll 1
+        for (int d = 0; d < ND; ++d) {
+            double Lm[4][4], Rm[4][4];
+            if constexpr (EQ == 1) euler_eigen(ub0, d == 0 ? 1.0 : 0.0, d == 0 ? 0.0 : 1.0, gamma, Lm, Rm);
+#pragma unroll 1
+            for (int k = 0; k < M; ++k) {
+                // characteristic field k of the stencil averages
+                double w[3][NPC];
+                double w0;
+                if constexpr (EQ == 1) {
+                    w0 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) w0 += Lm[k][c] * ub0[c];
+#pragma unroll
+                    for (int f = 0; f < 3; ++f)
+#pragma unroll
+                        for (int p = 0; p < NPC; ++p) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int c = 0; c < M; ++c) s += Lm[k][c] * av[f][p][c];
+                            w[f][p] = s;
+                        }
+                } else {
+                    w0 = ub0[0];
+#pragma unroll
+                    for (int f = 0; f < 3; ++f)
+#pragma unroll
+                        for (int p = 0; p < NPC; ++p) w[f][p] = av[f][p][0];
+                }
+                // Step 1: least-squares levels
+                double c2[NM], c3[NM], c5[NM];
+#pragma unroll
+                for (int j = 0; j < NM; ++j) c2[j] = c3[j] = c5[j] = 0.0;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) s += op[LO::X2 + j * 3 + f] * (w[f][0] - w0);
+                    c2[j] = s;
+                }
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) s += op[LO::X3 + j * 9 + p * 3 + f] * (w[f][p] - w0);
+                    c3[j] = s;
+                }
+                if constexpr (N >= 2) {
+                    constexpr int pl[5] = {0, 3, 4, 5, 6};
+#pragma unroll
+                    for (int j = 0; j < 14; ++j) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < 5; ++kk)
+#pragma unroll
+                            for (int f = 0; f < 3; ++f) s += op[LO::X5 + j * 15 + kk * 3 + f] * (w[f][pl[kk]] - w0);
+                        c5[j] = s;
+                    }
+                }
+                // Step 3: smoothness indicators of q_l
+                const double* bp = op + LO::BP;
+                double beta[4];
+                beta[1] = quad_form<NM, 2>(bp, c2);
+                beta[2] = quad_form<NM, 5>(bp, c3);
+                beta[3] = (N >= 2) ? quad_form<NM, NM>(bp, c5) : 0.0;
+                double gx[3], gy[3], b1[3];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double* mi = op + LO::MINV + 4 * f;
+                    const double d0 = w[f][1] - w[f][0], d1 = w[f][2] - w[f][0];
+                    gx[f] = mi[0] * d0 + mi[1] * d1;
+                    gy[f] = mi[2] * d0 + mi[3] * d1;
+                    b1[f] = area0 * (gx[f] * gx[f] + gy[f] * gy[f]);
+                }
+                {
+                    const double a01 = fabs(b1[0] - b1[1]), a12 = fabs(b1[1] - b1[2]), a20 = fabs(b1[2] - b1[0]);
+                    const double mm = (a01 * a01 + a12 * a12 + a20 * a20) / 3.0;
+                    const double num = mm * mm;
+                    double sg[3], ssum = 0.0;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        sg[f] = (1.0 / 3.0) * (1.0 + num / (b1[f] + eps));
+                        ssum += sg[f];
+                    }
+                    double mx = 0.0, my = 0.0;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        mx += (sg[f] / ssum) * gx[f];
+                        my += (sg[f] / ssum) * gy[f];
+                    }
+                    beta[0] = area0 * (mx * mx + my * my);
+                }
+                // Step 2: equivalent polynomials (mean-free parts; p_1 has none)
+                double p2[NM], p3[NM], p4[NM];
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    p2[j] = c2[j] / g2[1];
+                    p3[j] = (c3[j] - g3[1] * p2[j]) / g3[2];
+                    p4[j] = (N >= 2) ? (c5[j] - g5[1] * p2[j] - g5[2] * p3[j]) / g5[3] : 0.0;
+                }
+                // Step 4: tau and nonlinear weights
+                double om[4];
+                if (N == 1) {
+                    const double d31 = fabs(beta[2] - beta[0]), d32 = fabs(beta[2] - beta[1]);
+                    const double tau = (d31 * d31 + d32 * d32) / 4.0;
+                    double s = 0.0;
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) {
+                        om[l] = g3[l] * (1.0 + tau / (eps + beta[l]));
+                        s += om[l];
+                    }
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) om[l] /= s;
+                    om[3] = 0.0;
+                } else {
+                    const double d1 = fabs(beta[3] - beta[0]), d2 = fabs(beta[3] - beta[1]), d3 = fabs(beta[3] - beta[2]);
+                    const double tau = (d1 * d1 + d2 * d2 + d3 * d3) / 16.0;
+                    double s = 0.0;
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        om[l] = g5[l] * (1.0 + tau / (eps + beta[l]));
+                        s += om[l];
+                    }
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) om[l] /= s;
+                }
+                // reconstruction R = sum_l omega_l p_l and its projection
+                double Rc[NM];
+#pragma unroll
+                for (int j = 0; j < NM; ++j) Rc[j] = om[1] * p2[j] + om[2] * p3[j] + om[3] * p4[j];
+#pragma unroll
+                for (int i = 0; i < NP - 1; ++i) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NM; ++j) s += op[LO::PM + i * NM + j] * Rc[j];
+                    if constexpr (EQ == 1) {
+#pragma unroll
+                        for (int c = 0; c < M; ++c) res[c][i] += 0.5 * Rm[c][k] * s;
+                    } else {
+                        res[0][i] = s;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            outp[c * NP] = U0[c][0];
+#pragma unroll
+            for (int i = 1; i < NP; ++i) outp[c * NP + i] = res[c][i - 1];
+        }
+    }
+}
+
+template <int N, int M>
+__global__ __launch_bounds__(256) void k_scatter(int K, double* __restrict__ u,
+                                                 const int32_t* __restrict__ list,
+                                                 const uint32_t* __restrict__ count,
+                                                 const double* __restrict__ compact) {
+    constexpr int NP = Dims<N>::NP;
+    const uint32_t n = min(*count, (uint32_t)K);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int e = list[t];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int i = 1; i < NP; ++i) u[(size_t)(c * NP + i) * K + e] = compact[(size_t)t * (M * NP) + c * NP + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial data: quadrature points and L2 projection
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_ic_points(DevMesh msh, double* __restrict__ xy) {
+    constexpr int NQI = Dims<N>::NQI;
+    const int K = msh.K;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    const TabIC<N>& T = tabic<N>();
+    const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+    const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+    for (int q = 0; q < NQI; ++q) {
+        const double l1 = 0.5 * (1.0 + T.r[q]), l2 = 0.5 * (1.0 + T.s[q]);
+        xy[(size_t)q * K + e] = x0 + l1 * (x1 - x0) + l2 * (x2 - x0);
+        xy[(size_t)(NQI + q) * K + e] = y0 + l1 * (y1 - y0) + l2 * (y2 - y0);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_project(int K, int m, const double* __restrict__ vals,
+                                                 double* __restrict__ u) {
+    constexpr int NQI = Dims<N>::NQI, NP = Dims<N>::NP;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    const TabIC<N>& T = tabic<N>();
+    for (int c = 0; c < m; ++c) {
+        double acc[NP];
+#pragma unroll
+        for (int n = 0; n < NP; ++n) acc[n] = 0.0;
+        for (int q = 0; q < NQI; ++q) {
+            const double v = vals[(size_t)(c * NQI + q) * K + e];
+#pragma unroll
+            for (int n = 0; n < NP; ++n) acc[n] += T.wV[q][n] * v;
+        }
+#pragma unroll
+        for (int n = 0; n < NP; ++n) u[(size_t)(c * NP + n) * K + e] = acc[n];
+    }
+}
+
+template <int N>
+void fill_ic(TabIC<N>& t) {
+    Rule2D r = triangle_rule(Dims<N>::NI1);
+    double psi[Dims<N>::NP];
+    for (int q = 0; q < Dims<N>::NQI; ++q) {
+        t.r[q] = r.r[q];
+        t.s[q] = r.s[q];
+        basis_eval(N, r.r[q], r.s[q], psi);
+        for (int n = 0; n < Dims<N>::NP; ++n) t.wV[q][n] = r.w[q] * psi[n];
+    }
+}
+
+inline unsigned grid_for(int K, int bs) { return (unsigned)((K + bs - 1) / bs); }
+
+}  // namespace
+
+int ic_points_per_element(int N) {
+    return N == 1 ? Dims<1>::NQI : (N == 2 ? Dims<2>::NQI : Dims<3>::NQI);
+}
+
+int upload_tables_device() {
+    static Tab<1> t1;
+    static Tab<2> t2;
+    static Tab<3> t3;
+    static TabIC<1> i1;
+    static TabIC<2> i2;
+    static TabIC<3> i3;
+    static bool filled = false;
+    if (!filled) {
+        fill_tables<1>(t1);
+        fill_tables<2>(t2);
+        fill_tables<3>(t3);
+        fill_ic<1>(i1);
+        fill_ic<2>(i2);
+        fill_ic<3>(i3);
+        filled = true;
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab1), &t1, sizeof(t1)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab2), &t2, sizeof(t2)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab3), &t3, sizeof(t3)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic1), &i1, sizeof(i1)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic2), &i2, sizeof(i2)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic3), &i3, sizeof(i3)) != hipSuccess) return CSWDG_EHIP;
+    return CSWDG_OK;
+}
+
+#define CSWDG_DISPATCH_EN(EQV, NV, ...)                         \
+    do {                                                        \
+        if ((EQV) == 0 && (NV) == 1) { constexpr int EQ = 0, N = 1; __VA_ARGS__; } \
+        else if ((EQV) == 0 && (NV) == 2) { constexpr int EQ = 0, N = 2; __VA_ARGS__; } \
+        else if ((EQV) == 0 && (NV) == 3) { constexpr int EQ = 0, N = 3; __VA_ARGS__; } \
+        else if ((EQV) == 1 && (NV) == 1) { constexpr int EQ = 1, N = 1; __VA_ARGS__; } \
+        else if ((EQV) == 1 && (NV) == 2) { constexpr int EQ = 1, N = 2; __VA_ARGS__; } \
+        else if ((EQV) == 1 && (NV) == 3) { constexpr int EQ = 1, N = 3; __VA_ARGS__; } \
+        else return hipErrorInvalidValue;                       \
+    } while (0)
+
+hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode, const void* u,
+                                 const void* un, void* out, const double* dt, uint32_t* reset) {
+    const unsigned bs = 256, g = grid_for(m.K, bs);
+    const double* U = (const double*)u;
+    const double* UN = (const double*)un;
+    double* O = (double*)out;
+    CSWDG_DISPATCH_EN(c.eq, c.N, {
+        switch (mode) {
+            case 0: k_residual<EQ, N, 0><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+            case 1: k_residual<EQ, N, 1><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+            case 2: k_residual<EQ, N, 2><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+            case 3: k_residual<EQ, N, 3><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+            default: return hipErrorInvalidValue;
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, double hmin, double* dt,
+                         double* partial, uint32_t*, uint32_t* status, int nblocks) {
+    const double* U = (const double*)u;
+    CSWDG_DISPATCH_EN(c.eq, c.N, {
+        k_dt_partial<EQ, N><<<nblocks, 256, 0, c.stream>>>(m.K, U, c.gamma, partial, status);
+    });
+    k_dt_final<<<1, 256, 0, c.stream>>>(nblocks, partial, c.cfl, hmin, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags, double* R,
+                        int32_t* list, uint32_t* count) {
+    const unsigned bs = 256, g = grid_for(m.K, bs);
+    const double* U = (const double*)u;
+    CSWDG_DISPATCH_EN(c.eq, c.N, { k_kxrcf<EQ, N><<<g, bs, 0, c.stream>>>(m, U, flags, R, list, count, c.c_k); });
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_mask(const LaunchCtx& c, int K, const uint8_t* mask, uint8_t* flags,
+                               int32_t* list, uint32_t* count) {
+    k_compact_mask<<<grid_for(K, 256), 256, 0, c.stream>>>(K, mask, flags, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(const LaunchCtx& c, uint32_t* p, int n) {
+    k_zero_u32<<<grid_for(n, 256), 256, 0, c.stream>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, const double* ops,
+                          const int32_t* list, const uint32_t* count, double* compact, uint32_t* status,
+                          int max_cells) {
+    const unsigned bs = 64;
+    unsigned g = grid_for(max_cells, bs);
+    if (g > 8192u) g = 8192u;
+    if (g == 0) g = 1;
+    const double* U = (const double*)u;
+    CSWDG_DISPATCH_EN(c.eq, c.N, {
+        k_limiter<EQ, N><<<g, bs, 0, c.stream>>>(m, U, ops, list, count, compact, status, c.gamma, c.eps);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* list, const uint32_t* count,
+                          const double* compact, int max_cells) {
+    const unsigned bs = 256;
+    unsigned g = grid_for(max_cells, bs);
+    if (g > 4096u) g = 4096u;
+    if (g == 0) g = 1;
+    double* U = (double*)u;
+    CSWDG_DISPATCH_EN(c.eq, c.N, {
+        k_scatter<N, Phys<EQ>::M><<<g, bs, 0, c.stream>>>(K, U, list, count, compact);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_points(const LaunchCtx& c, const DevMesh& m, double* xy) {
+    const unsigned g = grid_for(m.K, 256);
+    if (c.N == 1) k_ic_points<1><<<g, 256, 0, c.stream>>>(m, xy);
+    else if (c.N == 2) k_ic_points<2><<<g, 256, 0, c.stream>>>(m, xy);
+    else if (c.N == 3) k_ic_points<3><<<g, 256, 0, c.stream>>>(m, xy);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const LaunchCtx& c, const DevMesh& m, const double* vals, void* u) {
+    const unsigned g = grid_for(m.K, 256);
+    const int mv = c.eq == 0 ? 1 : 4;
+    double* U = (double*)u;
+    if (c.N == 1) k_project<1><<<g, 256, 0, c.stream>>>(m.K, mv, vals, U);
+    else if (c.N == 2) k_project<2><<<g, 256, 0, c.stream>>>(m.K, mv, vals, U);
+    else if (c.N == 3) k_project<3><<<g, 256, 0, c.stream>>>(m.K, mv, vals, U);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace cswdg

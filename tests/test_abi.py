@@ -1,0 +1,65 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host connectivity builder agrees bit for bit with the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.mesh import BC_PERIODIC, BC_TRANSMISSIVE, connectivity
+from paper_2106_06280_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "cswdg.h")).read()
+    return sorted(set(re.findall(r"\b(cswdg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    syms = _declared_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(binding._SIGS), set(syms) ^ set(binding._SIGS)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (5, 3), (17, 4)])
+@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
+def test_host_connectivity_bit_exact(n, seed, bc):
+    v, t = inputs.jittered_mesh(n, -1.0, 3.0, 0.0, 2.0, seed=seed)
+    period = (4.0, 2.0)
+    t2 = t.copy()
+    t2[1::4, 1], t2[1::4, 2] = t[1::4, 2], t[1::4, 1]  # some clockwise triangles
+    tc, nbr, info = binding.host_connectivity(v, t2, bc, period)
+    otri, onbr, oinfo = connectivity(v, t2, bc, period)
+    assert np.array_equal(tc, otri.astype(np.int32))
+    assert np.array_equal(nbr, onbr)
+    assert np.array_equal(info, oinfo)
+
+
+def test_host_connectivity_errors():
+    v, t = inputs.jittered_mesh(3, seed=1)
+    bad = t.copy()
+    bad[0, 2] = bad[0, 1]
+    with pytest.raises(binding.CswdgError) as ei:
+        binding.host_connectivity(v, bad, BC_TRANSMISSIVE)
+    assert ei.value.code == -2
+    with pytest.raises(binding.CswdgError) as ei:
+        binding.host_connectivity(v, t, BC_PERIODIC, (1.5, 1.0))
+    assert ei.value.code == -2
+    with pytest.raises(binding.CswdgError) as ei:
+        binding.host_connectivity(v, t, 7, (1.0, 1.0))
+    assert ei.value.code == -1
+    dup = np.concatenate([t, t[:1]], axis=0)
+    with pytest.raises(binding.CswdgError):
+        binding.host_connectivity(v, dup, BC_TRANSMISSIVE)
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(ImportError):
+        binding.lib()
