@@ -1,0 +1,218 @@
+"""Throughput of one SSP-RK3 stage with the CSWENO limiter on MI355X.
+
+Default workload: 2D Euler, P2 DG (Np = 6), FP64, 999,698 jittered triangles
+on [0,1]^2 (707 x 707 squares, interior vertices jittered by +-0.1 h, seed
+1000), transmissive boundaries, four-quadrant piecewise-constant initial
+data drawn from the seed (rho in [0.1,1.5], p in [0.03,1.5], velocities in
+[-1,1]), KXRCF-flagged cells limited after every stage.
+
+A step is one full SSP-RK3 step (three stages, each: residual + RK combine,
+KXRCF indicator + compaction, CSWENO on the flagged cells, scatter), dt
+computed on the device.  The state stays in HBM; W warm-up steps, then K
+timed steps bracketed by device synchronisation.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    # name: (equation, N, n squares per side, seed, bc)
+    "p2_euler_1m": (1, 2, 707, 1000, 1),
+    "p2_euler_200k": (1, 2, 316, 1002, 1),
+    "p1_burgers_800": (0, 1, 20, 1001, 0),
+    "p3_euler_1m": (1, 3, 707, 1003, 0),
+}
+
+
+def make_problem(name):
+    from paper_2106_06280_amd import inputs
+    eq, N, n, seed, bc = WORKLOADS[name]
+    if name.startswith("p1_burgers"):
+        v, t = inputs.jittered_mesh(n, 0.0, 2.0, 0.0, 2.0, seed=seed)
+        ic = inputs.BurgersSine(a=0.5, b=0.25, k=math.pi)
+        period = (2.0, 2.0)
+    elif name.startswith("p3_euler"):
+        v, t = inputs.jittered_mesh(n, 0.0, 10.0, -5.0, 5.0, seed=seed)
+        ic = inputs.VortexCircles(seed=seed)
+        period = (10.0, 10.0)
+    else:
+        v, t = inputs.jittered_mesh(n, seed=seed)
+        ic = inputs.FourQuadrant(seed=seed)
+        period = (1.0, 1.0)
+    return eq, N, bc, v, t, ic, period
+
+
+def cell_mean_ic(name):
+    """Piecewise-constant initial data are loaded as exact cell means (the
+    higher modes of their L2 projection are dropped): the projection's Gibbs
+    undershoots would otherwise reach negative pressure at quadrature
+    points of cells cut by the quadrant lines."""
+    return name.startswith("p2_euler")
+
+
+def cpu_baseline(name, budget_s=12.0, sample=20000):
+    """The FP64 oracle on a bounded sample of the same workload: one stage
+    (residual for the sampled elements, KXRCF on them, CSWENO on the flagged
+    ones) at the projected initial state, repeated until the budget is used."""
+    import numpy as np
+
+    from oracle import csweno, kxrcf
+    from oracle.dg import DG
+    from oracle.mesh import Mesh
+
+    eq, N, bc, v, t, ic, period = make_problem(name)
+    M = Mesh(v, t, bc, period)
+    dg = DG(M, N, eq)
+    rng = np.random.default_rng(7)
+    S = np.sort(rng.choice(M.K, size=min(sample, M.K), replace=False))
+    # the state is needed on the sample and on its neighbours
+    need = np.unique(np.concatenate([S, M.nbr[S][M.nbr[S] >= 0].ravel()]))
+    u = np.zeros((M.K, dg.m, dg.Np))
+    u[need] = dg.project(ic, elems=need)
+    if cell_mean_ic(name):
+        u[:, :, 1:] = 0.0
+    c0 = os.times()
+    w0 = time.perf_counter()
+    reps = 0
+    times = []
+    while True:
+        t0 = time.perf_counter()
+        dg.residual(u, elems=S)
+        R, tr = kxrcf.indicator(dg, u, elems=S)
+        flagged = S[tr]
+        if len(flagged):
+            csweno.reconstruct(dg, u, flagged)
+        times.append(time.perf_counter() - t0)
+        reps += 1
+        if time.perf_counter() - w0 > budget_s or reps >= 50:
+            break
+    c1 = os.times()
+    wall = time.perf_counter() - w0
+    cpu = (c1.user - c0.user) + (c1.system - c0.system)
+    tmed = sorted(times)[len(times) // 2]
+    return {
+        "value": len(S) * dg.m * dg.Np / tmed,
+        "unit": "DOF-updates/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": (f"oracle stage (residual + KXRCF + CSWENO on flagged cells) for {len(S)} random elements "
+                   f"of the same {M.K}-triangle mesh at the projected initial state; median of {reps} "
+                   f"repetitions, {int(tr.sum())} flagged in the sample; host {os.cpu_count()} cpus"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    if int(os.environ.get("RANK", "0")) != 0:
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2106_06280_amd import binding
+
+    torch.cuda.set_device(0)
+    eq, N, bc, v, t, ic, period = make_problem(args.workload)
+    t_setup = time.perf_counter()
+    S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_KXRCF)
+    S.mesh_upload(v, t, bc, period)
+    u = S.project_fn(ic)
+    if cell_mean_ic(args.workload):
+        u[:, 1:, :] = 0.0
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    K = S.K
+    m, Np = S.m, S.Np
+    print(f"[bench] {args.workload}: K={K} m={m} Np={Np} setup {t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        S.ssprk3_step(u)
+    torch.cuda.synchronize()
+    S.status()
+    S.troubled_stats(reset=True)
+    if not args.no_profile:
+        S.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        S.ssprk3_step(u)
+    ev1.record()
+    torch.cuda.synchronize()
+    secs = ev0.elapsed_time(ev1) / 1000.0
+    status = S.status()
+    tot, calls = S.troubled_stats()
+    kt = S.kernel_times() if not args.no_profile else {}
+    S.profile(False)
+    print(f"[bench] {args.steps} steps in {secs*1e3:.2f} ms; status {status}", file=sys.stderr, flush=True)
+
+    stages = 3 * args.steps
+    dof = K * m * Np
+    value = dof * stages / secs
+    f = tot / max(1, calls * K)
+
+    roof = None
+    if kt:
+        tot_ms, cnt = kt["residual_rk"]
+        avg = tot_ms / max(cnt, 1) / 1000.0
+        Sb = 8 * Np * m  # bytes of one element's state
+        G = 6 * 8 + 3 * 4 + 4  # vertex coordinates, neighbour ids, packed face info
+        # per element and stage: read u^(i-1), write u^(i), read u^n on stages
+        # 2 and 3, geometry once (neighbour coefficients are the same array)
+        bytes_launch = K * (Sb * 8.0 / 3.0 + G)
+        ach = bytes_launch / avg / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_residual (volume + surface + LF flux + 1/J + RK combine)",
+                "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_launch)}
+    out = {
+        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P2 Euler, 1M tri)",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "triangles": K, "degree": N,
+                   "equation": "euler" if eq == 1 else "burgers", "dof": dof,
+                   "troubled_fraction": round(f, 5), "limiter": "kxrcf+csweno",
+                   "parallelism": "single-gpu"},
+        "roofline": roof,
+        "kernel_ms": {k: [round(a, 3), int(b)] for k, (a, b) in kt.items() if b},
+        "status_bits": status,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, budget_s=args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

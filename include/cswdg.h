@@ -177,6 +177,10 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
 
 /* Troubled-cell count of the last limiter call (host int, synchronous). */
 int cswdg_troubled_count(cswdg_solver* s, int64_t* count);
+/* Troubled cells summed over all limiter calls since the last reset, and the
+ * number of limiter calls (host ints; synchronous).  reset != 0 clears both
+ * after reading. */
+int cswdg_troubled_stats(cswdg_solver* s, int64_t* total_cells, int64_t* calls, int reset);
 /* Accumulated status bits CSWDG_STATUS_* since the last call (synchronous;
  * clears them). */
 int cswdg_status(cswdg_solver* s, uint32_t* flags);

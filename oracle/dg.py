@@ -74,14 +74,15 @@ class DG:
         self.PF = np.stack([basis.vandermonde(N, *quadrature.face_reference_points(f, t)) for f in range(3)])  # [3, g, Np]
 
     # ------------------------------------------------------------------
-    def project(self, fn, degree=None):
+    def project(self, fn, degree=None, elems=None):
         """L2 projection of fn(x, y) -> [K, q] or [K, q, m] onto the basis
-        with a collapsed rule exact to degree 2N+6."""
+        with a collapsed rule exact to degree 2N+6 (for the elements in
+        elems only when given)."""
         if degree is None:
             degree = 2 * self.N + 6
         r, s, w = quadrature.triangle_rule_for_degree(degree)
         Vh = basis.vandermonde(self.N, r, s)
-        x, y = self.mesh.physical_points(r, s)
+        x, y = self.mesh.physical_points(r, s, elems)
         vals = np.asarray(fn(x, y), dtype=np.float64)
         if vals.ndim == 2:
             vals = vals[..., None]

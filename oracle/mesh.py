@@ -69,32 +69,22 @@ def connectivity(vxy, tri, bc, period=(0.0, 0.0)):
     ks = key[order]
     nbr = -np.ones((K, 3), dtype=np.int32)
     info = np.zeros((K, 3), dtype=np.uint8)
-    boundary = []
-    i = 0
-    n = len(ks)
-    while i < n:
-        j = i
-        while j < n and ks[j] == ks[i]:
-            j += 1
-        cnt = j - i
-        if cnt > 2:
-            raise MeshError("non-manifold edge")
-        if cnt == 2:
-            h0, h1 = order[i], order[i + 1]
-            if a[h0] == a[h1]:
-                raise MeshError("inconsistently oriented neighbours")
-            e0, f0, e1, f1 = e[h0], f[h0], e[h1], f[h1]
-            nbr[e0, f0] = e1
-            nbr[e1, f1] = e0
-            info[e0, f0] = f1
-            info[e1, f1] = f0
-        else:
-            boundary.append(order[i])
-        i = j
-    boundary = np.array(boundary, dtype=np.int64)
+    # runs of equal keys: 1 = boundary edge, 2 = interior edge, >2 = error
+    starts = np.flatnonzero(np.r_[True, ks[1:] != ks[:-1]])
+    counts = np.diff(np.r_[starts, len(ks)])
+    if np.any(counts > 2):
+        raise MeshError("non-manifold edge")
+    pairs = starts[counts == 2]
+    h0, h1 = order[pairs], order[pairs + 1]
+    if np.any(a[h0] == a[h1]):
+        raise MeshError("inconsistently oriented neighbours")
+    nbr[e[h0], f[h0]] = e[h1]
+    nbr[e[h1], f[h1]] = e[h0]
+    info[e[h0], f[h0]] = f[h1]
+    info[e[h1], f[h1]] = f[h0]
+    boundary = np.asarray(order[starts[counts == 1]], dtype=np.int64)
     if bc == BC_TRANSMISSIVE:
-        for h in boundary:
-            info[e[h], f[h]] = INFO_BOUNDARY
+        info[e[boundary], f[boundary]] = INFO_BOUNDARY
         return tri, nbr, info
     if bc != BC_PERIODIC:
         raise MeshError("unknown boundary condition")
@@ -223,9 +213,9 @@ class Mesh:
     def neighbour_face(self):
         return (self.info & INFO_FACE_MASK).astype(np.int64)
 
-    def physical_points(self, r, s):
+    def physical_points(self, r, s, elems=None):
         """x, y [K, q] for reference points (r_q, s_q)."""
-        V = self.V
+        V = self.V if elems is None else self.V[np.asarray(elems)]
         lam1 = 0.5 * (1.0 + np.asarray(r))
         lam2 = 0.5 * (1.0 + np.asarray(s))
         x = V[:, 0, 0, None] + lam1 * (V[:, 1, 0, None] - V[:, 0, 0, None]) + lam2 * (V[:, 2, 0, None] - V[:, 0, 0, None])

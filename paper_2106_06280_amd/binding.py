@@ -56,6 +56,7 @@ _SIGS = {
     "cswdg_last_dt": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "cswdg_troubled_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "cswdg_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
+    "cswdg_troubled_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.c_int]),
     "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
@@ -242,6 +243,11 @@ class Solver:
         c = _I64()
         self._c(lib().cswdg_troubled_count(self.h, ctypes.byref(c)))
         return c.value
+
+    def troubled_stats(self, reset=False):
+        t, c = _I64(), _I64()
+        self._c(lib().cswdg_troubled_stats(self.h, ctypes.byref(t), ctypes.byref(c), 1 if reset else 0))
+        return t.value, c.value
 
     def status(self):
         v = ctypes.c_uint32()

@@ -43,6 +43,7 @@ struct cswdg_solver {
     int32_t* d_list = nullptr;
     uint32_t* d_count = nullptr;   // [0] troubled count
     uint32_t* d_status = nullptr;
+    unsigned long long* d_tstats = nullptr;  // troubled cells, limiter calls
     double* d_compact = nullptr;
     double* d_partial = nullptr;
     double* d_dt = nullptr;
@@ -71,7 +72,7 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
-                    s->d_status, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2};
+                    s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -81,6 +82,7 @@ void free_mesh(cswdg_solver* s) {
     s->d_flags = nullptr;
     s->d_list = nullptr;
     s->d_count = s->d_status = nullptr;
+    s->d_tstats = nullptr;
     s->d_compact = s->d_partial = s->d_dt = nullptr;
     s->d_T1 = s->d_T2 = nullptr;
     s->has_mesh = false;
@@ -127,7 +129,7 @@ int limit_into(cswdg_solver* s, const void* src, void* buf, uint8_t* flags_out, 
         return launch_limiter(s->ctx, s->dm, src, s->d_ops, s->d_list, s->d_count, s->d_compact, s->d_status, K);
     });
     if (e != hipSuccess) return hipfail(s, e, "limiter");
-    e = timed(s, KID_SCATTER, [&] { return launch_scatter(s->ctx, K, buf, s->d_list, s->d_count, s->d_compact, K); });
+    e = timed(s, KID_SCATTER, [&] { return launch_scatter(s->ctx, K, buf, s->d_list, s->d_count, s->d_compact, K, s->d_tstats); });
     if (e != hipSuccess) return hipfail(s, e, "scatter");
     return CSWDG_OK;
 }
@@ -249,6 +251,7 @@ int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt
         {(void**)&s->d_list, sizeof(int32_t) * K},
         {(void**)&s->d_count, sizeof(uint32_t) * 4},
         {(void**)&s->d_status, sizeof(uint32_t) * 4},
+        {(void**)&s->d_tstats, sizeof(unsigned long long) * 2},
         {(void**)&s->d_compact, sizeof(double) * NPM * K},
         {(void**)&s->d_partial, sizeof(double) * s->dt_blocks},
         {(void**)&s->d_dt, sizeof(double) * 2},
@@ -273,6 +276,8 @@ int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt
     uint32_t zeros[4] = {0, 0, 0, 0};
     cp(s->d_count, zeros, sizeof(zeros));
     cp(s->d_status, zeros, sizeof(zeros));
+    unsigned long long zz[2] = {0, 0};
+    cp(s->d_tstats, zz, sizeof(zz));
     if (e != hipSuccess) {
         free_mesh(s);
         return hipfail(s, e, "mesh upload");
@@ -422,6 +427,22 @@ int cswdg_troubled_count(cswdg_solver* s, int64_t* count) {
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hipfail(s, e, "troubled_count");
     *count = c;
+    return CSWDG_OK;
+}
+
+int cswdg_troubled_stats(cswdg_solver* s, int64_t* total_cells, int64_t* calls, int reset) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    unsigned long long v[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(v, s->d_tstats, sizeof(v), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess && reset) {
+        unsigned long long zz[2] = {0, 0};
+        e = hipMemcpy(s->d_tstats, zz, sizeof(zz), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hipfail(s, e, "troubled_stats");
+    if (total_cells) *total_cells = (int64_t)v[0];
+    if (calls) *calls = (int64_t)v[1];
     return CSWDG_OK;
 }
 

@@ -62,54 +62,54 @@ struct Frame {  // maps placed coordinates to the source element's physical fram
     }
 };
 
-// Householder QR pseudo-inverse X (c x r) of A (r x c), long double.
+// Householder QR pseudo-inverse X (c x r) of A (r x c).
 bool pinv(int r, int c, const double* A, double* X) {
-    long double R[16][16], QT[16][16];
+    double R[16][16], QT[16][16];
     for (int i = 0; i < r; ++i)
         for (int j = 0; j < c; ++j) R[i][j] = A[i * c + j];
     for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) QT[i][j] = (i == j) ? 1.0L : 0.0L;
+        for (int j = 0; j < r; ++j) QT[i][j] = (i == j) ? 1.0 : 0.0;
     for (int k = 0; k < c; ++k) {
-        long double nrm = 0;
+        double nrm = 0;
         for (int i = k; i < r; ++i) nrm += R[i][k] * R[i][k];
         nrm = std::sqrt(nrm);
         if (nrm == 0) continue;
-        long double alpha = R[k][k] > 0 ? -nrm : nrm;
-        long double v[16];
+        double alpha = R[k][k] > 0 ? -nrm : nrm;
+        double v[16];
         for (int i = 0; i < r; ++i) v[i] = 0;
         for (int i = k; i < r; ++i) v[i] = R[i][k];
         v[k] -= alpha;
-        long double vv = 0;
+        double vv = 0;
         for (int i = k; i < r; ++i) vv += v[i] * v[i];
         if (vv == 0) continue;
         for (int j = 0; j < c; ++j) {
-            long double s = 0;
+            double s = 0;
             for (int i = k; i < r; ++i) s += v[i] * R[i][j];
             s = 2 * s / vv;
             for (int i = k; i < r; ++i) R[i][j] -= s * v[i];
         }
         for (int j = 0; j < r; ++j) {
-            long double s = 0;
+            double s = 0;
             for (int i = k; i < r; ++i) s += v[i] * QT[i][j];
             s = 2 * s / vv;
             for (int i = k; i < r; ++i) QT[i][j] -= s * v[i];
         }
     }
-    long double dmax = 0, dmin = INFINITY;
+    double dmax = 0, dmin = INFINITY;
     for (int k = 0; k < c; ++k) {
         dmax = std::max(dmax, std::fabs(R[k][k]));
         dmin = std::min(dmin, std::fabs(R[k][k]));
     }
-    if (!(dmin > 1e-12L * dmax)) return false;
+    if (!(dmin > 1e-12 * dmax)) return false;
     // X = R^{-1} QT[0:c, :]
     for (int col = 0; col < r; ++col) {
-        long double y[16];
+        double y[16];
         for (int i = c - 1; i >= 0; --i) {
-            long double s = QT[i][col];
+            double s = QT[i][col];
             for (int j = i + 1; j < c; ++j) s -= R[i][j] * y[j];
             y[i] = s / R[i][i];
         }
-        for (int i = 0; i < c; ++i) X[i * r + col] = (double)y[i];
+        for (int i = 0; i < c; ++i) X[i * r + col] = y[i];
     }
     return true;
 }
@@ -327,6 +327,13 @@ struct OpBuilder {
         {
             const int nm = mono.n;
             double B[14][14] = {{0}};
+            double ihp[D::DTOP + 1], ap[D::DTOP + 1];
+            ihp[0] = 1.0;
+            ap[0] = 1.0 / area0;
+            for (int s = 1; s <= D::DTOP; ++s) {
+                ihp[s] = ihp[s - 1] / h0;
+                ap[s] = ap[s - 1] * area0;
+            }
             for (size_t q = 0; q < rBeta.w.size(); ++q) {
                 P2d x = map_tri(V0, rBeta.r[q], rBeta.s[q]);
                 double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
@@ -344,12 +351,12 @@ struct OpBuilder {
                             double coef = 1.0;
                             for (int t = 0; t < a1; ++t) coef *= (a - t);
                             for (int t = 0; t < a2; ++t) coef *= (b - t);
-                            double v = coef / std::pow(h0, s);
+                            double v = coef * ihp[s];
                             for (int t = 0; t < a - a1; ++t) v *= xi;
                             for (int t = 0; t < b - a2; ++t) v *= eta;
                             Dv[j] = v;
                         }
-                        double sc = std::pow(area0, s - 1) * wq;
+                        double sc = ap[s] * wq;
                         for (int i = 0; i < nm; ++i)
                             for (int j = 0; j < nm; ++j) B[i][j] += sc * Dv[i] * Dv[j];
                     }

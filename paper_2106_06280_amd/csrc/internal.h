@@ -97,9 +97,11 @@ hipError_t launch_zero_u32(const LaunchCtx& c, uint32_t* p, int n);
 hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, const double* ops,
                           const int32_t* list, const uint32_t* count, double* compact,
                           uint32_t* status, int max_cells);
-// write the compact results into u (modes >= 1)
+// write the compact results into u (modes >= 1); tstats (may be null)
+// accumulates (troubled cells, limiter calls)
 hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* list,
-                          const uint32_t* count, const double* compact, int max_cells);
+                          const uint32_t* count, const double* compact, int max_cells,
+                          unsigned long long* tstats);
 hipError_t launch_ic_points(const LaunchCtx& c, const DevMesh& m, double* xy);
 hipError_t launch_project(const LaunchCtx& c, const DevMesh& m, const double* vals, void* u);
 int ic_points_per_element(int N);

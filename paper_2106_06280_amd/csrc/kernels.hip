@@ -696,9 +696,14 @@ template <int N, int M>
 __global__ __launch_bounds__(256) void k_scatter(int K, double* __restrict__ u,
                                                  const int32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ count,
-                                                 const double* __restrict__ compact) {
+                                                 const double* __restrict__ compact,
+                                                 unsigned long long* __restrict__ tstats) {
     constexpr int NP = Dims<N>::NP;
     const uint32_t n = min(*count, (uint32_t)K);
+    if (tstats != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&tstats[0], (unsigned long long)n);
+        atomicAdd(&tstats[1], 1ull);
+    }
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
         const int e = list[t];
 #pragma unroll
@@ -867,14 +872,14 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
 }
 
 hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* list, const uint32_t* count,
-                          const double* compact, int max_cells) {
+                          const double* compact, int max_cells, unsigned long long* tstats) {
     const unsigned bs = 256;
     unsigned g = grid_for(max_cells, bs);
     if (g > 4096u) g = 4096u;
     if (g == 0) g = 1;
     double* U = (double*)u;
     CSWDG_DISPATCH_EN(c.eq, c.N, {
-        k_scatter<N, Phys<EQ>::M><<<g, bs, 0, c.stream>>>(K, U, list, count, compact);
+        k_scatter<N, Phys<EQ>::M><<<g, bs, 0, c.stream>>>(K, U, list, count, compact, tstats);
     });
     return hipGetLastError();
 }
