@@ -1,6 +1,7 @@
 // C ABI of the library (declared in include/cswdg.h).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -184,6 +185,9 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.cfl = p.cfl;
     s->ctx.c_k = p.c_k;
     s->ctx.eps = p.eps_weno;
+    // schedule choice for the residual kernel (a tuning knob; same results)
+    const char* rv = std::getenv("CSWDG_RESIDUAL_VARIANT");
+    s->ctx.residual_variant = rv ? std::atoi(rv) : 0;
     *out = s;
     return CSWDG_OK;
 }

@@ -13,10 +13,11 @@
 //   k_dt_*      cell-mean wave speeds -> dt (two-pass reduction).
 //   k_kxrcf     one thread per element: KXRCF indicator, then a wave ballot
 //               and one atomic per wave to append troubled cells to a list.
-//   k_limiter   one thread per troubled cell: subcell averages, the three
-//               (four) least-squares levels, smoothness indicators, WENO-Z
-//               weights and the projection, per characteristic field for
-//               Euler; results to a compact buffer (every cell reads the
+//   k_limiter   one lane per (troubled cell, characteristic direction,
+//               field): subcell averages, the three (four) least-squares
+//               levels, smoothness indicators, WENO-Z weights and the
+//               projection; a lane butterfly recombines the conserved
+//               moments; results to a compact buffer (every cell reads the
 //               pre-limit field).
 //   k_scatter   compact results -> state (modes >= 1).
 #include <hip/hip_runtime.h>
@@ -92,7 +93,8 @@ struct Phys<1> {
     static constexpr int M = 4;
     __device__ static __forceinline__ void flux(const double* U, double g, double* F, double* G) {
         double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double u = mu / rho, v = mv / rho;
+        double ir = 1.0 / rho;
+        double u = mu * ir, v = mv * ir;
         double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
         F[0] = mu;
         F[1] = mu * u + p;
@@ -106,14 +108,15 @@ struct Phys<1> {
     __device__ static __forceinline__ void normal_flux(const double* U, double nx, double ny, double g,
                                                        double* Fn, double& lam) {
         double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double u = mu / rho, v = mv / rho;
+        double ir = 1.0 / rho;
+        double u = mu * ir, v = mv * ir;
         double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
         double un = u * nx + v * ny;
         Fn[0] = mu * nx + mv * ny;
         Fn[1] = (mu * u + p) * nx + (mu * v) * ny;
         Fn[2] = (mv * u) * nx + (mv * v + p) * ny;
         Fn[3] = ((E + p) * u) * nx + ((E + p) * v) * ny;
-        lam = fabs(un) + sqrt(g * p / rho);
+        lam = fabs(un) + sqrt(g * p * ir);
     }
 };
 
@@ -121,11 +124,11 @@ struct Phys<1> {
 // Residual and RK stage
 // ---------------------------------------------------------------------------
 template <int EQ, int N, int MODE>
-__global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __restrict__ u,
-                                                  const double* __restrict__ un,
-                                                  double* __restrict__ out,
-                                                  const double* __restrict__ dtp, double gamma,
-                                                  uint32_t* __restrict__ cnt_reset) {
+__device__ __forceinline__ void residual_body(DevMesh msh, const double* __restrict__ u,
+                                              const double* __restrict__ un,
+                                              double* __restrict__ out,
+                                              const double* __restrict__ dtp, double gamma,
+                                              uint32_t* __restrict__ cnt_reset) {
     using D = Dims<N>;
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
@@ -182,7 +185,8 @@ __global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __r
         const int f1 = (f + 1) % 3;
         const double ex = X[f1] - X[f], ey = Y[f1] - Y[f];
         const double L = sqrt(ex * ex + ey * ey);
-        const double nx = ey / L, ny = -ex / L;
+        const double iL = 1.0 / L;
+        const double nx = ey * iL, ny = -ex * iL;
         const double sf = 0.5 * L * iJ;
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
@@ -240,6 +244,25 @@ __global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __r
             }
             out[idx] = v;
         }
+}
+
+// Two register budgets of the same body: the default lets the compiler use up
+// to 512 VGPRs (one wave per SIMD for the Euler cases); the second caps it at
+// 256 (two waves per SIMD, at the price of a few spills for P2/P3 Euler).
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __restrict__ u,
+                                                  const double* __restrict__ un, double* __restrict__ out,
+                                                  const double* __restrict__ dtp, double gamma,
+                                                  uint32_t* __restrict__ cnt_reset) {
+    residual_body<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
+}
+
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256, 2) void k_residual_w2(DevMesh msh, const double* __restrict__ u,
+                                                       const double* __restrict__ un, double* __restrict__ out,
+                                                       const double* __restrict__ dtp, double gamma,
+                                                       uint32_t* __restrict__ cnt_reset) {
+    residual_body<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,6 +476,19 @@ __device__ __forceinline__ double quad_form(const double* __restrict__ bp, const
     return s;
 }
 
+// One troubled cell is handled by LPC = (number of characteristic
+// directions) x (number of fields) lanes: lane (d, k) reconstructs
+// characteristic field k of direction d (Euler: 2 x 4 = 8 lanes; Burgers: 1).
+// The lanes of a cell read the same operator record and neighbour
+// coefficients (one cache line serves all of them) and combine their
+// moments with a butterfly over the cell's lanes.
+template <int EQ>
+struct LimLanes {
+    static constexpr int ND = (EQ == 1) ? 2 : 1;
+    static constexpr int M = Phys<EQ>::M;
+    static constexpr int LPC = ND * M;
+};
+
 template <int EQ, int N>
 __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __restrict__ u,
                                                 const double* __restrict__ ops,
@@ -464,231 +500,225 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __res
     using D = Dims<N>;
     using LO = OpLayout<N>;
     constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = D::NPIECE, NM = D::NMONO;
-    constexpr int ND = (EQ == 1) ? 2 : 1;
+    constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
+    constexpr int CPB = 64 / LPC;  // cells per block
     const int K = msh.K;
     const uint32_t ncell = min(*count, (uint32_t)K);
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ncell; t += gridDim.x * blockDim.x) {
-        const int e = list[t];
+    const int j = threadIdx.x % LPC;  // lane within the cell
+    const int d = j / M;              // characteristic direction
+    const int k = j % M;              // characteristic field
+    for (uint32_t base = blockIdx.x * CPB; base < ncell; base += gridDim.x * CPB) {
+        const uint32_t t = base + threadIdx.x / LPC;
+        const bool active = t < ncell;
+        const int e = active ? list[t] : 0;
         const double* __restrict__ op = ops + (size_t)e * LO::LEN;
-        double U0[M][NP];
+        const bool valid = active && op[LO::VALID] != 0.0;
+
+        double ub0[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c)
+        for (int c = 0; c < M; ++c) ub0[c] = u[(size_t)(c * NP) * K + e] * kPsi0;
+        // row k of L_d and column k of R_d at the mean of Delta0
+        double Lr[M], Rc[M];
+        if constexpr (EQ == 1) {
+            double Lm[4][4], Rm[4][4];
+            euler_eigen(ub0, d == 0 ? 1.0 : 0.0, d == 0 ? 0.0 : 1.0, gamma, Lm, Rm);
 #pragma unroll
-            for (int n = 0; n < NP; ++n) U0[c][n] = u[(size_t)(c * NP + n) * K + e];
-        double* outp = compact + (size_t)t * (M * NP);
-        if (op[LO::VALID] == 0.0) {
-            atomicOr(status, CSWDG_STATUS_RANK);
+            for (int c = 0; c < 4; ++c) {
+                double a = Lm[0][c], b = Rm[c][0];
 #pragma unroll
-            for (int c = 0; c < M; ++c)
-#pragma unroll
-                for (int n = 0; n < NP; ++n) outp[c * NP + n] = U0[c][n];
-            continue;
+                for (int kk = 1; kk < 4; ++kk) {
+                    a = (k == kk) ? Lm[kk][c] : a;
+                    b = (k == kk) ? Rm[c][kk] : b;
+                }
+                Lr[c] = a;
+                Rc[c] = b;
+            }
+        } else {
+            Lr[0] = 1.0;
+            Rc[0] = 1.0;
         }
-        // subcell averages of the source polynomials
+        double w0 = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) w0 += Lr[c] * ub0[c];
+
+        // field-k averages over the pieces of the three neighbours
         const uint32_t info4 = msh.info[e];
-        double av[3][NPC][M];
+        double w[3][NPC];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
             const int src = (inf & 0x40u) ? e : msh.nbr[f * K + e];
-            double Us[M][NP];
+            double ws[NP];
 #pragma unroll
-            for (int c = 0; c < M; ++c)
+            for (int n = 0; n < NP; ++n) {
+                double s = 0.0;
 #pragma unroll
-                for (int n = 0; n < NP; ++n) Us[c][n] = u[(size_t)(c * NP + n) * K + src];
+                for (int c = 0; c < M; ++c) s += Lr[c] * u[(size_t)(c * NP + n) * K + src];
+                ws[n] = s;
+            }
 #pragma unroll
             for (int p = 0; p < NPC; ++p) {
                 const double* a = op + LO::AVG + (f * NPC + p) * NP;
+                double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int n = 0; n < NP; ++n) s += a[n] * Us[c][n];
-                    av[f][p][c] = s;
-                }
+                for (int n = 0; n < NP; ++n) s += a[n] * ws[n];
+                w[f][p] = s;
             }
         }
-        double ub0[M];
+        // Step 1: least-squares levels (pseudo-inverses applied to
+        // piece average - mean of Delta0)
+        double c2[2], c3[5], c5[NM];
 #pragma unroll
-        for (int c = 0; c < M; ++c) ub0[c] = U0[c][0] * kPsi0;
-
-        const double h0 = op[LO::H0], area0 = op[LO::AREA0];
-        // linear weights gamma_{l,t} = h^{-(l-1)} / sum (Section 3.2, Step 2)
-        const double ih = 1.0 / h0;
-        double g2[2], g3[3], g5[4];
-        {
-            double s2 = 1.0 + ih;
-            g2[0] = 1.0 / s2;
-            g2[1] = ih / s2;
-            double s3 = 1.0 + ih + ih * ih;
-            g3[0] = 1.0 / s3;
-            g3[1] = ih / s3;
-            g3[2] = ih * ih / s3;
-            double s5 = 1.0 + ih + ih * ih + ih * ih * ih;
-            g5[0] = 1.0 / s5;
-            g5[1] = ih / s5;
-            g5[2] = ih * ih / s5;
-            g5[3] = ih * ih * ih / s5;
+        for (int jj = 0; jj < 2; ++jj) {
+            double s = 0.0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) s += op[LO::X2 + jj * 3 + f] * (w[f][0] - w0);
+            c2[jj] = s;
         }
-
+#pragma unroll
+        for (int jj = 0; jj < 5; ++jj) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) s += op[LO::X3 + jj * 9 + p * 3 + f] * (w[f][p] - w0);
+            c3[jj] = s;
+        }
+#pragma unroll
+        for (int jj = 0; jj < NM; ++jj) c5[jj] = 0.0;
+        if constexpr (N >= 2) {
+            constexpr int pl[5] = {0, 3, 4, 5, 6};
+#pragma unroll
+            for (int jj = 0; jj < 14; ++jj) {
+                double s = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < 5; ++kk)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) s += op[LO::X5 + jj * 15 + kk * 3 + f] * (w[f][pl[kk]] - w0);
+                c5[jj] = s;
+            }
+        }
+        // Step 3: smoothness indicators of q_2, q_3 (and q_5)
+        const double* bp = op + LO::BP;
+        double beta[4];
+        beta[1] = quad_form<NM, 2>(bp, c2);
+        beta[2] = quad_form<NM, 5>(bp, c3);
+        beta[3] = (N >= 2) ? quad_form<NM, NM>(bp, c5) : 0.0;
+        const double area0 = op[LO::AREA0];
+        {
+            double gx[3], gy[3], b1[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const double* mi = op + LO::MINV + 4 * f;
+                const double d0 = w[f][1] - w[f][0], d1 = w[f][2] - w[f][0];
+                gx[f] = mi[0] * d0 + mi[1] * d1;
+                gy[f] = mi[2] * d0 + mi[3] * d1;
+                b1[f] = area0 * (gx[f] * gx[f] + gy[f] * gy[f]);
+            }
+            const double a01 = fabs(b1[0] - b1[1]), a12 = fabs(b1[1] - b1[2]), a20 = fabs(b1[2] - b1[0]);
+            const double mm = (a01 * a01 + a12 * a12 + a20 * a20) / 3.0;
+            const double num = mm * mm;
+            double sg[3], ssum = 0.0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                sg[f] = (1.0 / 3.0) * (1.0 + num / (b1[f] + eps));
+                ssum += sg[f];
+            }
+            double mx = 0.0, my = 0.0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                mx += (sg[f] / ssum) * gx[f];
+                my += (sg[f] / ssum) * gy[f];
+            }
+            beta[0] = area0 * (mx * mx + my * my);
+        }
+        // Steps 2 and 4: linear weights gamma_{l,t} = h^{-(l-1)} / sum,
+        // WENO-Z weights, R = sum_l omega_l p_l written on c2, c3, c5
+        const double ih = 1.0 / op[LO::H0];
+        double A2, A3, A5;
+        {
+            const double s2 = 1.0 + ih, s3 = 1.0 + ih + ih * ih;
+            const double g22 = ih / s2;
+            const double g23 = ih / s3, g33 = ih * ih / s3;
+            if constexpr (N == 1) {
+                const double g13 = 1.0 / s3;
+                const double d31 = fabs(beta[2] - beta[0]), d32 = fabs(beta[2] - beta[1]);
+                const double tau = (d31 * d31 + d32 * d32) / 4.0;
+                const double o1 = g13 * (1.0 + tau / (eps + beta[0]));
+                const double o2 = g23 * (1.0 + tau / (eps + beta[1]));
+                const double o3 = g33 * (1.0 + tau / (eps + beta[2]));
+                const double os = o1 + o2 + o3;
+                const double w2 = o2 / os, w3 = o3 / os;
+                // p2 = c2/g22, p3 = (c3 - g23 p2)/g33
+                A3 = w3 / g33;
+                A2 = w2 / g22 - A3 * g23 / g22;
+                A5 = 0.0;
+            } else {
+                const double s5 = 1.0 + ih + ih * ih + ih * ih * ih;
+                const double g15 = 1.0 / s5, g25 = ih / s5, g35 = ih * ih / s5, g45 = ih * ih * ih / s5;
+                const double d1 = fabs(beta[3] - beta[0]), d2 = fabs(beta[3] - beta[1]), d3 = fabs(beta[3] - beta[2]);
+                const double tau = (d1 * d1 + d2 * d2 + d3 * d3) / 16.0;
+                const double o1 = g15 * (1.0 + tau / (eps + beta[0]));
+                const double o2 = g25 * (1.0 + tau / (eps + beta[1]));
+                const double o3 = g35 * (1.0 + tau / (eps + beta[2]));
+                const double o4 = g45 * (1.0 + tau / (eps + beta[3]));
+                const double os = o1 + o2 + o3 + o4;
+                const double w2 = o2 / os, w3 = o3 / os, w4 = o4 / os;
+                // p4 = (c5 - g25 p2 - g35 p3)/g45; collect the factors of c5, c3, c2
+                A5 = w4 / g45;
+                const double P3 = w3 - A5 * g35;  // factor of p3
+                A3 = P3 / g33;
+                const double P2 = w2 - A5 * g25 - A3 * g23;  // factor of p2
+                A2 = P2 / g22;
+            }
+        }
+        // Step 5: projection of R onto psi_1..psi_{Np-1}
+        double mom[NP - 1];
+#pragma unroll
+        for (int i = 0; i < NP - 1; ++i) {
+            const double* pm = op + LO::PM + i * NM;
+            double s = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < NM; ++jj) {
+                double r = A5 * c5[jj];
+                if (jj < 5) r += A3 * c3[jj];
+                if (jj < 2) r += A2 * c2[jj];
+                s += pm[jj] * r;
+            }
+            mom[i] = s;
+        }
+        // back to conserved variables: sum over (d, k) of R_d[c][k] mom_dk / ND
         double res[M][NP - 1];
 #pragma unroll
         for (int c = 0; c < M; ++c)
 #pragma unroll
-            for (int i = 0; i < NP - 1; ++i) res[c][i] = 0.0;
-
-#pragma unroll 1
-        for (int d = 0; d < ND; ++d) {
-            double Lm[4][4], Rm[4][4];
-            if constexpr (EQ == 1) euler_eigen(ub0, d == 0 ? 1.0 : 0.0, d == 0 ? 0.0 : 1.0, gamma, Lm, Rm);
-#pragma unroll 1
-            for (int k = 0; k < M; ++k) {
-                // characteristic field k of the stencil averages
-                double w[3][NPC];
-                double w0;
-                if constexpr (EQ == 1) {
-                    w0 = 0.0;
+            for (int i = 0; i < NP - 1; ++i) res[c][i] = (1.0 / ND) * Rc[c] * mom[i];
 #pragma unroll
-                    for (int c = 0; c < M; ++c) w0 += Lm[k][c] * ub0[c];
+        for (int o = 1; o < LPC; o <<= 1)
 #pragma unroll
-                    for (int f = 0; f < 3; ++f)
+            for (int c = 0; c < M; ++c)
 #pragma unroll
-                        for (int p = 0; p < NPC; ++p) {
-                            double s = 0.0;
+                for (int i = 0; i < NP - 1; ++i) res[c][i] += __shfl_xor(res[c][i], o, LPC);
+        if (active && j < M) {
+            double* outp = compact + (size_t)t * (M * NP) + j * NP;
+            double sel[NP - 1];
 #pragma unroll
-                            for (int c = 0; c < M; ++c) s += Lm[k][c] * av[f][p][c];
-                            w[f][p] = s;
-                        }
-                } else {
-                    w0 = ub0[0];
+            for (int i = 0; i < NP - 1; ++i) {
+                double v = res[0][i];
 #pragma unroll
-                    for (int f = 0; f < 3; ++f)
+                for (int c = 1; c < M; ++c) v = (j == c) ? res[c][i] : v;
+                sel[i] = v;
+            }
+            outp[0] = u[(size_t)(j * NP) * K + e];
+            if (valid) {
 #pragma unroll
-                        for (int p = 0; p < NPC; ++p) w[f][p] = av[f][p][0];
-                }
-                // Step 1: least-squares levels
-                double c2[NM], c3[NM], c5[NM];
+                for (int i = 1; i < NP; ++i) outp[i] = sel[i - 1];
+            } else {
 #pragma unroll
-                for (int j = 0; j < NM; ++j) c2[j] = c3[j] = c5[j] = 0.0;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) s += op[LO::X2 + j * 3 + f] * (w[f][0] - w0);
-                    c2[j] = s;
-                }
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int p = 0; p < 3; ++p)
-#pragma unroll
-                        for (int f = 0; f < 3; ++f) s += op[LO::X3 + j * 9 + p * 3 + f] * (w[f][p] - w0);
-                    c3[j] = s;
-                }
-                if constexpr (N >= 2) {
-                    constexpr int pl[5] = {0, 3, 4, 5, 6};
-#pragma unroll
-                    for (int j = 0; j < 14; ++j) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int kk = 0; kk < 5; ++kk)
-#pragma unroll
-                            for (int f = 0; f < 3; ++f) s += op[LO::X5 + j * 15 + kk * 3 + f] * (w[f][pl[kk]] - w0);
-                        c5[j] = s;
-                    }
-                }
-                // Step 3: smoothness indicators of q_l
-                const double* bp = op + LO::BP;
-                double beta[4];
-                beta[1] = quad_form<NM, 2>(bp, c2);
-                beta[2] = quad_form<NM, 5>(bp, c3);
-                beta[3] = (N >= 2) ? quad_form<NM, NM>(bp, c5) : 0.0;
-                double gx[3], gy[3], b1[3];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    const double* mi = op + LO::MINV + 4 * f;
-                    const double d0 = w[f][1] - w[f][0], d1 = w[f][2] - w[f][0];
-                    gx[f] = mi[0] * d0 + mi[1] * d1;
-                    gy[f] = mi[2] * d0 + mi[3] * d1;
-                    b1[f] = area0 * (gx[f] * gx[f] + gy[f] * gy[f]);
-                }
-                {
-                    const double a01 = fabs(b1[0] - b1[1]), a12 = fabs(b1[1] - b1[2]), a20 = fabs(b1[2] - b1[0]);
-                    const double mm = (a01 * a01 + a12 * a12 + a20 * a20) / 3.0;
-                    const double num = mm * mm;
-                    double sg[3], ssum = 0.0;
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        sg[f] = (1.0 / 3.0) * (1.0 + num / (b1[f] + eps));
-                        ssum += sg[f];
-                    }
-                    double mx = 0.0, my = 0.0;
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        mx += (sg[f] / ssum) * gx[f];
-                        my += (sg[f] / ssum) * gy[f];
-                    }
-                    beta[0] = area0 * (mx * mx + my * my);
-                }
-                // Step 2: equivalent polynomials (mean-free parts; p_1 has none)
-                double p2[NM], p3[NM], p4[NM];
-#pragma unroll
-                for (int j = 0; j < NM; ++j) {
-                    p2[j] = c2[j] / g2[1];
-                    p3[j] = (c3[j] - g3[1] * p2[j]) / g3[2];
-                    p4[j] = (N >= 2) ? (c5[j] - g5[1] * p2[j] - g5[2] * p3[j]) / g5[3] : 0.0;
-                }
-                // Step 4: tau and nonlinear weights
-                double om[4];
-                if (N == 1) {
-                    const double d31 = fabs(beta[2] - beta[0]), d32 = fabs(beta[2] - beta[1]);
-                    const double tau = (d31 * d31 + d32 * d32) / 4.0;
-                    double s = 0.0;
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) {
-                        om[l] = g3[l] * (1.0 + tau / (eps + beta[l]));
-                        s += om[l];
-                    }
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) om[l] /= s;
-                    om[3] = 0.0;
-                } else {
-                    const double d1 = fabs(beta[3] - beta[0]), d2 = fabs(beta[3] - beta[1]), d3 = fabs(beta[3] - beta[2]);
-                    const double tau = (d1 * d1 + d2 * d2 + d3 * d3) / 16.0;
-                    double s = 0.0;
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        om[l] = g5[l] * (1.0 + tau / (eps + beta[l]));
-                        s += om[l];
-                    }
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) om[l] /= s;
-                }
-                // reconstruction R = sum_l omega_l p_l and its projection
-                double Rc[NM];
-#pragma unroll
-                for (int j = 0; j < NM; ++j) Rc[j] = om[1] * p2[j] + om[2] * p3[j] + om[3] * p4[j];
-#pragma unroll
-                for (int i = 0; i < NP - 1; ++i) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NM; ++j) s += op[LO::PM + i * NM + j] * Rc[j];
-                    if constexpr (EQ == 1) {
-#pragma unroll
-                        for (int c = 0; c < M; ++c) res[c][i] += 0.5 * Rm[c][k] * s;
-                    } else {
-                        res[0][i] = s;
-                    }
-                }
+                for (int i = 1; i < NP; ++i) outp[i] = u[(size_t)(j * NP + i) * K + e];
             }
         }
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            outp[c * NP] = U0[c][0];
-#pragma unroll
-            for (int i = 1; i < NP; ++i) outp[c * NP + i] = res[c][i - 1];
-        }
+        if (active && !valid && j == 0) atomicOr(status, CSWDG_STATUS_RANK);
     }
 }
 
@@ -816,15 +846,22 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
     const double* U = (const double*)u;
     const double* UN = (const double*)un;
     double* O = (double*)out;
+#define CSWDG_RES_LAUNCH(KERN)                                                                   \
+    switch (mode) {                                                                              \
+        case 0: KERN<EQ, N, 0><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break; \
+        case 1: KERN<EQ, N, 1><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break; \
+        case 2: KERN<EQ, N, 2><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break; \
+        case 3: KERN<EQ, N, 3><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break; \
+        default: return hipErrorInvalidValue;                                                    \
+    }
     CSWDG_DISPATCH_EN(c.eq, c.N, {
-        switch (mode) {
-            case 0: k_residual<EQ, N, 0><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
-            case 1: k_residual<EQ, N, 1><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
-            case 2: k_residual<EQ, N, 2><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
-            case 3: k_residual<EQ, N, 3><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
-            default: return hipErrorInvalidValue;
+        if (c.residual_variant == 1) {
+            CSWDG_RES_LAUNCH(k_residual_w2)
+        } else {
+            CSWDG_RES_LAUNCH(k_residual)
         }
     });
+#undef CSWDG_RES_LAUNCH
     return hipGetLastError();
 }
 
@@ -861,8 +898,9 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
                           const int32_t* list, const uint32_t* count, double* compact, uint32_t* status,
                           int max_cells) {
     const unsigned bs = 64;
-    unsigned g = grid_for(max_cells, bs);
-    if (g > 8192u) g = 8192u;
+    const int lpc = c.eq == 1 ? LimLanes<1>::LPC : LimLanes<0>::LPC;
+    unsigned g = grid_for(max_cells, bs / lpc);
+    if (g > 16384u) g = 16384u;
     if (g == 0) g = 1;
     const double* U = (const double*)u;
     CSWDG_DISPATCH_EN(c.eq, c.N, {
