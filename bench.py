@@ -121,7 +121,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--residual-variant", type=int, default=None,
+                    help="residual kernel schedule (0 lean, 1 wide, 2 stream)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 10 device-to-device copies of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.residual_variant is not None:
+        os.environ["CSWDG_RESIDUAL_VARIANT"] = str(args.residual_variant)
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": a.numel() * 8, "dispatches": 10}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)

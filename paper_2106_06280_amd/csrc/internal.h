@@ -74,7 +74,7 @@ struct LaunchCtx {
     hipStream_t stream;
     int eq, N, precision;
     double gamma, cfl, c_k, eps;
-    int residual_variant;  // 0: up to 512 VGPRs; 1: 256 VGPRs (two waves per SIMD)
+    int residual_variant;  // residual schedule: 0 lean (default), 1 wide, 2 stream
 };
 
 int upload_tables_device();  // once per device

@@ -246,9 +246,11 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
         }
 }
 
-// Two register budgets of the same body: the default lets the compiler use up
-// to 512 VGPRs (one wave per SIMD for the Euler cases); the second caps it at
-// 256 (two waves per SIMD, at the price of a few spills for P2/P3 Euler).
+// Three schedules of the same arithmetic (results agree to rounding): "wide"
+// keeps the neighbour coefficients of all faces live (one wave per SIMD for
+// P2 Euler), "lean" (the default) bounds the live ranges to one face (two
+// waves per SIMD without spills), "stream" also re-reads the element's own
+// coefficients per face.
 template <int EQ, int N, int MODE>
 __global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __restrict__ u,
                                                   const double* __restrict__ un, double* __restrict__ out,
@@ -257,12 +259,298 @@ __global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __r
     residual_body<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
 }
 
+// Same arithmetic as residual_body with bounded live ranges: the face loop is
+// not unrolled (its tables are read with a uniform face index), and the
+// neighbour's traces are formed one conserved variable at a time, so only
+// the element's coefficients, the accumulators and one face's traces are
+// live at once.
 template <int EQ, int N, int MODE>
-__global__ __launch_bounds__(256, 2) void k_residual_w2(DevMesh msh, const double* __restrict__ u,
+__device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __restrict__ u,
+                                                   const double* __restrict__ un,
+                                                   double* __restrict__ out,
+                                                   const double* __restrict__ dtp, double gamma,
+                                                   uint32_t* __restrict__ cnt_reset) {
+    using D = Dims<N>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
+    const int K = msh.K;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
+    if (e >= K) return;
+    const Tab<N>& T = tab<N>();
+
+    double U[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) U[c][n] = u[(size_t)(c * NP + n) * K + e];
+
+    double acc[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) acc[c][n] = 0.0;
+    {
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        const double xr = 0.5 * (x1 - x0), xs = 0.5 * (x2 - x0);
+        const double yr = 0.5 * (y1 - y0), ys = 0.5 * (y2 - y0);
+        const double iJ = 1.0 / (xr * ys - xs * yr);
+        const double rx = ys * iJ, ry = -xs * iJ, sx = -yr * iJ, sy = xr * iJ;
+#pragma unroll 3
+        for (int q = 0; q < NQ; ++q) {
+            double uq[M], F[M], G[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) s += T.V[q][n] * U[c][n];
+                uq[c] = s;
+            }
+            Phys<EQ>::flux(uq, gamma, F, G);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double fr = rx * F[c] + ry * G[c];
+                const double fs = sx * F[c] + sy * G[c];
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] += T.wDr[q][i] * fr + T.wDs[q][i] * fs;
+            }
+        }
+    }
+
+    const uint32_t info4 = msh.info[e];
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+        const int f1 = (f == 2) ? 0 : f + 1;
+        const double xa = msh.vx[f * K + e], ya = msh.vy[f * K + e];
+        const double xb = msh.vx[f1 * K + e], yb = msh.vy[f1 * K + e];
+        const double ex = xb - xa, ey = yb - ya;
+        const double L = sqrt(ex * ex + ey * ey);
+        const double iL = 1.0 / L;
+        const double nx = ey * iL, ny = -ex * iL;
+        // L_f / (2 J) with 2 J = area; recomputed from the vertices
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        const double J = 0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+        const double sf = 0.5 * L / J;
+        const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+        const bool bnd = (inf & 0x40u) != 0u;
+        const int fp = (int)(inf & 3u);
+        const int nb = bnd ? e : msh.nbr[f * K + e];
+        double up[NE][M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double w[NP];
+#pragma unroll
+            for (int n = 0; n < NP; ++n) w[n] = u[(size_t)(c * NP + n) * K + nb];
+#pragma unroll
+            for (int g = 0; g < NE; ++g) {
+                double s = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) s += T.PF[fp][NE - 1 - g][n] * w[n];
+                up[g][c] = s;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < NE; ++g) {
+            double um[M], upg[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double a = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) a += T.PF[f][g][n] * U[c][n];
+                um[c] = a;
+                upg[c] = bnd ? a : up[g][c];
+            }
+            double Fm[M], Fp[M], lm, lp;
+            Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
+            Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
+            const double alpha = fmax(lm, lp);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
+                const double sFs = sf * Fs;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] -= T.wPF[f][g][i] * sFs;
+            }
+        }
+    }
+
+    double dt = 0.0;
+    if (MODE != 0) dt = *dtp;
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const size_t idx = (size_t)(c * NP + i) * K + e;
+            double v;
+            if (MODE == 0) {
+                v = acc[c][i];
+            } else if (MODE == 1) {
+                v = U[c][i] + dt * acc[c][i];
+            } else if (MODE == 2) {
+                v = 0.75 * un[idx] + 0.25 * (U[c][i] + dt * acc[c][i]);
+            } else {
+                v = (1.0 / 3.0) * un[idx] + (2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
+            }
+            out[idx] = v;
+        }
+}
+
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256) void k_residual_lean(DevMesh msh, const double* __restrict__ u,
                                                        const double* __restrict__ un, double* __restrict__ out,
                                                        const double* __restrict__ dtp, double gamma,
                                                        uint32_t* __restrict__ cnt_reset) {
-    residual_body<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
+    residual_body_lean<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
+}
+
+template <int EQ, int N, int MODE>
+__device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* __restrict__ u,
+                                                   const double* __restrict__ un,
+                                                   double* __restrict__ out,
+                                                   const double* __restrict__ dtp, double gamma,
+                                                   uint32_t* __restrict__ cnt_reset) {
+    using D = Dims<N>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
+    const int K = msh.K;
+    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
+    if (e >= K) return;
+    const Tab<N>& T = tab<N>();
+
+    // the element's coefficients are re-read (cache hits) in every phase
+    // instead of staying live; the opaque copy of the pointer keeps the
+    // compiler from reusing the first loads
+    const double* __restrict__ us = u;
+    double acc[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) acc[c][n] = 0.0;
+    {
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        const double xr = 0.5 * (x1 - x0), xs = 0.5 * (x2 - x0);
+        const double yr = 0.5 * (y1 - y0), ys = 0.5 * (y2 - y0);
+        const double iJ = 1.0 / (xr * ys - xs * yr);
+        const double rx = ys * iJ, ry = -xs * iJ, sx = -yr * iJ, sy = xr * iJ;
+        double U[M][NP];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int n = 0; n < NP; ++n) U[c][n] = us[(size_t)(c * NP + n) * K + e];
+#pragma unroll 3
+        for (int q = 0; q < NQ; ++q) {
+            double uq[M], F[M], G[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) s += T.V[q][n] * U[c][n];
+                uq[c] = s;
+            }
+            Phys<EQ>::flux(uq, gamma, F, G);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double fr = rx * F[c] + ry * G[c];
+                const double fs = sx * F[c] + sy * G[c];
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] += T.wDr[q][i] * fr + T.wDs[q][i] * fs;
+            }
+        }
+    }
+
+    const uint32_t info4 = msh.info[e];
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+        const int f1 = (f == 2) ? 0 : f + 1;
+        const double xa = msh.vx[f * K + e], ya = msh.vy[f * K + e];
+        const double xb = msh.vx[f1 * K + e], yb = msh.vy[f1 * K + e];
+        const double ex = xb - xa, ey = yb - ya;
+        const double L = sqrt(ex * ex + ey * ey);
+        const double iL = 1.0 / L;
+        const double nx = ey * iL, ny = -ex * iL;
+        // L_f / (2 J) with 2 J = area; recomputed from the vertices
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        const double J = 0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+        const double sf = 0.5 * L / J;
+        const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+        const bool bnd = (inf & 0x40u) != 0u;
+        const int fp = (int)(inf & 3u);
+        const int nb = bnd ? e : msh.nbr[f * K + e];
+        asm volatile("" : "+s"(us));
+        double up[NE][M], umf[NE][M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double w[NP], wo[NP];
+#pragma unroll
+            for (int n = 0; n < NP; ++n) {
+                w[n] = u[(size_t)(c * NP + n) * K + nb];
+                wo[n] = us[(size_t)(c * NP + n) * K + e];
+            }
+#pragma unroll
+            for (int g = 0; g < NE; ++g) {
+                double s = 0.0, a = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) {
+                    s += T.PF[fp][NE - 1 - g][n] * w[n];
+                    a += T.PF[f][g][n] * wo[n];
+                }
+                up[g][c] = s;
+                umf[g][c] = a;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < NE; ++g) {
+            double um[M], upg[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                um[c] = umf[g][c];
+                upg[c] = bnd ? umf[g][c] : up[g][c];
+            }
+            double Fm[M], Fp[M], lm, lp;
+            Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
+            Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
+            const double alpha = fmax(lm, lp);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
+                const double sFs = sf * Fs;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] -= T.wPF[f][g][i] * sFs;
+            }
+        }
+    }
+
+    double dt = 0.0;
+    if (MODE != 0) dt = *dtp;
+    asm volatile("" : "+s"(us));
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const size_t idx = (size_t)(c * NP + i) * K + e;
+            double v;
+            if (MODE == 0) {
+                v = acc[c][i];
+            } else if (MODE == 1) {
+                v = us[idx] + dt * acc[c][i];
+            } else if (MODE == 2) {
+                v = 0.75 * un[idx] + 0.25 * (us[idx] + dt * acc[c][i]);
+            } else {
+                v = (1.0 / 3.0) * un[idx] + (2.0 / 3.0) * (us[idx] + dt * acc[c][i]);
+            }
+            out[idx] = v;
+        }
+}
+
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256) void k_residual_stream(DevMesh msh, const double* __restrict__ u,
+                                                         const double* __restrict__ un, double* __restrict__ out,
+                                                         const double* __restrict__ dtp, double gamma,
+                                                         uint32_t* __restrict__ cnt_reset) {
+    residual_body_stream<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
 }
 
 // ---------------------------------------------------------------------------
@@ -856,9 +1144,11 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
     }
     CSWDG_DISPATCH_EN(c.eq, c.N, {
         if (c.residual_variant == 1) {
-            CSWDG_RES_LAUNCH(k_residual_w2)
-        } else {
             CSWDG_RES_LAUNCH(k_residual)
+        } else if (c.residual_variant == 2) {
+            CSWDG_RES_LAUNCH(k_residual_stream)
+        } else {
+            CSWDG_RES_LAUNCH(k_residual_lean)
         }
     });
 #undef CSWDG_RES_LAUNCH
