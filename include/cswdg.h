@@ -175,6 +175,32 @@ int cswdg_ssprk3_step(cswdg_solver* s, void* u, const double* dt_dev);
 /* Device pointer to the solver's last computed dt (valid for its lifetime). */
 int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
 
+/* ---- Adjoint (vector-Jacobian products; not part of the paper) ----------
+ * The limiter is differentiated with its troubled-cell set frozen (the KXRCF
+ * indicator is a switch, not differentiated); the Lax-Friedrichs max picks
+ * the first argument on ties and d|x|/dx = 0 at x = 0.  Deterministic (no
+ * floating-point atomics).  All buffers device, state layout. */
+
+/* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).
+ * u_bar must not alias r_bar. */
+int cswdg_dg_residual_vjp(cswdg_solver* s, const void* u, const void* r_bar, void* u_bar);
+/* w_bar = Lambda'(w)^T y_bar for the limiter cswdg_csweno_limit applied to w
+ * with troubled cells mask (device uint8 [K]; NULL = the KXRCF flags of w). */
+int cswdg_csweno_limit_vjp(cswdg_solver* s, const void* w, const uint8_t* mask, const void* y_bar,
+                           void* w_bar);
+/* Size in bytes of a step tape: the step's input, the three pre-limit stage
+ * states, the two limited intermediate states, the three troubled masks and
+ * dt. */
+int cswdg_tape_bytes(cswdg_solver* s, int64_t* bytes);
+/* cswdg_ssprk3_step in place on u, recording the tape (device buffer of
+ * cswdg_tape_bytes).  replay = 0: dt from dt_dev (or cswdg_max_dt of u when
+ * NULL) and masks from the limiter mode are computed and stored; replay = 1:
+ * the tape's dt and masks are reused (a step with frozen decisions). */
+int cswdg_ssprk3_step_tape(cswdg_solver* s, void* u, const double* dt_dev, void* tape, int replay);
+/* u_n_bar = (d u^{n+1} / d u^n)^T u_next_bar for the step recorded in tape,
+ * with its dt and masks frozen.  u_n_bar must not alias u_next_bar. */
+int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_bar, void* u_n_bar);
+
 /* Troubled-cell count of the last limiter call (host int, synchronous). */
 int cswdg_troubled_count(cswdg_solver* s, int64_t* count);
 /* Troubled cells summed over all limiter calls since the last reset, and the

@@ -57,6 +57,11 @@ _SIGS = {
     "cswdg_troubled_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "cswdg_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
     "cswdg_troubled_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.c_int]),
+    "cswdg_dg_residual_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
+    "cswdg_csweno_limit_vjp": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "cswdg_tape_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "cswdg_ssprk3_step_tape": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int]),
+    "cswdg_ssprk3_step_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
     "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
 }
@@ -233,6 +238,40 @@ class Solver:
     def ssprk3_step(self, u, dt=None):
         self._c(lib().cswdg_ssprk3_step(self.h, _ptr(u), _ptr(dt)))
         return u
+
+    # -- adjoint ------------------------------------------------------------
+    def dg_residual_vjp(self, u, r_bar, u_bar=None):
+        if u_bar is None:
+            u_bar = self.empty_state()
+        self._c(lib().cswdg_dg_residual_vjp(self.h, _ptr(u), _ptr(r_bar), _ptr(u_bar)))
+        return u_bar
+
+    def csweno_limit_vjp(self, w, y_bar, mask=None, w_bar=None):
+        if w_bar is None:
+            w_bar = self.empty_state()
+        m = None if mask is None else mask.to(device="cuda", dtype=self.torch.uint8).contiguous()
+        self._c(lib().cswdg_csweno_limit_vjp(self.h, _ptr(w), _ptr(m), _ptr(y_bar), _ptr(w_bar)))
+        return w_bar
+
+    def new_tape(self):
+        n = _I64()
+        self._c(lib().cswdg_tape_bytes(self.h, ctypes.byref(n)))
+        return self.torch.empty(n.value, dtype=self.torch.uint8, device="cuda")
+
+    def tape_dt(self, tape):
+        """dt stored in a tape (device tensor view)."""
+        n = tape.numel()
+        return tape[n - 256:n - 248].view(self.torch.float64)
+
+    def ssprk3_step_tape(self, u, tape, dt=None, replay=False):
+        self._c(lib().cswdg_ssprk3_step_tape(self.h, _ptr(u), _ptr(dt), _ptr(tape), 1 if replay else 0))
+        return u
+
+    def ssprk3_step_vjp(self, tape, y_bar, u_bar=None):
+        if u_bar is None:
+            u_bar = self.empty_state()
+        self._c(lib().cswdg_ssprk3_step_vjp(self.h, _ptr(tape), _ptr(y_bar), _ptr(u_bar)))
+        return u_bar
 
     def last_dt_ptr(self):
         p = ctypes.c_void_p()

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libcswdg.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "host_tables.cpp", "host_mesh.cpp", "host_ops.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "api.cpp", "host_tables.cpp", "host_mesh.cpp", "host_ops.cpp"]
 
 # Packed-FP32 instructions are disabled for device code; -O3 would otherwise
 # form them from plain float code.

@@ -16,8 +16,10 @@ namespace {
 
 thread_local std::string g_err;
 
-const char* kKernelNames[] = {"residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero", "project"};
-enum KernelId { KID_RESIDUAL = 0, KID_DT, KID_KXRCF, KID_COMPACT, KID_LIMITER, KID_SCATTER, KID_COPY, KID_ZERO, KID_PROJECT, KID_COUNT };
+const char* kKernelNames[] = {"residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero", "project",
+                              "residual_vjp", "limiter_vjp"};
+enum KernelId { KID_RESIDUAL = 0, KID_DT, KID_KXRCF, KID_COMPACT, KID_LIMITER, KID_SCATTER, KID_COPY, KID_ZERO, KID_PROJECT,
+                KID_RESIDUAL_VJP, KID_LIMITER_VJP, KID_COUNT };
 
 std::mutex g_dev_mutex;
 std::vector<int> g_dev_tables;  // devices whose constant tables are uploaded
@@ -50,6 +52,10 @@ struct cswdg_solver {
     double* d_dt = nullptr;
     void* d_T1 = nullptr;
     void* d_T2 = nullptr;
+    // adjoint scratch (allocated by the first adjoint call)
+    int32_t* d_slot = nullptr;
+    double* d_contrib = nullptr;
+    void* d_V = nullptr;
     int dt_blocks = 1024;
     int64_t n_rank = 0, n_foot = 0;
     // profiling
@@ -73,7 +79,8 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
-                    s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2};
+                    s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2,
+                    s->d_slot, s->d_contrib, s->d_V};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -86,6 +93,9 @@ void free_mesh(cswdg_solver* s) {
     s->d_tstats = nullptr;
     s->d_compact = s->d_partial = s->d_dt = nullptr;
     s->d_T1 = s->d_T2 = nullptr;
+    s->d_slot = nullptr;
+    s->d_contrib = nullptr;
+    s->d_V = nullptr;
     s->has_mesh = false;
 }
 
@@ -141,6 +151,55 @@ int rk_stage_impl(cswdg_solver* s, int stage, const void* u_n, const void* u_pre
     });
     if (e != hipSuccess) return hipfail(s, e, "residual");
     return limit_into(s, out, out, nullptr, nullptr, s->p.limiter_mode, true);
+}
+
+struct TapeView {
+    double* st[6];  // u0, w1, u1, w2, u2, w3
+    uint8_t* mask[3];
+    double* dt;
+};
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t tape_bytes(const cswdg_solver* s) {
+    const size_t sb = round256(sizeof(double) * s->state_elems);
+    const size_t mb = round256((size_t)s->mesh.K);
+    return 6 * sb + 3 * mb + 256;
+}
+
+TapeView tape_view(const cswdg_solver* s, void* tape) {
+    TapeView v;
+    char* p = (char*)tape;
+    const size_t sb = round256(sizeof(double) * s->state_elems);
+    const size_t mb = round256((size_t)s->mesh.K);
+    for (int i = 0; i < 6; ++i) v.st[i] = (double*)(p + i * sb);
+    for (int i = 0; i < 3; ++i) v.mask[i] = (uint8_t*)(p + 6 * sb + i * mb);
+    v.dt = (double*)(p + 6 * sb + 3 * mb);
+    return v;
+}
+
+int ensure_adjoint_scratch(cswdg_solver* s) {
+    if (s->d_slot) return CSWDG_OK;
+    const size_t K = (size_t)s->mesh.K;
+    if (hipMalloc((void**)&s->d_slot, sizeof(int32_t) * K) != hipSuccess ||
+        hipMalloc((void**)&s->d_contrib, sizeof(double) * 4 * s->state_elems) != hipSuccess ||
+        hipMalloc(&s->d_V, sizeof(double) * s->state_elems) != hipSuccess)
+        return fail(s, CSWDG_ENOMEM, "adjoint scratch allocation failed");
+    return CSWDG_OK;
+}
+
+// wbar = Lambda'(w)^T ybar with the troubled set given by mask
+int limiter_vjp_impl(cswdg_solver* s, const void* w, const uint8_t* mask, const void* ybar, void* wbar) {
+    const int K = (int)s->mesh.K;
+    hipError_t e = launch_zero_u32(s->ctx, s->d_count, 1);
+    if (e == hipSuccess) e = launch_compact_slots(s->ctx, K, mask, s->d_list, s->d_slot, s->d_count);
+    if (e == hipSuccess)
+        e = timed(s, KID_LIMITER_VJP, [&] {
+            return launch_limiter_vjp(s->ctx, s->dm, w, s->d_ops, s->d_list, s->d_count, ybar, s->d_contrib, K);
+        });
+    if (e == hipSuccess)
+        e = launch_limiter_gather(s->ctx, s->dm, mask, s->d_slot, s->d_contrib, ybar, wbar);
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "limiter vjp");
 }
 
 }  // namespace
@@ -291,6 +350,10 @@ int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt
     s->dm.vy = s->d_vy;
     s->dm.nbr = s->d_nbr;
     s->dm.info = s->d_info;
+    {
+        const char* xt = std::getenv("CSWDG_XCD_TILES");
+        s->dm.xcd_tiles = xt ? std::atoi(xt) : 1;
+    }
     s->has_mesh = true;
     return CSWDG_OK;
 }
@@ -463,6 +526,112 @@ int cswdg_status(cswdg_solver* s, uint32_t* flags) {
     if (s->n_foot > 0) v |= CSWDG_STATUS_FOOT;
     *flags = v;
     return CSWDG_OK;
+}
+
+int cswdg_dg_residual_vjp(cswdg_solver* s, const void* u, const void* r_bar, void* u_bar) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u || !r_bar || !u_bar || u_bar == r_bar) return fail(s, CSWDG_EINVAL, "bad pointers");
+    hipError_t e = timed(s, KID_RESIDUAL_VJP, [&] {
+        return launch_residual_vjp(s->ctx, s->dm, u, r_bar, u_bar, nullptr, nullptr, 0.0, 0.0, 1.0, 0);
+    });
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "residual vjp");
+}
+
+int cswdg_csweno_limit_vjp(cswdg_solver* s, const void* w, const uint8_t* mask, const void* y_bar, void* w_bar) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!w || !y_bar || !w_bar || w_bar == y_bar) return fail(s, CSWDG_EINVAL, "bad pointers");
+    rc = ensure_adjoint_scratch(s);
+    if (rc) return rc;
+    const uint8_t* m = mask;
+    if (!m) {
+        hipError_t e = launch_zero_u32(s->ctx, s->d_count, 1);
+        if (e == hipSuccess) e = launch_kxrcf(s->ctx, s->dm, w, s->d_flags, nullptr, s->d_list, s->d_count);
+        if (e != hipSuccess) return hipfail(s, e, "kxrcf");
+        m = s->d_flags;
+    }
+    return limiter_vjp_impl(s, w, m, y_bar, w_bar);
+}
+
+int cswdg_tape_bytes(cswdg_solver* s, int64_t* bytes) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!bytes) return fail(s, CSWDG_EINVAL, "null pointer");
+    *bytes = (int64_t)tape_bytes(s);
+    return CSWDG_OK;
+}
+
+int cswdg_ssprk3_step_tape(cswdg_solver* s, void* u, const double* dt_dev, void* tape, int replay) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u || !tape) return fail(s, CSWDG_EINVAL, "null pointer");
+    TapeView t = tape_view(s, tape);
+    const size_t bytes = sizeof(double) * s->state_elems;
+    const int K = (int)s->mesh.K;
+    hipError_t e = hipMemcpyAsync(t.st[0], u, bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hipfail(s, e, "tape copy");
+    if (!replay) {
+        if (dt_dev) {
+            e = hipMemcpyAsync(t.dt, dt_dev, sizeof(double), hipMemcpyDeviceToDevice, s->stream);
+            if (e != hipSuccess) return hipfail(s, e, "dt copy");
+        } else {
+            rc = cswdg_max_dt(s, u, t.dt);
+            if (rc) return rc;
+        }
+    }
+    const double* st_in[3] = {t.st[0], t.st[2], t.st[4]};
+    double* st_w[3] = {t.st[1], t.st[3], t.st[5]};
+    void* st_out[3] = {t.st[2], t.st[4], u};
+    for (int i = 0; i < 3; ++i) {
+        e = timed(s, KID_RESIDUAL, [&] {
+            return launch_residual_reset(s->ctx, s->dm, i + 1, st_in[i], t.st[0], st_w[i], t.dt, s->d_count);
+        });
+        if (e == hipSuccess) e = hipMemcpyAsync(st_out[i], st_w[i], bytes, hipMemcpyDeviceToDevice, s->stream);
+        if (e != hipSuccess) return hipfail(s, e, "tape stage");
+        if (s->p.limiter_mode == CSWDG_LIMIT_NONE) {
+            e = launch_zero_u32(s->ctx, (uint32_t*)t.mask[i], (int)(round256((size_t)K) / 4));
+            if (e != hipSuccess) return hipfail(s, e, "mask");
+            continue;
+        }
+        if (replay) rc = limit_into(s, st_w[i], st_out[i], nullptr, t.mask[i], CSWDG_LIMIT_KXRCF, true);
+        else rc = limit_into(s, st_w[i], st_out[i], t.mask[i], nullptr, s->p.limiter_mode, true);
+        if (rc) return rc;
+    }
+    return CSWDG_OK;
+}
+
+int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_bar, void* u_n_bar) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!tape || !u_next_bar || !u_n_bar || u_n_bar == u_next_bar) return fail(s, CSWDG_EINVAL, "bad pointers");
+    rc = ensure_adjoint_scratch(s);
+    if (rc) return rc;
+    TapeView t = tape_view(s, const_cast<void*>(tape));
+    const int nwords = (int)(2 * s->state_elems);  // doubles as pairs of 32-bit words
+    hipError_t e = launch_zero_u32(s->ctx, (uint32_t*)u_n_bar, nwords);
+    if (e != hipSuccess) return hipfail(s, e, "zero");
+    // stage 3: u^{n+1} = Lambda(1/3 u0 + 2/3 (u2 + dt L(u2)))
+    rc = limiter_vjp_impl(s, t.st[5], t.mask[2], u_next_bar, s->d_V);
+    if (rc) return rc;
+    e = timed(s, KID_RESIDUAL_VJP, [&] {
+        return launch_residual_vjp(s->ctx, s->dm, t.st[4], s->d_V, s->d_T2, u_n_bar, t.dt, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 0);
+    });
+    if (e != hipSuccess) return hipfail(s, e, "residual vjp");
+    // stage 2: u2 = Lambda(3/4 u0 + 1/4 (u1 + dt L(u1)))
+    rc = limiter_vjp_impl(s, t.st[3], t.mask[1], s->d_T2, s->d_V);
+    if (rc) return rc;
+    e = timed(s, KID_RESIDUAL_VJP, [&] {
+        return launch_residual_vjp(s->ctx, s->dm, t.st[2], s->d_V, s->d_T2, u_n_bar, t.dt, 0.75, 0.25, 0.25, 0);
+    });
+    if (e != hipSuccess) return hipfail(s, e, "residual vjp");
+    // stage 1: u1 = Lambda(u0 + dt L(u0))
+    rc = limiter_vjp_impl(s, t.st[1], t.mask[0], s->d_T2, s->d_V);
+    if (rc) return rc;
+    e = timed(s, KID_RESIDUAL_VJP, [&] {
+        return launch_residual_vjp(s->ctx, s->dm, t.st[0], s->d_V, u_n_bar, nullptr, t.dt, 0.0, 1.0, 1.0, 1);
+    });
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "residual vjp");
 }
 
 int cswdg_profile(cswdg_solver* s, int enable) {

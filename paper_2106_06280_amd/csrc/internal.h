@@ -68,6 +68,7 @@ struct DevMesh {
     const double* vy;      // [3][K]
     const int32_t* nbr;    // [3][K]
     const uint32_t* info;  // [K], face f in byte f
+    int xcd_tiles;         // 1: give each XCD a contiguous range of blocks
 };
 
 struct LaunchCtx {
@@ -77,7 +78,8 @@ struct LaunchCtx {
     int residual_variant;  // residual schedule: 0 lean (default), 1 wide, 2 stream
 };
 
-int upload_tables_device();  // once per device
+int upload_tables_device();   // once per device (both translation units)
+int upload_tables_adjoint();  // the adjoint unit's copy of the tables
 
 // residual (mode 0) or RK stage 1..3; dt read from device; reset (may be
 // null) is a counter set to zero by the kernel
@@ -106,5 +108,17 @@ hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* lis
 hipError_t launch_ic_points(const LaunchCtx& c, const DevMesh& m, double* xy);
 hipError_t launch_project(const LaunchCtx& c, const DevMesh& m, const double* vals, void* u);
 int ic_points_per_element(int N);
+
+// adjoint (adjoint.hip)
+hipError_t launch_residual_vjp(const LaunchCtx& c, const DevMesh& m, const void* u, const void* ybar,
+                               void* prev_bar, void* un_bar, const double* dt, double a, double c_id,
+                               double c_dt, int accumulate);
+hipError_t launch_compact_slots(const LaunchCtx& c, int K, const uint8_t* mask, int32_t* list, int32_t* slot,
+                                uint32_t* count);
+hipError_t launch_limiter_vjp(const LaunchCtx& c, const DevMesh& m, const void* w, const double* ops,
+                              const int32_t* list, const uint32_t* count, const void* ybar, double* contrib,
+                              int max_cells);
+hipError_t launch_limiter_gather(const LaunchCtx& c, const DevMesh& m, const uint8_t* mask, const int32_t* slot,
+                                 const double* contrib, const void* ybar, void* wbar);
 
 }  // namespace cswdg

@@ -24,101 +24,11 @@
 
 #include <cstdio>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace cswdg {
 
 namespace {
-
-template <int N>
-struct TabIC {
-    double r[Dims<N>::NQI], s[Dims<N>::NQI];
-    double wV[Dims<N>::NQI][Dims<N>::NP];
-};
-
-__constant__ Tab<1> c_tab1;
-__constant__ Tab<2> c_tab2;
-__constant__ Tab<3> c_tab3;
-__constant__ TabIC<1> c_ic1;
-__constant__ TabIC<2> c_ic2;
-__constant__ TabIC<3> c_ic3;
-
-template <int N>
-__device__ __forceinline__ const Tab<N>& tab();
-template <>
-__device__ __forceinline__ const Tab<1>& tab<1>() { return c_tab1; }
-template <>
-__device__ __forceinline__ const Tab<2>& tab<2>() { return c_tab2; }
-template <>
-__device__ __forceinline__ const Tab<3>& tab<3>() { return c_tab3; }
-template <int N>
-__device__ __forceinline__ const TabIC<N>& tabic();
-template <>
-__device__ __forceinline__ const TabIC<1>& tabic<1>() { return c_ic1; }
-template <>
-__device__ __forceinline__ const TabIC<2>& tabic<2>() { return c_ic2; }
-template <>
-__device__ __forceinline__ const TabIC<3>& tabic<3>() { return c_ic3; }
-
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
-// contiguous range of element tiles so that neighbour gathers stay in its L2.
-__device__ __forceinline__ int xcd_block(int b, int G) {
-    int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
-    return x * q + (x < r ? x : r) + k;
-}
-
-// ---------------------------------------------------------------------------
-// Physics: fluxes and wave speeds (Section 4 eqs. 2dBurgers, 2dEulerEquations)
-// ---------------------------------------------------------------------------
-template <int EQ>
-struct Phys;
-
-template <>
-struct Phys<0> {
-    static constexpr int M = 1;
-    __device__ static __forceinline__ void normal_flux(const double* u, double nx, double ny, double,
-                                                       double* Fn, double& lam) {
-        double h = 0.5 * u[0] * u[0];
-        Fn[0] = h * nx + h * ny;
-        lam = fabs(u[0] * (nx + ny));
-    }
-    __device__ static __forceinline__ void flux(const double* u, double, double* F, double* G) {
-        F[0] = 0.5 * u[0] * u[0];
-        G[0] = F[0];
-    }
-};
-
-template <>
-struct Phys<1> {
-    static constexpr int M = 4;
-    __device__ static __forceinline__ void flux(const double* U, double g, double* F, double* G) {
-        double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double ir = 1.0 / rho;
-        double u = mu * ir, v = mv * ir;
-        double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
-        F[0] = mu;
-        F[1] = mu * u + p;
-        F[2] = mv * u;
-        F[3] = (E + p) * u;
-        G[0] = mv;
-        G[1] = mu * v;
-        G[2] = mv * v + p;
-        G[3] = (E + p) * v;
-    }
-    __device__ static __forceinline__ void normal_flux(const double* U, double nx, double ny, double g,
-                                                       double* Fn, double& lam) {
-        double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double ir = 1.0 / rho;
-        double u = mu * ir, v = mv * ir;
-        double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
-        double un = u * nx + v * ny;
-        Fn[0] = mu * nx + mv * ny;
-        Fn[1] = (mu * u + p) * nx + (mu * v) * ny;
-        Fn[2] = (mv * u) * nx + (mv * v + p) * ny;
-        Fn[3] = ((E + p) * u) * nx + ((E + p) * v) * ny;
-        lam = fabs(un) + sqrt(g * p * ir);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Residual and RK stage
@@ -132,7 +42,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
     using D = Dims<N>;
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
-    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
     if (e >= K) return;
     const Tab<N>& T = tab<N>();
@@ -273,7 +183,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
     using D = Dims<N>;
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
-    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
     if (e >= K) return;
     const Tab<N>& T = tab<N>();
@@ -413,7 +323,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
     using D = Dims<N>;
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
-    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
     if (e >= K) return;
     const Tab<N>& T = tab<N>();
@@ -630,7 +540,7 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const double* __rest
     using D = Dims<N>;
     constexpr int NP = D::NP, NE = D::NE;
     const int K = msh.K;
-    const int e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     bool tr = false;
     if (e < K) {
         const Tab<N>& T = tab<N>();
@@ -727,56 +637,6 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // ---------------------------------------------------------------------------
 // CSWENO limiter (Section 3.2)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void euler_eigen(const double* U, double nx, double ny, double g,
-                                            double L[4][4], double R[4][4]) {
-    const double rho = U[0], u = U[1] / rho, v = U[2] / rho, E = U[3];
-    const double q2 = u * u + v * v;
-    const double p = (g - 1.0) * (E - 0.5 * rho * q2);
-    const double c = sqrt(g * p / rho);
-    const double H = (E + p) / rho;
-    const double un = u * nx + v * ny;
-    // right eigenvectors (columns): u_n - c, u_n (entropy), u_n (shear), u_n + c
-    R[0][0] = 1.0;            R[0][1] = 1.0;      R[0][2] = 0.0;              R[0][3] = 1.0;
-    R[1][0] = u - c * nx;     R[1][1] = u;        R[1][2] = -ny;              R[1][3] = u + c * nx;
-    R[2][0] = v - c * ny;     R[2][1] = v;        R[2][2] = nx;               R[2][3] = v + c * ny;
-    R[3][0] = H - c * un;     R[3][1] = 0.5 * q2; R[3][2] = -ny * u + nx * v; R[3][3] = H + c * un;
-    // closed-form inverse
-    const double b1 = (g - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
-    L[0][0] = 0.5 * (b2 + un / c); L[0][1] = 0.5 * (-b1 * u - nx / c); L[0][2] = 0.5 * (-b1 * v - ny / c); L[0][3] = 0.5 * b1;
-    L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;                   L[1][2] = b1 * v;                   L[1][3] = -b1;
-    L[2][0] = ny * u - nx * v;     L[2][1] = -ny;                      L[2][2] = nx;                       L[2][3] = 0.0;
-    L[3][0] = 0.5 * (b2 - un / c); L[3][1] = 0.5 * (-b1 * u + nx / c); L[3][2] = 0.5 * (-b1 * v + ny / c); L[3][3] = 0.5 * b1;
-}
-
-// c^T B c over the leading k x k block of the packed upper triangle of an
-// nm x nm matrix
-template <int NM, int KK>
-__device__ __forceinline__ double quad_form(const double* __restrict__ bp, const double* c) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < KK; ++i) {
-        const int row = i * NM - (i * (i - 1)) / 2;
-        double t = bp[row] * c[i];
-#pragma unroll
-        for (int j = i + 1; j < KK; ++j) t += 2.0 * bp[row + (j - i)] * c[j];
-        s += c[i] * t;
-    }
-    return s;
-}
-
-// One troubled cell is handled by LPC = (number of characteristic
-// directions) x (number of fields) lanes: lane (d, k) reconstructs
-// characteristic field k of direction d (Euler: 2 x 4 = 8 lanes; Burgers: 1).
-// The lanes of a cell read the same operator record and neighbour
-// coefficients (one cache line serves all of them) and combine their
-// moments with a butterfly over the cell's lanes.
-template <int EQ>
-struct LimLanes {
-    static constexpr int ND = (EQ == 1) ? 2 : 1;
-    static constexpr int M = Phys<EQ>::M;
-    static constexpr int LPC = ND * M;
-};
-
 template <int EQ, int N>
 __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __restrict__ u,
                                                 const double* __restrict__ ops,
@@ -1071,20 +931,6 @@ __global__ __launch_bounds__(256) void k_project(int K, int m, const double* __r
     }
 }
 
-template <int N>
-void fill_ic(TabIC<N>& t) {
-    Rule2D r = triangle_rule(Dims<N>::NI1);
-    double psi[Dims<N>::NP];
-    for (int q = 0; q < Dims<N>::NQI; ++q) {
-        t.r[q] = r.r[q];
-        t.s[q] = r.s[q];
-        basis_eval(N, r.r[q], r.s[q], psi);
-        for (int n = 0; n < Dims<N>::NP; ++n) t.wV[q][n] = r.w[q] * psi[n];
-    }
-}
-
-inline unsigned grid_for(int K, int bs) { return (unsigned)((K + bs - 1) / bs); }
-
 }  // namespace
 
 int ic_points_per_element(int N) {
@@ -1092,41 +938,11 @@ int ic_points_per_element(int N) {
 }
 
 int upload_tables_device() {
-    static Tab<1> t1;
-    static Tab<2> t2;
-    static Tab<3> t3;
-    static TabIC<1> i1;
-    static TabIC<2> i2;
-    static TabIC<3> i3;
-    static bool filled = false;
-    if (!filled) {
-        fill_tables<1>(t1);
-        fill_tables<2>(t2);
-        fill_tables<3>(t3);
-        fill_ic<1>(i1);
-        fill_ic<2>(i2);
-        fill_ic<3>(i3);
-        filled = true;
-    }
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab1), &t1, sizeof(t1)) != hipSuccess) return CSWDG_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab2), &t2, sizeof(t2)) != hipSuccess) return CSWDG_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab3), &t3, sizeof(t3)) != hipSuccess) return CSWDG_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic1), &i1, sizeof(i1)) != hipSuccess) return CSWDG_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic2), &i2, sizeof(i2)) != hipSuccess) return CSWDG_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic3), &i3, sizeof(i3)) != hipSuccess) return CSWDG_EHIP;
-    return CSWDG_OK;
+    int rc = upload_tables_here();
+    if (rc != CSWDG_OK) return rc;
+    return upload_tables_adjoint();
 }
 
-#define CSWDG_DISPATCH_EN(EQV, NV, ...)                         \
-    do {                                                        \
-        if ((EQV) == 0 && (NV) == 1) { constexpr int EQ = 0, N = 1; __VA_ARGS__; } \
-        else if ((EQV) == 0 && (NV) == 2) { constexpr int EQ = 0, N = 2; __VA_ARGS__; } \
-        else if ((EQV) == 0 && (NV) == 3) { constexpr int EQ = 0, N = 3; __VA_ARGS__; } \
-        else if ((EQV) == 1 && (NV) == 1) { constexpr int EQ = 1, N = 1; __VA_ARGS__; } \
-        else if ((EQV) == 1 && (NV) == 2) { constexpr int EQ = 1, N = 2; __VA_ARGS__; } \
-        else if ((EQV) == 1 && (NV) == 3) { constexpr int EQ = 1, N = 3; __VA_ARGS__; } \
-        else return hipErrorInvalidValue;                       \
-    } while (0)
 
 hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode, const void* u,
                                  const void* un, void* out, const double* dt, uint32_t* reset) {
