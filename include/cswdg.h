@@ -21,8 +21,8 @@
  *
  * State layout (device memory, caller-owned): [m][Np][K] contiguous, element
  * index fastest; m = 1 (Burgers) or 4 (Euler: rho, rho u, rho v, E);
- * Np = (N+1)(N+2)/2; element type double (precision 0) or float
- * (precision 1, "FP32-bulk": state in float, limiter arithmetic in double).
+ * Np = (N+1)(N+2)/2; element type double (precision 0, the only one
+ * implemented: cswdg_create rejects any other value with CSWDG_EINVAL).
  *
  * Streams: every call that takes device pointers is enqueued on the
  * solver's HIP stream (given at creation; NULL = default stream) and
@@ -72,6 +72,7 @@ extern "C" {
 #define CSWDG_STATUS_FOOT 0x8u      /* a perpendicular foot fell outside its side (midpoint used) */
 
 typedef struct cswdg_solver cswdg_solver;
+typedef struct cswdg_graph cswdg_graph;
 
 /* Parameters.  Zero-initialise and set what you need; a zero/negative value
  * selects the default shown. */
@@ -102,6 +103,26 @@ const char* cswdg_last_error(const cswdg_solver* s);
  * stencil operators of the limiter on the device.  Synchronous. */
 int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt,
                       const int32_t* tri, int bc, double period_x, double period_y);
+
+/* Upload n_inst independent triangulations (instances) as one mesh, the
+ * disjoint union of the instances: vertex and triangle arrays of the
+ * instances are concatenated (vxy [sum nv][2], tri [sum nt][3]; the vertex
+ * ids in tri are local to their instance), nv[i], nt[i] and bc[i] give
+ * instance i's sizes and boundary condition (host arrays of n_inst).  Each
+ * instance keeps its own connectivity, element ids are numbered instance
+ * after instance, and every periodic instance uses period_x/period_y.  Each
+ * instance advances with its own time step (dt arrays of the calls below
+ * hold one value per instance); every other call treats the union as one
+ * mesh, so one launch serves all instances.  Not for the adjoint calls,
+ * which take single-instance meshes.  Same validation as cswdg_mesh_upload
+ * per instance.  Synchronous. */
+int cswdg_mesh_upload_batch(cswdg_solver* s, int32_t n_inst, const int64_t* nv, const double* vxy,
+                            const int64_t* nt, const int32_t* tri, const int32_t* bc, double period_x,
+                            double period_y);
+/* Number of instances and (when offsets != NULL, host [n_inst + 1]) the
+ * first element of each instance, offsets[n_inst] = K.  A mesh from
+ * cswdg_mesh_upload is one instance. */
+int cswdg_instances(const cswdg_solver* s, int32_t* n_inst, int64_t* offsets);
 
 /* Number of elements, number of triangles re-oriented by the CCW fix. */
 int cswdg_mesh_info(const cswdg_solver* s, int64_t* n_elements, int64_t* n_flipped);
@@ -143,7 +164,9 @@ int cswdg_dg_residual(cswdg_solver* s, const void* u, void* r);
 
 /* *dt_dev (device double) = CFL * min_e(2 r_e) / max_e a(ubar_e) with r_e the
  * inradius and a the cell-mean wave speed (Burgers sqrt(2)|u|, Euler
- * |v| + c). */
+ * |v| + c) (the time step of Section 4's examples).  For a mesh of several
+ * instances dt_dev is a device array with one dt per instance, the min and
+ * max taken over that instance's elements. */
 int cswdg_max_dt(cswdg_solver* s, const void* u, double* dt_dev);
 
 /* KXRCF indicator (Section 3.1, eq. troubledCellIndicator): flags [K]
@@ -162,8 +185,9 @@ int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* 
 /* One stage of the table:tvd third-order RK (end of Section 3) followed by
  * the limiter: out = a u_n + b (u_prev + dt L(u_prev)) with
  * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 1, 2, 3, then limited
- * in place according to params.limiter_mode.  dt_dev: device double.  out
- * must not alias u_prev; out may alias u_n (stage 3 of an in-place step). */
+ * in place according to params.limiter_mode.  dt_dev: device double (one per
+ * instance).  out must not alias u_prev; out may alias u_n (stage 3 of an
+ * in-place step). */
 int cswdg_rk_stage(cswdg_solver* s, int stage, const void* u_n, const void* u_prev, void* out,
                    const double* dt_dev);
 
@@ -200,6 +224,40 @@ int cswdg_ssprk3_step_tape(cswdg_solver* s, void* u, const double* dt_dev, void*
 /* u_n_bar = (d u^{n+1} / d u^n)^T u_next_bar for the step recorded in tape,
  * with its dt and masks frozen.  u_n_bar must not alias u_next_bar. */
 int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_bar, void* u_n_bar);
+
+/* ---- Schedules, autotuning and graphs (launch configuration only; not part
+ * of the paper) ------------------------------------------------------------
+ * A schedule is int32 [3]: the residual kernel's variant (0 "lean": one
+ * face's neighbour data live at a time, 1 "wide": all three faces live,
+ * 2 "stream": own coefficients re-read per face), its threads per block
+ * (64, 128 or 256) and the XCD-contiguous block order (0 off, 1 on).  All
+ * schedules compute the same quantities; variants may differ in the last
+ * bits (summation order), block size and block order do not change results. */
+int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched);
+int cswdg_get_schedule(const cswdg_solver* s, int32_t* sched);
+/* Time every schedule on the residual of the state u (device, reps timed
+ * launches each after one untimed launch), keep the fastest and return it
+ * in sched (may be NULL); times_us (host, may be NULL, 18 entries) receives
+ * the mean microseconds per launch in the order variant-major, then block,
+ * then XCD order; *n_cand (may be NULL) the number of schedules timed.
+ * Synchronous. */
+int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched, double* times_us,
+                   int32_t* n_cand);
+/* Record nsteps SSP-RK3 steps (cswdg_ssprk3_step with dt computed per step)
+ * of each of n solvers on its state states[i] (device, state layout, fixed
+ * for the life of the graph), in the order step-major then solver, into one
+ * HIP graph.  Capture runs on a private stream after waiting for the
+ * solvers' streams; nothing is computed.  The schedule and limiter mode in
+ * force at capture are used by every launch. */
+int cswdg_graph_capture(int32_t n, cswdg_solver* const* solvers, void* const* states, int32_t nsteps,
+                        cswdg_graph** out);
+/* Enqueue the recorded steps on hip_stream (NULL = default stream): each
+ * launch advances every state by nsteps steps in place.  The solvers'
+ * scratch is shared with their eager calls: do not overlap the two. */
+int cswdg_graph_launch(cswdg_graph* g, void* hip_stream);
+/* Number of nodes (kernel launches) in the graph. */
+int cswdg_graph_nodes(const cswdg_graph* g, int64_t* nodes);
+int cswdg_graph_destroy(cswdg_graph* g);
 
 /* Troubled-cell count of the last limiter call (host int, synchronous). */
 int cswdg_troubled_count(cswdg_solver* s, int64_t* count);

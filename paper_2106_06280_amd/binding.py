@@ -64,6 +64,15 @@ _SIGS = {
     "cswdg_ssprk3_step_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
     "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "cswdg_mesh_upload_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
+    "cswdg_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+    "cswdg_set_schedule": (ctypes.c_int, [_P, _P]),
+    "cswdg_get_schedule": (ctypes.c_int, [_P, _P]),
+    "cswdg_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "cswdg_graph_capture": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "cswdg_graph_launch": (ctypes.c_int, [_P, _P]),
+    "cswdg_graph_nodes": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "cswdg_graph_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -147,6 +156,28 @@ class Solver:
                                         bc, float(period[0]), float(period[1])))
         self.K = tri.shape[0]
 
+    def mesh_upload_batch(self, meshes, bcs, period=(1.0, 1.0)):
+        """meshes: list of (vxy [nv][2], tri [nt][3]) with instance-local vertex
+        ids; bcs: one boundary condition per instance."""
+        nv = np.array([m[0].shape[0] for m in meshes], np.int64)
+        nt = np.array([m[1].shape[0] for m in meshes], np.int64)
+        vxy = np.ascontiguousarray(np.concatenate([np.asarray(m[0], np.float64) for m in meshes]))
+        tri = np.ascontiguousarray(np.concatenate([np.asarray(m[1], np.int32) for m in meshes]))
+        bc = np.ascontiguousarray(np.asarray(bcs, np.int32))
+        if bc.shape != (len(meshes),):
+            raise ValueError("one boundary condition per instance")
+        self._c(lib().cswdg_mesh_upload_batch(self.h, len(meshes), nv.ctypes.data, vxy.ctypes.data, nt.ctypes.data,
+                                              tri.ctypes.data, bc.ctypes.data, float(period[0]), float(period[1])))
+        self.K = int(nt.sum())
+
+    def instances(self):
+        """Instance offsets (numpy int64 [n_inst + 1])."""
+        n = ctypes.c_int32()
+        self._c(lib().cswdg_instances(self.h, ctypes.byref(n), None))
+        off = np.zeros(n.value + 1, np.int64)
+        self._c(lib().cswdg_instances(self.h, ctypes.byref(n), off.ctypes.data))
+        return off
+
     def mesh_info(self):
         k, f = _I64(), _I64()
         self._c(lib().cswdg_mesh_info(self.h, ctypes.byref(k), ctypes.byref(f)))
@@ -211,7 +242,7 @@ class Solver:
 
     def max_dt(self, u, dt=None):
         if dt is None:
-            dt = self.torch.zeros(1, dtype=self.torch.float64, device="cuda")
+            dt = self.torch.zeros(len(self.instances()) - 1, dtype=self.torch.float64, device="cuda")
         self._c(lib().cswdg_max_dt(self.h, _ptr(u), _ptr(dt)))
         return dt
 
@@ -293,6 +324,26 @@ class Solver:
         self._c(lib().cswdg_status(self.h, ctypes.byref(v)))
         return v.value
 
+    # -- schedules and autotuning --------------------------------------------
+    def set_schedule(self, variant, block, xcd):
+        a = np.array([variant, block, xcd], np.int32)
+        self._c(lib().cswdg_set_schedule(self.h, a.ctypes.data))
+
+    def get_schedule(self):
+        a = np.zeros(3, np.int32)
+        self._c(lib().cswdg_get_schedule(self.h, a.ctypes.data))
+        return tuple(int(x) for x in a)
+
+    def autotune(self, u, reps=5):
+        """Time every residual schedule on u; keep the fastest.  Returns
+        (schedule, {schedule: microseconds})."""
+        a = np.zeros(3, np.int32)
+        t = np.zeros(18, np.float64)
+        n = ctypes.c_int32()
+        self._c(lib().cswdg_autotune(self.h, _ptr(u), int(reps), a.ctypes.data, t.ctypes.data, ctypes.byref(n)))
+        cands = [(v, b, x) for v in (0, 1, 2) for b in (64, 128, 256) for x in (0, 1)]
+        return tuple(int(x) for x in a), {c: float(t[i]) for i, c in enumerate(cands[: n.value])}
+
     def profile(self, enable=True):
         self._c(lib().cswdg_profile(self.h, 1 if enable else 0))
 
@@ -304,3 +355,42 @@ class Solver:
         n = ctypes.c_int()
         self._c(lib().cswdg_kernel_times(self.h, names, tot, cnt, cap, ctypes.byref(n)))
         return {names[i].decode(): (tot[i], cnt[i]) for i in range(min(n.value, cap))}
+
+
+class Graph:
+    """nsteps SSP-RK3 steps of several solvers, each on its own state, recorded
+    into one HIP graph; launch() advances every state by nsteps steps."""
+
+    def __init__(self, solvers, states, nsteps):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)
+        self.states = list(states)  # kept alive: the graph holds their addresses
+        for s, u in zip(self.solvers, self.states):
+            if not u.is_contiguous() or tuple(u.shape) != (s.m, s.Np, s.K):
+                raise ValueError("state must be a contiguous [m, Np, K] tensor of its solver")
+        n = len(self.solvers)
+        hs = (ctypes.c_void_p * n)(*[s.h.value for s in self.solvers])
+        us = (ctypes.c_void_p * n)(*[u.data_ptr() for u in self.states])
+        g = ctypes.c_void_p()
+        _check(lib().cswdg_graph_capture(n, hs, us, int(nsteps), ctypes.byref(g)), None)
+        self.g = g
+        self.nsteps = nsteps
+
+    def launch(self, stream=None):
+        if stream is None:
+            stream = self.torch.cuda.current_stream()
+        _check(lib().cswdg_graph_launch(self.g, ctypes.c_void_p(stream.cuda_stream)), None)
+
+    def nodes(self):
+        n = _I64()
+        _check(lib().cswdg_graph_nodes(self.g, ctypes.byref(n)), None)
+        return n.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "g", None):
+                lib().cswdg_graph_destroy(self.g)
+                self.g = None
+        except Exception:
+            pass

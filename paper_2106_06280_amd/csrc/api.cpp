@@ -56,6 +56,13 @@ struct cswdg_solver {
     int32_t* d_slot = nullptr;
     double* d_contrib = nullptr;
     void* d_V = nullptr;
+    // instances (a mesh that is a disjoint union of independent meshes)
+    int n_inst = 1;
+    std::vector<int32_t> inst_off;
+    std::vector<double> inst_hmin;
+    int32_t* d_inst_off = nullptr;
+    double* d_inst_hmin = nullptr;
+    unsigned long long* d_amax = nullptr;
     int dt_blocks = 1024;
     int64_t n_rank = 0, n_foot = 0;
     // profiling
@@ -63,6 +70,12 @@ struct cswdg_solver {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> recs;  // kernel id, event index of the start
+};
+
+struct cswdg_graph {
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+    int64_t nodes = 0;
 };
 
 namespace {
@@ -80,7 +93,7 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
                     s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2,
-                    s->d_slot, s->d_contrib, s->d_V};
+                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -96,6 +109,12 @@ void free_mesh(cswdg_solver* s) {
     s->d_slot = nullptr;
     s->d_contrib = nullptr;
     s->d_V = nullptr;
+    s->d_inst_off = nullptr;
+    s->d_inst_hmin = nullptr;
+    s->d_amax = nullptr;
+    s->n_inst = 1;
+    s->inst_off.clear();
+    s->inst_hmin.clear();
     s->has_mesh = false;
 }
 
@@ -115,6 +134,12 @@ int check_ready(cswdg_solver* s) {
     if (!s) return fail(nullptr, CSWDG_EINVAL, "null solver");
     if (!s->has_mesh) return fail(s, CSWDG_ESTATE, "no mesh uploaded");
     if (hipSetDevice(s->device) != hipSuccess) return fail(s, CSWDG_EHIP, "hipSetDevice failed");
+    return CSWDG_OK;
+}
+
+// the adjoint's tape holds one dt: single-instance meshes only
+int check_single(cswdg_solver* s) {
+    if (s->n_inst != 1) return fail(s, CSWDG_EINVAL, "adjoint calls take a single-instance mesh");
     return CSWDG_OK;
 }
 
@@ -202,6 +227,8 @@ int limiter_vjp_impl(cswdg_solver* s, const void* w, const uint8_t* mask, const 
     return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "limiter vjp");
 }
 
+int upload_mesh(cswdg_solver* s);
+
 }  // namespace
 
 extern "C" {
@@ -247,6 +274,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     // schedule choice for the residual kernel (a tuning knob; same results)
     const char* rv = std::getenv("CSWDG_RESIDUAL_VARIANT");
     s->ctx.residual_variant = rv ? std::atoi(rv) : 0;
+    s->ctx.residual_block = 256;
     *out = s;
     return CSWDG_OK;
 }
@@ -285,76 +313,42 @@ int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt
     std::string msg;
     int rc = build_mesh(nv, vxy, nt, tri, bc, px, py, s->mesh, msg);
     if (rc != CSWDG_OK) return fail(s, rc, msg);
-    const int64_t K = s->mesh.K;
-    std::vector<double> ops;
-    rc = build_limiter_ops(s->mesh, s->p.degree, ops, s->n_rank, s->n_foot);
-    if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
-    std::vector<int32_t> nbrT(3 * K);
-    std::vector<uint32_t> info4(K);
-    for (int64_t e = 0; e < K; ++e) {
-        uint32_t w = 0;
-        for (int f = 0; f < 3; ++f) {
-            nbrT[f * K + e] = s->mesh.nbr[3 * e + f];
-            w |= (uint32_t)s->mesh.info[3 * e + f] << (8 * f);
-        }
-        info4[e] = w;
+    s->n_inst = 1;
+    s->inst_off = {0, (int32_t)s->mesh.K};
+    s->inst_hmin = {s->mesh.hmin};
+    return upload_mesh(s);
+}
+
+int cswdg_mesh_upload_batch(cswdg_solver* s, int32_t n_inst, const int64_t* nv, const double* vxy,
+                            const int64_t* nt, const int32_t* tri, const int32_t* bc, double px, double py) {
+    if (!s) return fail(nullptr, CSWDG_EINVAL, "null solver");
+    if (n_inst < 1 || !nv || !vxy || !nt || !tri || !bc) return fail(s, CSWDG_EINVAL, "bad batch arguments");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(s, CSWDG_EHIP, "hipSetDevice failed");
+    (void)hipStreamSynchronize(s->stream);
+    free_mesh(s);
+    std::vector<HostMesh> parts((size_t)n_inst);
+    std::string msg;
+    int64_t vo = 0, to = 0;
+    for (int32_t i = 0; i < n_inst; ++i) {
+        if (nv[i] < 3 || nt[i] < 1) return fail(s, CSWDG_EINVAL, "instance " + std::to_string(i) + ": empty mesh");
+        int rc = build_mesh(nv[i], vxy + 2 * vo, nt[i], tri + 3 * to, bc[i], px, py, parts[i], msg);
+        if (rc != CSWDG_OK) return fail(s, rc, "instance " + std::to_string(i) + ": " + msg);
+        vo += nv[i];
+        to += nt[i];
     }
-    const size_t NPM = (size_t)s->M * s->NP;
-    s->state_elems = NPM * K;
-    struct A {
-        void** p;
-        size_t bytes;
-    } allocs[] = {
-        {(void**)&s->d_vx, sizeof(double) * 3 * K},
-        {(void**)&s->d_vy, sizeof(double) * 3 * K},
-        {(void**)&s->d_nbr, sizeof(int32_t) * 3 * K},
-        {(void**)&s->d_info, sizeof(uint32_t) * K},
-        {(void**)&s->d_ops, sizeof(double) * ops.size()},
-        {(void**)&s->d_flags, (size_t)K},
-        {(void**)&s->d_list, sizeof(int32_t) * K},
-        {(void**)&s->d_count, sizeof(uint32_t) * 4},
-        {(void**)&s->d_status, sizeof(uint32_t) * 4},
-        {(void**)&s->d_tstats, sizeof(unsigned long long) * 2},
-        {(void**)&s->d_compact, sizeof(double) * NPM * K},
-        {(void**)&s->d_partial, sizeof(double) * s->dt_blocks},
-        {(void**)&s->d_dt, sizeof(double) * 2},
-        {(void**)&s->d_T1, sizeof(double) * NPM * K},
-        {(void**)&s->d_T2, sizeof(double) * NPM * K},
-    };
-    for (auto& a : allocs) {
-        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
-            free_mesh(s);
-            return fail(s, CSWDG_ENOMEM, "device allocation failed");
-        }
-    }
-    hipError_t e = hipSuccess;
-    auto cp = [&](void* d, const void* h, size_t b) {
-        if (e == hipSuccess) e = hipMemcpy(d, h, b, hipMemcpyHostToDevice);
-    };
-    cp(s->d_vx, s->mesh.vx.data(), sizeof(double) * 3 * K);
-    cp(s->d_vy, s->mesh.vy.data(), sizeof(double) * 3 * K);
-    cp(s->d_nbr, nbrT.data(), sizeof(int32_t) * 3 * K);
-    cp(s->d_info, info4.data(), sizeof(uint32_t) * K);
-    cp(s->d_ops, ops.data(), sizeof(double) * ops.size());
-    uint32_t zeros[4] = {0, 0, 0, 0};
-    cp(s->d_count, zeros, sizeof(zeros));
-    cp(s->d_status, zeros, sizeof(zeros));
-    unsigned long long zz[2] = {0, 0};
-    cp(s->d_tstats, zz, sizeof(zz));
-    if (e != hipSuccess) {
-        free_mesh(s);
-        return hipfail(s, e, "mesh upload");
-    }
-    s->dm.K = (int)K;
-    s->dm.vx = s->d_vx;
-    s->dm.vy = s->d_vy;
-    s->dm.nbr = s->d_nbr;
-    s->dm.info = s->d_info;
-    {
-        const char* xt = std::getenv("CSWDG_XCD_TILES");
-        s->dm.xcd_tiles = xt ? std::atoi(xt) : 1;
-    }
-    s->has_mesh = true;
+    int rc = concat_meshes(parts, s->mesh, s->inst_off, s->inst_hmin, msg);
+    if (rc != CSWDG_OK) return fail(s, rc, msg);
+    parts.clear();
+    s->n_inst = n_inst;
+    return upload_mesh(s);
+}
+
+int cswdg_instances(const cswdg_solver* s, int32_t* n_inst, int64_t* offsets) {
+    if (!s || !s->has_mesh) return fail(const_cast<cswdg_solver*>(s), CSWDG_ESTATE, "no mesh uploaded");
+    if (!n_inst) return fail(const_cast<cswdg_solver*>(s), CSWDG_EINVAL, "null pointer");
+    *n_inst = s->n_inst;
+    if (offsets)
+        for (int i = 0; i <= s->n_inst; ++i) offsets[i] = s->inst_off[i];
     return CSWDG_OK;
 }
 
@@ -425,6 +419,8 @@ int cswdg_max_dt(cswdg_solver* s, const void* u, double* dt_dev) {
     int nb = std::min(s->dt_blocks, (int)((s->mesh.K + 255) / 256));
     if (nb < 1) nb = 1;
     hipError_t e = timed(s, KID_DT, [&] {
+        if (s->n_inst > 1)
+            return launch_max_dt_inst(s->ctx, s->dm, u, s->d_inst_hmin, dt_dev, s->d_amax, s->d_status);
         return launch_max_dt(s->ctx, s->dm, u, s->mesh.hmin, dt_dev, s->d_partial, nullptr, s->d_status, nb);
     });
     return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "max_dt");
@@ -531,6 +527,8 @@ int cswdg_status(cswdg_solver* s, uint32_t* flags) {
 int cswdg_dg_residual_vjp(cswdg_solver* s, const void* u, const void* r_bar, void* u_bar) {
     int rc = check_ready(s);
     if (rc) return rc;
+    rc = check_single(s);
+    if (rc) return rc;
     if (!u || !r_bar || !u_bar || u_bar == r_bar) return fail(s, CSWDG_EINVAL, "bad pointers");
     hipError_t e = timed(s, KID_RESIDUAL_VJP, [&] {
         return launch_residual_vjp(s->ctx, s->dm, u, r_bar, u_bar, nullptr, nullptr, 0.0, 0.0, 1.0, 0);
@@ -540,6 +538,8 @@ int cswdg_dg_residual_vjp(cswdg_solver* s, const void* u, const void* r_bar, voi
 
 int cswdg_csweno_limit_vjp(cswdg_solver* s, const void* w, const uint8_t* mask, const void* y_bar, void* w_bar) {
     int rc = check_ready(s);
+    if (rc) return rc;
+    rc = check_single(s);
     if (rc) return rc;
     if (!w || !y_bar || !w_bar || w_bar == y_bar) return fail(s, CSWDG_EINVAL, "bad pointers");
     rc = ensure_adjoint_scratch(s);
@@ -564,6 +564,8 @@ int cswdg_tape_bytes(cswdg_solver* s, int64_t* bytes) {
 
 int cswdg_ssprk3_step_tape(cswdg_solver* s, void* u, const double* dt_dev, void* tape, int replay) {
     int rc = check_ready(s);
+    if (rc) return rc;
+    rc = check_single(s);
     if (rc) return rc;
     if (!u || !tape) return fail(s, CSWDG_EINVAL, "null pointer");
     TapeView t = tape_view(s, tape);
@@ -604,6 +606,8 @@ int cswdg_ssprk3_step_tape(cswdg_solver* s, void* u, const double* dt_dev, void*
 int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_bar, void* u_n_bar) {
     int rc = check_ready(s);
     if (rc) return rc;
+    rc = check_single(s);
+    if (rc) return rc;
     if (!tape || !u_next_bar || !u_n_bar || u_n_bar == u_next_bar) return fail(s, CSWDG_EINVAL, "bad pointers");
     rc = ensure_adjoint_scratch(s);
     if (rc) return rc;
@@ -632,6 +636,164 @@ int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_
         return launch_residual_vjp(s->ctx, s->dm, t.st[0], s->d_V, u_n_bar, nullptr, t.dt, 0.0, 1.0, 1.0, 1);
     });
     return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "residual vjp");
+}
+
+int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched) {
+    if (!s || !sched) return fail(s, CSWDG_EINVAL, "null argument");
+    if (sched[0] < 0 || sched[0] > 2 || (sched[1] != 64 && sched[1] != 128 && sched[1] != 256) ||
+        (sched[2] != 0 && sched[2] != 1))
+        return fail(s, CSWDG_EINVAL, "schedule: variant 0..2, block 64/128/256, xcd 0/1");
+    s->ctx.residual_variant = sched[0];
+    s->ctx.residual_block = sched[1];
+    s->dm.xcd_tiles = sched[2];
+    return CSWDG_OK;
+}
+
+int cswdg_get_schedule(const cswdg_solver* s, int32_t* sched) {
+    if (!s || !sched) return fail(const_cast<cswdg_solver*>(s), CSWDG_EINVAL, "null argument");
+    sched[0] = s->ctx.residual_variant;
+    sched[1] = s->ctx.residual_block;
+    sched[2] = s->dm.xcd_tiles;
+    return CSWDG_OK;
+}
+
+int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched, double* times_us, int32_t* n_cand) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u || reps < 1) return fail(s, CSWDG_EINVAL, "autotune needs a state and reps >= 1");
+    const int variants[3] = {0, 1, 2}, blocks[3] = {64, 128, 256}, xcds[2] = {0, 1};
+    hipEvent_t ev[2];
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+        return fail(s, CSWDG_EHIP, "hipEventCreate failed");
+    const bool prof = s->prof;
+    s->prof = false;
+    const LaunchCtx saved = s->ctx;
+    const int saved_xcd = s->dm.xcd_tiles;
+    double best = INFINITY;
+    int bi = -1, k = 0;
+    hipError_t e = hipSuccess;
+    for (int v : variants)
+        for (int b : blocks)
+            for (int x : xcds) {
+                s->ctx.residual_variant = v;
+                s->ctx.residual_block = b;
+                s->dm.xcd_tiles = x;
+                // one untimed launch, then reps timed launches of the residual
+                e = launch_residual_reset(s->ctx, s->dm, 0, u, nullptr, s->d_T1, nullptr, nullptr);
+                if (e == hipSuccess) e = hipEventRecord(ev[0], s->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    e = launch_residual_reset(s->ctx, s->dm, 0, u, nullptr, s->d_T1, nullptr, nullptr);
+                if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (e != hipSuccess) break;
+                const double us = 1000.0 * ms / reps;
+                if (times_us) times_us[k] = us;
+                if (us < best) {
+                    best = us;
+                    bi = k;
+                }
+                ++k;
+            }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    s->prof = prof;
+    s->ctx = saved;
+    s->dm.xcd_tiles = saved_xcd;
+    if (e != hipSuccess) return hipfail(s, e, "autotune");
+    if (n_cand) *n_cand = k;
+    const int32_t choice[3] = {variants[bi / 6], blocks[(bi / 2) % 3], xcds[bi % 2]};
+    if (sched)
+        for (int i = 0; i < 3; ++i) sched[i] = choice[i];
+    return cswdg_set_schedule(s, choice);
+}
+
+int cswdg_graph_capture(int32_t n, cswdg_solver* const* solvers, void* const* states, int32_t nsteps,
+                        cswdg_graph** out) {
+    if (!out || n < 1 || !solvers || !states || nsteps < 1) return fail(nullptr, CSWDG_EINVAL, "bad capture arguments");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!solvers[i] || !states[i]) return fail(nullptr, CSWDG_EINVAL, "null solver or state");
+        int rc = check_ready(solvers[i]);
+        if (rc) return rc;
+        if (solvers[i]->device != solvers[0]->device) return fail(nullptr, CSWDG_EINVAL, "solvers on different devices");
+    }
+    // capture on a private stream of default priority; the members' work is
+    // ordered before the capture by a full device wait
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(nullptr, CSWDG_EHIP, "capture stream");
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipStreamSynchronize(solvers[i]->stream);
+    std::vector<hipStream_t> saved(n);
+    std::vector<bool> prof(n);
+    for (int i = 0; i < n; ++i) {
+        saved[i] = solvers[i]->stream;
+        prof[i] = solvers[i]->prof;
+        solvers[i]->stream = cs;
+        solvers[i]->ctx.stream = cs;
+        solvers[i]->prof = false;
+    }
+    int rc = CSWDG_OK;
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int t = 0; t < nsteps && rc == CSWDG_OK; ++t)
+            for (int i = 0; i < n && rc == CSWDG_OK; ++i) rc = cswdg_ssprk3_step(solvers[i], states[i], nullptr);
+        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+    }
+    for (int i = 0; i < n; ++i) {
+        solvers[i]->stream = saved[i];
+        solvers[i]->ctx.stream = saved[i];
+        solvers[i]->prof = prof[i];
+    }
+    hipGraphExec_t exec = nullptr;
+    if (rc == CSWDG_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    size_t nodes = 0;
+    if (rc == CSWDG_OK && e == hipSuccess) e = hipGraphGetNodes(graph, nullptr, &nodes);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (rc != CSWDG_OK) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return fail(nullptr, CSWDG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    cswdg_graph* g = new (std::nothrow) cswdg_graph();
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(nullptr, CSWDG_ENOMEM, "out of host memory");
+    }
+    g->exec = exec;
+    g->device = solvers[0]->device;
+    g->nodes = (int64_t)nodes;
+    *out = g;
+    return CSWDG_OK;
+}
+
+int cswdg_graph_launch(cswdg_graph* g, void* hip_stream) {
+    if (!g) return fail(nullptr, CSWDG_EINVAL, "null graph");
+    if (hipSetDevice(g->device) != hipSuccess) return fail(nullptr, CSWDG_EHIP, "hipSetDevice failed");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)hip_stream);
+    return e == hipSuccess ? CSWDG_OK : fail(nullptr, CSWDG_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+}
+
+int cswdg_graph_nodes(const cswdg_graph* g, int64_t* nodes) {
+    if (!g || !nodes) return fail(nullptr, CSWDG_EINVAL, "null argument");
+    *nodes = g->nodes;
+    return CSWDG_OK;
+}
+
+int cswdg_graph_destroy(cswdg_graph* g) {
+    if (!g) return CSWDG_OK;
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(g->exec);
+    delete g;
+    return CSWDG_OK;
 }
 
 int cswdg_profile(cswdg_solver* s, int enable) {
@@ -675,3 +837,92 @@ int cswdg_kernel_times(cswdg_solver* s, const char** names, double* total_ms, in
 }
 
 }  // extern "C"
+
+namespace {
+
+// device copies of s->mesh (built on the host) and the per-element operators
+int upload_mesh(cswdg_solver* s) {
+    int rc;
+    const int64_t K = s->mesh.K;
+    std::vector<double> ops;
+    rc = build_limiter_ops(s->mesh, s->p.degree, ops, s->n_rank, s->n_foot);
+    if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
+    std::vector<int32_t> nbrT(3 * K);
+    std::vector<uint32_t> info4(K);
+    for (int64_t e = 0; e < K; ++e) {
+        uint32_t w = 0;
+        for (int f = 0; f < 3; ++f) {
+            nbrT[f * K + e] = s->mesh.nbr[3 * e + f];
+            w |= (uint32_t)s->mesh.info[3 * e + f] << (8 * f);
+        }
+        info4[e] = w;
+    }
+    const size_t NPM = (size_t)s->M * s->NP;
+    s->state_elems = NPM * K;
+    struct A {
+        void** p;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&s->d_vx, sizeof(double) * 3 * K},
+        {(void**)&s->d_vy, sizeof(double) * 3 * K},
+        {(void**)&s->d_nbr, sizeof(int32_t) * 3 * K},
+        {(void**)&s->d_info, sizeof(uint32_t) * K},
+        {(void**)&s->d_ops, sizeof(double) * ops.size()},
+        {(void**)&s->d_flags, (size_t)K},
+        {(void**)&s->d_list, sizeof(int32_t) * K},
+        {(void**)&s->d_count, sizeof(uint32_t) * 4},
+        {(void**)&s->d_status, sizeof(uint32_t) * 4},
+        {(void**)&s->d_tstats, sizeof(unsigned long long) * 2},
+        {(void**)&s->d_compact, sizeof(double) * NPM * K},
+        {(void**)&s->d_partial, sizeof(double) * s->dt_blocks},
+        {(void**)&s->d_dt, sizeof(double) * std::max(2, s->n_inst)},
+        {(void**)&s->d_inst_off, sizeof(int32_t) * (s->n_inst + 1)},
+        {(void**)&s->d_inst_hmin, sizeof(double) * s->n_inst},
+        {(void**)&s->d_amax, sizeof(unsigned long long) * s->n_inst},
+        {(void**)&s->d_T1, sizeof(double) * NPM * K},
+        {(void**)&s->d_T2, sizeof(double) * NPM * K},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            free_mesh(s);
+            return fail(s, CSWDG_ENOMEM, "device allocation failed");
+        }
+    }
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* d, const void* h, size_t b) {
+        if (e == hipSuccess) e = hipMemcpy(d, h, b, hipMemcpyHostToDevice);
+    };
+    cp(s->d_vx, s->mesh.vx.data(), sizeof(double) * 3 * K);
+    cp(s->d_vy, s->mesh.vy.data(), sizeof(double) * 3 * K);
+    cp(s->d_nbr, nbrT.data(), sizeof(int32_t) * 3 * K);
+    cp(s->d_info, info4.data(), sizeof(uint32_t) * K);
+    cp(s->d_ops, ops.data(), sizeof(double) * ops.size());
+    uint32_t zeros[4] = {0, 0, 0, 0};
+    cp(s->d_count, zeros, sizeof(zeros));
+    cp(s->d_status, zeros, sizeof(zeros));
+    unsigned long long zz[2] = {0, 0};
+    cp(s->d_tstats, zz, sizeof(zz));
+    cp(s->d_inst_off, s->inst_off.data(), sizeof(int32_t) * (s->n_inst + 1));
+    cp(s->d_inst_hmin, s->inst_hmin.data(), sizeof(double) * s->n_inst);
+    if (e == hipSuccess) e = hipMemset(s->d_amax, 0, sizeof(unsigned long long) * s->n_inst);
+    if (e != hipSuccess) {
+        free_mesh(s);
+        return hipfail(s, e, "mesh upload");
+    }
+    s->dm.K = (int)K;
+    s->dm.vx = s->d_vx;
+    s->dm.vy = s->d_vy;
+    s->dm.nbr = s->d_nbr;
+    s->dm.info = s->d_info;
+    s->dm.n_inst = s->n_inst;
+    s->dm.inst_off = s->d_inst_off;
+    {
+        const char* xt = std::getenv("CSWDG_XCD_TILES");
+        s->dm.xcd_tiles = xt ? std::atoi(xt) : 1;
+    }
+    s->has_mesh = true;
+    return CSWDG_OK;
+}
+
+
+}  // namespace

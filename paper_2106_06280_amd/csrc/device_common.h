@@ -77,6 +77,18 @@ __device__ __forceinline__ int xcd_block(int b, int G, int on = 1) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// instance holding element e (binary search over the instance offsets)
+__device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
+    if (m.n_inst <= 1) return 0;
+    int lo = 0, hi = m.n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (e >= m.inst_off[mid]) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Physics: fluxes and wave speeds (Section 4 eqs. 2dBurgers, 2dEulerEquations)
 // ---------------------------------------------------------------------------

@@ -178,4 +178,59 @@ int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri_in,
     return CSWDG_OK;
 }
 
+int concat_meshes(const std::vector<HostMesh>& parts, HostMesh& out, std::vector<int32_t>& off,
+                  std::vector<double>& hmin, std::string& msg) {
+    int64_t K = 0;
+    for (const HostMesh& p : parts) K += p.K;
+    if (parts.empty() || K > (int64_t)0x3fffffff) {
+        msg = "mesh: instance count or total size out of range";
+        return CSWDG_EINVAL;
+    }
+    out = HostMesh();
+    out.K = K;
+    out.bc = parts[0].bc;
+    out.px = parts[0].px;
+    out.py = parts[0].py;
+    out.hmin = INFINITY;
+    for (const HostMesh& p : parts) {
+        // periodic shifts are applied with the union's period
+        if (p.bc == CSWDG_BC_PERIODIC && (p.px != out.px || p.py != out.py)) {
+            msg = "mesh: periodic instances must share one period";
+            return CSWDG_EINVAL;
+        }
+    }
+    out.tri.resize(3 * K);
+    out.nbr.resize(3 * K);
+    out.info.resize(3 * K);
+    out.vx.resize(3 * K);
+    out.vy.resize(3 * K);
+    off.assign(parts.size() + 1, 0);
+    hmin.assign(parts.size(), 0.0);
+    int64_t e0 = 0, v0 = 0;
+    for (size_t i = 0; i < parts.size(); ++i) {
+        const HostMesh& p = parts[i];
+        off[i] = (int32_t)e0;
+        hmin[i] = p.hmin;
+        out.hmin = std::min(out.hmin, p.hmin);
+        out.n_flipped += p.n_flipped;
+        int32_t vmax = -1;
+        for (int64_t j = 0; j < 3 * p.K; ++j) {
+            out.tri[3 * e0 + j] = (int32_t)(p.tri[j] + v0);
+            vmax = std::max(vmax, p.tri[j]);
+            const bool bnd = (p.info[j] & 0x40) != 0;
+            out.nbr[3 * e0 + j] = bnd ? p.nbr[j] : (int32_t)(p.nbr[j] + e0);
+            out.info[3 * e0 + j] = p.info[j];
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int64_t e = 0; e < p.K; ++e) {
+                out.vx[k * K + e0 + e] = p.vx[k * p.K + e];
+                out.vy[k * K + e0 + e] = p.vy[k * p.K + e];
+            }
+        e0 += p.K;
+        v0 += (int64_t)vmax + 1;
+    }
+    off[parts.size()] = (int32_t)K;
+    return CSWDG_OK;
+}
+
 }  // namespace cswdg

@@ -54,6 +54,12 @@ struct HostMesh {
 int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc, double px,
                double py, HostMesh& m, std::string& msg);
 
+// disjoint union of independently built meshes (instances): vertex and element
+// ids are offset, faces keep their own neighbours; off[i] is the first element
+// of instance i (off[n] = K) and hmin[i] its time-step length scale
+int concat_meshes(const std::vector<HostMesh>& parts, HostMesh& out, std::vector<int32_t>& off,
+                  std::vector<double>& hmin, std::string& msg);
+
 // per-element limiter operators (host_ops.cpp); returns number of
 // rank-deficient elements and perpendicular feet that fell outside
 int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank,
@@ -69,6 +75,8 @@ struct DevMesh {
     const int32_t* nbr;    // [3][K]
     const uint32_t* info;  // [K], face f in byte f
     int xcd_tiles;         // 1: give each XCD a contiguous range of blocks
+    int n_inst;            // independent meshes held (1 for a single mesh)
+    const int32_t* inst_off;  // [n_inst + 1] first element of each instance
 };
 
 struct LaunchCtx {
@@ -76,6 +84,7 @@ struct LaunchCtx {
     int eq, N, precision;
     double gamma, cfl, c_k, eps;
     int residual_variant;  // residual schedule: 0 lean (default), 1 wide, 2 stream
+    int residual_block;    // residual threads per block: 64, 128 or 256
 };
 
 int upload_tables_device();   // once per device (both translation units)
@@ -89,6 +98,10 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
 hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, double hmin,
                          double* dt, double* partial, uint32_t* counter, uint32_t* status,
                          int nblocks);
+// the same per instance: dt[i] = cfl * hmin[i] / amax_i; amax_bits ([n_inst],
+// zero on entry) is left zero for the next call
+hipError_t launch_max_dt_inst(const LaunchCtx& c, const DevMesh& m, const void* u, const double* hmin,
+                              double* dt, unsigned long long* amax_bits, uint32_t* status);
 // KXRCF flags (+ optional R) and the compacted list of troubled cells
 hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags,
                         double* R, int32_t* list, uint32_t* count);

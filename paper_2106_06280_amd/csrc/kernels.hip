@@ -136,7 +136,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
     }
 
     double dt = 0.0;
-    if (MODE != 0) dt = *dtp;
+    if (MODE != 0) dt = dtp[inst_of(msh, e)];
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
@@ -286,7 +286,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
     }
 
     double dt = 0.0;
-    if (MODE != 0) dt = *dtp;
+    if (MODE != 0) dt = dtp[inst_of(msh, e)];
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
@@ -434,7 +434,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
     }
 
     double dt = 0.0;
-    if (MODE != 0) dt = *dtp;
+    if (MODE != 0) dt = dtp[inst_of(msh, e)];
     asm volatile("" : "+s"(us));
 #pragma unroll
     for (int c = 0; c < M; ++c)
@@ -516,6 +516,60 @@ __global__ __launch_bounds__(256) void k_dt_final(int nblocks, const double* __r
         for (int i = 1; i < (int)(blockDim.x >> 6); ++i) b = fmax(b, red[i]);
         *dt = cfl * hmin / b;
     }
+}
+
+// Per-instance time steps for a mesh holding several independent instances:
+// wave maxima go to the instance's slot with an integer atomic max on the bit
+// pattern (monotone for non-negative doubles); a wave spanning an instance
+// boundary falls back to one atomic per lane. Non-finite speeds are skipped
+// (and flagged), as fmax does in the single-mesh reduction.
+template <int EQ, int N>
+__global__ __launch_bounds__(256) void k_dt_inst(DevMesh msh, const double* __restrict__ u, double gamma,
+                                                 unsigned long long* __restrict__ amax_bits,
+                                                 uint32_t* __restrict__ status) {
+    constexpr int NP = Dims<N>::NP, M = Phys<EQ>::M;
+    const int K = msh.K;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    uint32_t st = 0;
+    int ins = msh.n_inst - 1;
+    if (e < K) {
+        ins = inst_of(msh, e);
+        double ub[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) ub[c] = u[(size_t)(c * NP) * K + e] * kPsi0;
+        if constexpr (EQ == 0) {
+            s = 1.41421356237309504880 * fabs(ub[0]);
+        } else {
+            double rho = ub[0], vx = ub[1] / rho, vy = ub[2] / rho;
+            double p = (gamma - 1.0) * (ub[3] - 0.5 * rho * (vx * vx + vy * vy));
+            if (!(rho > 0.0) || !(p > 0.0)) st |= CSWDG_STATUS_NEGATIVE;
+            s = sqrt(vx * vx + vy * vy) + sqrt(gamma * p / rho);
+        }
+        if (!isfinite(s)) {
+            st |= CSWDG_STATUS_NONFINITE;
+            s = 0.0;
+        }
+    }
+    const int i0 = __shfl(ins, 0);
+    if (__ballot(ins != i0) == 0ull) {
+        double a = s;
+        for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+        if ((threadIdx.x & 63) == 0 && a > 0.0) atomicMax(&amax_bits[i0], (unsigned long long)__double_as_longlong(a));
+    } else if (s > 0.0) {
+        atomicMax(&amax_bits[ins], (unsigned long long)__double_as_longlong(s));
+    }
+    if (st) atomicOr(status, st);
+}
+
+__global__ __launch_bounds__(256) void k_dt_inst_final(int n, unsigned long long* __restrict__ amax_bits,
+                                                       double cfl, const double* __restrict__ hmin,
+                                                       double* __restrict__ dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = __longlong_as_double((long long)amax_bits[i]);
+    dt[i] = cfl * hmin[i] / a;
+    amax_bits[i] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -946,7 +1000,8 @@ int upload_tables_device() {
 
 hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode, const void* u,
                                  const void* un, void* out, const double* dt, uint32_t* reset) {
-    const unsigned bs = 256, g = grid_for(m.K, bs);
+    const unsigned bs = (c.residual_block == 64 || c.residual_block == 128) ? (unsigned)c.residual_block : 256u;
+    const unsigned g = grid_for(m.K, bs);
     const double* U = (const double*)u;
     const double* UN = (const double*)un;
     double* O = (double*)out;
@@ -978,6 +1033,15 @@ hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, do
         k_dt_partial<EQ, N><<<nblocks, 256, 0, c.stream>>>(m.K, U, c.gamma, partial, status);
     });
     k_dt_final<<<1, 256, 0, c.stream>>>(nblocks, partial, c.cfl, hmin, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_dt_inst(const LaunchCtx& c, const DevMesh& m, const void* u, const double* hmin,
+                              double* dt, unsigned long long* amax_bits, uint32_t* status) {
+    const double* U = (const double*)u;
+    const unsigned g = grid_for(m.K, 256);
+    CSWDG_DISPATCH_EN(c.eq, c.N, { k_dt_inst<EQ, N><<<g, 256, 0, c.stream>>>(m, U, c.gamma, amax_bits, status); });
+    k_dt_inst_final<<<grid_for(m.n_inst, 256), 256, 0, c.stream>>>(m.n_inst, amax_bits, c.cfl, hmin, dt);
     return hipGetLastError();
 }
 

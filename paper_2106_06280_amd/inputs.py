@@ -247,3 +247,67 @@ class VortexCircles:
 def random_coefficients(shape, seed, scale=1.0):
     """Seeded normal draws (used as raw modal coefficients in parity tests)."""
     return scale * _rng(seed).standard_normal(size=shape)
+
+
+# ----------------------------------------------------------------------------
+# Batches of independent instances (many small problems advanced together).
+# ----------------------------------------------------------------------------
+
+class BurgersSmoothJump:
+    """u0 = a + b sin(2 pi (kx x + ky y)) + c 1[x . nhat > s] on [0,1]^2."""
+
+    def __init__(self, a, b, kx, ky, c, nx, ny, s):
+        self.a, self.b, self.kx, self.ky, self.c = a, b, kx, ky, c
+        self.nx, self.ny, self.s = nx, ny, s
+
+    def __call__(self, x, y):
+        x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+        jump = (x * self.nx + y * self.ny > self.s).astype(np.float64)
+        return self.a + self.b * np.sin(2 * math.pi * (self.kx * x + self.ky * y)) + self.c * jump
+
+
+class EulerSmoothJump:
+    """rho = 1 + 0.2 sin(2 pi (kx x + ky y)) with a half-plane jump added to
+    rho and p; constant velocity."""
+
+    def __init__(self, kx, ky, drho, dp, u, v, nx, ny, s, gamma=GAMMA_GAS):
+        self.kx, self.ky, self.drho, self.dp, self.u, self.v = kx, ky, drho, dp, u, v
+        self.nx, self.ny, self.s, self.gamma = nx, ny, s, gamma
+
+    def __call__(self, x, y):
+        x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+        jump = (x * self.nx + y * self.ny > self.s).astype(np.float64)
+        rho = 1.0 + 0.2 * np.sin(2 * math.pi * (self.kx * x + self.ky * y)) + self.drho * jump
+        p = 1.0 + self.dp * jump
+        return primitive_to_conservative(rho, self.u, self.v, p, self.gamma)
+
+
+def batch_instances(n_inst=256, seed=1004, k_lo=2000, k_hi=60000, n_burgers=None):
+    """Seeded descriptions of independent instances on [0,1]^2: the first
+    n_burgers (default half) are Burgers (periodic), the rest Euler
+    (transmissive).  Triangle counts are drawn log-uniformly in [k_lo, k_hi].
+    Each entry: dict(eq, bc, n, mesh_seed, ic)."""
+    rng = _rng(seed)
+    if n_burgers is None:
+        n_burgers = n_inst // 2
+    out = []
+    for i in range(n_inst):
+        k = math.exp(rng.uniform(math.log(k_lo), math.log(k_hi)))
+        n = max(2, n_for_target(k))
+        mesh_seed = int(rng.integers(1 << 31))
+        th = rng.uniform(0.0, 2 * math.pi)
+        nx, ny = math.cos(th), math.sin(th)
+        # the half-plane boundary passes through a point of the unit square
+        px, py = rng.uniform(0.25, 0.75, size=2)
+        s = nx * px + ny * py
+        kx, ky = (int(t) for t in rng.integers(1, 3, size=2))
+        if i < n_burgers:
+            ic = BurgersSmoothJump(a=rng.uniform(0.2, 0.8), b=rng.uniform(0.1, 0.5), kx=kx, ky=ky,
+                                   c=rng.uniform(-0.5, 0.5), nx=nx, ny=ny, s=s)
+            out.append(dict(eq=0, bc=0, n=n, mesh_seed=mesh_seed, ic=ic))
+        else:
+            u, v = rng.uniform(-0.5, 0.5, size=2)
+            ic = EulerSmoothJump(kx=kx, ky=ky, drho=rng.uniform(0.2, 1.0), dp=rng.uniform(0.2, 1.0),
+                                 u=u, v=v, nx=nx, ny=ny, s=s)
+            out.append(dict(eq=1, bc=1, n=n, mesh_seed=mesh_seed, ic=ic))
+    return out
