@@ -10,6 +10,17 @@ A step is one full SSP-RK3 step (three stages, each: residual + RK combine,
 KXRCF indicator + compaction, CSWENO on the flagged cells, scatter), dt
 computed on the device.  The state stays in HBM; W warm-up steps, then K
 timed steps bracketed by device synchronisation.  Prints one JSON line.
+The line also carries the adjoint/forward time ratio: one step's
+vector-Jacobian product (troubled sets and dt frozen) against one forward
+step, on the same workload.
+
+--workload c4_batch: 256 independent P2 instances on [0,1]^2 (half Burgers,
+periodic; half Euler, transmissive), triangle counts log-uniform in
+[2000, 60000] (seed 1004), smooth-plus-jump initial data; each equation's
+instances form one disjoint-union mesh; the residual schedule is autotuned;
+K steps of both solvers are captured into one HIP graph and timed as one
+graph launch (after one untimed launch), then checked bit for bit against
+the same steps run eagerly.
 """
 from __future__ import annotations
 
@@ -51,6 +62,142 @@ def make_problem(name):
         ic = inputs.FourQuadrant(seed=seed)
         period = (1.0, 1.0)
     return eq, N, bc, v, t, ic, period
+
+
+BATCH_SEED = 1004
+
+
+def make_batch():
+    from paper_2106_06280_amd import inputs
+    desc = inputs.batch_instances(n_inst=256, seed=BATCH_SEED)
+    groups = {}
+    for d in desc:
+        v, t = inputs.jittered_mesh(d["n"], seed=d["mesh_seed"])
+        groups.setdefault(d["eq"], []).append((v, t, d["bc"], d["ic"]))
+    return groups
+
+
+def project_instances(S, insts):
+    """Initial coefficients of a multi-instance solver: each instance's
+    function evaluated at its own projection points, projected on the GPU."""
+    import numpy as np
+    import torch
+    xy = S.ic_points().cpu().numpy()
+    off = S.instances()
+    nq = xy.shape[1]
+    vals = np.empty((S.m, nq, S.K))
+    for i, (_, _, _, ic) in enumerate(insts):
+        a, b = off[i], off[i + 1]
+        v = np.asarray(ic(xy[0][:, a:b], xy[1][:, a:b]), dtype=np.float64)
+        vals[:, :, a:b] = v[None] if v.ndim == 2 else np.moveaxis(v, -1, 0)
+    return S.project(torch.from_numpy(vals).to("cuda"))
+
+
+def run_batch(args):
+    import torch
+
+    from paper_2106_06280_amd import binding
+
+    t0 = time.perf_counter()
+    groups = make_batch()
+    solvers, states, info = [], [], []
+    for eq in sorted(groups):
+        insts = groups[eq]
+        S = binding.Solver(eq, 2, limiter_mode=binding.LIMIT_KXRCF)
+        S.mesh_upload_batch([(v, t) for v, t, _, _ in insts], [bc for _, _, bc, _ in insts], (1.0, 1.0))
+        u = project_instances(S, insts)
+        sched, times = S.autotune(u, reps=5)
+        solvers.append(S)
+        states.append(u)
+        info.append({"equation": "euler" if eq == 1 else "burgers", "instances": len(insts), "triangles": S.K,
+                     "dof": S.K * S.m * S.Np, "schedule": {"variant": sched[0], "block": sched[1], "xcd": sched[2]},
+                     "schedule_us": round(times[sched], 2), "default_schedule_us": round(times[(0, 256, 1)], 2)})
+    torch.cuda.synchronize()
+    print(f"[bench] c4_batch setup {time.perf_counter() - t0:.1f}s: "
+          + ", ".join(f"{d['equation']} {d['instances']} inst K={d['triangles']}" for d in info),
+          file=sys.stderr, flush=True)
+    g = binding.Graph(solvers, states, nsteps=args.steps)
+    g.launch()  # warm-up: advances the states by `steps`
+    torch.cuda.synchronize()
+    for S in solvers:
+        S.status()
+        S.troubled_stats(reset=True)
+    start = [u.clone() for u in states]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    g.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    secs = ev0.elapsed_time(ev1) / 1000.0
+    status = [S.status() for S in solvers]
+    f = [S.troubled_stats()[0] / max(1, 3 * args.steps * S.K) for S in solvers]
+    # the same steps eagerly (plain launches) from the same start: timed, and
+    # compared bit for bit with the graph's result
+    eager = [u.clone() for u in start]
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        for S, u in zip(solvers, eager):
+            S.ssprk3_step(u)
+    ev1.record()
+    torch.cuda.synchronize()
+    secs_eager = ev0.elapsed_time(ev1) / 1000.0
+    same = all(torch.equal(a, b) for a, b in zip(eager, states))
+    dof = sum(d["dof"] for d in info)
+    value = dof * 3 * args.steps / secs
+    for d, fr in zip(info, f):
+        d["troubled_fraction"] = round(fr, 5)
+    out = {
+        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (batched P2 instances)",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.steps,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c4_batch", "instances": 256, "triangles": sum(d["triangles"] for d in info),
+                   "dof": dof, "degree": 2, "groups": info, "graph_nodes": g.nodes(),
+                   "parallelism": "single-gpu"},
+        "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
+                  "graph_equals_eager": bool(same)},
+        "status_bits": status,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_ratio(S, u, fwd_ms_per_step, reps=5):
+    """One step's vector-Jacobian product (tape recorded once, dt and troubled
+    sets frozen) timed against one forward step."""
+    import torch
+    tape = S.new_tape()
+    w = u.clone()
+    S.ssprk3_step_tape(w, tape)
+    ybar = torch.ones_like(u)
+    ubar = torch.empty_like(u)
+    S.ssprk3_step_vjp(tape, ybar, ubar)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        ev0.record()
+        S.ssprk3_step_vjp(tape, ybar, ubar)
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    t = sorted(times)[len(times) // 2]
+    ok = bool(torch.isfinite(ubar).all())
+    del tape
+    return {"ratio": round(t / fwd_ms_per_step, 3), "vjp_ms_per_step": round(t, 3),
+            "fwd_ms_per_step": round(fwd_ms_per_step, 3), "finite": ok,
+            "what": "step VJP (3 x limiter VJP with frozen troubled set + residual/RK VJP) / forward step"}
 
 
 def measured_traffic(workload):
@@ -133,7 +280,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS) + ["c4_batch"])
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
@@ -159,12 +307,14 @@ def main():
     if int(os.environ.get("RANK", "0")) != 0:
         return
 
-    import numpy as np
     import torch
 
     from paper_2106_06280_amd import binding
 
     torch.cuda.set_device(0)
+    if args.workload == "c4_batch":
+        run_batch(args)
+        return
     eq, N, bc, v, t, ic, period = make_problem(args.workload)
     t_setup = time.perf_counter()
     S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_KXRCF)
@@ -219,8 +369,9 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
                 "kernel": "k_residual (volume + surface + LF flux + 1/J + RK combine)",
                 "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_launch)}
+    adj = None if args.no_adjoint else adjoint_ratio(S, u, secs * 1e3 / args.steps)
     out = {
-        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P2 Euler, 1M tri)",
+        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P2 Euler, 1M tri); adjoint/fwd ratio",
         "value": value,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
@@ -237,6 +388,7 @@ def main():
                    "troubled_fraction": round(f, 5), "limiter": "kxrcf+csweno",
                    "parallelism": "single-gpu"},
         "roofline": roof,
+        "adjoint": adj,
         "kernel_ms": {k: [round(a, 3), int(b)] for k, (a, b) in kt.items() if b},
         "status_bits": status,
     }
