@@ -241,17 +241,28 @@ __global__ __launch_bounds__(256) void k_compact_slots(int K, const uint8_t* __r
                                                        int32_t* __restrict__ list,
                                                        int32_t* __restrict__ slot,
                                                        uint32_t* __restrict__ count) {
+    // segment 0 only (the slots are global list positions); one atomic per block
+    __shared__ uint32_t wbase[4];
+    __shared__ uint32_t bbase;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     const bool tr = (e < K) && mask[e] != 0;
     const unsigned long long bal = __ballot(tr ? 1 : 0);
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    const int total = __popcll(bal);
-    uint32_t base = 0;
-    if (lane == 0 && total > 0) base = atomicAdd(count, (uint32_t)total);
-    base = __shfl(base, 0);
+    if (lane == 0) wbase[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0u;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            const uint32_t c = wbase[i];
+            wbase[i] = acc;
+            acc += c;
+        }
+        bbase = acc ? atomicAdd(count, acc) : 0u;
+    }
+    __syncthreads();
     if (e < K) {
-        const uint32_t pos = base + (uint32_t)before;
+        const uint32_t pos = bbase + wbase[w] + (uint32_t)before;
         if (tr && pos < (uint32_t)K) list[pos] = e;
         slot[e] = tr ? (int32_t)pos : -1;
     }
@@ -271,14 +282,16 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
     constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
     constexpr int CPB = 64 / LPC;
     const int K = msh.K;
-    const uint32_t ncell = min(*count, (uint32_t)K);
+    uint32_t pre[kListSegs + 1];
+    seg_prefix(count, K, pre);
+    const uint32_t ncell = pre[kListSegs];
     const int j = threadIdx.x % LPC;
     const int d = j / M;
     const int k = j % M;
     for (uint32_t base = blockIdx.x * CPB; base < ncell; base += gridDim.x * CPB) {
         const uint32_t t = base + threadIdx.x / LPC;
         const bool active = t < ncell;
-        const int e = active ? list[t] : 0;
+        const int e = active ? seg_elem(list, pre, K, t) : 0;
         const double* __restrict__ op = ops + (size_t)e * LO::LEN;
         const bool valid = active && op[LO::VALID] != 0.0;
 

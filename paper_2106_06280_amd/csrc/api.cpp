@@ -44,7 +44,7 @@ struct cswdg_solver {
     double* d_ops = nullptr;
     uint8_t* d_flags = nullptr;
     int32_t* d_list = nullptr;
-    uint32_t* d_count = nullptr;   // [0] troubled count
+    uint32_t* d_count = nullptr;   // troubled-list segment counters (kCountWords)
     uint32_t* d_status = nullptr;
     unsigned long long* d_tstats = nullptr;  // troubled cells, limiter calls
     double* d_compact = nullptr;
@@ -152,7 +152,7 @@ int limit_into(cswdg_solver* s, const void* src, void* buf, uint8_t* flags_out, 
     if (mode == CSWDG_LIMIT_NONE) return CSWDG_OK;
     uint8_t* flags = flags_out ? flags_out : s->d_flags;
     if (!count_zeroed) {
-        e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, 1); });
+        e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, kCountWords); });
         if (e != hipSuccess) return hipfail(s, e, "zero");
     }
     if (mask || mode == CSWDG_LIMIT_ALL) {
@@ -216,7 +216,7 @@ int ensure_adjoint_scratch(cswdg_solver* s) {
 // wbar = Lambda'(w)^T ybar with the troubled set given by mask
 int limiter_vjp_impl(cswdg_solver* s, const void* w, const uint8_t* mask, const void* ybar, void* wbar) {
     const int K = (int)s->mesh.K;
-    hipError_t e = launch_zero_u32(s->ctx, s->d_count, 1);
+    hipError_t e = launch_zero_u32(s->ctx, s->d_count, kCountWords);
     if (e == hipSuccess) e = launch_compact_slots(s->ctx, K, mask, s->d_list, s->d_slot, s->d_count);
     if (e == hipSuccess)
         e = timed(s, KID_LIMITER_VJP, [&] {
@@ -430,7 +430,7 @@ int cswdg_kxrcf(cswdg_solver* s, const void* u, uint8_t* flags, double* R) {
     int rc = check_ready(s);
     if (rc) return rc;
     if (!u || !flags) return fail(s, CSWDG_EINVAL, "null pointer");
-    hipError_t e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, 1); });
+    hipError_t e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, kCountWords); });
     if (e == hipSuccess)
         e = timed(s, KID_KXRCF, [&] { return launch_kxrcf(s->ctx, s->dm, u, flags, R, s->d_list, s->d_count); });
     return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "kxrcf");
@@ -485,11 +485,13 @@ int cswdg_troubled_count(cswdg_solver* s, int64_t* count) {
     int rc = check_ready(s);
     if (rc) return rc;
     if (!count) return fail(s, CSWDG_EINVAL, "null pointer");
-    uint32_t c = 0;
-    hipError_t e = hipMemcpyAsync(&c, s->d_count, sizeof(c), hipMemcpyDeviceToHost, s->stream);
+    uint32_t c[kCountWords];
+    hipError_t e = hipMemcpyAsync(c, s->d_count, sizeof(c), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hipfail(s, e, "troubled_count");
-    *count = c;
+    int64_t tot = 0;
+    for (int x = 0; x < kListSegs; ++x) tot += std::min<int64_t>(c[x * kCountStride], s->mesh.K);
+    *count = tot;
     return CSWDG_OK;
 }
 
@@ -546,7 +548,7 @@ int cswdg_csweno_limit_vjp(cswdg_solver* s, const void* w, const uint8_t* mask, 
     if (rc) return rc;
     const uint8_t* m = mask;
     if (!m) {
-        hipError_t e = launch_zero_u32(s->ctx, s->d_count, 1);
+        hipError_t e = launch_zero_u32(s->ctx, s->d_count, kCountWords);
         if (e == hipSuccess) e = launch_kxrcf(s->ctx, s->dm, w, s->d_flags, nullptr, s->d_list, s->d_count);
         if (e != hipSuccess) return hipfail(s, e, "kxrcf");
         m = s->d_flags;
@@ -869,8 +871,8 @@ int upload_mesh(cswdg_solver* s) {
         {(void**)&s->d_info, sizeof(uint32_t) * K},
         {(void**)&s->d_ops, sizeof(double) * ops.size()},
         {(void**)&s->d_flags, (size_t)K},
-        {(void**)&s->d_list, sizeof(int32_t) * K},
-        {(void**)&s->d_count, sizeof(uint32_t) * 4},
+        {(void**)&s->d_list, sizeof(int32_t) * K * kListSegs},
+        {(void**)&s->d_count, sizeof(uint32_t) * kCountWords},
         {(void**)&s->d_status, sizeof(uint32_t) * 4},
         {(void**)&s->d_tstats, sizeof(unsigned long long) * 2},
         {(void**)&s->d_compact, sizeof(double) * NPM * K},
@@ -897,9 +899,9 @@ int upload_mesh(cswdg_solver* s) {
     cp(s->d_nbr, nbrT.data(), sizeof(int32_t) * 3 * K);
     cp(s->d_info, info4.data(), sizeof(uint32_t) * K);
     cp(s->d_ops, ops.data(), sizeof(double) * ops.size());
-    uint32_t zeros[4] = {0, 0, 0, 0};
-    cp(s->d_count, zeros, sizeof(zeros));
-    cp(s->d_status, zeros, sizeof(zeros));
+    std::vector<uint32_t> zeros(kCountWords, 0u);
+    cp(s->d_count, zeros.data(), sizeof(uint32_t) * kCountWords);
+    cp(s->d_status, zeros.data(), sizeof(uint32_t) * 4);
     unsigned long long zz[2] = {0, 0};
     cp(s->d_tstats, zz, sizeof(zz));
     cp(s->d_inst_off, s->inst_off.data(), sizeof(int32_t) * (s->n_inst + 1));

@@ -77,6 +77,53 @@ __device__ __forceinline__ int xcd_block(int b, int G, int on = 1) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// ---------------------------------------------------------------------------
+// Troubled-cell lists: kListSegs segments of capacity K (segment x at
+// list + x K), each with its own counter at count[x * kCountStride] (one
+// 128-byte line each). A block appends with one atomic on its own segment,
+// so appends from different XCDs do not serialise on one address.
+// Consumers walk a global index t over the concatenated segments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void seg_prefix(const uint32_t* __restrict__ count, int K, uint32_t pre[kListSegs + 1]) {
+    pre[0] = 0u;
+#pragma unroll
+    for (int x = 0; x < kListSegs; ++x) pre[x + 1] = pre[x] + min(count[x * kCountStride], (uint32_t)K);
+}
+
+__device__ __forceinline__ int seg_elem(const int32_t* __restrict__ list, const uint32_t pre[kListSegs + 1], int K,
+                                        uint32_t t) {
+    int x = 0;
+#pragma unroll
+    for (int y = 1; y < kListSegs; ++y) x += (t >= pre[y]) ? 1 : 0;
+    return list[(size_t)x * K + (t - pre[x])];
+}
+
+// block-wide append of the elements with tr set (every thread of the block
+// must call it; blockDim.x a multiple of 64, at most 1024)
+__device__ __forceinline__ void append_list_block(bool tr, int e, int32_t* __restrict__ list,
+                                                  uint32_t* __restrict__ count, int K, int seg) {
+    __shared__ uint32_t wbase[16];
+    __shared__ uint32_t bbase;
+    const unsigned long long mask = __ballot(tr ? 1 : 0);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wbase[w] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0u;
+        const int nw = (int)(blockDim.x >> 6);
+        for (int i = 0; i < nw; ++i) {
+            const uint32_t c = wbase[i];
+            wbase[i] = acc;
+            acc += c;
+        }
+        bbase = acc ? atomicAdd(&count[seg * kCountStride], acc) : 0u;
+    }
+    __syncthreads();
+    const uint32_t pos = bbase + wbase[w] + (uint32_t)before;
+    if (tr && pos < (uint32_t)K) list[(size_t)seg * K + pos] = e;
+}
+
 // instance holding element e (binary search over the instance offsets)
 __device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
     if (m.n_inst <= 1) return 0;

@@ -68,6 +68,11 @@ int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_
 // ----------------------------------------------------------------------------
 // device views and launchers (kernels.hip)
 // ----------------------------------------------------------------------------
+// troubled-cell list layout: segments and counter stride (in uint32)
+constexpr int kListSegs = 8;
+constexpr int kCountStride = 32;
+constexpr int kCountWords = kListSegs * kCountStride;
+
 struct DevMesh {
     int K;
     const double* vx;      // [3][K]

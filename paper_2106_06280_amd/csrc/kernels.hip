@@ -43,7 +43,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
-    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
     const Tab<N>& T = tab<N>();
 
@@ -184,7 +184,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
-    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
     const Tab<N>& T = tab<N>();
 
@@ -324,7 +324,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
-    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *cnt_reset = 0u;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
     const Tab<N>& T = tab<N>();
 
@@ -575,16 +575,6 @@ __global__ __launch_bounds__(256) void k_dt_inst_final(int n, unsigned long long
 // ---------------------------------------------------------------------------
 // KXRCF indicator + compaction (Section 3.1)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void append_list(bool tr, int e, int32_t* list, uint32_t* count, int cap) {
-    const unsigned long long mask = __ballot(tr ? 1 : 0);
-    const int lane = threadIdx.x & 63;
-    const int before = __popcll(mask & ((1ull << lane) - 1ull));
-    const int total = __popcll(mask);
-    uint32_t base = 0;
-    if (lane == 0 && total > 0) base = atomicAdd(count, (uint32_t)total);
-    base = __shfl(base, 0);
-    if (tr && base + (uint32_t)before < (uint32_t)cap) list[base + before] = e;
-}
 
 template <int EQ, int N>
 __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const double* __restrict__ u,
@@ -667,7 +657,7 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const double* __rest
         flags[e] = tr ? 1 : 0;
         if (Rout) Rout[e] = R;
     }
-    append_list(tr, e, list, count, K);
+    append_list_block(tr, e, list, count, K, blockIdx.x & (kListSegs - 1));
 }
 
 __global__ __launch_bounds__(256) void k_compact_mask(int K, const uint8_t* __restrict__ mask,
@@ -680,7 +670,7 @@ __global__ __launch_bounds__(256) void k_compact_mask(int K, const uint8_t* __re
         tr = mask ? (mask[e] != 0) : true;
         if (flags) flags[e] = tr ? 1 : 0;
     }
-    append_list(tr, e, list, count, K);
+    append_list_block(tr, e, list, count, K, blockIdx.x & (kListSegs - 1));
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
@@ -705,14 +695,16 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __res
     constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
     constexpr int CPB = 64 / LPC;  // cells per block
     const int K = msh.K;
-    const uint32_t ncell = min(*count, (uint32_t)K);
+    uint32_t pre[kListSegs + 1];
+    seg_prefix(count, K, pre);
+    const uint32_t ncell = pre[kListSegs];
     const int j = threadIdx.x % LPC;  // lane within the cell
     const int d = j / M;              // characteristic direction
     const int k = j % M;              // characteristic field
     for (uint32_t base = blockIdx.x * CPB; base < ncell; base += gridDim.x * CPB) {
         const uint32_t t = base + threadIdx.x / LPC;
         const bool active = t < ncell;
-        const int e = active ? list[t] : 0;
+        const int e = active ? seg_elem(list, pre, K, t) : 0;
         const double* __restrict__ op = ops + (size_t)e * LO::LEN;
         const bool valid = active && op[LO::VALID] != 0.0;
 
@@ -931,13 +923,15 @@ __global__ __launch_bounds__(256) void k_scatter(int K, double* __restrict__ u,
                                                  const double* __restrict__ compact,
                                                  unsigned long long* __restrict__ tstats) {
     constexpr int NP = Dims<N>::NP;
-    const uint32_t n = min(*count, (uint32_t)K);
+    uint32_t pre[kListSegs + 1];
+    seg_prefix(count, K, pre);
+    const uint32_t n = pre[kListSegs];
     if (tstats != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
         atomicAdd(&tstats[0], (unsigned long long)n);
         atomicAdd(&tstats[1], 1ull);
     }
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const int e = list[t];
+        const int e = seg_elem(list, pre, K, t);
 #pragma unroll
         for (int c = 0; c < M; ++c)
 #pragma unroll
