@@ -229,7 +229,8 @@ int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_
  * of the paper) ------------------------------------------------------------
  * A schedule is int32 [3]: the residual kernel's variant (0 "lean": one
  * face's neighbour data live at a time, 1 "wide": all three faces live,
- * 2 "stream": own coefficients re-read per face), its threads per block
+ * 2 "stream": own coefficients re-read per face, 3 "compact": quadrature
+ * point loops rolled; the default is {3, 128, 1}), its threads per block
  * (64, 128 or 256) and the XCD-contiguous block order (0 off, 1 on).  All
  * schedules compute the same quantities; variants may differ in the last
  * bits (summation order), block size and block order do not change results. */
@@ -237,7 +238,7 @@ int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched);
 int cswdg_get_schedule(const cswdg_solver* s, int32_t* sched);
 /* Time every schedule on the residual of the state u (device, reps timed
  * launches each after one untimed launch), keep the fastest and return it
- * in sched (may be NULL); times_us (host, may be NULL, 18 entries) receives
+ * in sched (may be NULL); times_us (host, may be NULL, 24 entries) receives
  * the mean microseconds per launch in the order variant-major, then block,
  * then XCD order; *n_cand (may be NULL) the number of schedules timed.
  * Synchronous. */

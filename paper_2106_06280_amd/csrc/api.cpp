@@ -273,8 +273,8 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.eps = p.eps_weno;
     // schedule choice for the residual kernel (a tuning knob; same results)
     const char* rv = std::getenv("CSWDG_RESIDUAL_VARIANT");
-    s->ctx.residual_variant = rv ? std::atoi(rv) : 0;
-    s->ctx.residual_block = 256;
+    s->ctx.residual_variant = rv ? std::atoi(rv) : 3;
+    s->ctx.residual_block = 128;
     *out = s;
     return CSWDG_OK;
 }
@@ -642,9 +642,9 @@ int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_
 
 int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched) {
     if (!s || !sched) return fail(s, CSWDG_EINVAL, "null argument");
-    if (sched[0] < 0 || sched[0] > 2 || (sched[1] != 64 && sched[1] != 128 && sched[1] != 256) ||
+    if (sched[0] < 0 || sched[0] > 3 || (sched[1] != 64 && sched[1] != 128 && sched[1] != 256) ||
         (sched[2] != 0 && sched[2] != 1))
-        return fail(s, CSWDG_EINVAL, "schedule: variant 0..2, block 64/128/256, xcd 0/1");
+        return fail(s, CSWDG_EINVAL, "schedule: variant 0..3, block 64/128/256, xcd 0/1");
     s->ctx.residual_variant = sched[0];
     s->ctx.residual_block = sched[1];
     s->dm.xcd_tiles = sched[2];
@@ -663,7 +663,7 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
     int rc = check_ready(s);
     if (rc) return rc;
     if (!u || reps < 1) return fail(s, CSWDG_EINVAL, "autotune needs a state and reps >= 1");
-    const int variants[3] = {0, 1, 2}, blocks[3] = {64, 128, 256}, xcds[2] = {0, 1};
+    const int variants[4] = {0, 1, 2, 3}, blocks[3] = {64, 128, 256}, xcds[2] = {0, 1};
     hipEvent_t ev[2];
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
         return fail(s, CSWDG_EHIP, "hipEventCreate failed");

@@ -157,12 +157,33 @@ struct Phys<0> {
     }
 };
 
+// reciprocal: hardware estimate refined by two Newton-Raphson steps
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+// square root: reciprocal square-root estimate refined by Newton-Raphson
+// (Goldschmidt form), then one correction of the root
+__device__ __forceinline__ double sqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    double h = 0.5 * y;
+    double g = a * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, g, a);
+    return fma(r, h, g);
+}
+
 template <>
 struct Phys<1> {
     static constexpr int M = 4;
     __device__ static __forceinline__ void flux(const double* U, double g, double* F, double* G) {
         double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double ir = 1.0 / rho;
+        double ir = rcp_nr(rho);
         double u = mu * ir, v = mv * ir;
         double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
         F[0] = mu;
@@ -177,15 +198,15 @@ struct Phys<1> {
     __device__ static __forceinline__ void normal_flux(const double* U, double nx, double ny, double g,
                                                        double* Fn, double& lam) {
         double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double ir = 1.0 / rho;
+        double ir = rcp_nr(rho);
         double u = mu * ir, v = mv * ir;
         double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
         double un = u * nx + v * ny;
-        Fn[0] = mu * nx + mv * ny;
-        Fn[1] = (mu * u + p) * nx + (mu * v) * ny;
-        Fn[2] = (mv * u) * nx + (mv * v + p) * ny;
-        Fn[3] = ((E + p) * u) * nx + ((E + p) * v) * ny;
-        lam = fabs(un) + sqrt(g * p * ir);
+        Fn[0] = rho * un;
+        Fn[1] = mu * un + p * nx;
+        Fn[2] = mv * un + p * ny;
+        Fn[3] = (E + p) * un;
+        lam = fabs(un) + sqrt_nr(g * p * ir);
     }
 };
 

@@ -88,7 +88,7 @@ struct LaunchCtx {
     hipStream_t stream;
     int eq, N, precision;
     double gamma, cfl, c_k, eps;
-    int residual_variant;  // residual schedule: 0 lean (default), 1 wide, 2 stream
+    int residual_variant;  // residual schedule: 0 lean, 1 wide, 2 stream, 3 compact (default)
     int residual_block;    // residual threads per block: 64, 128 or 256
 };
 

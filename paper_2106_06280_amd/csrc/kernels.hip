@@ -156,11 +156,11 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
         }
 }
 
-// Three schedules of the same arithmetic (results agree to rounding): "wide"
+// Four schedules of the same arithmetic (results agree to rounding): "wide"
 // keeps the neighbour coefficients of all faces live (one wave per SIMD for
-// P2 Euler), "lean" (the default) bounds the live ranges to one face (two
-// waves per SIMD without spills), "stream" also re-reads the element's own
-// coefficients per face.
+// P2 Euler), "lean" bounds the live ranges to one face (two waves per SIMD
+// without spills), "stream" also re-reads the element's own coefficients per
+// face, "compact" (below, the default) rolls the quadrature-point loops.
 template <int EQ, int N, int MODE>
 __global__ __launch_bounds__(256) void k_residual(DevMesh msh, const double* __restrict__ u,
                                                   const double* __restrict__ un, double* __restrict__ out,
@@ -304,6 +304,139 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
             }
             out[idx] = v;
         }
+}
+
+// "compact" (the default): the lean arithmetic with the quadrature-point
+// loops rolled, which bounds the live registers to the element's own
+// coefficients, the accumulators and one point's values.
+template <int EQ, int N, int MODE>
+__device__ __forceinline__ void residual_body_compact(DevMesh msh, const double* __restrict__ u,
+                                                   const double* __restrict__ un,
+                                                   double* __restrict__ out,
+                                                   const double* __restrict__ dtp, double gamma,
+                                                   uint32_t* __restrict__ cnt_reset) {
+    using D = Dims<N>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
+    const int K = msh.K;
+    const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
+    if (e >= K) return;
+    const Tab<N>& T = tab<N>();
+
+    double U[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) U[c][n] = u[(size_t)(c * NP + n) * K + e];
+
+    double acc[M][NP];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) acc[c][n] = 0.0;
+    {
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        const double xr = 0.5 * (x1 - x0), xs = 0.5 * (x2 - x0);
+        const double yr = 0.5 * (y1 - y0), ys = 0.5 * (y2 - y0);
+        const double iJ = 1.0 / (xr * ys - xs * yr);
+        const double rx = ys * iJ, ry = -xs * iJ, sx = -yr * iJ, sy = xr * iJ;
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            double uq[M], F[M], G[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) s += T.V[q][n] * U[c][n];
+                uq[c] = s;
+            }
+            Phys<EQ>::flux(uq, gamma, F, G);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double fr = rx * F[c] + ry * G[c];
+                const double fs = sx * F[c] + sy * G[c];
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] += T.wDr[q][i] * fr + T.wDs[q][i] * fs;
+            }
+        }
+    }
+
+    const uint32_t info4 = msh.info[e];
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+        const int f1 = (f == 2) ? 0 : f + 1;
+        const double xa = msh.vx[f * K + e], ya = msh.vy[f * K + e];
+        const double xb = msh.vx[f1 * K + e], yb = msh.vy[f1 * K + e];
+        const double ex = xb - xa, ey = yb - ya;
+        const double L = sqrt(ex * ex + ey * ey);
+        const double iL = 1.0 / L;
+        const double nx = ey * iL, ny = -ex * iL;
+        // L_f / (2 J) with 2 J = area; recomputed from the vertices
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        const double J = 0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+        const double sf = 0.5 * L / J;
+        const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+        const bool bnd = (inf & 0x40u) != 0u;
+        const int fp = (int)(inf & 3u);
+        const int nb = bnd ? e : msh.nbr[f * K + e];
+        const int gr = NE - 1;
+#pragma unroll 1
+        for (int g = 0; g < NE; ++g) {
+            double um[M], upg[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double a = 0.0, b = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) {
+                    a += T.PF[f][g][n] * U[c][n];
+                    b += T.PF[fp][gr - g][n] * u[(size_t)(c * NP + n) * K + nb];
+                }
+                um[c] = a;
+                upg[c] = bnd ? a : b;
+            }
+            double Fm[M], Fp[M], lm, lp;
+            Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
+            Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
+            const double alpha = fmax(lm, lp);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
+                const double sFs = sf * Fs;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) acc[c][i] -= T.wPF[f][g][i] * sFs;
+            }
+        }
+    }
+
+    double dt = 0.0;
+    if (MODE != 0) dt = dtp[inst_of(msh, e)];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const size_t idx = (size_t)(c * NP + i) * K + e;
+            double v;
+            if (MODE == 0) {
+                v = acc[c][i];
+            } else if (MODE == 1) {
+                v = U[c][i] + dt * acc[c][i];
+            } else if (MODE == 2) {
+                v = 0.75 * un[idx] + 0.25 * (U[c][i] + dt * acc[c][i]);
+            } else {
+                v = (1.0 / 3.0) * un[idx] + (2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
+            }
+            out[idx] = v;
+        }
+}
+
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256) void k_residual_compact(DevMesh msh, const double* __restrict__ u,
+                                                          const double* __restrict__ un, double* __restrict__ out,
+                                                          const double* __restrict__ dtp, double gamma,
+                                                          uint32_t* __restrict__ cnt_reset) {
+    residual_body_compact<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
 }
 
 template <int EQ, int N, int MODE>
@@ -1012,6 +1145,8 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
             CSWDG_RES_LAUNCH(k_residual)
         } else if (c.residual_variant == 2) {
             CSWDG_RES_LAUNCH(k_residual_stream)
+        } else if (c.residual_variant == 3) {
+            CSWDG_RES_LAUNCH(k_residual_compact)
         } else {
             CSWDG_RES_LAUNCH(k_residual_lean)
         }
