@@ -38,17 +38,19 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 WORKLOADS = {
-    # name: (equation, N, n squares per side, seed, bc)
-    "p2_euler_1m": (1, 2, 707, 1000, 1),
-    "p2_euler_200k": (1, 2, 316, 1002, 1),
-    "p1_burgers_800": (0, 1, 20, 1001, 0),
-    "p3_euler_1m": (1, 3, 707, 1003, 0),
+    # name: (equation, N, n squares per side, seed, bc, precision)
+    "p2_euler_1m": (1, 2, 707, 1000, 1, 0),
+    "p2_euler_200k": (1, 2, 316, 1002, 1, 0),
+    "p2_euler_1m_fp32": (1, 2, 707, 1000, 1, 1),
+    "p2_euler_200k_fp32": (1, 2, 316, 1002, 1, 1),
+    "p1_burgers_800": (0, 1, 20, 1001, 0, 0),
+    "p3_euler_1m": (1, 3, 707, 1003, 0, 0),
 }
 
 
 def make_problem(name):
     from paper_2106_06280_amd import inputs
-    eq, N, n, seed, bc = WORKLOADS[name]
+    eq, N, n, seed, bc, _ = WORKLOADS[name]
     if name.startswith("p1_burgers"):
         v, t = inputs.jittered_mesh(n, 0.0, 2.0, 0.0, 2.0, seed=seed)
         ic = inputs.BurgersSine(a=0.5, b=0.25, k=math.pi)
@@ -316,8 +318,9 @@ def main():
         run_batch(args)
         return
     eq, N, bc, v, t, ic, period = make_problem(args.workload)
+    precision = WORKLOADS[args.workload][5]
     t_setup = time.perf_counter()
-    S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_KXRCF)
+    S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_KXRCF, precision=precision)
     S.mesh_upload(v, t, bc, period)
     u = S.project_fn(ic)
     if cell_mean_ic(args.workload):
@@ -359,7 +362,7 @@ def main():
     if kt:
         tot_ms, cnt = kt["residual_rk"]
         avg = tot_ms / max(cnt, 1) / 1000.0
-        Sb = 8 * Np * m  # bytes of one element's state
+        Sb = (4 if precision == 1 else 8) * Np * m  # bytes of one element's state
         G = 6 * 8 + 3 * 4 + 4  # vertex coordinates, neighbour ids, packed face info
         # per element and stage: read u^(i-1), write u^(i), read u^n on stages
         # 2 and 3, geometry once (neighbour coefficients are the same array)
@@ -369,7 +372,7 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
                 "kernel": "k_residual_compact (volume + surface + LF flux + 1/J + RK combine)",
                 "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_launch)}
-    adj = None if args.no_adjoint else adjoint_ratio(S, u, secs * 1e3 / args.steps)
+    adj = None if (args.no_adjoint or precision == 1) else adjoint_ratio(S, u, secs * 1e3 / args.steps)
     out = {
         "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P2 Euler, 1M tri); adjoint/fwd ratio",
         "value": value,
@@ -381,9 +384,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if precision == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "triangles": K, "degree": N,
+                   "precision": "fp32-bulk (float state and residual, FP64 dt/indicator/limiter)" if precision == 1 else "fp64",
                    "equation": "euler" if eq == 1 else "burgers", "dof": dof,
                    "troubled_fraction": round(f, 5), "limiter": "kxrcf+csweno",
                    "parallelism": "single-gpu"},

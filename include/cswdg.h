@@ -21,8 +21,11 @@
  *
  * State layout (device memory, caller-owned): [m][Np][K] contiguous, element
  * index fastest; m = 1 (Burgers) or 4 (Euler: rho, rho u, rho v, E);
- * Np = (N+1)(N+2)/2; element type double (precision 0, the only one
- * implemented: cswdg_create rejects any other value with CSWDG_EINVAL).
+ * Np = (N+1)(N+2)/2; element type double (precision 0) or float
+ * (precision 1, "FP32-bulk": the state is stored in float and the residual
+ * and RK combine compute in float; dt, the KXRCF indicator and the limiter
+ * compute in double from the float state and the limiter's results are
+ * rounded to float; the adjoint calls take FP64 solvers only).
  *
  * Streams: every call that takes device pointers is enqueued on the
  * solver's HIP stream (given at creation; NULL = default stream) and
@@ -79,7 +82,7 @@ typedef struct cswdg_graph cswdg_graph;
 typedef struct cswdg_params {
     int equation;     /* CSWDG_EQ_BURGERS (eq. 2dBurgers) or CSWDG_EQ_EULER (eq. 2dEulerEquations) */
     int degree;       /* N = 1, 2 or 3 (Section 2, eq. modalForm2D) */
-    int precision;    /* 0 FP64 everywhere; 1 FP32 state/residual/indicator, FP64 limiter */
+    int precision;    /* 0 FP64 everywhere; 1 FP32-bulk: float state and residual, FP64 dt/indicator/limiter */
     int limiter_mode; /* CSWDG_LIMIT_* used by cswdg_ssprk3_step (default KXRCF) */
     double gas_gamma; /* ratio of specific heats, default 1.4 (Section 4) */
     double cfl;       /* default 0.3/(2N+1) */

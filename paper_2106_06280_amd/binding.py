@@ -132,7 +132,8 @@ class Solver:
         h = ctypes.c_void_p()
         _check(lib().cswdg_create(ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None)
         self.h = h
-        self.equation, self.degree = equation, degree
+        self.equation, self.degree, self.precision = equation, degree, precision
+        self.dtype = torch.float32 if precision == 1 else torch.float64
         self.m = 1 if equation == EQ_BURGERS else 4
         self.Np = (degree + 1) * (degree + 2) // 2
         self.K = 0
@@ -197,17 +198,17 @@ class Solver:
 
     # -- state helpers ----------------------------------------------------
     def empty_state(self):
-        return self.torch.empty((self.m, self.Np, self.K), dtype=self.torch.float64, device="cuda")
+        return self.torch.empty((self.m, self.Np, self.K), dtype=self.dtype, device="cuda")
 
     def to_device(self, u_kmn):
         """Oracle layout [K, m, Np] (numpy) -> device layout [m, Np, K]."""
         a = np.ascontiguousarray(np.transpose(np.asarray(u_kmn, dtype=np.float64), (1, 2, 0)))
-        return self.torch.from_numpy(a).to("cuda")
+        return self.torch.from_numpy(a).to(device="cuda", dtype=self.dtype)
 
     @staticmethod
     def to_host(u):
         """Device layout [m, Np, K] -> numpy [K, m, Np]."""
-        return np.ascontiguousarray(np.transpose(u.detach().cpu().numpy(), (2, 0, 1)))
+        return np.ascontiguousarray(np.transpose(u.detach().double().cpu().numpy(), (2, 0, 1)))
 
     def ic_points(self):
         nq = ctypes.c_int32()

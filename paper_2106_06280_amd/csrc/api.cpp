@@ -137,11 +137,14 @@ int check_ready(cswdg_solver* s) {
     return CSWDG_OK;
 }
 
-// the adjoint's tape holds one dt: single-instance meshes only
+// the adjoint's tape holds one dt: single-instance FP64 solvers only
 int check_single(cswdg_solver* s) {
     if (s->n_inst != 1) return fail(s, CSWDG_EINVAL, "adjoint calls take a single-instance mesh");
+    if (s->p.precision != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take an FP64 solver");
     return CSWDG_OK;
 }
+
+size_t elem_bytes(const cswdg_solver* s) { return s->p.precision == 1 ? sizeof(float) : sizeof(double); }
 
 // limit `buf` in place: troubled list from mask or KXRCF, limiter reading
 // `src` (the pre-limit field), scatter into buf
@@ -240,7 +243,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     if (p.equation != CSWDG_EQ_BURGERS && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "equation must be CSWDG_EQ_BURGERS or CSWDG_EQ_EULER");
     if (p.degree < 1 || p.degree > 3) return fail(nullptr, CSWDG_EINVAL, "degree must be 1, 2 or 3");
-    if (p.precision != 0) return fail(nullptr, CSWDG_EINVAL, "only precision 0 (FP64) is implemented");
+    if (p.precision != 0 && p.precision != 1) return fail(nullptr, CSWDG_EINVAL, "precision must be 0 (FP64) or 1 (FP32-bulk)");
     if (p.limiter_mode < 0 || p.limiter_mode > 2) return fail(nullptr, CSWDG_EINVAL, "bad limiter_mode");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
     if (!(p.cfl > 0)) p.cfl = 0.3 / (2 * p.degree + 1);
@@ -440,7 +443,7 @@ int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* 
     int rc = check_ready(s);
     if (rc) return rc;
     if (!u_in || !u_out || u_in == u_out) return fail(s, CSWDG_EINVAL, "u_in and u_out must be distinct non-null buffers");
-    const size_t bytes = sizeof(double) * s->state_elems;
+    const size_t bytes = elem_bytes(s) * s->state_elems;
     hipError_t e = timed(s, KID_COPY, [&] { return hipMemcpyAsync(u_out, u_in, bytes, hipMemcpyDeviceToDevice, s->stream); });
     if (e != hipSuccess) return hipfail(s, e, "copy");
     int mode = mask_in ? CSWDG_LIMIT_KXRCF : (s->p.limiter_mode == CSWDG_LIMIT_ALL ? CSWDG_LIMIT_ALL : CSWDG_LIMIT_KXRCF);
@@ -677,6 +680,12 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
     for (int v : variants)
         for (int b : blocks)
             for (int x : xcds) {
+                if (s->p.precision == 1 && v != 3) {
+                    // FP32-bulk runs the compact schedule only
+                    if (times_us) times_us[k] = INFINITY;
+                    ++k;
+                    continue;
+                }
                 s->ctx.residual_variant = v;
                 s->ctx.residual_block = b;
                 s->dm.xcd_tiles = x;

@@ -48,6 +48,9 @@ struct TabIC {
 __constant__ Tab<1> c_tab1;
 __constant__ Tab<2> c_tab2;
 __constant__ Tab<3> c_tab3;
+__constant__ TabF<1> c_tabf1;
+__constant__ TabF<2> c_tabf2;
+__constant__ TabF<3> c_tabf3;
 __constant__ TabIC<1> c_ic1;
 __constant__ TabIC<2> c_ic2;
 __constant__ TabIC<3> c_ic3;
@@ -60,6 +63,25 @@ template <>
 __device__ __forceinline__ const Tab<2>& tab<2>() { return c_tab2; }
 template <>
 __device__ __forceinline__ const Tab<3>& tab<3>() { return c_tab3; }
+// tables in the residual's arithmetic type
+template <int N, typename R>
+struct TabOf;
+template <int N>
+struct TabOf<N, double> {
+    __device__ static __forceinline__ const Tab<N>& get() { return tab<N>(); }
+};
+template <>
+struct TabOf<1, float> {
+    __device__ static __forceinline__ const TabF<1>& get() { return c_tabf1; }
+};
+template <>
+struct TabOf<2, float> {
+    __device__ static __forceinline__ const TabF<2>& get() { return c_tabf2; }
+};
+template <>
+struct TabOf<3, float> {
+    __device__ static __forceinline__ const TabF<3>& get() { return c_tabf3; }
+};
 template <int N>
 __device__ __forceinline__ const TabIC<N>& tabic();
 template <>
@@ -139,31 +161,19 @@ __device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
 // ---------------------------------------------------------------------------
 // Physics: fluxes and wave speeds (Section 4 eqs. 2dBurgers, 2dEulerEquations)
 // ---------------------------------------------------------------------------
-template <int EQ>
-struct Phys;
-
-template <>
-struct Phys<0> {
-    static constexpr int M = 1;
-    __device__ static __forceinline__ void normal_flux(const double* u, double nx, double ny, double,
-                                                       double* Fn, double& lam) {
-        double h = 0.5 * u[0] * u[0];
-        Fn[0] = h * nx + h * ny;
-        lam = fabs(u[0] * (nx + ny));
-    }
-    __device__ static __forceinline__ void flux(const double* u, double, double* F, double* G) {
-        F[0] = 0.5 * u[0] * u[0];
-        G[0] = F[0];
-    }
-};
-
-// reciprocal: hardware estimate refined by two Newton-Raphson steps
+// reciprocal: hardware estimate refined by Newton-Raphson (two steps in
+// double, one in single precision)
 __device__ __forceinline__ double rcp_nr(double x) {
     double r = __builtin_amdgcn_rcp(x);
     double e = fma(-x, r, 1.0);
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
 }
 // square root: reciprocal square-root estimate refined by Newton-Raphson
 // (Goldschmidt form), then one correction of the root
@@ -177,15 +187,40 @@ __device__ __forceinline__ double sqrt_nr(double a) {
     r = fma(-g, g, a);
     return fma(r, h, g);
 }
+__device__ __forceinline__ float sqrt_nr(float a) { return __builtin_sqrtf(a); }
+__device__ __forceinline__ double abs_r(double a) { return fabs(a); }
+__device__ __forceinline__ float abs_r(float a) { return fabsf(a); }
+__device__ __forceinline__ double max_r(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float max_r(float a, float b) { return fmaxf(a, b); }
+
+template <int EQ>
+struct Phys;
+
+template <>
+struct Phys<0> {
+    static constexpr int M = 1;
+    template <typename R>
+    __device__ static __forceinline__ void normal_flux(const R* u, R nx, R ny, R, R* Fn, R& lam) {
+        R h = R(0.5) * u[0] * u[0];
+        Fn[0] = h * nx + h * ny;
+        lam = abs_r(u[0] * (nx + ny));
+    }
+    template <typename R>
+    __device__ static __forceinline__ void flux(const R* u, R, R* F, R* G) {
+        F[0] = R(0.5) * u[0] * u[0];
+        G[0] = F[0];
+    }
+};
 
 template <>
 struct Phys<1> {
     static constexpr int M = 4;
-    __device__ static __forceinline__ void flux(const double* U, double g, double* F, double* G) {
-        double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double ir = rcp_nr(rho);
-        double u = mu * ir, v = mv * ir;
-        double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+    template <typename R>
+    __device__ static __forceinline__ void flux(const R* U, R g, R* F, R* G) {
+        R rho = U[0], mu = U[1], mv = U[2], E = U[3];
+        R ir = rcp_nr(rho);
+        R u = mu * ir, v = mv * ir;
+        R p = (g - R(1)) * (E - R(0.5) * rho * (u * u + v * v));
         F[0] = mu;
         F[1] = mu * u + p;
         F[2] = mv * u;
@@ -195,18 +230,18 @@ struct Phys<1> {
         G[2] = mv * v + p;
         G[3] = (E + p) * v;
     }
-    __device__ static __forceinline__ void normal_flux(const double* U, double nx, double ny, double g,
-                                                       double* Fn, double& lam) {
-        double rho = U[0], mu = U[1], mv = U[2], E = U[3];
-        double ir = rcp_nr(rho);
-        double u = mu * ir, v = mv * ir;
-        double p = (g - 1.0) * (E - 0.5 * rho * (u * u + v * v));
-        double un = u * nx + v * ny;
+    template <typename R>
+    __device__ static __forceinline__ void normal_flux(const R* U, R nx, R ny, R g, R* Fn, R& lam) {
+        R rho = U[0], mu = U[1], mv = U[2], E = U[3];
+        R ir = rcp_nr(rho);
+        R u = mu * ir, v = mv * ir;
+        R p = (g - R(1)) * (E - R(0.5) * rho * (u * u + v * v));
+        R un = u * nx + v * ny;
         Fn[0] = rho * un;
         Fn[1] = mu * un + p * nx;
         Fn[2] = mv * un + p * ny;
         Fn[3] = (E + p) * un;
-        lam = fabs(un) + sqrt_nr(g * p * ir);
+        lam = abs_r(un) + sqrt_nr(g * p * ir);
     }
 };
 
@@ -279,6 +314,23 @@ void fill_ic(TabIC<N>& t) {
 
 inline unsigned grid_for(int K, int bs) { return (unsigned)((K + bs - 1) / bs); }
 
+template <int N>
+void to_float(const Tab<N>& t, TabF<N>& f) {
+    using D = Dims<N>;
+    for (int q = 0; q < D::NQ; ++q)
+        for (int n = 0; n < D::NP; ++n) {
+            f.V[q][n] = (float)t.V[q][n];
+            f.wDr[q][n] = (float)t.wDr[q][n];
+            f.wDs[q][n] = (float)t.wDs[q][n];
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int g = 0; g < D::NE; ++g)
+            for (int n = 0; n < D::NP; ++n) {
+                f.PF[a][g][n] = (float)t.PF[a][g][n];
+                f.wPF[a][g][n] = (float)t.wPF[a][g][n];
+            }
+}
+
 inline int upload_tables_here() {
     static Tab<1> t1;
     static Tab<2> t2;
@@ -299,6 +351,15 @@ inline int upload_tables_here() {
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab1), &t1, sizeof(t1)) != hipSuccess) return CSWDG_EHIP;
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab2), &t2, sizeof(t2)) != hipSuccess) return CSWDG_EHIP;
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_tab3), &t3, sizeof(t3)) != hipSuccess) return CSWDG_EHIP;
+    static TabF<1> f1;
+    static TabF<2> f2;
+    static TabF<3> f3;
+    to_float(t1, f1);
+    to_float(t2, f2);
+    to_float(t3, f3);
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tabf1), &f1, sizeof(f1)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tabf2), &f2, sizeof(f2)) != hipSuccess) return CSWDG_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_tabf3), &f3, sizeof(f3)) != hipSuccess) return CSWDG_EHIP;
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic1), &i1, sizeof(i1)) != hipSuccess) return CSWDG_EHIP;
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic2), &i2, sizeof(i2)) != hipSuccess) return CSWDG_EHIP;
     if (hipMemcpyToSymbol(HIP_SYMBOL(c_ic3), &i3, sizeof(i3)) != hipSuccess) return CSWDG_EHIP;
@@ -316,6 +377,18 @@ inline int upload_tables_here() {
         else if ((EQV) == 1 && (NV) == 2) { constexpr int EQ = 1, N = 2; __VA_ARGS__; } \
         else if ((EQV) == 1 && (NV) == 3) { constexpr int EQ = 1, N = 3; __VA_ARGS__; } \
         else return hipErrorInvalidValue;                       \
+    } while (0)
+
+// the same with the state's storage type S (double, or float for FP32-bulk)
+#define CSWDG_DISPATCH_ENP(EQV, NV, PV, ...)                  \
+    do {                                                      \
+        if ((PV) == 1) {                                      \
+            using S = float;                                  \
+            CSWDG_DISPATCH_EN(EQV, NV, __VA_ARGS__);          \
+        } else {                                              \
+            using S = double;                                 \
+            CSWDG_DISPATCH_EN(EQV, NV, __VA_ARGS__);          \
+        }                                                     \
     } while (0)
 
 }  // namespace cswdg

@@ -309,10 +309,10 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
 // "compact" (the default): the lean arithmetic with the quadrature-point
 // loops rolled, which bounds the live registers to the element's own
 // coefficients, the accumulators and one point's values.
-template <int EQ, int N, int MODE>
-__device__ __forceinline__ void residual_body_compact(DevMesh msh, const double* __restrict__ u,
-                                                   const double* __restrict__ un,
-                                                   double* __restrict__ out,
+template <int EQ, int N, int MODE, typename R>
+__device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __restrict__ u,
+                                                   const R* __restrict__ un,
+                                                   R* __restrict__ out,
                                                    const double* __restrict__ dtp, double gamma,
                                                    uint32_t* __restrict__ cnt_reset) {
     using D = Dims<N>;
@@ -321,41 +321,42 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const double*
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
-    const Tab<N>& T = tab<N>();
+    const auto& T = TabOf<N, R>::get();
+    const R gm = (R)gamma;
 
-    double U[M][NP];
+    R U[M][NP];
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
         for (int n = 0; n < NP; ++n) U[c][n] = u[(size_t)(c * NP + n) * K + e];
 
-    double acc[M][NP];
+    R acc[M][NP];
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
-        for (int n = 0; n < NP; ++n) acc[c][n] = 0.0;
+        for (int n = 0; n < NP; ++n) acc[c][n] = R(0);
     {
         const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
         const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
         const double xr = 0.5 * (x1 - x0), xs = 0.5 * (x2 - x0);
         const double yr = 0.5 * (y1 - y0), ys = 0.5 * (y2 - y0);
         const double iJ = 1.0 / (xr * ys - xs * yr);
-        const double rx = ys * iJ, ry = -xs * iJ, sx = -yr * iJ, sy = xr * iJ;
+        const R rx = (R)(ys * iJ), ry = (R)(-xs * iJ), sx = (R)(-yr * iJ), sy = (R)(xr * iJ);
 #pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
-            double uq[M], F[M], G[M];
+            R uq[M], F[M], G[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                double s = 0.0;
+                R s = R(0);
 #pragma unroll
                 for (int n = 0; n < NP; ++n) s += T.V[q][n] * U[c][n];
                 uq[c] = s;
             }
-            Phys<EQ>::flux(uq, gamma, F, G);
+            Phys<EQ>::flux(uq, gm, F, G);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const double fr = rx * F[c] + ry * G[c];
-                const double fs = sx * F[c] + sy * G[c];
+                const R fr = rx * F[c] + ry * G[c];
+                const R fs = sx * F[c] + sy * G[c];
 #pragma unroll
                 for (int i = 0; i < NP; ++i) acc[c][i] += T.wDr[q][i] * fr + T.wDs[q][i] * fs;
             }
@@ -371,12 +372,12 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const double*
         const double ex = xb - xa, ey = yb - ya;
         const double L = sqrt(ex * ex + ey * ey);
         const double iL = 1.0 / L;
-        const double nx = ey * iL, ny = -ex * iL;
+        const R nx = (R)(ey * iL), ny = (R)(-ex * iL);
         // L_f / (2 J) with 2 J = area; recomputed from the vertices
         const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
         const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
         const double J = 0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
-        const double sf = 0.5 * L / J;
+        const R sf = (R)(0.5 * L / J);
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
         const int fp = (int)(inf & 3u);
@@ -384,10 +385,10 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const double*
         const int gr = NE - 1;
 #pragma unroll 1
         for (int g = 0; g < NE; ++g) {
-            double um[M], upg[M];
+            R um[M], upg[M];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                double a = 0.0, b = 0.0;
+                R a = R(0), b = R(0);
 #pragma unroll
                 for (int n = 0; n < NP; ++n) {
                     a += T.PF[f][g][n] * U[c][n];
@@ -396,47 +397,55 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const double*
                 um[c] = a;
                 upg[c] = bnd ? a : b;
             }
-            double Fm[M], Fp[M], lm, lp;
-            Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
-            Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
-            const double alpha = fmax(lm, lp);
+            R Fm[M], Fp[M], lm, lp;
+            Phys<EQ>::normal_flux(um, nx, ny, gm, Fm, lm);
+            Phys<EQ>::normal_flux(upg, nx, ny, gm, Fp, lp);
+            const R alpha = max_r(lm, lp);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
-                const double sFs = sf * Fs;
+                const R Fs = R(0.5) * (Fm[c] + Fp[c]) - R(0.5) * alpha * (upg[c] - um[c]);
+                const R sFs = sf * Fs;
 #pragma unroll
                 for (int i = 0; i < NP; ++i) acc[c][i] -= T.wPF[f][g][i] * sFs;
             }
         }
     }
 
-    double dt = 0.0;
-    if (MODE != 0) dt = dtp[inst_of(msh, e)];
+    R dt = R(0);
+    if (MODE != 0) dt = (R)dtp[inst_of(msh, e)];
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
             const size_t idx = (size_t)(c * NP + i) * K + e;
-            double v;
+            R v;
             if (MODE == 0) {
                 v = acc[c][i];
             } else if (MODE == 1) {
                 v = U[c][i] + dt * acc[c][i];
             } else if (MODE == 2) {
-                v = 0.75 * un[idx] + 0.25 * (U[c][i] + dt * acc[c][i]);
+                v = R(0.75) * un[idx] + R(0.25) * (U[c][i] + dt * acc[c][i]);
             } else {
-                v = (1.0 / 3.0) * un[idx] + (2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
+                v = R(1.0 / 3.0) * un[idx] + R(2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
             }
             out[idx] = v;
         }
 }
 
-template <int EQ, int N, int MODE>
-__global__ __launch_bounds__(256) void k_residual_compact(DevMesh msh, const double* __restrict__ u,
-                                                          const double* __restrict__ un, double* __restrict__ out,
+template <int EQ, int N, int MODE, typename R>
+__global__ __launch_bounds__(256) void k_residual_compact(DevMesh msh, const R* __restrict__ u,
+                                                          const R* __restrict__ un, R* __restrict__ out,
                                                           const double* __restrict__ dtp, double gamma,
                                                           uint32_t* __restrict__ cnt_reset) {
-    residual_body_compact<EQ, N, MODE>(msh, u, un, out, dtp, gamma, cnt_reset);
+    residual_body_compact<EQ, N, MODE, R>(msh, u, un, out, dtp, gamma, cnt_reset);
+}
+
+template <int EQ, int N, int MODE>
+__global__ __launch_bounds__(256) void k_residual_compact_d(DevMesh msh, const double* __restrict__ u,
+                                                            const double* __restrict__ un, double* __restrict__ out,
+                                                            const double* __restrict__ dtp, double gamma,
+                                                            uint32_t* __restrict__ cnt_reset) {
+    residual_body_compact<EQ, N, MODE, double>(msh, u, un, out, dtp, gamma, cnt_reset);
 }
 
 template <int EQ, int N, int MODE>
@@ -599,8 +608,8 @@ __global__ __launch_bounds__(256) void k_residual_stream(DevMesh msh, const doub
 // ---------------------------------------------------------------------------
 // Time step: cell-mean wave speeds (block maxima, then one block)
 // ---------------------------------------------------------------------------
-template <int EQ, int N>
-__global__ __launch_bounds__(256) void k_dt_partial(int K, const double* __restrict__ u,
+template <int EQ, int N, typename S>
+__global__ __launch_bounds__(256) void k_dt_partial(int K, const S* __restrict__ u,
                                                     double gamma, double* __restrict__ partial,
                                                     uint32_t* __restrict__ status) {
     constexpr int NP = Dims<N>::NP, M = Phys<EQ>::M;
@@ -656,8 +665,8 @@ __global__ __launch_bounds__(256) void k_dt_final(int nblocks, const double* __r
 // pattern (monotone for non-negative doubles); a wave spanning an instance
 // boundary falls back to one atomic per lane. Non-finite speeds are skipped
 // (and flagged), as fmax does in the single-mesh reduction.
-template <int EQ, int N>
-__global__ __launch_bounds__(256) void k_dt_inst(DevMesh msh, const double* __restrict__ u, double gamma,
+template <int EQ, int N, typename S>
+__global__ __launch_bounds__(256) void k_dt_inst(DevMesh msh, const S* __restrict__ u, double gamma,
                                                  unsigned long long* __restrict__ amax_bits,
                                                  uint32_t* __restrict__ status) {
     constexpr int NP = Dims<N>::NP, M = Phys<EQ>::M;
@@ -709,8 +718,8 @@ __global__ __launch_bounds__(256) void k_dt_inst_final(int n, unsigned long long
 // KXRCF indicator + compaction (Section 3.1)
 // ---------------------------------------------------------------------------
 
-template <int EQ, int N>
-__global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const double* __restrict__ u,
+template <int EQ, int N, typename S>
+__global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict__ u,
                                                uint8_t* __restrict__ flags, double* __restrict__ Rout,
                                                int32_t* __restrict__ list,
                                                uint32_t* __restrict__ count, double ck) {
@@ -814,8 +823,8 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // ---------------------------------------------------------------------------
 // CSWENO limiter (Section 3.2)
 // ---------------------------------------------------------------------------
-template <int EQ, int N>
-__global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __restrict__ u,
+template <int EQ, int N, typename S>
+__global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict__ u,
                                                 const double* __restrict__ ops,
                                                 const int32_t* __restrict__ list,
                                                 const uint32_t* __restrict__ count,
@@ -1049,8 +1058,8 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const double* __res
     }
 }
 
-template <int N, int M>
-__global__ __launch_bounds__(256) void k_scatter(int K, double* __restrict__ u,
+template <int N, int M, typename S>
+__global__ __launch_bounds__(256) void k_scatter(int K, S* __restrict__ u,
                                                  const int32_t* __restrict__ list,
                                                  const uint32_t* __restrict__ count,
                                                  const double* __restrict__ compact,
@@ -1068,7 +1077,7 @@ __global__ __launch_bounds__(256) void k_scatter(int K, double* __restrict__ u,
 #pragma unroll
         for (int c = 0; c < M; ++c)
 #pragma unroll
-            for (int i = 1; i < NP; ++i) u[(size_t)(c * NP + i) * K + e] = compact[(size_t)t * (M * NP) + c * NP + i];
+            for (int i = 1; i < NP; ++i) u[(size_t)(c * NP + i) * K + e] = (S)compact[(size_t)t * (M * NP) + c * NP + i];
     }
 }
 
@@ -1091,9 +1100,9 @@ __global__ __launch_bounds__(256) void k_ic_points(DevMesh msh, double* __restri
     }
 }
 
-template <int N>
+template <int N, typename S>
 __global__ __launch_bounds__(256) void k_project(int K, int m, const double* __restrict__ vals,
-                                                 double* __restrict__ u) {
+                                                 S* __restrict__ u) {
     constexpr int NQI = Dims<N>::NQI, NP = Dims<N>::NP;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= K) return;
@@ -1108,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_project(int K, int m, const double* __r
             for (int n = 0; n < NP; ++n) acc[n] += T.wV[q][n] * v;
         }
 #pragma unroll
-        for (int n = 0; n < NP; ++n) u[(size_t)(c * NP + n) * K + e] = acc[n];
+        for (int n = 0; n < NP; ++n) u[(size_t)(c * NP + n) * K + e] = (S)acc[n];
     }
 }
 
@@ -1140,13 +1149,29 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
         case 3: KERN<EQ, N, 3><<<g, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break; \
         default: return hipErrorInvalidValue;                                                    \
     }
+    if (c.precision == 1) {
+        // FP32-bulk: single-precision state and arithmetic, compact schedule
+        const float* UF = (const float*)u;
+        const float* UNF = (const float*)un;
+        float* OF = (float*)out;
+        CSWDG_DISPATCH_EN(c.eq, c.N, {
+            switch (mode) {
+                case 0: k_residual_compact<EQ, N, 0, float><<<g, bs, 0, c.stream>>>(m, UF, UNF, OF, dt, c.gamma, reset); break;
+                case 1: k_residual_compact<EQ, N, 1, float><<<g, bs, 0, c.stream>>>(m, UF, UNF, OF, dt, c.gamma, reset); break;
+                case 2: k_residual_compact<EQ, N, 2, float><<<g, bs, 0, c.stream>>>(m, UF, UNF, OF, dt, c.gamma, reset); break;
+                case 3: k_residual_compact<EQ, N, 3, float><<<g, bs, 0, c.stream>>>(m, UF, UNF, OF, dt, c.gamma, reset); break;
+                default: return hipErrorInvalidValue;
+            }
+        });
+        return hipGetLastError();
+    }
     CSWDG_DISPATCH_EN(c.eq, c.N, {
         if (c.residual_variant == 1) {
             CSWDG_RES_LAUNCH(k_residual)
         } else if (c.residual_variant == 2) {
             CSWDG_RES_LAUNCH(k_residual_stream)
         } else if (c.residual_variant == 3) {
-            CSWDG_RES_LAUNCH(k_residual_compact)
+            CSWDG_RES_LAUNCH(k_residual_compact_d)
         } else {
             CSWDG_RES_LAUNCH(k_residual_lean)
         }
@@ -1157,9 +1182,8 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
 
 hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, double hmin, double* dt,
                          double* partial, uint32_t*, uint32_t* status, int nblocks) {
-    const double* U = (const double*)u;
-    CSWDG_DISPATCH_EN(c.eq, c.N, {
-        k_dt_partial<EQ, N><<<nblocks, 256, 0, c.stream>>>(m.K, U, c.gamma, partial, status);
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_dt_partial<EQ, N, S><<<nblocks, 256, 0, c.stream>>>(m.K, (const S*)u, c.gamma, partial, status);
     });
     k_dt_final<<<1, 256, 0, c.stream>>>(nblocks, partial, c.cfl, hmin, dt);
     return hipGetLastError();
@@ -1167,9 +1191,10 @@ hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, do
 
 hipError_t launch_max_dt_inst(const LaunchCtx& c, const DevMesh& m, const void* u, const double* hmin,
                               double* dt, unsigned long long* amax_bits, uint32_t* status) {
-    const double* U = (const double*)u;
     const unsigned g = grid_for(m.K, 256);
-    CSWDG_DISPATCH_EN(c.eq, c.N, { k_dt_inst<EQ, N><<<g, 256, 0, c.stream>>>(m, U, c.gamma, amax_bits, status); });
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_dt_inst<EQ, N, S><<<g, 256, 0, c.stream>>>(m, (const S*)u, c.gamma, amax_bits, status);
+    });
     k_dt_inst_final<<<grid_for(m.n_inst, 256), 256, 0, c.stream>>>(m.n_inst, amax_bits, c.cfl, hmin, dt);
     return hipGetLastError();
 }
@@ -1177,8 +1202,9 @@ hipError_t launch_max_dt_inst(const LaunchCtx& c, const DevMesh& m, const void* 
 hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags, double* R,
                         int32_t* list, uint32_t* count) {
     const unsigned bs = 256, g = grid_for(m.K, bs);
-    const double* U = (const double*)u;
-    CSWDG_DISPATCH_EN(c.eq, c.N, { k_kxrcf<EQ, N><<<g, bs, 0, c.stream>>>(m, U, flags, R, list, count, c.c_k); });
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_kxrcf<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, flags, R, list, count, c.c_k);
+    });
     return hipGetLastError();
 }
 
@@ -1201,9 +1227,8 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
     unsigned g = grid_for(max_cells, bs / lpc);
     if (g > 16384u) g = 16384u;
     if (g == 0) g = 1;
-    const double* U = (const double*)u;
-    CSWDG_DISPATCH_EN(c.eq, c.N, {
-        k_limiter<EQ, N><<<g, bs, 0, c.stream>>>(m, U, ops, list, count, compact, status, c.gamma, c.eps);
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_limiter<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma, c.eps);
     });
     return hipGetLastError();
 }
@@ -1214,9 +1239,8 @@ hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* lis
     unsigned g = grid_for(max_cells, bs);
     if (g > 4096u) g = 4096u;
     if (g == 0) g = 1;
-    double* U = (double*)u;
-    CSWDG_DISPATCH_EN(c.eq, c.N, {
-        k_scatter<N, Phys<EQ>::M><<<g, bs, 0, c.stream>>>(K, U, list, count, compact, tstats);
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_scatter<N, Phys<EQ>::M, S><<<g, bs, 0, c.stream>>>(K, (S*)u, list, count, compact, tstats);
     });
     return hipGetLastError();
 }
@@ -1233,11 +1257,9 @@ hipError_t launch_ic_points(const LaunchCtx& c, const DevMesh& m, double* xy) {
 hipError_t launch_project(const LaunchCtx& c, const DevMesh& m, const double* vals, void* u) {
     const unsigned g = grid_for(m.K, 256);
     const int mv = c.eq == 0 ? 1 : 4;
-    double* U = (double*)u;
-    if (c.N == 1) k_project<1><<<g, 256, 0, c.stream>>>(m.K, mv, vals, U);
-    else if (c.N == 2) k_project<2><<<g, 256, 0, c.stream>>>(m.K, mv, vals, U);
-    else if (c.N == 3) k_project<3><<<g, 256, 0, c.stream>>>(m.K, mv, vals, U);
-    else return hipErrorInvalidValue;
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_project<N, S><<<g, 256, 0, c.stream>>>(m.K, mv, vals, (S*)u);
+    });
     return hipGetLastError();
 }
 

@@ -41,6 +41,17 @@ struct Tab {
     double wmean[D::NP];         // mean of psi_n over the reference triangle
 };
 
+// The residual's tables in single precision (FP32-bulk mode).
+template <int N>
+struct TabF {
+    using D = Dims<N>;
+    float V[D::NQ][D::NP];
+    float wDr[D::NQ][D::NP];
+    float wDs[D::NQ][D::NP];
+    float PF[3][D::NE][D::NP];
+    float wPF[3][D::NE][D::NP];
+};
+
 // Layout of the per-element limiter operator record (doubles).
 template <int N>
 struct OpLayout {
