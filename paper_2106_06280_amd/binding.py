@@ -149,6 +149,32 @@ class Solver:
     def _c(self, rc):
         _check(rc, self.h)
 
+    # -- argument checks (the C ABI takes raw pointers and cannot check sizes) --
+    def _n_inst(self):
+        if not hasattr(self, "_ninst"):
+            self._ninst = len(self.instances()) - 1
+        return self._ninst
+
+    def _dev(self, t, name, shape, dtype):
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected a contiguous CUDA tensor {tuple(shape)} {dtype}, "
+                             f"got {tuple(t.shape)} {t.dtype} (cuda={t.is_cuda}, contiguous={t.is_contiguous()})")
+        return t
+
+    def _st(self, t, name="state"):
+        return self._dev(t, name, (self.m, self.Np, self.K), self.dtype)
+
+    def _dt(self, t, name="dt"):
+        return self._dev(t, name, (self._n_inst(),), self.torch.float64)
+
+    def _mask(self, m):
+        if m is None:
+            return None
+        m = m.to(device="cuda", dtype=self.torch.uint8).contiguous()
+        return self._dev(m, "mask", (self.K,), self.torch.uint8)
+
     # -- mesh ------------------------------------------------------------
     def mesh_upload(self, vxy, tri, bc, period=(0.0, 0.0)):
         vxy = np.ascontiguousarray(vxy, dtype=np.float64)
@@ -156,6 +182,7 @@ class Solver:
         self._c(lib().cswdg_mesh_upload(self.h, vxy.shape[0], vxy.ctypes.data, tri.shape[0], tri.ctypes.data,
                                         bc, float(period[0]), float(period[1])))
         self.K = tri.shape[0]
+        self.__dict__.pop("_ninst", None)
 
     def mesh_upload_batch(self, meshes, bcs, period=(1.0, 1.0)):
         """meshes: list of (vxy [nv][2], tri [nt][3]) with instance-local vertex
@@ -170,6 +197,7 @@ class Solver:
         self._c(lib().cswdg_mesh_upload_batch(self.h, len(meshes), nv.ctypes.data, vxy.ctypes.data, nt.ctypes.data,
                                               tri.ctypes.data, bc.ctypes.data, float(period[0]), float(period[1])))
         self.K = int(nt.sum())
+        self.__dict__.pop("_ninst", None)
 
     def instances(self):
         """Instance offsets (numpy int64 [n_inst + 1])."""
@@ -219,7 +247,9 @@ class Solver:
 
     def project(self, vals):
         """vals [m, nq, K] device double -> coefficients."""
-        vals = vals.contiguous()
+        nq = ctypes.c_int32()
+        self._c(lib().cswdg_ic_points(self.h, None, ctypes.byref(nq)))
+        vals = self._dev(vals.contiguous(), "vals", (self.m, nq.value, self.K), self.torch.float64)
         u = self.empty_state()
         self._c(lib().cswdg_project(self.h, _ptr(vals), _ptr(u)))
         return u
@@ -232,24 +262,31 @@ class Solver:
             v = v[None]
         else:
             v = np.moveaxis(v, -1, 0)
+        if v.shape[0] != self.m:
+            raise ValueError(f"fn returns {v.shape[0]} variable(s); this solver has {self.m}")
         return self.project(self.torch.from_numpy(np.ascontiguousarray(v)).to("cuda"))
 
     # -- operators --------------------------------------------------------
     def dg_residual(self, u, r=None):
         if r is None:
             r = self.empty_state()
+        self._st(u, "u")
+        self._st(r, "r")
         self._c(lib().cswdg_dg_residual(self.h, _ptr(u), _ptr(r)))
         return r
 
     def max_dt(self, u, dt=None):
         if dt is None:
-            dt = self.torch.zeros(len(self.instances()) - 1, dtype=self.torch.float64, device="cuda")
+            dt = self.torch.zeros(self._n_inst(), dtype=self.torch.float64, device="cuda")
+        self._st(u, "u")
+        self._dt(dt)
         self._c(lib().cswdg_max_dt(self.h, _ptr(u), _ptr(dt)))
         return dt
 
     def kxrcf(self, u, want_R=True):
         flags = self.torch.zeros(self.K, dtype=self.torch.uint8, device="cuda")
         R = self.torch.zeros(self.K, dtype=self.torch.float64, device="cuda") if want_R else None
+        self._st(u, "u")
         self._c(lib().cswdg_kxrcf(self.h, _ptr(u), _ptr(flags), _ptr(R)))
         return flags, R
 
@@ -257,17 +294,25 @@ class Solver:
         if u_out is None:
             u_out = self.empty_state()
         flags = self.torch.zeros(self.K, dtype=self.torch.uint8, device="cuda")
-        m = None
-        if mask is not None:
-            m = mask.to(device="cuda", dtype=self.torch.uint8).contiguous()
+        m = self._mask(mask)
+        self._st(u_in, "u_in")
+        self._st(u_out, "u_out")
         self._c(lib().cswdg_csweno_limit(self.h, _ptr(u_in), _ptr(u_out), _ptr(flags), _ptr(m)))
         return u_out, flags
 
     def rk_stage(self, stage, u_n, u_prev, out, dt):
+        if int(stage) > 1:
+            self._st(u_n, "u_n")
+        self._st(u_prev, "u_prev")
+        self._st(out, "out")
+        self._dt(dt)
         self._c(lib().cswdg_rk_stage(self.h, int(stage), _ptr(u_n), _ptr(u_prev), _ptr(out), _ptr(dt)))
         return out
 
     def ssprk3_step(self, u, dt=None):
+        self._st(u, "u")
+        if dt is not None:
+            self._dt(dt)
         self._c(lib().cswdg_ssprk3_step(self.h, _ptr(u), _ptr(dt)))
         return u
 
@@ -275,13 +320,19 @@ class Solver:
     def dg_residual_vjp(self, u, r_bar, u_bar=None):
         if u_bar is None:
             u_bar = self.empty_state()
+        self._st(u, "u")
+        self._st(r_bar, "r_bar")
+        self._st(u_bar, "u_bar")
         self._c(lib().cswdg_dg_residual_vjp(self.h, _ptr(u), _ptr(r_bar), _ptr(u_bar)))
         return u_bar
 
     def csweno_limit_vjp(self, w, y_bar, mask=None, w_bar=None):
         if w_bar is None:
             w_bar = self.empty_state()
-        m = None if mask is None else mask.to(device="cuda", dtype=self.torch.uint8).contiguous()
+        m = self._mask(mask)
+        self._st(w, "w")
+        self._st(y_bar, "y_bar")
+        self._st(w_bar, "w_bar")
         self._c(lib().cswdg_csweno_limit_vjp(self.h, _ptr(w), _ptr(m), _ptr(y_bar), _ptr(w_bar)))
         return w_bar
 
@@ -295,13 +346,25 @@ class Solver:
         n = tape.numel()
         return tape[n - 256:n - 248].view(self.torch.float64)
 
+    def _tape(self, tape):
+        n = _I64()
+        self._c(lib().cswdg_tape_bytes(self.h, ctypes.byref(n)))
+        return self._dev(tape, "tape", (n.value,), self.torch.uint8)
+
     def ssprk3_step_tape(self, u, tape, dt=None, replay=False):
+        self._st(u, "u")
+        self._tape(tape)
+        if dt is not None:
+            self._dt(dt)
         self._c(lib().cswdg_ssprk3_step_tape(self.h, _ptr(u), _ptr(dt), _ptr(tape), 1 if replay else 0))
         return u
 
     def ssprk3_step_vjp(self, tape, y_bar, u_bar=None):
         if u_bar is None:
             u_bar = self.empty_state()
+        self._tape(tape)
+        self._st(y_bar, "y_bar")
+        self._st(u_bar, "u_bar")
         self._c(lib().cswdg_ssprk3_step_vjp(self.h, _ptr(tape), _ptr(y_bar), _ptr(u_bar)))
         return u_bar
 
@@ -341,6 +404,7 @@ class Solver:
         a = np.zeros(3, np.int32)
         t = np.zeros(24, np.float64)
         n = ctypes.c_int32()
+        self._st(u, "u")
         self._c(lib().cswdg_autotune(self.h, _ptr(u), int(reps), a.ctypes.data, t.ctypes.data, ctypes.byref(n)))
         cands = [(v, b, x) for v in (0, 1, 2, 3) for b in (64, 128, 256) for x in (0, 1)]
         return tuple(int(x) for x in a), {c: float(t[i]) for i, c in enumerate(cands[: n.value])}

@@ -214,3 +214,29 @@ def test_mass_conserved_by_limited_step(torch):
         S.ssprk3_step(ud)
     m1 = (ud[:, 0, :].double() * torch.from_numpy(M.J).cuda()).sum(dim=1)
     assert torch.all(torch.abs(m1 - m0) <= 1e-13 * torch.abs(m0).clamp(min=1.0))
+
+
+def test_binding_rejects_mismatched_buffers(torch):
+    """The C ABI takes raw pointers; the binding checks every buffer's shape,
+    dtype and device before a launch (a scalar function projected with an
+    Euler solver, a state of the wrong size or type)."""
+    M, dg, S = _case(1, 2, 6, BC_PERIODIC, seed=5)
+    with pytest.raises(ValueError):
+        S.project_fn(lambda x, y: 1.0 + 0.0 * x)
+    with pytest.raises(ValueError):
+        S.project(torch.zeros((1, 36, M.K), dtype=torch.float64, device="cuda"))
+    u = S.to_device(_smooth_state(dg, 1, seed=1))
+    with pytest.raises(ValueError):
+        S.dg_residual(u[:, :, :-1].contiguous())
+    with pytest.raises(ValueError):
+        S.dg_residual(u.float())
+    with pytest.raises(ValueError):
+        S.ssprk3_step(u.cpu())
+    with pytest.raises(ValueError):
+        S.csweno_limit(u, mask=torch.ones(M.K + 1, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        S.rk_stage(1, None, u, torch.empty_like(u), torch.zeros(2, dtype=torch.float64, device="cuda"))
+    # nothing was launched: the state is untouched and the solver still works
+    assert torch.equal(u, S.to_device(_smooth_state(dg, 1, seed=1)))
+    S.ssprk3_step(u)
+    assert S.status() & 0x3 == 0
