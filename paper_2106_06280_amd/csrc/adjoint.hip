@@ -315,7 +315,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                 Lr[c] = a;
                 Rc[c] = bb;
             }
-#pragma unroll
+#pragma unroll 1
             for (int cc = 0; cc < 4; ++cc) {
                 Dual U4[4], Ld[4][4], Rd[4][4];
 #pragma unroll
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
 #pragma unroll
         for (int jj = 0; jj < NM; ++jj) c5[jj] = 0.0;
         if constexpr (N >= 2) {
-#pragma unroll
+#pragma unroll 1
             for (int jj = 0; jj < 14; ++jj) {
                 double s = 0.0;
 #pragma unroll
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             Rcb[c] = s / ND;
         }
         double Rcoefb[NM];
-#pragma unroll
+#pragma unroll 1
         for (int jj = 0; jj < NM; ++jj) {
             double s = 0.0;
 #pragma unroll
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             }
         }
         // beta of q_l: c^T B c over the leading blocks -> 2 beta_bar B c
-#pragma unroll
+#pragma unroll 1
         for (int i = 0; i < NM; ++i) {
             double s5 = 0.0, s3v = 0.0, s2v = 0.0;
 #pragma unroll
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                 w0b -= s;
             }
         if constexpr (N >= 2) {
-#pragma unroll
+#pragma unroll 1
             for (int kk = 0; kk < 5; ++kk)
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
@@ -662,13 +662,17 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                     w0b -= s;
                 }
         }
-        // piece averages and field projection
-        double Usb[3][M][NP], Lrb[M], ub0b[M];
+        // piece averages and field projection, one face at a time: the
+        // cell's contribution to face f's source coefficients is the sum over
+        // the cell's lanes of Lr[c] wsb[n]; the lanes' sums are formed face by
+        // face so that only one face's block is live
+        double Lrb[M], ub0b[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             Lrb[c] = ub0[c] * w0b;
             ub0b[c] = Lr[c] * w0b;
         }
+        double* rec = contrib + (size_t)t * (4 * M * NP);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             double wsb[NP];
@@ -679,15 +683,32 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                 for (int p = 0; p < NPC; ++p) s += op[LO::AVG + (f * NPC + p) * NP + n] * wb[f][p];
                 wsb[n] = s;
             }
+            double Usb[M][NP];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 double s = 0.0;
 #pragma unroll
                 for (int n = 0; n < NP; ++n) {
-                    Usb[f][c][n] = Lr[c] * wsb[n];
+                    Usb[c][n] = Lr[c] * wsb[n];
                     s += u[(size_t)(c * NP + n) * K + srcs[f]] * wsb[n];
                 }
                 Lrb[c] += s;
+            }
+#pragma unroll
+            for (int o = 1; o < LPC; o <<= 1)
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+#pragma unroll
+                    for (int n = 0; n < NP; ++n) Usb[c][n] += __shfl_xor(Usb[c][n], o, LPC);
+            if (active && j < M) {
+                // record [slot 0 = the cell][slots 1..3 = sources of faces 0..2][m][Np]
+#pragma unroll
+                for (int n = 0; n < NP; ++n) {
+                    double v = Usb[0][n];
+#pragma unroll
+                    for (int c = 1; c < M; ++c) v = (j == c) ? Usb[c][n] : v;
+                    rec[(1 + f) * M * NP + j * NP + n] = valid ? v : 0.0;
+                }
             }
         }
         // characteristic matrices depend on the cell mean
@@ -703,36 +724,17 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
         double U0b[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) U0b[c] = kPsi0 * ub0b[c];
-        // sum over the lanes of the cell
 #pragma unroll
-        for (int o = 1; o < LPC; o <<= 1) {
+        for (int o = 1; o < LPC; o <<= 1)
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                U0b[c] += __shfl_xor(U0b[c], o, LPC);
-#pragma unroll
-                for (int f = 0; f < 3; ++f)
-#pragma unroll
-                    for (int n = 0; n < NP; ++n) Usb[f][c][n] += __shfl_xor(Usb[f][c][n], o, LPC);
-            }
-        }
+            for (int c = 0; c < M; ++c) U0b[c] += __shfl_xor(U0b[c], o, LPC);
         if (active && j < M) {
-            // record [slot 0 = the cell][slots 1..3 = sources of faces 0..2][m][Np]
-            double* rec = contrib + (size_t)t * (4 * M * NP);
             double sel0 = U0b[0];
 #pragma unroll
             for (int c = 1; c < M; ++c) sel0 = (j == c) ? U0b[c] : sel0;
             rec[j * NP] = valid ? sel0 : 0.0;
 #pragma unroll
             for (int n = 1; n < NP; ++n) rec[j * NP + n] = 0.0;
-#pragma unroll
-            for (int f = 0; f < 3; ++f)
-#pragma unroll
-                for (int n = 0; n < NP; ++n) {
-                    double v = Usb[f][0][n];
-#pragma unroll
-                    for (int c = 1; c < M; ++c) v = (j == c) ? Usb[f][c][n] : v;
-                    rec[(1 + f) * M * NP + j * NP + n] = valid ? v : 0.0;
-                }
         }
     }
 }
