@@ -279,6 +279,12 @@ int cswdg_status(cswdg_solver* s, uint32_t* flags);
  * total milliseconds and launch counts; *n receives the number of kernel
  * classes.  Synchronous. */
 int cswdg_profile(cswdg_solver* s, int enable);
+/* Restrict the recording to the kernel classes whose bit is set in
+ * kernel_mask (bit i = entry i of cswdg_kernel_times: 0 residual_rk,
+ * 1 max_dt, 2 kxrcf, 3 compact_mask, 4 limiter, 5 scatter, 6 copy, 7 zero,
+ * 8 project, 9 residual_vjp, 10 limiter_vjp); all classes by default.
+ * Fewer events disturb the timed launches less. */
+int cswdg_profile_select(cswdg_solver* s, uint32_t kernel_mask);
 int cswdg_kernel_times(cswdg_solver* s, const char** names, double* total_ms, int64_t* counts,
                        int cap, int* n);
 

@@ -63,6 +63,7 @@ _SIGS = {
     "cswdg_ssprk3_step_tape": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int]),
     "cswdg_ssprk3_step_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
     "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "cswdg_profile_select": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cswdg_mesh_upload_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "cswdg_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
@@ -409,7 +410,14 @@ class Solver:
         cands = [(v, b, x) for v in (0, 1, 2, 3) for b in (64, 128, 256) for x in (0, 1)]
         return tuple(int(x) for x in a), {c: float(t[i]) for i, c in enumerate(cands[: n.value])}
 
-    def profile(self, enable=True):
+    KERNEL_CLASSES = ("residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero",
+                      "project", "residual_vjp", "limiter_vjp")
+
+    def profile(self, enable=True, only=None):
+        """HIP-event timing of every launch (or only of the named kernel
+        classes) until profile(False)."""
+        mask = 0xFFFFFFFF if only is None else sum(1 << self.KERNEL_CLASSES.index(k) for k in only)
+        self._c(lib().cswdg_profile_select(self.h, mask))
         self._c(lib().cswdg_profile(self.h, 1 if enable else 0))
 
     def kernel_times(self):

@@ -67,6 +67,7 @@ struct cswdg_solver {
     int64_t n_rank = 0, n_foot = 0;
     // profiling
     bool prof = false;
+    uint32_t prof_mask = ~0u;  // kernel classes recorded while profiling
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> recs;  // kernel id, event index of the start
@@ -120,7 +121,7 @@ void free_mesh(cswdg_solver* s) {
 
 template <class F>
 hipError_t timed(cswdg_solver* s, int kid, F&& f) {
-    if (!s->prof || s->ev_used + 2 > s->ev_pool.size()) return f();
+    if (!s->prof || !((s->prof_mask >> kid) & 1u) || s->ev_used + 2 > s->ev_pool.size()) return f();
     size_t i = s->ev_used;
     s->ev_used += 2;
     (void)hipEventRecord(s->ev_pool[i], s->stream);
@@ -821,6 +822,12 @@ int cswdg_profile(cswdg_solver* s, int enable) {
         s->ev_used = 0;
         s->recs.clear();
     }
+    return CSWDG_OK;
+}
+
+int cswdg_profile_select(cswdg_solver* s, uint32_t kernel_mask) {
+    if (!s) return fail(nullptr, CSWDG_EINVAL, "null solver");
+    s->prof_mask = kernel_mask;
     return CSWDG_OK;
 }
 
