@@ -251,9 +251,11 @@ def _beta_matrix(V0, x0, y0, h0, area0, d):
     return B
 
 
-def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False):
+def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True):
     """New coefficients for the troubled cells elems: [T, m, Np].  Mode 0
-    is copied from u."""
+    is copied from u.  linear_only: the weights are the linear weights
+    (omega = gamma); characteristic=False (Euler): the conserved variables
+    are reconstructed directly instead of the characteristic fields."""
     M = dg.mesh
     E = np.asarray(elems, dtype=np.int64)
     T = len(E)
@@ -294,7 +296,10 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False):
         return b - data0[:, None, :]
 
     # characteristic transforms
-    if dg.eq == EQ_EULER:
+    if dg.eq == EQ_EULER and not characteristic:
+        Ls = [np.broadcast_to(np.eye(m), (T, m, m))]
+        Rs = [np.broadcast_to(np.eye(m), (T, m, m))]
+    elif dg.eq == EQ_EULER:
         Ubar = ubar0
         dirs = [(1.0, 0.0), (0.0, 1.0)]
         Ls = [euler_left_eigenvectors(Ubar, nx, ny, dg.gamma) for nx, ny in dirs]
@@ -396,13 +401,13 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False):
     return out
 
 
-def limit(dg: DG, u, mask):
+def limit(dg: DG, u, mask, linear_only=False, characteristic=True):
     """Apply the limiter to the cells where mask is true (simultaneous
     update: every reconstruction reads the pre-limit u)."""
     E = np.nonzero(np.asarray(mask))[0]
     out = u.copy()
     if len(E):
-        out[E] = reconstruct(dg, u, E)
+        out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic)
     return out
 
 

@@ -21,8 +21,10 @@ from .dg import DG
 from .physics import EQ_BURGERS
 
 
-def indicator(dg: DG, u, elems=None, c_k=1.0):
-    """Returns (R [len], troubled bool [len])."""
+def indicator(dg: DG, u, elems=None, c_k=1.0, norm="l2"):
+    """Returns (R [len], troubled bool [len]).  norm = "l2": the literal
+    (int U^2 dA)^(1/2); "rms": the same divided by |Delta|^(1/2), a
+    mesh-scale-free variant of the paper's "standard L2 norm"."""
     M = dg.mesh
     E = np.arange(M.K) if elems is None else np.asarray(elems)
     ue = u[E]
@@ -50,9 +52,13 @@ def indicator(dg: DG, u, elems=None, c_k=1.0):
         ds = 0.5 * M.L[E, f][:, None] * dg.ew[None, :]
         num += np.sum(np.where(inflow, ds * (Um - Up), 0.0), axis=1)
         length += np.sum(np.where(inflow, ds, 0.0), axis=1)
-    norm = np.sqrt(M.J[E] * np.sum(ue[:, 0, :] ** 2, axis=1))
+    if norm == "rms":
+        # int U^2 dA / |Delta| = J sum U_n^2 / (2 J)
+        nrm = np.sqrt(0.5 * np.sum(ue[:, 0, :] ** 2, axis=1))
+    else:
+        nrm = np.sqrt(M.J[E] * np.sum(ue[:, 0, :] ** 2, axis=1))
     h = M.circumradius[E]
-    denom = h ** ((dg.N + 1) / 2.0) * length * norm
-    ok = (length > 0.0) & (norm > 0.0)
+    denom = h ** ((dg.N + 1) / 2.0) * length * nrm
+    ok = (length > 0.0) & (nrm > 0.0)
     R = np.where(ok, np.abs(num) / np.where(ok, denom, 1.0), 0.0)
     return R, R > c_k

@@ -34,6 +34,7 @@ def test_piecewise_constant_jump_closed_form():
         U = np.zeros((M.K, 1, d.Np))
         U[:, 0, 0] = cval * math.sqrt(2.0)
         R, tr = kxrcf.indicator(d, U)
+        Rr, _ = kxrcf.indicator(d, U, norm="rms")
         for e in range(M.K):
             num = 0.0
             ln = 0.0
@@ -42,10 +43,13 @@ def test_piecewise_constant_jump_closed_form():
                     num += M.L[e, f] * (cval[e] - cval[M.nbr[e, f]])
                     ln += M.L[e, f]
             if ln == 0:
-                exp = 0.0
+                exp = exp_rms = 0.0
             else:
                 exp = abs(num) / (M.circumradius[e] ** ((N + 1) / 2) * ln * cval[e] * math.sqrt(M.area[e]))
+                # the RMS of a constant over the cell is the constant itself
+                exp_rms = abs(num) / (M.circumradius[e] ** ((N + 1) / 2) * ln * cval[e])
             assert math.isclose(R[e], exp, rel_tol=1e-12, abs_tol=1e-14)
+            assert math.isclose(Rr[e], exp_rms, rel_tol=1e-12, abs_tol=1e-14)
         assert tr.sum() > 0
 
 
