@@ -88,6 +88,10 @@ typedef struct cswdg_params {
     double cfl;       /* default 0.3/(2N+1) */
     double c_k;       /* KXRCF threshold C_K, default 1 (Section 3.1) */
     double eps_weno;  /* epsilon of the nonlinear weights, default 1e-10 (Section 3.2) */
+    /* readings of the paper (0 = the default reading): */
+    int kxrcf_norm;   /* ||U_j|| of Section 3.1: 0 the literal (int U^2 dA)^(1/2), 1 divided by |Delta|^(1/2) (RMS) */
+    int char_mode;    /* Euler limiting (Section 3.2, last paragraph): 0 characteristic fields, 1 conserved variables */
+    int weights_mode; /* Section 3.2 Step 4: 0 nonlinear weights, 1 the linear weights (omega = gamma) */
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream

@@ -142,6 +142,8 @@ int check_ready(cswdg_solver* s) {
 int check_single(cswdg_solver* s) {
     if (s->n_inst != 1) return fail(s, CSWDG_EINVAL, "adjoint calls take a single-instance mesh");
     if (s->p.precision != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take an FP64 solver");
+    if (s->p.char_mode != 0 || s->p.weights_mode != 0)
+        return fail(s, CSWDG_EINVAL, "adjoint calls take the default limiter readings (char_mode = weights_mode = 0)");
     return CSWDG_OK;
 }
 
@@ -246,6 +248,9 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     if (p.degree < 1 || p.degree > 3) return fail(nullptr, CSWDG_EINVAL, "degree must be 1, 2 or 3");
     if (p.precision != 0 && p.precision != 1) return fail(nullptr, CSWDG_EINVAL, "precision must be 0 (FP64) or 1 (FP32-bulk)");
     if (p.limiter_mode < 0 || p.limiter_mode > 2) return fail(nullptr, CSWDG_EINVAL, "bad limiter_mode");
+    if (p.kxrcf_norm < 0 || p.kxrcf_norm > 1 || p.char_mode < 0 || p.char_mode > 1 || p.weights_mode < 0 ||
+        p.weights_mode > 1)
+        return fail(nullptr, CSWDG_EINVAL, "kxrcf_norm, char_mode and weights_mode must be 0 or 1");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
     if (!(p.cfl > 0)) p.cfl = 0.3 / (2 * p.degree + 1);
     if (!(p.c_k > 0)) p.c_k = 1.0;
@@ -279,6 +284,9 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     const char* rv = std::getenv("CSWDG_RESIDUAL_VARIANT");
     s->ctx.residual_variant = rv ? std::atoi(rv) : 3;
     s->ctx.residual_block = 128;
+    s->ctx.kxrcf_rms = p.kxrcf_norm;
+    s->ctx.char_comp = p.char_mode;
+    s->ctx.weights_linear = p.weights_mode;
     *out = s;
     return CSWDG_OK;
 }

@@ -90,6 +90,9 @@ struct LaunchCtx {
     double gamma, cfl, c_k, eps;
     int residual_variant;  // residual schedule: 0 lean, 1 wide, 2 stream, 3 compact (default)
     int residual_block;    // residual threads per block: 64, 128 or 256
+    int kxrcf_rms;         // KXRCF norm divided by |Delta|^(1/2)
+    int char_comp;         // Euler limiting on the conserved variables
+    int weights_linear;    // limiter weights omega = gamma
 };
 
 int upload_tables_device();   // once per device (both translation units)

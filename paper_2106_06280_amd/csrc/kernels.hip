@@ -722,7 +722,7 @@ template <int EQ, int N, typename S>
 __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict__ u,
                                                uint8_t* __restrict__ flags, double* __restrict__ Rout,
                                                int32_t* __restrict__ list,
-                                               uint32_t* __restrict__ count, double ck) {
+                                               uint32_t* __restrict__ count, double ck, int rms) {
     using D = Dims<N>;
     constexpr int NP = D::NP, NE = D::NE;
     const int K = msh.K;
@@ -790,7 +790,8 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
         double ss = 0.0;
 #pragma unroll
         for (int n = 0; n < NP; ++n) ss += U0[n] * U0[n];
-        const double norm = sqrt(J * ss);
+        // literal L2 norm, or its RMS over the cell (int U^2 dA / (2 J))
+        const double norm = rms ? sqrt(0.5 * ss) : sqrt(J * ss);
         const double h = Ls[0] * Ls[1] * Ls[2] / (4.0 * (2.0 * J));
         const double hp = (N == 1) ? h : ((N == 2) ? h * sqrt(h) : h * h);
         double R = 0.0;
@@ -830,7 +831,7 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
                                                 const uint32_t* __restrict__ count,
                                                 double* __restrict__ compact,
                                                 uint32_t* __restrict__ status, double gamma,
-                                                double eps) {
+                                                double eps, int comp, int lin) {
     using D = Dims<N>;
     using LO = OpLayout<N>;
     constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = D::NPIECE, NM = D::NMONO;
@@ -858,6 +859,13 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
         if constexpr (EQ == 1) {
             double Lm[4][4], Rm[4][4];
             euler_eigen(ub0, d == 0 ? 1.0 : 0.0, d == 0 ? 0.0 : 1.0, gamma, Lm, Rm);
+            if (comp) {
+                // conserved variables: both "directions" use the identity
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) Lm[a][b] = Rm[a][b] = (a == b) ? 1.0 : 0.0;
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 double a = Lm[0][c], b = Rm[c][0];
@@ -979,7 +987,8 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
             if constexpr (N == 1) {
                 const double g13 = 1.0 / s3;
                 const double d31 = fabs(beta[2] - beta[0]), d32 = fabs(beta[2] - beta[1]);
-                const double tau = (d31 * d31 + d32 * d32) / 4.0;
+                // tau = 0 gives the linear weights (omega = gamma)
+                const double tau = lin ? 0.0 : (d31 * d31 + d32 * d32) / 4.0;
                 const double o1 = g13 * (1.0 + tau / (eps + beta[0]));
                 const double o2 = g23 * (1.0 + tau / (eps + beta[1]));
                 const double o3 = g33 * (1.0 + tau / (eps + beta[2]));
@@ -993,7 +1002,7 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
                 const double s5 = 1.0 + ih + ih * ih + ih * ih * ih;
                 const double g15 = 1.0 / s5, g25 = ih / s5, g35 = ih * ih / s5, g45 = ih * ih * ih / s5;
                 const double d1 = fabs(beta[3] - beta[0]), d2 = fabs(beta[3] - beta[1]), d3 = fabs(beta[3] - beta[2]);
-                const double tau = (d1 * d1 + d2 * d2 + d3 * d3) / 16.0;
+                const double tau = lin ? 0.0 : (d1 * d1 + d2 * d2 + d3 * d3) / 16.0;
                 const double o1 = g15 * (1.0 + tau / (eps + beta[0]));
                 const double o2 = g25 * (1.0 + tau / (eps + beta[1]));
                 const double o3 = g35 * (1.0 + tau / (eps + beta[2]));
@@ -1203,7 +1212,7 @@ hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uin
                         int32_t* list, uint32_t* count) {
     const unsigned bs = 256, g = grid_for(m.K, bs);
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        k_kxrcf<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, flags, R, list, count, c.c_k);
+        k_kxrcf<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, flags, R, list, count, c.c_k, c.kxrcf_rms);
     });
     return hipGetLastError();
 }
@@ -1228,7 +1237,8 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
     if (g > 16384u) g = 16384u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        k_limiter<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma, c.eps);
+        k_limiter<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma, c.eps,
+                                                      c.char_comp, c.weights_linear);
     });
     return hipGetLastError();
 }

@@ -240,3 +240,61 @@ def test_binding_rejects_mismatched_buffers(torch):
     assert torch.equal(u, S.to_device(_smooth_state(dg, 1, seed=1)))
     S.ssprk3_step(u)
     assert S.status() & 0x3 == 0
+
+
+def _case_opts(eq, N, n, bc, seed, **opts):
+    b = _binding()
+    v, t = inputs.jittered_mesh(n, seed=seed)
+    M = Mesh(v, t, bc, (1.0, 1.0))
+    dg = DG(M, N, eq)
+    S = b.Solver(eq, N, **opts)
+    S.mesh_upload(v, t, bc, (1.0, 1.0))
+    return M, dg, S
+
+
+@pytest.mark.parametrize("eq,N", EQN)
+def test_kxrcf_rms_norm_flags_bit_exact(torch, eq, N):
+    """kxrcf_norm = 1: the indicator's norm divided by |Delta|^(1/2)."""
+    M, dg, S = _case_opts(eq, N, 20, BC_TRANSMISSIVE, seed=62, kxrcf_norm=1)
+    u = _jump_state(dg, eq, seed=6)
+    flags, R = S.kxrcf(S.to_device(u))
+    Ro, fo = kxrcf.indicator(dg, u, norm="rms")
+    ties = np.abs(Ro - 1.0) < TIE
+    assert ties.sum() == 0
+    assert np.array_equal(flags.cpu().numpy().astype(bool), fo)
+    assert fo.sum() > 0 and (~fo).sum() > 0
+    assert np.all(np.abs(R.cpu().numpy() - Ro) <= TOL * np.maximum(Ro, 1.0) + 1e-10)
+
+
+@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_limiter_component_mode(torch, N, bc):
+    """char_mode = 1: the Euler limiter on the conserved variables."""
+    M, dg, S = _case_opts(1, N, 12, bc, seed=72 + N, char_mode=1)
+    mask = np.ones(M.K, bool)
+    for u in (_jump_state(dg, 1, seed=7), _smooth_state(dg, 1, seed=8)):
+        out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+        got = S.to_host(out)
+        exp = csweno.limit(dg, u, mask, characteristic=False)
+        assert np.array_equal(got[:, :, 0], u[:, :, 0])
+        assert _relerr(got, exp) < TOL
+
+
+@pytest.mark.parametrize("eq,N", EQN)
+def test_limiter_linear_weights(torch, eq, N):
+    """weights_mode = 1: omega = gamma; on global polynomial data of degree N
+    the reconstruction returns the data on interior cells."""
+    M, dg, S = _case_opts(eq, N, 12, BC_PERIODIC, seed=82 + N, weights_mode=1)
+    mask = np.ones(M.K, bool)
+    u = _jump_state(dg, eq, seed=9)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    assert _relerr(S.to_host(out), csweno.limit(dg, u, mask, linear_only=True)) < TOL
+    # degree-N polynomial data on a transmissive mesh, cells away from the boundary
+    M, dg, S = _case_opts(0, N, 8, BC_TRANSMISSIVE, seed=92, weights_mode=1)
+    poly = lambda x, y: 0.3 + 0.5 * x - 0.4 * y + (0.6 * x * y - 0.3 * y * y if N >= 2 else 0.0) + \
+        (0.2 * x ** 3 if N >= 3 else 0.0)
+    u = dg.project(poly)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    got = S.to_host(out)
+    inner = ~np.any((M.info & 0x40) != 0, axis=1)
+    assert np.abs(got[inner] - u[inner]).max() < 1e-10
