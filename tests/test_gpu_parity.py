@@ -298,3 +298,29 @@ def test_limiter_linear_weights(torch, eq, N):
     got = S.to_host(out)
     inner = ~np.any((M.info & 0x40) != 0, axis=1)
     assert np.abs(got[inner] - u[inner]).max() < 1e-10
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("eq,N", EQN)
+def test_residual_schedules_parity(torch, eq, N, variant):
+    """Every residual schedule (the default compact one is covered above)
+    against the oracle, on a mesh with a ragged last block."""
+    M, dg, S = _case(eq, N, 12, BC_TRANSMISSIVE, seed=141 + N)
+    S.set_schedule(variant, 128, 1)
+    u = _smooth_state(dg, eq, seed=N)
+    r = S.to_host(S.dg_residual(S.to_device(u)))
+    assert _relerr(r, dg.residual(u)) < TOL
+    # the RK combine of each stage
+    dt = 0.5 * dg.max_dt(u)
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    ud = S.to_device(u)
+    prev = S.to_device(_smooth_state(dg, eq, seed=N + 10))
+    for stage, (a, b) in ((1, (0.0, 1.0)), (2, (0.75, 0.25)), (3, (1.0 / 3.0, 2.0 / 3.0))):
+        S2 = _binding().Solver(eq, N, limiter_mode=2)
+        S2.mesh_upload(*inputs.jittered_mesh(12, seed=141 + N), BC_TRANSMISSIVE, (1.0, 1.0))
+        S2.set_schedule(variant, 128, 1)
+        out = S2.empty_state()
+        S2.rk_stage(stage, ud, prev, out, dtd)
+        pv = S.to_host(prev)
+        exp = a * u + b * (pv + dt * dg.residual(pv))
+        assert _relerr(S.to_host(out), exp) < TOL, stage
