@@ -59,7 +59,7 @@ import numpy as np
 from . import basis, quadrature
 from .dg import DG, PSI0
 from .mesh import INFO_BOUNDARY
-from .physics import EQ_EULER, euler_left_eigenvectors, euler_right_eigenvectors
+from .physics import EQ_EULER, euler_left_eigenvectors, euler_right_eigenvectors, ghost_state
 
 EPS = 1e-10
 LAMBDA1 = 1.0 / 3.0
@@ -280,6 +280,18 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     avg = {}
     for name in pcs:
         avg[name] = np.stack([neighbour_average(dg, u, E, nid, shift, f, pcs[name][:, f]) for f in range(3)], axis=1)
+    # ghost cells of boundary faces carry the boundary's ghost state: the
+    # mirrored polynomial (outflow), the same with its normal momentum
+    # reversed (reflective wall), the inflow state on every piece (inflow);
+    # averaging commutes with the reflection
+    for f in range(3):
+        isb = (M.info[E, f] & INFO_BOUNDARY) != 0
+        if not isb.any():
+            continue
+        kind = np.where(isb, M.info[E, f] & 3, 0)
+        for name in pcs:
+            g = ghost_state(dg.eq, avg[name][:, f], kind, M.nx[E, f], M.ny[E, f], dg.inflow)
+            avg[name][:, f] = np.where(isb[:, None], g, avg[name][:, f])
     ubar0 = u[E, :, 0] * PSI0  # [T, m]
 
     # scaled-monomial averages

@@ -12,7 +12,10 @@ Readings (the paper prints a structured-mesh/1D form of the weak form and
   its inverse is the factor 1/J;
 * the neighbour traverses a shared edge in the opposite direction, so
   Gauss point g of one side meets point n_e-1-g of the other;
-* transmissive boundary: the exterior trace equals the interior trace;
+* boundary faces (Section 4, Examples 4-6): outflow / transmissive, the
+  exterior trace equals the interior trace; reflective wall, the interior
+  trace with its normal momentum reversed; inflow, a prescribed state
+  (`DG.inflow`);
 * time step dt = CFL * min_e(2 r_e) / a_max with r_e the inradius and a_max
   the largest cell-mean wave speed; CFL defaults to 0.3/(2N+1).
 
@@ -30,7 +33,7 @@ import numpy as np
 
 from . import basis, quadrature
 from .mesh import Mesh
-from .physics import EQ_BURGERS, EQ_EULER, cell_mean_speed, flux, lax_friedrichs, n_vars
+from .physics import EQ_BURGERS, EQ_EULER, cell_mean_speed, flux, ghost_state, lax_friedrichs, n_vars
 
 # Section 3.2, table:tvd (order 3): u^(i) = sum_l alpha_il u^(l) + beta_il dt L(u^(l))
 RK3_ALPHA = [[1.0], [0.75, 0.25], [1.0 / 3.0, 0.0, 2.0 / 3.0]]
@@ -72,6 +75,7 @@ class DG:
         t, tw = quadrature.edge_rule(N)
         self.et, self.ew = t, tw
         self.PF = np.stack([basis.vandermonde(N, *quadrature.face_reference_points(f, t)) for f in range(3)])  # [3, g, Np]
+        self.inflow = np.zeros(self.m)  # state of inflow boundary faces (conserved variables)
 
     # ------------------------------------------------------------------
     def project(self, fn, degree=None, elems=None):
@@ -122,9 +126,10 @@ class DG:
             nb_safe = np.where(isb, E, nb)
             sel = PFrev[fprime[E, f]]  # [k, g, n]
             up = np.einsum("kgn,kcn->kgc", sel, u[nb_safe])
-            up = np.where(isb[:, None, None], um, up)
             nx = np.broadcast_to(M.nx[E, f][:, None], um.shape[:2])
             ny = np.broadcast_to(M.ny[E, f][:, None], um.shape[:2])
+            kind = np.broadcast_to((M.info[E, f] & 3)[:, None], um.shape[:2])
+            up = np.where(isb[:, None, None], ghost_state(self.eq, um, kind, nx, ny, self.inflow), up)
             Fn = lax_friedrichs(self.eq, um, up, nx, ny, self.gamma)
             scale = M.L[E, f] / (2.0 * M.J[E])
             surf += scale[:, None, None] * np.einsum("g,gi,kgc->kci", self.ew, self.PF[f], Fn)

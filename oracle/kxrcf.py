@@ -41,7 +41,11 @@ def indicator(dg: DG, u, elems=None, c_k=1.0, norm="l2"):
         sel = PFrev[fprime[E, f]]
         up = np.einsum("kgn,kn->kg", sel, u[nb_safe, 0, :])
         Um = um[..., 0]
-        Up = np.where(isb[:, None], Um, up)
+        # boundary faces: the ghost state's indicator variable (the interior
+        # trace on outflow and wall faces, the inflow state's on inflow faces)
+        kind = M.info[E, f] & 3
+        Ub = np.where((kind == 2)[:, None], dg.inflow[0], Um)
+        Up = np.where(isb[:, None], Ub, up)
         if dg.eq == EQ_BURGERS:
             vx = vy = Um
         else:

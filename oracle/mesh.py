@@ -25,6 +25,9 @@ BC_TRANSMISSIVE = 1
 
 INFO_FACE_MASK = 0x3
 INFO_BOUNDARY = 0x40
+# kind of a boundary face, kept in the face bits of its info byte
+# (Section 4, Examples 4-6: outflow / non-reflecting, reflective wall, inflow)
+BKIND_OUTFLOW, BKIND_WALL, BKIND_INFLOW = 0, 1, 2
 
 
 class MeshError(ValueError):
@@ -209,6 +212,19 @@ class Mesh:
 
     def boundary_mask(self):
         return (self.info & INFO_BOUNDARY) != 0
+
+    def set_boundary_kinds(self, kinds):
+        """kinds [K, 3]: for boundary faces BKIND_OUTFLOW (the default), _WALL
+        or _INFLOW; entries of interior faces are ignored."""
+        kinds = np.asarray(kinds)
+        if kinds.shape != self.info.shape or np.any((kinds < 0) | (kinds > 2)):
+            raise ValueError("boundary kinds: [K, 3] array of 0, 1, 2")
+        b = self.boundary_mask()
+        self.info = np.where(b, INFO_BOUNDARY | kinds.astype(np.uint8), self.info).astype(np.uint8)
+
+    def boundary_kind(self):
+        """[K, 3]: the kind of each boundary face, -1 on interior faces."""
+        return np.where(self.boundary_mask(), (self.info & INFO_FACE_MASK).astype(np.int64), -1)
 
     def neighbour_face(self):
         return (self.info & INFO_FACE_MASK).astype(np.int64)

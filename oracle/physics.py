@@ -111,3 +111,21 @@ def euler_eigenvalues(Ubar, nx, ny, gamma=1.4):
     c = np.sqrt(gamma * p / rho)
     un = u * nx + v * ny
     return np.stack([un - c, un, un, un + c], axis=-1)
+
+
+def ghost_state(eq, um, kind, nx, ny, inflow):
+    """Exterior trace at boundary points (Section 4, Examples 4-6).
+    um [..., m] interior trace, kind [...] (0 outflow: the interior trace;
+    1 reflective wall: the interior trace with its normal momentum reversed;
+    2 inflow: the prescribed state inflow [m]), nx, ny [...] the outward
+    normal."""
+    up = np.array(um, dtype=np.float64, copy=True)
+    kind = np.broadcast_to(kind, um.shape[:-1])
+    if eq == EQ_EULER:
+        mn = um[..., 1] * nx + um[..., 2] * ny
+        wall = kind == 1
+        up[..., 1] = np.where(wall, um[..., 1] - 2.0 * mn * nx, up[..., 1])
+        up[..., 2] = np.where(wall, um[..., 2] - 2.0 * mn * ny, up[..., 2])
+    inflow = np.asarray(inflow, dtype=np.float64)
+    up = np.where((kind == 2)[..., None], np.broadcast_to(inflow, up.shape), up)
+    return up
