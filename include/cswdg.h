@@ -40,7 +40,8 @@
  * f+1 (mod 3).  Connectivity info byte: bits 0-1 the neighbour's local face,
  * bits 2-3 / 4-5 the x / y shift code (0 none, 1 add +period, 2 add -period
  * to the neighbour's coordinates to place it next to the element), bit 6 set
- * on a transmissive boundary face (neighbour id -1).
+ * on a boundary face (neighbour id -1), whose bits 0-1 then hold its kind
+ * (cswdg_set_boundary: 0 outflow, the default).
  */
 #ifndef CSWDG_H
 #define CSWDG_H
@@ -130,6 +131,20 @@ int cswdg_mesh_upload_batch(cswdg_solver* s, int32_t n_inst, const int64_t* nv, 
  * first element of each instance, offsets[n_inst] = K.  A mesh from
  * cswdg_mesh_upload is one instance. */
 int cswdg_instances(const cswdg_solver* s, int32_t* n_inst, int64_t* offsets);
+
+/* Boundary conditions of the boundary faces (Section 4, Examples 4-6):
+ * kinds (host uint8 [K][3], may be NULL to keep them; read for boundary
+ * faces only, interior entries ignored): 0 outflow (exterior trace = interior
+ * trace, the default), 1 reflective wall (interior trace with its normal
+ * momentum reversed; for Burgers the same as outflow), 2 inflow (the state
+ * inflow, host double [m] of conserved variables, may be NULL to keep the
+ * last one; zero after a mesh upload).  The limiter's ghost cell across a
+ * boundary face is Delta0's mirror image carrying the same exterior state
+ * (the mirrored polynomial, with reversed normal momentum at a wall, or the
+ * inflow state on every piece); KXRCF sees the ghost's density.  Adjoint
+ * calls reject meshes with wall or inflow faces.  Another kind than 0, 1, 2
+ * is CSWDG_EINVAL.  Synchronous. */
+int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* inflow);
 
 /* Number of elements, number of triangles re-oriented by the CCW fix. */
 int cswdg_mesh_info(const cswdg_solver* s, int64_t* n_elements, int64_t* n_flipped);

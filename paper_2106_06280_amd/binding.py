@@ -65,6 +65,7 @@ _SIGS = {
     "cswdg_ssprk3_step_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
     "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "cswdg_profile_select": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "cswdg_set_boundary": (ctypes.c_int, [_P, _P, _P]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cswdg_mesh_upload_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "cswdg_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
@@ -201,6 +202,22 @@ class Solver:
                                               tri.ctypes.data, bc.ctypes.data, float(period[0]), float(period[1])))
         self.K = int(nt.sum())
         self.__dict__.pop("_ninst", None)
+
+    def set_boundary(self, kinds=None, inflow=None):
+        """kinds [K, 3] (0 outflow, 1 wall, 2 inflow; read on boundary faces);
+        inflow: conserved state [m] of inflow faces."""
+        k = None
+        if kinds is not None:
+            k = np.ascontiguousarray(np.asarray(kinds, dtype=np.uint8))
+            if k.shape != (self.K, 3):
+                raise ValueError(f"kinds: expected ({self.K}, 3), got {k.shape}")
+        s = None
+        if inflow is not None:
+            s = np.ascontiguousarray(np.asarray(inflow, dtype=np.float64))
+            if s.shape != (self.m,):
+                raise ValueError(f"inflow: expected ({self.m},), got {s.shape}")
+        self._c(lib().cswdg_set_boundary(self.h, None if k is None else k.ctypes.data,
+                                         None if s is None else s.ctypes.data))
 
     def instances(self):
         """Instance offsets (numpy int64 [n_inst + 1])."""

@@ -63,6 +63,8 @@ struct cswdg_solver {
     int32_t* d_inst_off = nullptr;
     double* d_inst_hmin = nullptr;
     unsigned long long* d_amax = nullptr;
+    double* d_inflow = nullptr;   // [m] state of inflow boundary faces
+    int64_t n_special = 0;        // boundary faces of wall or inflow kind
     int dt_blocks = 1024;
     int64_t n_rank = 0, n_foot = 0;
     // profiling
@@ -94,7 +96,7 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
                     s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2,
-                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax};
+                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -113,6 +115,8 @@ void free_mesh(cswdg_solver* s) {
     s->d_inst_off = nullptr;
     s->d_inst_hmin = nullptr;
     s->d_amax = nullptr;
+    s->d_inflow = nullptr;
+    s->n_special = 0;
     s->n_inst = 1;
     s->inst_off.clear();
     s->inst_hmin.clear();
@@ -144,6 +148,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.precision != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take an FP64 solver");
     if (s->p.char_mode != 0 || s->p.weights_mode != 0)
         return fail(s, CSWDG_EINVAL, "adjoint calls take the default limiter readings (char_mode = weights_mode = 0)");
+    if (s->n_special != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take meshes without wall or inflow faces");
     return CSWDG_OK;
 }
 
@@ -361,6 +366,40 @@ int cswdg_instances(const cswdg_solver* s, int32_t* n_inst, int64_t* offsets) {
     *n_inst = s->n_inst;
     if (offsets)
         for (int i = 0; i <= s->n_inst; ++i) offsets[i] = s->inst_off[i];
+    return CSWDG_OK;
+}
+
+int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* inflow) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    const int64_t K = s->mesh.K;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hipfail(s, e, "set_boundary");
+    if (kinds) {
+        int64_t special = 0;
+        for (int64_t i = 0; i < 3 * K; ++i) {
+            if (!(s->mesh.info[i] & 0x40)) continue;
+            if (kinds[i] > 2) return fail(s, CSWDG_EINVAL, "boundary kind must be 0 (outflow), 1 (wall) or 2 (inflow)");
+            special += kinds[i] != 0;
+        }
+        std::vector<uint32_t> info4(K);
+        for (int64_t el = 0; el < K; ++el) {
+            uint32_t w = 0;
+            for (int f = 0; f < 3; ++f) {
+                uint8_t& b = s->mesh.info[3 * el + f];
+                if (b & 0x40) b = (uint8_t)(0x40 | kinds[3 * el + f]);
+                w |= (uint32_t)b << (8 * f);
+            }
+            info4[el] = w;
+        }
+        e = hipMemcpy(s->d_info, info4.data(), sizeof(uint32_t) * K, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hipfail(s, e, "set_boundary");
+        s->n_special = special;
+    }
+    if (inflow) {
+        e = hipMemcpy(s->d_inflow, inflow, sizeof(double) * s->M, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hipfail(s, e, "set_boundary");
+    }
     return CSWDG_OK;
 }
 
@@ -905,6 +944,7 @@ int upload_mesh(cswdg_solver* s) {
         {(void**)&s->d_inst_off, sizeof(int32_t) * (s->n_inst + 1)},
         {(void**)&s->d_inst_hmin, sizeof(double) * s->n_inst},
         {(void**)&s->d_amax, sizeof(unsigned long long) * s->n_inst},
+        {(void**)&s->d_inflow, sizeof(double) * 4},
         {(void**)&s->d_T1, sizeof(double) * NPM * K},
         {(void**)&s->d_T2, sizeof(double) * NPM * K},
     };
@@ -931,6 +971,7 @@ int upload_mesh(cswdg_solver* s) {
     cp(s->d_inst_off, s->inst_off.data(), sizeof(int32_t) * (s->n_inst + 1));
     cp(s->d_inst_hmin, s->inst_hmin.data(), sizeof(double) * s->n_inst);
     if (e == hipSuccess) e = hipMemset(s->d_amax, 0, sizeof(unsigned long long) * s->n_inst);
+    if (e == hipSuccess) e = hipMemset(s->d_inflow, 0, sizeof(double) * 4);
     if (e != hipSuccess) {
         free_mesh(s);
         return hipfail(s, e, "mesh upload");
@@ -941,6 +982,8 @@ int upload_mesh(cswdg_solver* s) {
     s->dm.nbr = s->d_nbr;
     s->dm.info = s->d_info;
     s->dm.n_inst = s->n_inst;
+    s->dm.inflow = s->d_inflow;
+    s->n_special = 0;
     s->dm.inst_off = s->d_inst_off;
     {
         const char* xt = std::getenv("CSWDG_XCD_TILES");

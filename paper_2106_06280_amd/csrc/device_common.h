@@ -146,6 +146,26 @@ __device__ __forceinline__ void append_list_block(bool tr, int e, int32_t* __res
     if (tr && pos < (uint32_t)K) list[(size_t)seg * K + pos] = e;
 }
 
+// Exterior trace of a boundary face (Section 4, Examples 4-6), given the
+// interior trace um and up already set to it (outflow): a reflective wall
+// reverses the normal momentum, an inflow face takes the prescribed state.
+// The kind is kept in the face bits of the boundary face's info byte.
+template <int EQ, typename R>
+__device__ __forceinline__ void boundary_trace(const R* um, R* up, uint32_t inf, R nx, R ny,
+                                               const double* __restrict__ inflow) {
+    // selects rather than branches keep up[] in registers
+    constexpr int M = (EQ == 1) ? 4 : 1;
+    const uint32_t kind = inf & 3u;
+    if constexpr (EQ == 1) {
+        const R mn = um[1] * nx + um[2] * ny;
+        const R w1 = um[1] - R(2) * mn * nx, w2 = um[2] - R(2) * mn * ny;
+        up[1] = (kind == 1u) ? w1 : up[1];
+        up[2] = (kind == 1u) ? w2 : up[2];
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) up[c] = (kind == 2u) ? (R)inflow[c] : up[c];
+}
+
 // instance holding element e (binary search over the instance offsets)
 __device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
     if (m.n_inst <= 1) return 0;

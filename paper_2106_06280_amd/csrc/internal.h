@@ -80,6 +80,7 @@ struct DevMesh {
     const int32_t* nbr;    // [3][K]
     const uint32_t* info;  // [K], face f in byte f
     int xcd_tiles;         // 1: give each XCD a contiguous range of blocks
+    const double* inflow;  // [m] state of inflow boundary faces (conserved variables)
     int n_inst;            // independent meshes held (1 for a single mesh)
     const int32_t* inst_off;  // [n_inst + 1] first element of each instance
 };

@@ -121,6 +121,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
                 um[c] = a;
                 up[c] = bnd ? a : b;
             }
+            if (bnd) boundary_trace<EQ>(um, up, inf, nx, ny, msh.inflow);
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(up, nx, ny, gamma, Fp, lp);
@@ -271,6 +272,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
                 um[c] = a;
                 upg[c] = bnd ? a : up[g][c];
             }
+            if (bnd) boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow);
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
@@ -397,6 +399,7 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
                 um[c] = a;
                 upg[c] = bnd ? a : b;
             }
+            if (bnd) boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow);
             R Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gm, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gm, Fp, lp);
@@ -561,6 +564,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
                 um[c] = umf[g][c];
                 upg[c] = bnd ? umf[g][c] : up[g][c];
             }
+            if (bnd) boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow);
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
@@ -780,7 +784,9 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
                 }
                 const double vn = vx * nx + vy * ny;
                 if (vn < 0.0) {
-                    const double up = bnd ? um : upv;
+                    // boundary faces: the interior trace (outflow, wall) or the
+                    // inflow state's indicator variable (inflow)
+                    const double up = bnd ? (((inf & 3u) == 2u) ? msh.inflow[0] : um) : upv;
                     const double ds = 0.5 * L * T.we[g];
                     num += ds * (um - up);
                     len += ds;
@@ -891,13 +897,41 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
-            const int src = (inf & 0x40u) ? e : msh.nbr[f * K + e];
+            const bool bnd = (inf & 0x40u) != 0u;
+            const uint32_t kind = bnd ? (inf & 3u) : 0u;
+            const int src = bnd ? e : msh.nbr[f * K + e];
+            // row of the field for this face's source: a wall's mirror ghost
+            // carries the reflected momentum, so its averages map through the
+            // reflection (row Lr times the symmetric reflection matrix)
+            double Lf[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) Lf[c] = Lr[c];
+            if constexpr (EQ == 1) {
+                if (kind == 1u) {
+                    const int f1 = (f == 2) ? 0 : f + 1;
+                    const double ex = msh.vx[f1 * K + e] - msh.vx[f * K + e];
+                    const double ey = msh.vy[f1 * K + e] - msh.vy[f * K + e];
+                    const double iL = 1.0 / sqrt(ex * ex + ey * ey);
+                    const double nx = ey * iL, ny = -ex * iL;
+                    Lf[1] = Lr[1] * (1.0 - 2.0 * nx * nx) - Lr[2] * (2.0 * nx * ny);
+                    Lf[2] = -Lr[1] * (2.0 * nx * ny) + Lr[2] * (1.0 - 2.0 * ny * ny);
+                }
+            }
+            if (kind == 2u) {
+                // inflow ghost: the prescribed state on every piece
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < M; ++c) s += Lr[c] * msh.inflow[c];
+#pragma unroll
+                for (int p = 0; p < NPC; ++p) w[f][p] = s;
+                continue;
+            }
             double ws[NP];
 #pragma unroll
             for (int n = 0; n < NP; ++n) {
                 double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < M; ++c) s += Lr[c] * u[(size_t)(c * NP + n) * K + src];
+                for (int c = 0; c < M; ++c) s += Lf[c] * u[(size_t)(c * NP + n) * K + src];
                 ws[n] = s;
             }
 #pragma unroll

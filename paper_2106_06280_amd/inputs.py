@@ -68,6 +68,89 @@ def jittered_mesh(n: int, x0: float = 0.0, x1: float = 1.0, y0: float = 0.0,
     return vxy, tri
 
 
+def forward_step_mesh(s: int, jitter: float = 0.1, seed: int = 0):
+    """Wind tunnel of length 4 and width 1 with a step of height 0.2 starting
+    1 from the inlet (Section 4, Example 6): [0,4] x [0,1] without the block
+    (1,4] x [0,0.2).  Jittered structured triangulation with s squares per
+    unit length (s a multiple of 5, so the step's sides lie on grid lines);
+    3.4 s^2 squares, 6.8 s^2 triangles.  Vertices strictly inside the
+    domain move by iid U(-jitter h, jitter h) per coordinate (h = 1/s);
+    vertices on the outer walls, the inlet, the outlet and the step keep
+    their places.  Returns (vxy, tri) as jittered_mesh does, unused
+    vertices removed."""
+    if s < 5 or s % 5:
+        raise ValueError("forward_step_mesh: s must be a positive multiple of 5")
+    n, ny, js = 4 * s, s, s // 5
+    v0, tri = jittered_mesh(n, 0.0, 4.0, 0.0, 1.0, jitter=0.0, ny=ny)
+    I = np.tile(np.arange(n + 1), ny + 1)
+    J = np.repeat(np.arange(ny + 1), n + 1)
+    on_step = ((I == s) & (J <= js)) | ((J == js) & (I >= s))
+    in_step = (I > s) & (J < js)
+    free = (I > 0) & (I < n) & (J > 0) & (J < ny) & ~on_step & ~in_step
+    d = _rng(seed).uniform(-1.0, 1.0, size=(len(v0), 2))
+    vxy = v0 + (jitter / s) * d * free[:, None]
+    c = v0[tri].mean(axis=1)
+    tri = tri[~((c[:, 0] > 1.0) & (c[:, 1] < 0.2))]
+    used = np.unique(tri)
+    remap = np.full(len(v0), -1, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    return vxy[used].copy(), remap[tri].astype(np.int32)
+
+
+FFSTEP_OUTFLOW, FFSTEP_WALL, FFSTEP_INFLOW = 0, 1, 2  # boundary kinds, as the solver numbers them
+
+
+def forward_step_kinds(vxy, tri):
+    """[K, 3] boundary kind of face f (vertices f and f+1) of each element of
+    a forward_step_mesh: inflow on the inlet x = 0, outflow on the outlet
+    x = 4, reflective wall on the tunnel walls and the step (Section 4,
+    Example 6).  Entries of interior faces are 1 and are not read."""
+    a = vxy[tri]
+    b = vxy[np.roll(tri, -1, axis=1)]
+    xm = 0.5 * (a[..., 0] + b[..., 0])
+    return np.where(xm < 1e-12, FFSTEP_INFLOW, np.where(xm > 4.0 - 1e-12, FFSTEP_OUTFLOW, FFSTEP_WALL))
+
+
+# Mach 3 uniform flow of the forward-step problem: gamma = 1.4, rho = 1.4,
+# p = 1 (sound speed 1), u = 3, v = 0.
+FFSTEP_PRIMITIVE = (1.4, 3.0, 0.0, 1.0)
+
+
+class UniformFlow:
+    """Constant state given by primitive variables (rho, u, v, p)."""
+
+    def __init__(self, rho, u, v, p):
+        self.state = primitive_to_conservative(rho, u, v, p)
+
+    def __call__(self, x, y):
+        return np.broadcast_to(self.state, np.shape(x) + (4,)).copy()
+
+
+class ForwardStepShock:
+    """Synthetic shocked state of the forward-step flow (Section 4, Example 6):
+    the uniform Mach 3 flow (FFSTEP_PRIMITIVE) ahead of a curved bow shock
+    x = x0 - a y^2 standing in front of the step, and behind it the state
+    that a normal shock leaves in that flow (Rankine-Hugoniot jump relations:
+    rho2/rho1 = (g+1) M^2 / ((g-1) M^2 + 2), p2/p1 = 1 + 2g (M^2 - 1)/(g+1),
+    u2 = u1 rho1/rho2).  x0 ~ U(0.7, 0.9) and a ~ U(0.2, 0.5) from the seed."""
+
+    def __init__(self, seed: int = 0, gamma: float = GAMMA_GAS):
+        rng = _rng(seed)
+        self.x0 = float(rng.uniform(0.7, 0.9))
+        self.a = float(rng.uniform(0.2, 0.5))
+        rho1, u1, v1, p1 = FFSTEP_PRIMITIVE
+        M2 = u1 * u1 / (gamma * p1 / rho1)
+        rho2 = rho1 * (gamma + 1.0) * M2 / ((gamma - 1.0) * M2 + 2.0)
+        p2 = p1 * (1.0 + 2.0 * gamma * (M2 - 1.0) / (gamma + 1.0))
+        self.pre = primitive_to_conservative(rho1, u1, v1, p1, gamma)
+        self.post = primitive_to_conservative(rho2, u1 * rho1 / rho2, 0.0, p2, gamma)
+
+    def __call__(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        behind = x > self.x0 - self.a * np.asarray(y) ** 2
+        return np.where(behind[..., None], self.post, self.pre)
+
+
 def n_for_target(k_target: int) -> int:
     """Squares per side so that 2 n^2 is closest to the requested triangle count."""
     return int(round(math.sqrt(k_target / 2.0)))

@@ -30,3 +30,70 @@ def test_batch_instances_are_seeded_and_in_range():
         ic = d["ic"]
         side = x * ic.nx + y * ic.ny > ic.s
         assert side.any() and (~side).any()
+
+
+def _boundary_faces(vxy, tri):
+    """(element, face) pairs whose edge belongs to one triangle only."""
+    e = np.sort(np.stack([tri, np.roll(tri, -1, axis=1)], axis=-1), axis=-1).reshape(-1, 2)
+    _, inv, cnt = np.unique(e, axis=0, return_inverse=True, return_counts=True)
+    b = (cnt[inv.ravel()] == 1).reshape(tri.shape)
+    return b
+
+
+def test_forward_step_mesh_geometry():
+    """Tunnel [0,4] x [0,1] without the step (1,4] x [0,0.2) (Section 4,
+    Example 6): 6.8 s^2 counter-clockwise triangles covering area 3.4, no
+    vertex inside the step, every boundary edge on the tunnel or step sides
+    and the kinds inlet / outlet / wall where they belong."""
+    for s in (5, 10, 20):
+        v, t = inputs.forward_step_mesh(s, seed=s)
+        assert t.shape == (round(6.8 * s * s), 3)
+        a = v[t]
+        ar = 0.5 * ((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
+                    - (a[:, 2, 0] - a[:, 0, 0]) * (a[:, 1, 1] - a[:, 0, 1]))
+        assert ar.min() > 0.5 * 0.5 * (0.8 / s) ** 2
+        assert math.isclose(ar.sum(), 3.4, rel_tol=1e-13)
+        assert not np.any((v[:, 0] > 1 + 1e-12) & (v[:, 1] < 0.2 - 1e-12))
+        assert len(np.unique(t)) == len(v)
+        b = _boundary_faces(v, t)
+        p, q = v[t], v[np.roll(t, -1, axis=1)]
+        xm, ym = 0.5 * (p[..., 0] + q[..., 0]), 0.5 * (p[..., 1] + q[..., 1])
+        flat = lambda z, c: np.abs(z - c) < 1e-12
+        on_side = (flat(xm, 0) | flat(xm, 4) | flat(ym, 1) | (flat(ym, 0) & (xm < 1))
+                   | (flat(xm, 1) & (ym < 0.2)) | (flat(ym, 0.2) & (xm > 1)))
+        assert np.array_equal(b, b & on_side) and on_side[b].all()
+        k = inputs.forward_step_kinds(v, t)[b]
+        assert (k == inputs.FFSTEP_INFLOW).sum() == s
+        assert (k == inputs.FFSTEP_OUTFLOW).sum() == round(0.8 * s)
+        assert (k == inputs.FFSTEP_WALL).sum() == round(8.2 * s)
+    # seeded
+    v1, _ = inputs.forward_step_mesh(10, seed=4)
+    v2, _ = inputs.forward_step_mesh(10, seed=4)
+    assert np.array_equal(v1, v2)
+    state = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE).state
+    rho, u, v, p = inputs.FFSTEP_PRIMITIVE
+    assert math.isclose(u / math.sqrt(1.4 * p / rho), 3.0)
+    assert np.allclose(state, [1.4, 4.2, 0.0, 1.0 / 0.4 + 0.5 * 1.4 * 9.0])
+
+
+def test_forward_step_shock_satisfies_jump_conditions():
+    """The two states of ForwardStepShock carry equal normal fluxes of mass,
+    momentum and energy (a stationary normal shock), and the state behind
+    is the compressive one (subsonic, denser)."""
+    f = inputs.ForwardStepShock(seed=1005)
+    g = inputs.GAMMA_GAS
+
+    def flux(q):
+        rho, m, _, E = q
+        u = m / rho
+        p = (g - 1.0) * (E - 0.5 * m * u)
+        return np.array([m, m * u + p, u * (E + p)]), p, rho, u
+
+    fa, pa, ra, ua = flux(f.pre)
+    fb, pb, rb, ub = flux(f.post)
+    assert np.allclose(fa, fb, rtol=1e-14)
+    assert rb > ra and pb > pa and ub / math.sqrt(g * pb / rb) < 1.0 < ua / math.sqrt(g * pa / ra)
+    x = np.array([0.0, 3.9, f.x0 - f.a * 0.25 - 1e-9, f.x0 - f.a * 0.25 + 1e-9])
+    y = np.array([0.5, 0.5, 0.5, 0.5])
+    w = f(x, y)
+    assert np.array_equal(w[[0, 2]], np.stack([f.pre, f.pre])) and np.array_equal(w[[1, 3]], np.stack([f.post, f.post]))

@@ -145,3 +145,39 @@ def test_inflow_ghost_is_the_inflow_state():
     out2 = csweno.reconstruct(d, U, cells)
     assert np.abs(out2 - out).max() > 1e-6
     assert np.array_equal(out[:, :, 0], U[cells][:, :, 0])
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_forward_step_uniform_mach3_closed_form(N):
+    """Uniform Mach 3 flow in the forward-step tunnel (Section 4, Example 6)
+    with the inflow state equal to it: the residual vanishes except in the
+    cells on the step's vertical face, where the wall meets the flow head-on.
+    There the reflected ghost carries the opposite normal momentum, so the
+    LF flux has no mass or energy part and x-momentum flux
+    rho u^2 + p + alpha rho u with alpha = |u| + c.  The rates of the domain
+    integrals are then inlet minus outlet (length 1 and 0.8) minus that wall
+    flux over the step height 0.2:
+    mass 0.2 rho u, x-momentum 0.2 (rho u^2 + p) - 0.2 (rho u^2 + p + 4 rho u),
+    energy 0.2 (E + p) u."""
+    v, t = inputs.forward_step_mesh(10, seed=3)
+    M = Mesh(v, t, BC_TRANSMISSIVE)
+    M.set_boundary_kinds(inputs.forward_step_kinds(v, t))
+    d = DG(M, N, 1)
+    rho, u0, _, p = inputs.FFSTEP_PRIMITIVE
+    ic = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
+    d.inflow = ic.state.copy()
+    U = d.project(ic)
+    R = d.residual(U)
+    # integrals: the mean mode times the cell's Jacobian times sqrt 2
+    assert math.isclose(math.sqrt(2.0) * np.sum(M.J * U[:, 0, 0]), rho * 3.4, rel_tol=1e-13)
+    rate = math.sqrt(2.0) * np.sum(M.J[:, None] * R[:, :, 0], axis=0)
+    E = p / 0.4 + 0.5 * rho * u0 * u0
+    exp = [0.2 * rho * u0, 0.2 * (rho * u0 * u0 + p) - 0.2 * (rho * u0 * u0 + p + 4.0 * rho * u0), 0.0,
+           0.2 * (E + p) * u0]
+    assert np.allclose(rate, exp, rtol=1e-12, atol=1e-12)
+    kind = M.boundary_kind()
+    a, b = M.V, np.roll(M.V, -1, axis=1)
+    xm, ym = 0.5 * (a[..., 0] + b[..., 0]), 0.5 * (a[..., 1] + b[..., 1])
+    head_on = np.any((kind == BKIND_WALL) & (np.abs(xm - 1.0) < 1e-12) & (ym < 0.2), axis=1)
+    assert head_on.sum() == 2
+    assert np.abs(R[~head_on]).max() < 1e-12 * np.abs(R).max()
