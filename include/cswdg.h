@@ -74,6 +74,7 @@ extern "C" {
 #define CSWDG_STATUS_NEGATIVE 0x2u  /* a non-positive Euler cell-mean density or pressure */
 #define CSWDG_STATUS_RANK 0x4u      /* a stencil least-squares system was rank deficient */
 #define CSWDG_STATUS_FOOT 0x8u      /* a perpendicular foot fell outside its side (midpoint used) */
+#define CSWDG_STATUS_SCALED 0x10u   /* the positivity scaling changed a cell (only with positivity = 1) */
 
 typedef struct cswdg_solver cswdg_solver;
 typedef struct cswdg_graph cswdg_graph;
@@ -93,6 +94,9 @@ typedef struct cswdg_params {
     int kxrcf_norm;   /* ||U_j|| of Section 3.1: 0 the literal (int U^2 dA)^(1/2), 1 divided by |Delta|^(1/2) (RMS) */
     int char_mode;    /* Euler limiting (Section 3.2, last paragraph): 0 characteristic fields, 1 conserved variables */
     int weights_mode; /* Section 3.2 Step 4: 0 nonlinear weights, 1 the linear weights (omega = gamma) */
+    /* not in the paper: 1 = after the limiter of every RK stage, the
+     * positivity-preserving scaling of cswdg_positivity (Euler only) */
+    int positivity;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream
@@ -288,6 +292,23 @@ int cswdg_troubled_count(cswdg_solver* s, int64_t* count);
  * number of limiter calls (host ints; synchronous).  reset != 0 clears both
  * after reading. */
 int cswdg_troubled_stats(cswdg_solver* s, int64_t* total_cells, int64_t* calls, int reset);
+/* Positivity-preserving scaling of an Euler state u (device [4][Np][K], in
+ * place; not part of the paper's method, which has no positivity limiter).
+ * Zhang and Shu's scaling (J. Comput. Phys. 229 (2010) 8918-8934; on
+ * triangles Zhang, Xia and Shu, J. Sci. Comput. 50 (2012) 29-62) at the
+ * points where the residual evaluates the solution (its volume points and
+ * the Gauss points of the three edges): with eps = min(1e-13, rhobar,
+ * pbar), the density's modes above the mean are multiplied by
+ * theta1 = min(1, (rhobar - eps)/(rhobar - min rho)), then every
+ * variable's modes above the mean by theta2, the smallest t in [0, 1] at
+ * which the pressure of (1 - t) Ubar + t U(x_q) reaches eps over the
+ * points below eps (1 if none).  Cell means are left bit for bit; a cell
+ * whose mean has rho <= 0 or p <= 0 (or is not finite) is left as it is.
+ * Sets CSWDG_STATUS_SCALED when a cell changed.  CSWDG_EINVAL for Burgers.
+ * With params.positivity = 1, cswdg_ssprk3_step (and graphs of it) apply it
+ * after the limiter of every stage. */
+int cswdg_positivity(cswdg_solver* s, void* u);
+
 /* Accumulated status bits CSWDG_STATUS_* since the last call (synchronous;
  * clears them). */
 int cswdg_status(cswdg_solver* s, uint32_t* flags);
@@ -301,7 +322,8 @@ int cswdg_profile(cswdg_solver* s, int enable);
 /* Restrict the recording to the kernel classes whose bit is set in
  * kernel_mask (bit i = entry i of cswdg_kernel_times: 0 residual_rk,
  * 1 max_dt, 2 kxrcf, 3 compact_mask, 4 limiter, 5 scatter, 6 copy, 7 zero,
- * 8 project, 9 residual_vjp, 10 limiter_vjp); all classes by default.
+ * 8 project, 9 residual_vjp, 10 limiter_vjp, 11 positivity); all classes
+ * by default.
  * Fewer events disturb the timed launches less. */
 int cswdg_profile_select(cswdg_solver* s, uint32_t kernel_mask);
 int cswdg_kernel_times(cswdg_solver* s, const char** names, double* total_ms, int64_t* counts,

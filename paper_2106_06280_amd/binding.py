@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libcswdg.so")
 EQ_BURGERS, EQ_EULER = 0, 1
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 LIMIT_KXRCF, LIMIT_ALL, LIMIT_NONE = 0, 1, 2
-STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_RANK, STATUS_FOOT = 1, 2, 4, 8
+STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_RANK, STATUS_FOOT, STATUS_SCALED = 1, 2, 4, 8, 16
 
 _lib = None
 
@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
     _fields_ = [("equation", ctypes.c_int), ("degree", ctypes.c_int), ("precision", ctypes.c_int),
                 ("limiter_mode", ctypes.c_int), ("gas_gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("c_k", ctypes.c_double), ("eps_weno", ctypes.c_double), ("kxrcf_norm", ctypes.c_int),
-                ("char_mode", ctypes.c_int), ("weights_mode", ctypes.c_int)]
+                ("char_mode", ctypes.c_int), ("weights_mode", ctypes.c_int), ("positivity", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -66,6 +66,7 @@ _SIGS = {
     "cswdg_profile": (ctypes.c_int, [_P, ctypes.c_int]),
     "cswdg_profile_select": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "cswdg_set_boundary": (ctypes.c_int, [_P, _P, _P]),
+    "cswdg_positivity": (ctypes.c_int, [_P, _P]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cswdg_mesh_upload_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "cswdg_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
@@ -125,11 +126,11 @@ class Solver:
     """One solver = one equation, degree and mesh on the current GPU."""
 
     def __init__(self, equation, degree, limiter_mode=LIMIT_KXRCF, precision=0, gamma=1.4, cfl=0.0,
-                 c_k=0.0, eps=0.0, stream=None, kxrcf_norm=0, char_mode=0, weights_mode=0):
+                 c_k=0.0, eps=0.0, stream=None, kxrcf_norm=0, char_mode=0, weights_mode=0, positivity=0):
         import torch
         self.torch = torch
         p = Params(equation, degree, precision, limiter_mode, gamma, cfl, c_k, eps, kxrcf_norm, char_mode,
-                   weights_mode)
+                   weights_mode, positivity)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -329,6 +330,13 @@ class Solver:
         self._c(lib().cswdg_rk_stage(self.h, int(stage), _ptr(u_n), _ptr(u_prev), _ptr(out), _ptr(dt)))
         return out
 
+    def positivity(self, u):
+        """Positivity-preserving scaling of an Euler state in place (not part
+        of the paper's method; see cswdg_positivity)."""
+        self._st(u, "u")
+        self._c(lib().cswdg_positivity(self.h, _ptr(u)))
+        return u
+
     def ssprk3_step(self, u, dt=None):
         self._st(u, "u")
         if dt is not None:
@@ -430,7 +438,7 @@ class Solver:
         return tuple(int(x) for x in a), {c: float(t[i]) for i, c in enumerate(cands[: n.value])}
 
     KERNEL_CLASSES = ("residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero",
-                      "project", "residual_vjp", "limiter_vjp")
+                      "project", "residual_vjp", "limiter_vjp", "positivity")
 
     def profile(self, enable=True, only=None):
         """HIP-event timing of every launch (or only of the named kernel

@@ -17,9 +17,9 @@ namespace {
 thread_local std::string g_err;
 
 const char* kKernelNames[] = {"residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero", "project",
-                              "residual_vjp", "limiter_vjp"};
+                              "residual_vjp", "limiter_vjp", "positivity"};
 enum KernelId { KID_RESIDUAL = 0, KID_DT, KID_KXRCF, KID_COMPACT, KID_LIMITER, KID_SCATTER, KID_COPY, KID_ZERO, KID_PROJECT,
-                KID_RESIDUAL_VJP, KID_LIMITER_VJP, KID_COUNT };
+                KID_RESIDUAL_VJP, KID_LIMITER_VJP, KID_POSITIVITY, KID_COUNT };
 
 std::mutex g_dev_mutex;
 std::vector<int> g_dev_tables;  // devices whose constant tables are uploaded
@@ -149,6 +149,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.char_mode != 0 || s->p.weights_mode != 0)
         return fail(s, CSWDG_EINVAL, "adjoint calls take the default limiter readings (char_mode = weights_mode = 0)");
     if (s->n_special != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take meshes without wall or inflow faces");
+    if (s->p.positivity != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take solvers without the positivity scaling");
     return CSWDG_OK;
 }
 
@@ -186,7 +187,11 @@ int rk_stage_impl(cswdg_solver* s, int stage, const void* u_n, const void* u_pre
         return launch_residual_reset(s->ctx, s->dm, stage, u_prev, u_n, out, dt, s->d_count);
     });
     if (e != hipSuccess) return hipfail(s, e, "residual");
-    return limit_into(s, out, out, nullptr, nullptr, s->p.limiter_mode, true);
+    int rc = limit_into(s, out, out, nullptr, nullptr, s->p.limiter_mode, true);
+    if (rc || !s->p.positivity) return rc;
+    e = timed(s, KID_POSITIVITY, [&] { return launch_positivity(s->ctx, s->dm, out, s->d_status); });
+    if (e != hipSuccess) return hipfail(s, e, "positivity");
+    return CSWDG_OK;
 }
 
 struct TapeView {
@@ -256,6 +261,9 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     if (p.kxrcf_norm < 0 || p.kxrcf_norm > 1 || p.char_mode < 0 || p.char_mode > 1 || p.weights_mode < 0 ||
         p.weights_mode > 1)
         return fail(nullptr, CSWDG_EINVAL, "kxrcf_norm, char_mode and weights_mode must be 0 or 1");
+    if (p.positivity < 0 || p.positivity > 1) return fail(nullptr, CSWDG_EINVAL, "positivity must be 0 or 1");
+    if (p.positivity && p.equation != CSWDG_EQ_EULER)
+        return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
     if (!(p.cfl > 0)) p.cfl = 0.3 / (2 * p.degree + 1);
     if (!(p.c_k > 0)) p.c_k = 1.0;
@@ -522,6 +530,16 @@ int cswdg_ssprk3_step(cswdg_solver* s, void* u, const double* dt_dev) {
     rc = rk_stage_impl(s, 2, u, s->d_T1, s->d_T2, dt);
     if (rc) return rc;
     return rk_stage_impl(s, 3, u, s->d_T2, u, dt);
+}
+
+int cswdg_positivity(cswdg_solver* s, void* u) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u) return fail(s, CSWDG_EINVAL, "null state");
+    if (s->p.equation != CSWDG_EQ_EULER) return fail(s, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
+    hipError_t e = timed(s, KID_POSITIVITY, [&] { return launch_positivity(s->ctx, s->dm, u, s->d_status); });
+    if (e != hipSuccess) return hipfail(s, e, "positivity");
+    return CSWDG_OK;
 }
 
 int cswdg_last_dt(cswdg_solver* s, double** dt_dev) {

@@ -118,6 +118,8 @@ hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uin
 hipError_t launch_compact_mask(const LaunchCtx& c, int K, const uint8_t* mask, uint8_t* flags,
                                int32_t* list, uint32_t* count);
 hipError_t launch_zero_u32(const LaunchCtx& c, uint32_t* p, int n);
+// positivity-preserving scaling of an Euler state in place (all elements)
+hipError_t launch_positivity(const LaunchCtx& c, const DevMesh& m, void* u, uint32_t* status);
 // limiter over the list; results to the compact buffer
 hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, const double* ops,
                           const int32_t* list, const uint32_t* count, double* compact,

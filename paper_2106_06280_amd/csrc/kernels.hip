@@ -20,6 +20,8 @@
 //               moments; results to a compact buffer (every cell reads the
 //               pre-limit field).
 //   k_scatter   compact results -> state (modes >= 1).
+//   k_positivity  optional, not in the paper: Zhang-Shu positivity scaling
+//               of every Euler cell at the residual's evaluation points.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -1125,6 +1127,97 @@ __global__ __launch_bounds__(256) void k_scatter(int K, S* __restrict__ u,
 }
 
 // ---------------------------------------------------------------------------
+// Positivity-preserving scaling (not part of the paper's method): Zhang and
+// Shu's scaling of the modes above the cell mean, first of the density so
+// that rho >= eps, then of all variables so that p >= eps, at the volume
+// points and the edge Gauss points where the residual evaluates u_h;
+// eps = min(1e-13, rhobar, pbar).  The pressure factor of a point below eps
+// is the root in [0, 1] of rho(t) (E(t) - eps/(gamma-1)) - |m(t)|^2 / 2 = 0
+// along U(t) = Ubar + t (U_q - Ubar), a quadratic in t whose value is >= 0
+// at t = 0 and < 0 at t = 1.  One thread per element; cells whose mean is
+// not admissible are left alone; a cell is rewritten only when scaled.
+// ---------------------------------------------------------------------------
+template <int NP>
+__device__ __forceinline__ double dot_modes(const double (&c)[NP], const double* __restrict__ phi) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) r = fma(c[i], phi[i], r);
+    return r;
+}
+
+__device__ __forceinline__ double pressure_root(const double (&ub)[4], const double (&uq)[4], double e) {
+    const double dr = uq[0] - ub[0], d1 = uq[1] - ub[1], d2 = uq[2] - ub[2], dE = uq[3] - ub[3];
+    const double a = dr * dE - 0.5 * (d1 * d1 + d2 * d2);
+    const double b = ub[0] * dE + dr * (ub[3] - e) - (ub[1] * d1 + ub[2] * d2);
+    const double c = ub[0] * (ub[3] - e) - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]);
+    double t;
+    if (fabs(a) <= 1e-14 * (fabs(b) + fabs(c))) {
+        t = (b < 0.0) ? -c / b : 0.0;
+    } else {
+        const double sq = sqrt(fmax(b * b - 4.0 * a * c, 0.0));
+        const double q = -0.5 * (b + copysign(sq, b));
+        const double r1 = q / a;
+        const double r2 = (q != 0.0) ? c / q : 0.0;
+        t = (r1 >= 0.0 && r1 <= 1.0) ? r1 : r2;
+    }
+    return fmin(fmax(t, 0.0), 1.0);
+}
+
+template <int N, typename S>
+__global__ __launch_bounds__(256) void k_positivity(int K, S* __restrict__ u, double gamma,
+                                                    uint32_t* __restrict__ status) {
+    using D = Dims<N>;
+    constexpr int NP = D::NP, NQ = D::NQ, NE = D::NE;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    const Tab<N>& T = tab<N>();
+    double c[4][NP];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) c[v][i] = (double)u[(size_t)(v * NP + i) * K + e];
+    const double psi0 = T.V[0][0];
+    double ub[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ub[v] = c[v][0] * psi0;
+    const double gm1 = gamma - 1.0;
+    const double pb = gm1 * (ub[3] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2]) / ub[0]);
+    if (!(ub[0] > 0.0) || !(pb > 0.0) || !(pb < INFINITY) || !(ub[0] < INFINITY)) return;
+    const double eps = fmin(1e-13, fmin(ub[0], pb));
+    // density
+    double rmin = INFINITY;
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) rmin = fmin(rmin, dot_modes<NP>(c[0], T.V[q]));
+#pragma unroll 1
+    for (int fg = 0; fg < 3 * NE; ++fg) rmin = fmin(rmin, dot_modes<NP>(c[0], T.PF[fg / NE][fg % NE]));
+    double th1 = 1.0;
+    if (rmin < eps) {
+        th1 = (ub[0] - eps) / (ub[0] - rmin);
+#pragma unroll
+        for (int i = 1; i < NP; ++i) c[0][i] *= th1;
+    }
+    // pressure
+    const double ee = eps / gm1;
+    double th2 = 1.0;
+#pragma unroll 1
+    for (int q = 0; q < NQ + 3 * NE; ++q) {
+        const double* phi = (q < NQ) ? T.V[q] : T.PF[(q - NQ) / NE][(q - NQ) % NE];
+        double uq[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) uq[v] = dot_modes<NP>(c[v], phi);
+        const double pq = gm1 * (uq[3] - 0.5 * (uq[1] * uq[1] + uq[2] * uq[2]) / uq[0]);
+        if (pq < eps) th2 = fmin(th2, pressure_root(ub, uq, ee));
+    }
+    if (th1 < 1.0 || th2 < 1.0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int i = 1; i < NP; ++i) u[(size_t)(v * NP + i) * K + e] = (S)(c[v][i] * th2);
+        atomicOr(status, CSWDG_STATUS_SCALED);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Initial data: quadrature points and L2 projection
 // ---------------------------------------------------------------------------
 template <int N>
@@ -1285,6 +1378,16 @@ hipError_t launch_scatter(const LaunchCtx& c, int K, void* u, const int32_t* lis
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
         k_scatter<N, Phys<EQ>::M, S><<<g, bs, 0, c.stream>>>(K, (S*)u, list, count, compact, tstats);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_positivity(const LaunchCtx& c, const DevMesh& m, void* u, uint32_t* status) {
+    if (c.eq != 1) return hipErrorInvalidValue;
+    if (m.K == 0) return hipSuccess;
+    const unsigned g = grid_for(m.K, 256);
+    CSWDG_DISPATCH_ENP(1, c.N, c.precision, {
+        k_positivity<N, S><<<g, 256, 0, c.stream>>>(m.K, (S*)u, c.gamma, status);
     });
     return hipGetLastError();
 }
