@@ -301,8 +301,8 @@ int cswdg_troubled_stats(cswdg_solver* s, int64_t* total_cells, int64_t* calls, 
  * pbar), the density's modes above the mean are multiplied by
  * theta1 = min(1, (rhobar - eps)/(rhobar - min rho)), then every
  * variable's modes above the mean by theta2, the smallest t in [0, 1] at
- * which the pressure of (1 - t) Ubar + t U(x_q) reaches eps over the
- * points below eps (1 if none).  Cell means are left bit for bit; a cell
+ * which the pressure of (1 - t) Ubar + t U(x_q) reaches
+ * eps_p = max(eps, 1e-10 pbar) over the points below eps_p (1 if none).  Cell means are left bit for bit; a cell
  * whose mean has rho <= 0 or p <= 0 (or is not finite) is left as it is.
  * Sets CSWDG_STATUS_SCALED when a cell changed.  CSWDG_EINVAL for Burgers.
  * With params.positivity = 1, cswdg_ssprk3_step (and graphs of it) apply it

@@ -6,7 +6,7 @@ baseline use it.
 The method is Zhang and Shu's (J. Comput. Phys. 229 (2010) 8918-8934) as
 extended to triangles by Zhang, Xia and Shu (J. Sci. Comput. 50 (2012)
 29-62): with the cell mean Ubar admissible, the modes above the mean are
-scaled towards it until density and then pressure are at least eps at
+scaled towards it until density and pressure reach their floors at
 every point where the residual evaluates the solution (its volume points
 and the Gauss points of the three edges):
 
@@ -14,18 +14,23 @@ and the Gauss points of the three edges):
    pbar <= 0 or a non-finite value is left as it is;
 2. theta1 = min(1, (rhobar - eps) / (rhobar - min_q rho_q)) scales the
    density's modes 1..Np-1;
-3. with that density, each point q whose pressure is below eps gets the
-   t_q in [0, 1] at which the pressure of (1 - t) Ubar + t U_q equals eps;
+3. with that density, each point q whose pressure is below the pressure
+   floor eps_p = max(eps, 1e-10 pbar) gets the t_q in [0, 1] at which the
+   pressure of (1 - t) Ubar + t U_q equals eps_p;
    the pressure is concave in U where rho > 0, so there is exactly one such
    t, found here by bisection to machine precision; theta2 = min_q t_q (1
-   if no point is below eps);
+   if no point is below eps_p);
 4. theta2 scales the modes 1..Np-1 of every variable.
 
-The cell mean (mode 0) is untouched, bit for bit.
+The cell mean (mode 0) is untouched, bit for bit.  The pressure floor is
+relative to the mean pressure, not Zhang and Shu's absolute 1e-13: near
+vacuum points (small rho_q) the pressure changes fast along the segment,
+and the rounding of the root then leaves the pressure up to about 1e-12
+away from the floor, below zero with a floor of 1e-13.
 
 Parity pins (tests/test_oracle_positivity.py): cells that are already
-positive come back unchanged; after scaling every point has rho, p >= eps
-(up to rounding) and the means are unchanged; a one-cell case with linear
+positive come back unchanged; after scaling every point is at or above
+the floors (up to rounding) and touches one of them and the means are unchanged; a one-cell case with linear
 density has theta1 in closed form; the pressure step against a brute-force
 scan of t.
 """
@@ -73,13 +78,14 @@ def scale(dg: DG, u, iters=64):
     # 3-4: pressure
     U = np.einsum("qn,kcn->kqc", P, out)  # [K, q, 4]
     p_q = _pressure(U, g)
-    below = ok[:, None] & (p_q < eps[:, None])
+    eps_p = np.maximum(eps, 1e-10 * pbar)
+    below = ok[:, None] & (p_q < eps_p[:, None])
     theta2 = np.ones(len(out))
     rows = np.nonzero(below.any(axis=1))[0]
     if len(rows):
         Ub = ubar[rows][:, None, :]
         dU = U[rows] - Ub
-        e = eps[rows][:, None]
+        e = eps_p[rows][:, None]
         lo = np.zeros(dU.shape[:2])
         hi = np.ones(dU.shape[:2])
         for _ in range(iters):

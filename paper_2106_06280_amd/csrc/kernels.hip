@@ -1129,10 +1129,12 @@ __global__ __launch_bounds__(256) void k_scatter(int K, S* __restrict__ u,
 // ---------------------------------------------------------------------------
 // Positivity-preserving scaling (not part of the paper's method): Zhang and
 // Shu's scaling of the modes above the cell mean, first of the density so
-// that rho >= eps, then of all variables so that p >= eps, at the volume
+// that rho >= eps, then of all variables so that p >= eps_p, at the volume
 // points and the edge Gauss points where the residual evaluates u_h;
-// eps = min(1e-13, rhobar, pbar).  The pressure factor of a point below eps
-// is the root in [0, 1] of rho(t) (E(t) - eps/(gamma-1)) - |m(t)|^2 / 2 = 0
+// eps = min(1e-13, rhobar, pbar), eps_p = max(eps, 1e-10 pbar) (a floor
+// relative to the mean pressure keeps the rounding of the root, large near
+// vacuum, from ending below zero).  The pressure factor of a point below
+// eps_p is the root in [0, 1] of rho(t) (E(t) - eps_p/(gamma-1)) - |m(t)|^2/2
 // along U(t) = Ubar + t (U_q - Ubar), a quadratic in t whose value is >= 0
 // at t = 0 and < 0 at t = 1.  One thread per element; cells whose mean is
 // not admissible are left alone; a cell is rewritten only when scaled.
@@ -1197,7 +1199,8 @@ __global__ __launch_bounds__(256) void k_positivity(int K, S* __restrict__ u, do
         for (int i = 1; i < NP; ++i) c[0][i] *= th1;
     }
     // pressure
-    const double ee = eps / gm1;
+    const double eps_p = fmax(eps, 1e-10 * pb);
+    const double ee = eps_p / gm1;
     double th2 = 1.0;
 #pragma unroll 1
     for (int q = 0; q < NQ + 3 * NE; ++q) {
@@ -1206,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_positivity(int K, S* __restrict__ u, do
 #pragma unroll
         for (int v = 0; v < 4; ++v) uq[v] = dot_modes<NP>(c[v], phi);
         const double pq = gm1 * (uq[3] - 0.5 * (uq[1] * uq[1] + uq[2] * uq[2]) / uq[0]);
-        if (pq < eps) th2 = fmin(th2, pressure_root(ub, uq, ee));
+        if (pq < eps_p) th2 = fmin(th2, pressure_root(ub, uq, ee));
     }
     if (th1 < 1.0 || th2 < 1.0) {
 #pragma unroll
