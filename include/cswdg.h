@@ -110,7 +110,10 @@ const char* cswdg_last_error(const cswdg_solver* s);
 /* Upload a triangulation (Section 2, eq. triangulation): host arrays
  * vxy [nv][2] (double) and tri [nt][3] (int32 vertex ids), read
  * synchronously and not retained.  bc = CSWDG_BC_*; period_x/period_y are
- * the domain periods for periodic meshes (ignored otherwise).  Builds the
+ * the domain periods for periodic meshes (ignored otherwise); a periodic
+ * mesh with one period 0 is periodic in the other direction only, and its
+ * unpaired boundary edges become boundary faces (outflow until
+ * cswdg_set_boundary says otherwise), as Example 4's sides.  Builds the
  * connectivity on the host, the element geometry and the per-element
  * stencil operators of the limiter on the device.  Synchronous. */
 int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt,

@@ -110,10 +110,14 @@ def connectivity(vxy, tri, bc, period=(0.0, 0.0)):
         match += m
         which = np.where(m, si, which)
     cnt = match.sum(axis=1)
-    if np.any(cnt != 1):
+    # periodic in one direction only (the other period 0, as Example 4's
+    # sides): edges without a partner stay boundary faces
+    one_way = (Px == 0.0) != (Py == 0.0)
+    if np.any(cnt > 1) or (not one_way and np.any(cnt != 1)):
         raise MeshError("unmatched or ambiguous periodic boundary edge")
+    info[e[boundary[cnt == 0]], f[boundary[cnt == 0]]] = INFO_BOUNDARY
     q = np.argmax(match, axis=1)
-    for p in range(len(boundary)):
+    for p in np.nonzero(cnt == 1)[0]:
         hp, hq = boundary[p], boundary[q[p]]
         sx, sy = shifts[which[p, q[p]]]
         ep, fp, eq_, fq = e[hp], f[hp], e[hq], f[hq]
@@ -144,13 +148,13 @@ def connectivity_bruteforce(vxy, tri, bc, period=(0.0, 0.0)):
                     qb = vxy[tri[e2, (f2 + 1) % 3]]
                     cands = [(0.0, 0.0)]
                     if bc == BC_PERIODIC:
-                        cands += [(Px, 0.0), (-Px, 0.0), (0.0, Py), (0.0, -Py)]
+                        cands += [c for c in [(Px, 0.0), (-Px, 0.0), (0.0, Py), (0.0, -Py)] if c != (0.0, 0.0)]
                     for sx, sy in cands:
                         if (np.allclose(qa + (sx, sy), pb, rtol=0, atol=1e-12)
                                 and np.allclose(qb + (sx, sy), pa, rtol=0, atol=1e-12)):
                             found.append((e2, f2, sx, sy))
             if len(found) == 0:
-                if bc == BC_PERIODIC:
+                if bc == BC_PERIODIC and Px != 0.0 and Py != 0.0:
                     raise MeshError("unmatched")
                 info[e, f] = INFO_BOUNDARY
             else:

@@ -149,6 +149,12 @@ int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri_in,
                     }
                 }
             }
+            // periodic in one direction only (the other period 0): an edge
+            // without a partner stays a boundary face
+            if (matches == 0 && (px == 0.0) != (py == 0.0)) {
+                m.info[boundary[p]] = 0x40;
+                continue;
+            }
             if (matches != 1) {
                 msg = "mesh: unmatched or ambiguous periodic boundary edge";
                 return CSWDG_EBADMESH;

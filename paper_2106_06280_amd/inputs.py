@@ -282,6 +282,30 @@ class FourQuadrant:
         return primitive_to_conservative(s[..., 0], s[..., 1], s[..., 2], s[..., 3])
 
 
+class ShockEntropyWave:
+    """Example 4 (Section 4): a shock at x = 0.125 moving right into density
+    sine waves on [0,1]^2, with the printed states (rho, u, v, p) =
+    (3.857143, 2.629369, 0, 10.333333) for x < 0.125 and
+    (1 + 0.2 sin(16 pi x), 0, 0, 1) otherwise; non-reflecting sides at x = 0
+    and x = 1, periodic in y.  The post-shock state is that of a Mach 3
+    shock running into rho = 1, p = 1, whose speed the mass jump condition
+    gives as shock_speed()."""
+
+    X0 = 0.125
+    POST = (3.857143, 2.629369, 0.0, 10.333333)
+
+    def __call__(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        pre = primitive_to_conservative(1.0 + 0.2 * np.sin(16.0 * np.pi * x), 0.0 * x, 0.0 * x, 1.0 + 0.0 * x)
+        post = primitive_to_conservative(*self.POST)
+        return np.where((x < self.X0)[..., None], post, pre)
+
+    @classmethod
+    def shock_speed(cls, rho_pre=1.0):
+        rho2, u2 = cls.POST[0], cls.POST[1]
+        return rho2 * u2 / (rho2 - rho_pre)
+
+
 # Printed initial states of the paper's Example 7 (configurations 3 and 12),
 # quadrant order as in FourQuadrant: (rho, u, v, p).
 RIEMANN_CONFIG3 = np.array([

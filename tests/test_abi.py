@@ -27,10 +27,10 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (5, 3), (17, 4)])
-@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
-def test_host_connectivity_bit_exact(n, seed, bc):
+@pytest.mark.parametrize("bc,period", [(BC_PERIODIC, (4.0, 2.0)), (BC_TRANSMISSIVE, (4.0, 2.0)),
+                                       (BC_PERIODIC, (4.0, 0.0)), (BC_PERIODIC, (0.0, 2.0))])
+def test_host_connectivity_bit_exact(n, seed, bc, period):
     v, t = inputs.jittered_mesh(n, -1.0, 3.0, 0.0, 2.0, seed=seed)
-    period = (4.0, 2.0)
     t2 = t.copy()
     t2[1::4, 1], t2[1::4, 2] = t[1::4, 2], t[1::4, 1]  # some clockwise triangles
     tc, nbr, info = binding.host_connectivity(v, t2, bc, period)

@@ -262,3 +262,59 @@ def test_forward_step_full_size_sampled(torch):
     exp = csweno.reconstruct(dg, u, E)
     assert np.array_equal(got[:, :, 0], u[E, :, 0])
     assert _relerr(got, exp) < 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_periodic_in_y_only_steps(torch, N):
+    """Example 4's domain: periodic in y, non-reflecting (outflow) sides at
+    x = 0 and x = 1 (a periodic mesh with period_x = 0); four steps of its
+    shock / entropy-wave data (cell means in the cells the shock line cuts)
+    against the oracle on the same mesh, every cell limited: ahead of the
+    shock the gas is at rest, where KXRCF's inflow test reads the sign of
+    rounding-level velocities and the two sides may flag different cells."""
+    from paper_2106_06280_amd import binding
+    v, t = inputs.jittered_mesh(8, seed=77)
+    M = Mesh(v, t, 0, (0.0, 1.0))
+    assert M.boundary_mask().sum() == 16
+    dg = DG(M, N, 1)
+    S = binding.Solver(1, N, limiter_mode=binding.LIMIT_ALL)
+    S.mesh_upload(v, t, 0, (0.0, 1.0))
+    u = dg.project(inputs.ShockEntropyWave())
+    u[np.abs(M.centroid[:, 0] - 0.125) < 1.0 / 8, :, 1:] = 0.0
+    ud = S.to_device(u)
+    lim = lambda w: csweno.limit(dg, w, np.ones(M.K, bool))
+    for _ in range(4):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert S.status() & 0x3 == 0
+
+
+def test_example4_shock_position_p1(torch):
+    """Example 4 at h = 1/100 (20,000 triangles), P1 with the positivity
+    scaling, run to the paper's t = 0.178: the shock (the rightmost cell
+    mean with p > 5.5, between the post-shock 10.33 and the pre-shock 1)
+    stands where the jump conditions move it, 0.125 + s t with
+    s = rho2 u2 / (rho2 - 1) = 3.5496, within one mesh width (the density
+    waves ahead change the speed only slightly)."""
+    import math
+    from paper_2106_06280_amd import binding
+    n, t_end = 100, 0.178
+    v, t = inputs.jittered_mesh(n, seed=1006)
+    S = binding.Solver(1, 1, positivity=1)
+    S.mesh_upload(v, t, 0, (0.0, 1.0))
+    u = S.project_fn(inputs.ShockEntropyWave())
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tt = 0.0
+    while tt < t_end:
+        S.max_dt(u, dt)
+        dt.clamp_(max=t_end - tt)
+        S.ssprk3_step(u, dt)
+        tt += float(dt.item())
+    assert S.status() & 0x3 == 0
+    m = (u[:, 0, :] / math.sqrt(2.0)).cpu().numpy()
+    p = 0.4 * (m[3] - 0.5 * (m[1] ** 2 + m[2] ** 2) / m[0])
+    xs = v[t].mean(axis=1)[p > 5.5, 0].max()
+    exp = 0.125 + inputs.ShockEntropyWave.shock_speed() * t_end
+    print(f"shock at {xs:.4f}, jump conditions {exp:.4f}", flush=True)
+    assert abs(xs - exp) < 1.0 / n

@@ -97,3 +97,20 @@ def test_forward_step_shock_satisfies_jump_conditions():
     y = np.array([0.5, 0.5, 0.5, 0.5])
     w = f(x, y)
     assert np.array_equal(w[[0, 2]], np.stack([f.pre, f.pre])) and np.array_equal(w[[1, 3]], np.stack([f.post, f.post]))
+
+
+def test_example4_states_are_a_mach3_shock():
+    """The printed post-shock state of Example 4 and rho = 1, u = 0, p = 1
+    satisfy the jump conditions of a shock moving at s = 3 c (Mach 3, c =
+    sqrt(1.4)) to the precision of the printed digits."""
+    g = inputs.GAMMA_GAS
+    s = inputs.ShockEntropyWave.shock_speed()
+    assert abs(s - 3.0 * math.sqrt(g)) < 1e-6
+    r2, u2, _, p2 = inputs.ShockEntropyWave.POST
+    E2 = p2 / (g - 1.0) + 0.5 * r2 * u2 * u2
+    r1, u1, p1 = 1.0, 0.0, 1.0
+    E1 = p1 / (g - 1.0)
+    # F(U2) - F(U1) = s (U2 - U1) for mass, momentum, energy
+    assert abs((r2 * u2 - r1 * u1) - s * (r2 - r1)) < 1e-5
+    assert abs((r2 * u2 * u2 + p2 - p1) - s * (r2 * u2)) < 1e-5 * p2
+    assert abs((u2 * (E2 + p2)) - s * (E2 - E1)) < 1e-5 * E2

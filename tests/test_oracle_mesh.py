@@ -11,13 +11,29 @@ from paper_2106_06280_amd import inputs
 
 
 @pytest.mark.parametrize("n", [1, 2, 3])
-@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
-def test_connectivity_matches_bruteforce(n, bc):
+@pytest.mark.parametrize("bc,period", [(BC_PERIODIC, (2.0, 2.0)), (BC_TRANSMISSIVE, (2.0, 2.0)),
+                                       (BC_PERIODIC, (2.0, 0.0)), (BC_PERIODIC, (0.0, 2.0))])
+def test_connectivity_matches_bruteforce(n, bc, period):
     v, t = inputs.jittered_mesh(n, 0.0, 2.0, -1.0, 1.0, seed=10 + n)
-    a = connectivity(v, t, bc, (2.0, 2.0))
-    b = connectivity_bruteforce(v, t, bc, (2.0, 2.0))
+    a = connectivity(v, t, bc, period)
+    b = connectivity_bruteforce(v, t, bc, period)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_periodic_in_one_direction():
+    """Periodic in y only (Example 4's sides): the n faces on x = 0 and the n
+    on x = 1 are boundary faces, the faces on y = 0 and y = 1 are paired
+    with a y shift."""
+    n = 4
+    v, t = inputs.jittered_mesh(n, seed=3)
+    tri, nbr, info = connectivity(v, t, BC_PERIODIC, (0.0, 1.0))
+    nb = (info & INFO_BOUNDARY) != 0
+    assert nb.sum() == 2 * n and np.all(nbr[nb] == -1)
+    mid = 0.5 * (v[tri] + v[np.roll(tri, -1, axis=1)])
+    assert np.all((np.abs(mid[nb][:, 0]) < 1e-12) | (np.abs(mid[nb][:, 0] - 1.0) < 1e-12))
+    cy = (info >> 4) & 3
+    assert (cy != 0).sum() == 2 * n and np.all((info >> 2) & 3 == 0)
 
 
 def test_connectivity_symmetric_and_shifts_cancel():
