@@ -97,6 +97,11 @@ typedef struct cswdg_params {
     /* not in the paper: 1 = after the limiter of every RK stage, the
      * positivity-preserving scaling of cswdg_positivity (Euler only) */
     int positivity;
+    /* Lax-Friedrichs constant (end of Section 2): 0 local, the larger normal
+     * wave speed of the two traces at each edge point; 1 global, one
+     * constant per residual and instance, the largest cell-mean wave speed
+     * of the residual's input state (the bound the time step uses) */
+    int lf_mode;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream

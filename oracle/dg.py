@@ -5,7 +5,10 @@ Readings (the paper prints a structured-mesh/1D form of the weak form and
 'f_hat_n = f(u_hat_n)', which has no meaning for a modal basis):
 
 * the flux is integrated by quadrature of F(u_h) (volume) and of the
-  Lax-Friedrichs flux of the two traces (edges);
+  Lax-Friedrichs flux of the two traces (edges), with alpha local to each
+  edge point (the larger normal wave speed of the two traces) or, with
+  `DG.lf_mode = 1`, one global constant per residual: the largest
+  cell-mean wave speed of the state;
 * L(u)_i = (1/J) [ sum_q w_q J grad(psi_i).F(u_h)(x_q)
                    - sum_f (L_f/2) sum_g w_g psi_i(x_g) F*.n_f ];
   with the orthonormal basis the mass matrix is J I (eq. massMatrix2D), so
@@ -76,6 +79,10 @@ class DG:
         self.et, self.ew = t, tw
         self.PF = np.stack([basis.vandermonde(N, *quadrature.face_reference_points(f, t)) for f in range(3)])  # [3, g, Np]
         self.inflow = np.zeros(self.m)  # state of inflow boundary faces (conserved variables)
+        # Lax-Friedrichs constant (end of Section 2): 0 local per point (the
+        # default reading), 1 one global constant per residual, the largest
+        # cell-mean wave speed of the state (the bound the time step uses)
+        self.lf_mode = 0
 
     # ------------------------------------------------------------------
     def project(self, fn, degree=None, elems=None):
@@ -119,6 +126,9 @@ class DG:
         PFrev = self.PF[:, ::-1, :]
         fprime = M.neighbour_face()
         bnd = M.boundary_mask()
+        a_glob = None
+        if self.lf_mode == 1:
+            a_glob = float(np.max(cell_mean_speed(self.eq, self.cell_means(u), self.gamma)))
         for f in range(3):
             um = np.einsum("gn,kcn->kgc", self.PF[f], ue)
             nb = M.nbr[E, f]
@@ -130,7 +140,7 @@ class DG:
             ny = np.broadcast_to(M.ny[E, f][:, None], um.shape[:2])
             kind = np.broadcast_to((M.info[E, f] & 3)[:, None], um.shape[:2])
             up = np.where(isb[:, None, None], ghost_state(self.eq, um, kind, nx, ny, self.inflow), up)
-            Fn = lax_friedrichs(self.eq, um, up, nx, ny, self.gamma)
+            Fn = lax_friedrichs(self.eq, um, up, nx, ny, self.gamma, a_glob)
             scale = M.L[E, f] / (2.0 * M.J[E])
             surf += scale[:, None, None] * np.einsum("g,gi,kgc->kci", self.ew, self.PF[f], Fn)
         return vol - surf

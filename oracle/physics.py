@@ -56,15 +56,20 @@ def normal_speed(eq, U, nx, ny, gamma=1.4):
     return np.abs(u * nx + v * ny) + c
 
 
-def lax_friedrichs(eq, Um, Up, nx, ny, gamma=1.4):
-    """Local Lax-Friedrichs normal flux F*.n for traces Um (inside), Up."""
+def lax_friedrichs(eq, Um, Up, nx, ny, gamma=1.4, alpha=None):
+    """Lax-Friedrichs normal flux F*.n for traces Um (inside), Up: local
+    (alpha per point from the two traces) unless a global constant alpha is
+    given."""
     fm, gm = flux(eq, Um, gamma)
     fp, gp = flux(eq, Up, gamma)
     nxe = nx[..., None]
     nye = ny[..., None]
     Fm = fm * nxe + gm * nye
     Fp = fp * nxe + gp * nye
-    alpha = np.maximum(normal_speed(eq, Um, nx, ny, gamma), normal_speed(eq, Up, nx, ny, gamma))
+    if alpha is None:
+        alpha = np.maximum(normal_speed(eq, Um, nx, ny, gamma), normal_speed(eq, Up, nx, ny, gamma))
+    else:
+        alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), nx.shape)
     return 0.5 * (Fm + Fp) - 0.5 * alpha[..., None] * (Up - Um)
 
 

@@ -64,6 +64,7 @@ struct cswdg_solver {
     double* d_inst_hmin = nullptr;
     unsigned long long* d_amax = nullptr;
     double* d_inflow = nullptr;   // [m] state of inflow boundary faces
+    double* d_lfa = nullptr;      // [n_inst] global Lax-Friedrichs constants (lf_mode = 1)
     int64_t n_special = 0;        // boundary faces of wall or inflow kind
     int dt_blocks = 1024;
     int64_t n_rank = 0, n_foot = 0;
@@ -96,7 +97,7 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
                     s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2,
-                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow};
+                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow, s->d_lfa};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -116,6 +117,7 @@ void free_mesh(cswdg_solver* s) {
     s->d_inst_hmin = nullptr;
     s->d_amax = nullptr;
     s->d_inflow = nullptr;
+    s->d_lfa = nullptr;
     s->n_special = 0;
     s->n_inst = 1;
     s->inst_off.clear();
@@ -150,6 +152,7 @@ int check_single(cswdg_solver* s) {
         return fail(s, CSWDG_EINVAL, "adjoint calls take the default limiter readings (char_mode = weights_mode = 0)");
     if (s->n_special != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take meshes without wall or inflow faces");
     if (s->p.positivity != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take solvers without the positivity scaling");
+    if (s->p.lf_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the local Lax-Friedrichs flux (lf_mode = 0)");
     return CSWDG_OK;
 }
 
@@ -182,8 +185,16 @@ int limit_into(cswdg_solver* s, const void* src, void* buf, uint8_t* flags_out, 
     return CSWDG_OK;
 }
 
+// the global Lax-Friedrichs constants of u, for a residual of u (lf_mode = 1)
+hipError_t lf_prepare(cswdg_solver* s, const void* u) {
+    if (!s->p.lf_mode) return hipSuccess;
+    return timed(s, KID_DT, [&] { return launch_lf_alpha(s->ctx, s->dm, u, s->d_amax, s->d_lfa, s->d_status); });
+}
+
 int rk_stage_impl(cswdg_solver* s, int stage, const void* u_n, const void* u_prev, void* out, const double* dt) {
-    hipError_t e = timed(s, KID_RESIDUAL, [&] {
+    hipError_t e = lf_prepare(s, u_prev);
+    if (e != hipSuccess) return hipfail(s, e, "Lax-Friedrichs constant");
+    e = timed(s, KID_RESIDUAL, [&] {
         return launch_residual_reset(s->ctx, s->dm, stage, u_prev, u_n, out, dt, s->d_count);
     });
     if (e != hipSuccess) return hipfail(s, e, "residual");
@@ -262,6 +273,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         p.weights_mode > 1)
         return fail(nullptr, CSWDG_EINVAL, "kxrcf_norm, char_mode and weights_mode must be 0 or 1");
     if (p.positivity < 0 || p.positivity > 1) return fail(nullptr, CSWDG_EINVAL, "positivity must be 0 or 1");
+    if (p.lf_mode < 0 || p.lf_mode > 1) return fail(nullptr, CSWDG_EINVAL, "lf_mode must be 0 or 1");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
@@ -467,7 +479,9 @@ int cswdg_dg_residual(cswdg_solver* s, const void* u, void* r) {
     int rc = check_ready(s);
     if (rc) return rc;
     if (!u || !r || u == r) return fail(s, CSWDG_EINVAL, "u and r must be distinct non-null buffers");
-    hipError_t e = timed(s, KID_RESIDUAL, [&] { return launch_residual_reset(s->ctx, s->dm, 0, u, nullptr, r, nullptr, nullptr); });
+    hipError_t e = lf_prepare(s, u);
+    if (e == hipSuccess)
+        e = timed(s, KID_RESIDUAL, [&] { return launch_residual_reset(s->ctx, s->dm, 0, u, nullptr, r, nullptr, nullptr); });
     return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "residual");
 }
 
@@ -742,7 +756,7 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
     const int saved_xcd = s->dm.xcd_tiles;
     double best = INFINITY;
     int bi = -1, k = 0;
-    hipError_t e = hipSuccess;
+    hipError_t e = lf_prepare(s, u);
     for (int v : variants)
         for (int b : blocks)
             for (int x : xcds) {
@@ -963,6 +977,7 @@ int upload_mesh(cswdg_solver* s) {
         {(void**)&s->d_inst_hmin, sizeof(double) * s->n_inst},
         {(void**)&s->d_amax, sizeof(unsigned long long) * s->n_inst},
         {(void**)&s->d_inflow, sizeof(double) * 4},
+        {(void**)&s->d_lfa, sizeof(double) * s->n_inst},
         {(void**)&s->d_T1, sizeof(double) * NPM * K},
         {(void**)&s->d_T2, sizeof(double) * NPM * K},
     };
@@ -1003,6 +1018,7 @@ int upload_mesh(cswdg_solver* s) {
     s->dm.inflow = s->d_inflow;
     s->n_special = 0;
     s->dm.inst_off = s->d_inst_off;
+    s->dm.lf_alpha = s->p.lf_mode ? s->d_lfa : nullptr;
     {
         const char* xt = std::getenv("CSWDG_XCD_TILES");
         s->dm.xcd_tiles = xt ? std::atoi(xt) : 1;

@@ -178,6 +178,13 @@ __device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
     return lo;
 }
 
+// Lax-Friedrichs constant of the element's instance when one global constant
+// per residual is set (DevMesh::lf_alpha), else -1 (local: the larger
+// normal wave speed of the two traces at each point)
+__device__ __forceinline__ double lf_global(const DevMesh& m, int e) {
+    return m.lf_alpha ? m.lf_alpha[inst_of(m, e)] : -1.0;
+}
+
 // ---------------------------------------------------------------------------
 // Physics: fluxes and wave speeds (Section 4 eqs. 2dBurgers, 2dEulerEquations)
 // ---------------------------------------------------------------------------

@@ -83,6 +83,7 @@ struct DevMesh {
     const double* inflow;  // [m] state of inflow boundary faces (conserved variables)
     int n_inst;            // independent meshes held (1 for a single mesh)
     const int32_t* inst_off;  // [n_inst + 1] first element of each instance
+    const double* lf_alpha;   // [n_inst] global Lax-Friedrichs constants, or null (local)
 };
 
 struct LaunchCtx {
@@ -118,6 +119,10 @@ hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uin
 hipError_t launch_compact_mask(const LaunchCtx& c, int K, const uint8_t* mask, uint8_t* flags,
                                int32_t* list, uint32_t* count);
 hipError_t launch_zero_u32(const LaunchCtx& c, uint32_t* p, int n);
+// global Lax-Friedrichs constants: alpha[i] = the largest cell-mean wave
+// speed of instance i of u (amax_bits [n_inst] zero on entry and exit)
+hipError_t launch_lf_alpha(const LaunchCtx& c, const DevMesh& m, const void* u, unsigned long long* amax_bits,
+                           double* alpha, uint32_t* status);
 // positivity-preserving scaling of an Euler state in place (all elements)
 hipError_t launch_positivity(const LaunchCtx& c, const DevMesh& m, void* u, uint32_t* status);
 // limiter over the list; results to the compact buffer

@@ -47,6 +47,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
+    const double ag = lf_global(msh, e);  // < 0: local Lax-Friedrichs
     const Tab<N>& T = tab<N>();
 
     double U[M][NP];
@@ -127,7 +128,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(up, nx, ny, gamma, Fp, lp);
-            const double alpha = fmax(lm, lp);
+            const double alpha = (ag >= 0.0) ? ag : fmax(lm, lp);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (up[c] - um[c]);
@@ -189,6 +190,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
+    const double ag = lf_global(msh, e);  // < 0: local Lax-Friedrichs
     const Tab<N>& T = tab<N>();
 
     double U[M][NP];
@@ -278,7 +280,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
-            const double alpha = fmax(lm, lp);
+            const double alpha = (ag >= 0.0) ? ag : fmax(lm, lp);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
@@ -325,6 +327,7 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
+    const double ag = lf_global(msh, e);  // < 0: local Lax-Friedrichs
     const auto& T = TabOf<N, R>::get();
     const R gm = (R)gamma;
 
@@ -405,7 +408,7 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
             R Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gm, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gm, Fp, lp);
-            const R alpha = max_r(lm, lp);
+            const R alpha = (ag >= 0.0) ? (R)ag : max_r(lm, lp);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const R Fs = R(0.5) * (Fm[c] + Fp[c]) - R(0.5) * alpha * (upg[c] - um[c]);
@@ -473,6 +476,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
     if (e >= K) return;
+    const double ag = lf_global(msh, e);  // < 0: local Lax-Friedrichs
     const Tab<N>& T = tab<N>();
 
     // the element's coefficients are re-read (cache hits) in every phase
@@ -570,7 +574,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
-            const double alpha = fmax(lm, lp);
+            const double alpha = (ag >= 0.0) ? ag : fmax(lm, lp);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
@@ -717,6 +721,16 @@ __global__ __launch_bounds__(256) void k_dt_inst_final(int n, unsigned long long
     if (i >= n) return;
     const double a = __longlong_as_double((long long)amax_bits[i]);
     dt[i] = cfl * hmin[i] / a;
+    amax_bits[i] = 0ull;
+}
+
+// the global Lax-Friedrichs constant of each instance: its largest cell-mean
+// wave speed (the reduction of k_dt_inst), left for the residual
+__global__ __launch_bounds__(256) void k_lf_alpha_final(int n, unsigned long long* __restrict__ amax_bits,
+                                                        double* __restrict__ alpha) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    alpha[i] = __longlong_as_double((long long)amax_bits[i]);
     amax_bits[i] = 0ull;
 }
 
@@ -1335,6 +1349,16 @@ hipError_t launch_max_dt_inst(const LaunchCtx& c, const DevMesh& m, const void* 
         k_dt_inst<EQ, N, S><<<g, 256, 0, c.stream>>>(m, (const S*)u, c.gamma, amax_bits, status);
     });
     k_dt_inst_final<<<grid_for(m.n_inst, 256), 256, 0, c.stream>>>(m.n_inst, amax_bits, c.cfl, hmin, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_lf_alpha(const LaunchCtx& c, const DevMesh& m, const void* u, unsigned long long* amax_bits,
+                           double* alpha, uint32_t* status) {
+    const unsigned g = grid_for(m.K, 256);
+    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        k_dt_inst<EQ, N, S><<<g, 256, 0, c.stream>>>(m, (const S*)u, c.gamma, amax_bits, status);
+    });
+    k_lf_alpha_final<<<grid_for(m.n_inst, 256), 256, 0, c.stream>>>(m.n_inst, amax_bits, alpha);
     return hipGetLastError();
 }
 

@@ -324,3 +324,71 @@ def test_residual_schedules_parity(torch, eq, N, variant):
         pv = S.to_host(prev)
         exp = a * u + b * (pv + dt * dg.residual(pv))
         assert _relerr(S.to_host(out), exp) < TOL, stage
+
+
+def _lf_case(eq, N, n, bc, seed, **kw):
+    b = _binding()
+    v, t = inputs.jittered_mesh(n, seed=seed)
+    M = Mesh(v, t, bc, (1.0, 1.0))
+    dg = DG(M, N, eq)
+    dg.lf_mode = 1
+    S = b.Solver(eq, N, lf_mode=1, **kw)
+    S.mesh_upload(v, t, bc, (1.0, 1.0))
+    return M, dg, S
+
+
+@pytest.mark.parametrize("variant", [3, 0, 2])
+@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
+@pytest.mark.parametrize("eq,N", EQN)
+def test_residual_global_lax_friedrichs(torch, eq, N, bc, variant):
+    """lf_mode = 1: one Lax-Friedrichs constant per residual, the largest
+    cell-mean wave speed of the input, in every residual schedule."""
+    M, dg, S = _lf_case(eq, N, 12, bc, seed=151 + N)
+    S.set_schedule(variant, 128, 1)
+    for u in (_smooth_state(dg, eq, seed=N), _jump_state(dg, eq, seed=N)):
+        r = S.to_host(S.dg_residual(S.to_device(u)))
+        ref = dg.residual(u)
+        assert _relerr(r, ref) < TOL
+    # and it is not the local flux on discontinuous data
+    dg.lf_mode = 0
+    assert np.abs(dg.residual(u) - ref).max() > 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("eq,N", [(0, 2), (1, 2)])
+def test_steps_global_lax_friedrichs(torch, eq, N):
+    M, dg, S = _lf_case(eq, N, 12, BC_TRANSMISSIVE, seed=161)
+    u = _jump_state(dg, eq, seed=3)
+    ud = S.to_device(u)
+    lim = lambda v: csweno.limit(dg, v, kxrcf.indicator(dg, v)[1])
+    for _ in range(3):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert S.status() & 0x7 == 0
+
+
+def test_global_lax_friedrichs_per_instance(torch):
+    """A batch with lf_mode = 1 takes each instance's own constant: equal bit
+    for bit to the instances run alone; adjoint calls reject the mode."""
+    b = _binding()
+    meshes, sol, us = [], [], []
+    for i, n in enumerate((5, 8, 6)):
+        v, t = inputs.jittered_mesh(n, seed=300 + i)
+        meshes.append((v, t))
+        S = b.Solver(1, 2, lf_mode=1)
+        S.mesh_upload(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+        sol.append(S)
+        us.append(S.project_fn(inputs.FourQuadrant(seed=10 + i, xc=0.45, yc=0.55, rho_range=(0.6, 1.4),
+                                                  p_range=(0.6, 1.4), vel_range=(-0.5, 0.5))))
+    B = b.Solver(1, 2, lf_mode=1)
+    B.mesh_upload_batch(meshes, [BC_TRANSMISSIVE] * 3, (1.0, 1.0))
+    ub = torch.cat(us, dim=2).contiguous()
+    off = B.instances()
+    for _ in range(3):
+        B.ssprk3_step(ub)
+        for S, u in zip(sol, us):
+            S.ssprk3_step(u)
+    for i, u in enumerate(us):
+        assert torch.equal(ub[:, :, off[i]:off[i + 1]], u), i
+    with pytest.raises(b.CswdgError):
+        sol[0].dg_residual_vjp(us[0], us[0].clone())

@@ -32,14 +32,17 @@ def _poly(N):
     return u, ux, uy
 
 
+@pytest.mark.parametrize("lf", [0, 1])
 @pytest.mark.parametrize("N", [1, 2, 3])
-def test_burgers_residual_exact_on_global_polynomials(N):
+def test_burgers_residual_exact_on_global_polynomials(N, lf):
     """Transmissive boundaries and continuous polynomial data: every face
-    flux equals the physical flux, so L(u) = Pi_N(-div F(u)) exactly with
-    the volume and edge rules' degrees (3N-1 and 3N)."""
+    flux equals the physical flux (whatever the Lax-Friedrichs constant,
+    local or global, since the traces agree), so L(u) = Pi_N(-div F(u))
+    exactly with the volume and edge rules' degrees (3N-1 and 3N)."""
     v, t = inputs.jittered_mesh(4, -1, 1, -1, 1, seed=2)
     M = Mesh(v, t, BC_TRANSMISSIVE)
     d = DG(M, N, 0)
+    d.lf_mode = lf
     u, ux, uy = _poly(N)
     U = d.project(u)
     L = d.residual(U)
@@ -57,11 +60,13 @@ def test_euler_freestream(bc, N):
     assert np.abs(d.residual(U)).max() < 1e-12
 
 
+@pytest.mark.parametrize("lf", [0, 1])
 @pytest.mark.parametrize("N", [1, 2, 3])
-def test_conservation_periodic(N):
+def test_conservation_periodic(N, lf):
     v, t = inputs.jittered_mesh(5, seed=6)
     M = Mesh(v, t, BC_PERIODIC, (1.0, 1.0))
     d = DG(M, N, 1)
+    d.lf_mode = lf
     rng = np.random.default_rng(N)
     U = d.project(inputs.IsentropicVortex(beta=2.0, x0=0.5, y0=0.5, period_x=1, period_y=1))
     U[:, :, 1:] += 0.01 * rng.standard_normal(U[:, :, 1:].shape)
@@ -116,3 +121,27 @@ def test_burgers_convergence_without_limiter(N):
 def test_entropy_wave_convergence_without_limiter(N):
     _, o = oracle_runs.convergence("entropy", N, [8, 16], 0.2, False)
     assert abs(o[-1] - ORDERS[(2, N)][0]) < 0.45, o
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_global_lax_friedrichs_dissipates_more(N):
+    """Burgers, cellwise-constant data on a periodic mesh: the rate of the
+    discrete energy sum_e J_e u_e L_e is the flux part minus the
+    dissipation alpha/2 |jump|^2 summed over faces, so the global constant
+    (the largest cell-mean speed, never below a face's local alpha) gives a
+    rate at most the local one's, and strictly below where some face's
+    local alpha is smaller."""
+    v, t = inputs.jittered_mesh(6, seed=8)
+    M = Mesh(v, t, BC_PERIODIC, (1.0, 1.0))
+    rng = np.random.default_rng(3)
+    rates = []
+    for lf in (0, 1):
+        d = DG(M, N, 0)
+        d.lf_mode = lf
+        U = np.zeros((M.K, 1, d.Np))
+        U[:, 0, 0] = rng.uniform(-1.0, 1.0, M.K) if lf == 0 else U0
+        if lf == 0:
+            U0 = U[:, 0, 0].copy()
+        L = d.residual(U)
+        rates.append(np.sum(M.J * U[:, 0, 0] * L[:, 0, 0]))
+    assert rates[1] < rates[0] - 1e-6 * abs(rates[0])
