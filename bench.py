@@ -29,7 +29,8 @@ inflow of the uniform Mach 3 flow (rho 1.4, u 3, v 0, p 1) at x = 0,
 outflow at x = 4, reflective walls elsewhere; initialised with that flow.
 The positivity-preserving scaling (not in the paper) follows the limiter
 of every stage: without it the impulsive start at the step loses
-positivity within two steps.  The flow first develops for --develop steps
+positivity within two steps.  --workload p1_euler_ffstep: the same with
+P1, whose run to the paper's t = 4 is part of the default line.  The flow first develops for --develop steps
 (default 4000, untimed, in graph launches of 100 steps); then K steps are
 timed as one graph launch (after one untimed launch) and as plain
 launches.  --t-end T adds a run from the initial flow to time T (the
@@ -198,12 +199,12 @@ def run_batch(args):
 FFSTEP = {"s": 110, "seed": 1005}
 
 
-def ffstep_solver():
+def ffstep_solver(degree=2):
     from paper_2106_06280_amd import binding, inputs
     v, t = inputs.forward_step_mesh(FFSTEP["s"], seed=FFSTEP["seed"])
     kinds = inputs.forward_step_kinds(v, t)
     inflow = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
-    S = binding.Solver(binding.EQ_EULER, 2, limiter_mode=binding.LIMIT_KXRCF, positivity=1)
+    S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1)
     S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
     S.set_boundary(kinds, inflow.state)
     return S, v, t, kinds, inflow
@@ -246,13 +247,14 @@ def run_to_time(S, u, t_end, check_every=1000):
     return {"t": float(t.item()), "steps": steps, "seconds": round(time.perf_counter() - t0, 3)}
 
 
-def run_ffstep(args):
+def run_ffstep(args, degree=2):
     import torch
 
     from paper_2106_06280_amd import binding
 
+    name = f"p{degree}_euler_ffstep"
     t0 = time.perf_counter()
-    S, _, _, _, inflow = ffstep_solver()
+    S, _, _, _, inflow = ffstep_solver(degree)
     u = S.project_fn(inflow)
     K, m, Np = S.K, S.m, S.Np
     chunk = 100
@@ -261,7 +263,7 @@ def run_ffstep(args):
         dev.launch()
     torch.cuda.synchronize()
     st_dev = S.status()
-    print(f"[bench] p2_euler_ffstep: K={K}, developed {args.develop} steps in "
+    print(f"[bench] {name}: K={K}, developed {args.develop} steps in "
           f"{time.perf_counter() - t0:.1f}s, status {st_dev}", file=sys.stderr, flush=True)
     g = binding.Graph([S], [u], nsteps=args.steps)
     g.launch()  # warm-up
@@ -300,7 +302,7 @@ def run_ffstep(args):
     bytes_launch = K * (8 * Np * m * 8.0 / 3.0 + 6 * 8 + 3 * 4 + 4)
     ach = bytes_launch / avg / 1e9
     out = {
-        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P2 Euler, forward-facing step)",
+        "metric": f"DOF-updates/s per SSP-RK stage incl. CSWENO (P{degree} Euler, forward-facing step)",
         "value": dof * 3 * args.steps / secs,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
@@ -312,7 +314,7 @@ def run_ffstep(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "p2_euler_ffstep", "triangles": K, "degree": 2, "dof": dof,
+        "config": {"workload": name, "triangles": K, "degree": degree, "dof": dof,
                    "developed_steps": args.develop, "troubled_fraction": round(tot / max(1, calls * K), 5),
                    "boundaries": "inflow x=0, outflow x=4, reflective walls", "limiter": "kxrcf+csweno",
                    "parallelism": "single-gpu"},
@@ -325,10 +327,11 @@ def run_ffstep(args):
         "status_bits": status,
         "status_bits_develop": st_dev,
     }
-    if args.t_end > 0:
+    t_end = args.t_end if args.t_end is not None else (4.0 if degree == 1 else 0.0)
+    if t_end > 0:
         u2 = S.project_fn(inflow)
         S.status()
-        run = run_to_time(S, u2, args.t_end)
+        run = run_to_time(S, u2, t_end)
         run["status_bits"] = S.status()
         run["finite"] = bool(torch.isfinite(u2).all())
         means = u2[:, 0, :] / math.sqrt(2.0)
@@ -501,11 +504,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS) + ["c4_batch", "p2_euler_ffstep", "p1_euler_shock_entropy"])
+    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS) + ["c4_batch", "p2_euler_ffstep", "p1_euler_ffstep",
+                                                                  "p1_euler_shock_entropy"])
     ap.add_argument("--develop", type=int, default=4000,
                     help="p2_euler_ffstep: untimed steps that develop the flow first")
-    ap.add_argument("--t-end", type=float, default=0.0,
-                    help="p2_euler_ffstep: also run from the initial flow to this time")
+    ap.add_argument("--t-end", type=float, default=None,
+                    help="p2/p1_euler_ffstep: also run from the initial flow to this time "
+                         "(default: none for P2, the paper's 4 for P1)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -540,8 +545,8 @@ def main():
     if args.workload == "c4_batch":
         run_batch(args)
         return
-    if args.workload == "p2_euler_ffstep":
-        run_ffstep(args)
+    if args.workload in ("p2_euler_ffstep", "p1_euler_ffstep"):
+        run_ffstep(args, degree=int(args.workload[1]))
         return
     if args.workload == "p1_euler_shock_entropy":
         run_shock_entropy(args)

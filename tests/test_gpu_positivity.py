@@ -135,3 +135,34 @@ def test_forward_step_full_size_runs_positive(torch):
     p = 0.4 * (means[:, 3] - 0.5 * (means[:, 1] ** 2 + means[:, 2] ** 2) / means[:, 0])
     assert means[:, 0].min() > 0 and p.min() > 0
     print(f"status {st}, min rho {means[:, 0].min():.4f}, min p {p.min():.4f}", flush=True)
+
+
+def test_forward_step_p1_reaches_the_papers_time(torch):
+    """Example 6 at its full size with P1 and the scaling runs to the
+    paper's t = 4 (about 50,000 steps): finite, positive cell means, and
+    the reflected shocks compress the gas well above the inflow density."""
+    import math
+    import time
+    from paper_2106_06280_amd import binding
+    M, dg, S, ic = _ffstep(110, seed=1005, N=1)
+    u = S.project_fn(ic)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.status()
+    t0 = time.perf_counter()
+    steps = 0
+    while float(t.item()) < 4.0:
+        for _ in range(1000):
+            S.max_dt(u, dt)
+            S.ssprk3_step(u, dt)
+            t += dt
+        steps += 1000
+        assert S.status() & (binding.STATUS_NONFINITE | binding.STATUS_NEGATIVE) == 0, steps
+        assert steps < 80000
+    means = (u[:, 0, :] / math.sqrt(2.0)).cpu().numpy()
+    p = 0.4 * (means[3] - 0.5 * (means[1] ** 2 + means[2] ** 2) / means[0])
+    print(f"t = {float(t.item()):.3f} after {steps} steps, {time.perf_counter() - t0:.1f} s; "
+          f"rho in [{means[0].min():.3f}, {means[0].max():.3f}]", flush=True)
+    assert bool(torch.isfinite(u).all())
+    assert means[0].min() > 0 and p.min() > 0
+    assert means[0].max() > 3.0
