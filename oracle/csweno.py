@@ -282,15 +282,21 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
         avg[name] = np.stack([neighbour_average(dg, u, E, nid, shift, f, pcs[name][:, f]) for f in range(3)], axis=1)
     # ghost cells of boundary faces carry the boundary's ghost state: the
     # mirrored polynomial (outflow), the same with its normal momentum
-    # reversed (reflective wall), the inflow state on every piece (inflow);
-    # averaging commutes with the reflection
+    # reversed (reflective wall), the inflow state on every piece (inflow),
+    # the moving shock's state at the face midpoint and the solution time on
+    # every piece (moving shock); averaging commutes with the reflection
     for f in range(3):
         isb = (M.info[E, f] & INFO_BOUNDARY) != 0
         if not isb.any():
             continue
         kind = np.where(isb, M.info[E, f] & 3, 0)
+        xm = ym = None
+        if dg.shock is not None:
+            mid = 0.5 * (M.V[E, f] + M.V[E, (f + 1) % 3])
+            xm, ym = mid[:, 0], mid[:, 1]
         for name in pcs:
-            g = ghost_state(dg.eq, avg[name][:, f], kind, M.nx[E, f], M.ny[E, f], dg.inflow)
+            g = ghost_state(dg.eq, avg[name][:, f], kind, M.nx[E, f], M.ny[E, f], dg.inflow, dg.shock, xm, ym,
+                            dg.time)
             avg[name][:, f] = np.where(isb[:, None], g, avg[name][:, f])
     ubar0 = u[E, :, 0] * PSI0  # [T, m]
 

@@ -83,6 +83,12 @@ class DG:
         # default reading), 1 one global constant per residual, the largest
         # cell-mean wave speed of the state (the bound the time step uses)
         self.lf_mode = 0
+        # moving planar shock of boundary kind 3 (Example 5's top boundary):
+        # dict(n, d0, w, post, pre) of physics.moving_shock_state, and the
+        # solution time; a step evaluates the residual of its stages at
+        # t, t + dt and t + dt/2 and the limiter at t, then advances t
+        self.shock = None
+        self.time = 0.0
 
     # ------------------------------------------------------------------
     def project(self, fn, degree=None, elems=None):
@@ -109,9 +115,11 @@ class DG:
         return u[:, :, 0] * PSI0
 
     # ------------------------------------------------------------------
-    def residual(self, u, elems=None):
-        """L(u) for the elements in elems (all if None): [len, m, Np]."""
+    def residual(self, u, elems=None, t=None):
+        """L(u) for the elements in elems (all if None): [len, m, Np]; t is
+        the time of u for the moving-shock boundary (self.time if None)."""
         M = self.mesh
+        t = self.time if t is None else t
         E = np.arange(M.K) if elems is None else np.asarray(elems)
         ue = u[E]
         # volume term: sum_q w_q (dpsi/dr (r_x f + r_y g) + dpsi/ds (s_x f + s_y g))
@@ -134,12 +142,16 @@ class DG:
             nb = M.nbr[E, f]
             isb = bnd[E, f]
             nb_safe = np.where(isb, E, nb)
-            sel = PFrev[fprime[E, f]]  # [k, g, n]
+            sel = PFrev[np.where(isb, 0, fprime[E, f])]  # [k, g, n]; boundary faces: unused
             up = np.einsum("kgn,kcn->kgc", sel, u[nb_safe])
             nx = np.broadcast_to(M.nx[E, f][:, None], um.shape[:2])
             ny = np.broadcast_to(M.ny[E, f][:, None], um.shape[:2])
             kind = np.broadcast_to((M.info[E, f] & 3)[:, None], um.shape[:2])
-            up = np.where(isb[:, None, None], ghost_state(self.eq, um, kind, nx, ny, self.inflow), up)
+            xg = yg = None
+            if self.shock is not None:
+                xg, yg = M.physical_points(*quadrature.face_reference_points(f, self.et), elems=E)
+            up = np.where(isb[:, None, None], ghost_state(self.eq, um, kind, nx, ny, self.inflow, self.shock, xg, yg, t),
+                          up)
             Fn = lax_friedrichs(self.eq, um, up, nx, ny, self.gamma, a_glob)
             scale = M.L[E, f] / (2.0 * M.J[E])
             surf += scale[:, None, None] * np.einsum("g,gi,kgc->kci", self.ew, self.PF[f], Fn)
@@ -157,7 +169,15 @@ class DG:
         return rk_stage(i, stages, dt, self.residual, limiter)
 
     def ssprk3_step(self, u, dt, limiter=None):
-        return ssprk3_step(u, dt, self.residual, limiter)
+        """One step from self.time: the residual of stage i's input at
+        t + c dt with c = 0, 1, 1/2 (the times of u^n, u^(1), u^(2)); then
+        self.time advances by dt."""
+        stages = [u]
+        t0 = self.time
+        for i, c in zip((1, 2, 3), (0.0, 1.0, 0.5)):
+            stages.append(rk_stage(i, stages, dt, lambda v, c=c: self.residual(v, t=t0 + c * dt), limiter))
+        self.time = t0 + dt
+        return stages[-1]
 
     # ------------------------------------------------------------------
     def errors(self, u, exact_fn, component=0, degree=None):

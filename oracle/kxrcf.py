@@ -17,8 +17,9 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import quadrature
 from .dg import DG
-from .physics import EQ_BURGERS
+from .physics import EQ_BURGERS, moving_shock_state
 
 
 def indicator(dg: DG, u, elems=None, c_k=1.0, norm="l2"):
@@ -38,13 +39,18 @@ def indicator(dg: DG, u, elems=None, c_k=1.0, norm="l2"):
         nb = M.nbr[E, f]
         isb = bnd[E, f]
         nb_safe = np.where(isb, E, nb)
-        sel = PFrev[fprime[E, f]]
+        sel = PFrev[np.where(isb, 0, fprime[E, f])]
         up = np.einsum("kgn,kn->kg", sel, u[nb_safe, 0, :])
         Um = um[..., 0]
         # boundary faces: the ghost state's indicator variable (the interior
-        # trace on outflow and wall faces, the inflow state's on inflow faces)
+        # trace on outflow and wall faces, the inflow state's on inflow
+        # faces, the moving shock's state at the point and the solution
+        # time on moving-shock faces)
         kind = M.info[E, f] & 3
         Ub = np.where((kind == 2)[:, None], dg.inflow[0], Um)
+        if dg.shock is not None and np.any(kind == 3):
+            xg, yg = M.physical_points(*quadrature.face_reference_points(f, dg.et), elems=E)
+            Ub = np.where((kind == 3)[:, None], moving_shock_state(dg.shock, xg, yg, dg.time)[..., 0], Ub)
         Up = np.where(isb[:, None], Ub, up)
         if dg.eq == EQ_BURGERS:
             vx = vy = Um

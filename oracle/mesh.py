@@ -27,7 +27,7 @@ INFO_FACE_MASK = 0x3
 INFO_BOUNDARY = 0x40
 # kind of a boundary face, kept in the face bits of its info byte
 # (Section 4, Examples 4-6: outflow / non-reflecting, reflective wall, inflow)
-BKIND_OUTFLOW, BKIND_WALL, BKIND_INFLOW = 0, 1, 2
+BKIND_OUTFLOW, BKIND_WALL, BKIND_INFLOW, BKIND_SHOCK = 0, 1, 2, 3
 
 
 class MeshError(ValueError):
@@ -218,11 +218,12 @@ class Mesh:
         return (self.info & INFO_BOUNDARY) != 0
 
     def set_boundary_kinds(self, kinds):
-        """kinds [K, 3]: for boundary faces BKIND_OUTFLOW (the default), _WALL
-        or _INFLOW; entries of interior faces are ignored."""
+        """kinds [K, 3]: for boundary faces BKIND_OUTFLOW (the default), _WALL,
+        _INFLOW or _SHOCK (a moving planar shock); entries of interior faces
+        are ignored."""
         kinds = np.asarray(kinds)
-        if kinds.shape != self.info.shape or np.any((kinds < 0) | (kinds > 2)):
-            raise ValueError("boundary kinds: [K, 3] array of 0, 1, 2")
+        if kinds.shape != self.info.shape or np.any((kinds < 0) | (kinds > 3)):
+            raise ValueError("boundary kinds: [K, 3] array of 0, 1, 2, 3")
         b = self.boundary_mask()
         self.info = np.where(b, INFO_BOUNDARY | kinds.astype(np.uint8), self.info).astype(np.uint8)
 

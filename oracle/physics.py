@@ -118,12 +118,23 @@ def euler_eigenvalues(Ubar, nx, ny, gamma=1.4):
     return np.stack([un - c, un, un, un + c], axis=-1)
 
 
-def ghost_state(eq, um, kind, nx, ny, inflow):
+def moving_shock_state(shock, x, y, t):
+    """The state on either side of a planar shock moving at constant speed
+    (the top boundary of Section 4, Example 5): shock = dict(n=(nx, ny),
+    d0=d0, w=w, post=[m], pre=[m]); the post-shock state where
+    n.x < d0 + w t, the pre-shock state elsewhere.  x, y [...] -> [..., m]."""
+    behind = shock["n"][0] * np.asarray(x) + shock["n"][1] * np.asarray(y) < shock["d0"] + shock["w"] * t
+    return np.where(behind[..., None], np.asarray(shock["post"], dtype=np.float64),
+                    np.asarray(shock["pre"], dtype=np.float64))
+
+
+def ghost_state(eq, um, kind, nx, ny, inflow, shock=None, x=None, y=None, t=0.0):
     """Exterior trace at boundary points (Section 4, Examples 4-6).
     um [..., m] interior trace, kind [...] (0 outflow: the interior trace;
     1 reflective wall: the interior trace with its normal momentum reversed;
-    2 inflow: the prescribed state inflow [m]), nx, ny [...] the outward
-    normal."""
+    2 inflow: the prescribed state inflow [m]; 3 moving shock: the state of
+    moving_shock_state at the points x, y [...] and time t), nx, ny [...]
+    the outward normal."""
     up = np.array(um, dtype=np.float64, copy=True)
     kind = np.broadcast_to(kind, um.shape[:-1])
     if eq == EQ_EULER:
@@ -133,4 +144,6 @@ def ghost_state(eq, um, kind, nx, ny, inflow):
         up[..., 2] = np.where(wall, um[..., 2] - 2.0 * mn * ny, up[..., 2])
     inflow = np.asarray(inflow, dtype=np.float64)
     up = np.where((kind == 2)[..., None], np.broadcast_to(inflow, up.shape), up)
+    if shock is not None and np.any(kind == 3):
+        up = np.where((kind == 3)[..., None], moving_shock_state(shock, x, y, t), up)
     return up

@@ -306,6 +306,59 @@ class ShockEntropyWave:
         return rho2 * u2 / (rho2 - rho_pre)
 
 
+class DoubleMachReflection:
+    """Example 5 (Section 4): a right-moving Mach 10 shock in [0,4] x [0,1],
+    through (1/6, 0) at 60 degrees to the x axis, into gas at rest with
+    rho = 1.4, p = 1 (gamma = 1.4, sound speed 1); behind it the
+    normal-shock state of that gas, rho = 8, p = 116.5, velocity 8.25 along
+    the shock normal (cos 30, -sin 30).  The shock line moves along its
+    normal n = (sin 60, -cos 60) at speed 10: post-shock where
+    n.x < n.(1/6, 0) + 10 t.  shock() gives these parameters in the form the
+    solver's moving-shock boundary takes."""
+
+    X0 = 1.0 / 6.0
+    PRE = (1.4, 0.0, 0.0, 1.0)
+    POST = (8.0, 8.25 * np.cos(np.pi / 6.0), -8.25 * np.sin(np.pi / 6.0), 116.5)
+    N = (np.sin(np.pi / 3.0), -np.cos(np.pi / 3.0))
+    SPEED = 10.0
+
+    @classmethod
+    def shock(cls):
+        return {"n": cls.N, "d0": cls.N[0] * cls.X0, "w": cls.SPEED,
+                "post": primitive_to_conservative(*cls.POST), "pre": primitive_to_conservative(*cls.PRE)}
+
+    def __call__(self, x, y):
+        sh = self.shock()
+        behind = sh["n"][0] * np.asarray(x) + sh["n"][1] * np.asarray(y) < sh["d0"]
+        return np.where(behind[..., None], sh["post"], sh["pre"])
+
+
+def dmr_mesh(s: int, jitter: float = 0.1, seed: int = 0):
+    """[0,4] x [0,1] with s squares per unit length (4 s x s squares,
+    8 s^2 triangles), interior vertices jittered (Example 5's domain)."""
+    return jittered_mesh(4 * s, 0.0, 4.0, 0.0, 1.0, jitter=jitter, seed=seed, ny=s)
+
+
+DMR_OUTFLOW, DMR_WALL, DMR_INFLOW, DMR_SHOCK = 0, 1, 2, 3  # boundary kinds, as the solver numbers them
+
+
+def dmr_kinds(vxy, tri):
+    """[K, 3] boundary kinds of Example 5 by face midpoint: inflow of the
+    post-shock state at x = 0 and on the bottom for x < 1/6, reflective wall
+    on the rest of the bottom, outflow at x = 4, the moving shock's states
+    on the top.  Interior entries are 0 and are not read."""
+    a = vxy[tri]
+    b = vxy[np.roll(tri, -1, axis=1)]
+    xm = 0.5 * (a[..., 0] + b[..., 0])
+    ym = 0.5 * (a[..., 1] + b[..., 1])
+    k = np.zeros(tri.shape, dtype=np.int64)
+    k = np.where(ym < 1e-12, np.where(xm < DoubleMachReflection.X0, DMR_INFLOW, DMR_WALL), k)
+    k = np.where(ym > 1.0 - 1e-12, DMR_SHOCK, k)
+    k = np.where(xm < 1e-12, DMR_INFLOW, k)
+    k = np.where(xm > 4.0 - 1e-12, DMR_OUTFLOW, k)
+    return k
+
+
 # Printed initial states of the paper's Example 7 (configurations 3 and 12),
 # quadrant order as in FourQuadrant: (rho, u, v, p).
 RIEMANN_CONFIG3 = np.array([

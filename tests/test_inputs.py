@@ -114,3 +114,29 @@ def test_example4_states_are_a_mach3_shock():
     assert abs((r2 * u2 - r1 * u1) - s * (r2 - r1)) < 1e-5
     assert abs((r2 * u2 * u2 + p2 - p1) - s * (r2 * u2)) < 1e-5 * p2
     assert abs((u2 * (E2 + p2)) - s * (E2 - E1)) < 1e-5 * E2
+
+
+def test_double_mach_states_are_a_mach10_shock():
+    """Example 5's states satisfy the jump conditions of a shock moving at
+    speed 10 along n into gas at rest (to the printed digits), and the
+    shock line's position at y = 1 is the familiar 1/6 + (1 + 20 t)/sqrt 3."""
+    g = inputs.GAMMA_GAS
+    D = inputs.DoubleMachReflection
+    sh = D.shock()
+    n = np.array(sh["n"])
+    r1, u1, v1, p1 = D.PRE
+    r2, u2, v2, p2 = D.POST
+    un2 = u2 * n[0] + v2 * n[1]
+    s = sh["w"]
+    assert abs(r2 * un2 - s * (r2 - r1)) < 1e-3 * r2 * un2
+    assert abs((r2 * un2 * un2 + p2 - p1) - s * r2 * un2) < 1e-3 * p2
+    E1 = p1 / (g - 1.0)
+    E2 = p2 / (g - 1.0) + 0.5 * r2 * (u2 * u2 + v2 * v2)
+    assert abs(un2 * (E2 + p2) - s * (E2 - E1)) < 1e-3 * E2
+    assert abs(math.sqrt(g * p1 / r1) - 1.0) < 1e-15
+    for t in (0.0, 0.1, 0.2):
+        xs = (sh["d0"] + s * t - n[1] * 1.0) / n[0]
+        assert math.isclose(xs, 1.0 / 6.0 + (1.0 + 20.0 * t) / math.sqrt(3.0), rel_tol=1e-13)
+    v, tri = inputs.dmr_mesh(10, seed=1)
+    k = inputs.dmr_kinds(v, tri)
+    assert tri.shape[0] == 800

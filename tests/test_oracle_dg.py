@@ -145,3 +145,20 @@ def test_global_lax_friedrichs_dissipates_more(N):
         L = d.residual(U)
         rates.append(np.sum(M.J * U[:, 0, 0] * L[:, 0, 0]))
     assert rates[1] < rates[0] - 1e-6 * abs(rates[0])
+
+
+def test_step_stage_times_integrate_quadratics_exactly():
+    """DG.ssprk3_step evaluates the residual of its stages at t, t + dt and
+    t + dt/2 (the times of u^n, u^(1), u^(2) in table:tvd): with a residual
+    that depends on time only, one step integrates t^2 exactly and
+    advances the solution time by dt."""
+    v, t = inputs.jittered_mesh(2, seed=1)
+    d = DG(Mesh(v, t, BC_PERIODIC, (1.0, 1.0)), 1, 0)
+    d.residual = lambda u, elems=None, t=None: np.full_like(u, t * t)
+    d.time = 0.3
+    dt = 0.2
+    u = np.zeros((d.mesh.K, 1, d.Np))
+    out = d.ssprk3_step(u, dt)
+    exact = ((0.3 + dt) ** 3 - 0.3 ** 3) / 3.0
+    assert np.allclose(out, exact, rtol=1e-14, atol=0)
+    assert math.isclose(d.time, 0.5, rel_tol=1e-15)
