@@ -37,6 +37,15 @@ launches.  --t-end T adds a run from the initial flow to time T (the
 paper's is 4), dt accumulated on the device, the last step cut to end at
 T, and reports its wall time.
 
+--workload p1_euler_dmr: the double Mach reflection (Section 4, Example 5)
+at the paper's h = 1/200: [0,4] x [0,1] with 800 x 200 squares (320,000
+jittered triangles, seed 1007), P1, FP64, the positivity scaling on;
+post-shock inflow at x = 0 and on the bottom up to x = 1/6, reflective wall
+beyond, outflow at x = 4, the exact Mach 10 shock position imposed on the
+top; initial data the planar shock (cell means in the cells it cuts).
+--develop steps (default 1000) first, then K steps timed as one graph
+launch and as plain launches.
+
 --workload p1_euler_shock_entropy: Example 4 (Section 4) at the paper's
 h = 1/200: 80,000 jittered triangles on [0,1]^2 (seed 1006), periodic in y,
 outflow sides at x = 0 and 1, P1, FP64, the positivity scaling on; the
@@ -340,6 +349,86 @@ def run_ffstep(args, degree=2):
     print(json.dumps(out), flush=True)
 
 
+def run_dmr(args):
+    import numpy as np
+    import torch
+
+    from paper_2106_06280_amd import binding, inputs
+
+    D = inputs.DoubleMachReflection
+    sh = D.shock()
+    v, t = inputs.dmr_mesh(200, seed=1007)
+    S = binding.Solver(binding.EQ_EULER, 1, limiter_mode=binding.LIMIT_KXRCF, positivity=1)
+    S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
+    S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
+    S.set_boundary(inputs.dmr_kinds(v, t), sh["post"])
+    u = S.project_fn(D())
+    side = v[t] @ np.array(sh["n"]) - sh["d0"]
+    cut = torch.from_numpy(~(np.all(side < 0, axis=1) | np.all(side > 0, axis=1))).cuda()
+    u[:, 1:, cut] = 0.0
+    K, m, Np = S.K, S.m, S.Np
+    t0 = time.perf_counter()
+    chunk = 100
+    dev = binding.Graph([S], [u], nsteps=chunk)
+    for _ in range(max(0, args.develop) // chunk):
+        dev.launch()
+    torch.cuda.synchronize()
+    st_dev = S.status()
+    t_dev = float(S.time()[0])
+    print(f"[bench] p1_euler_dmr: K={K}, developed {args.develop} steps to t = {t_dev:.4f} in "
+          f"{time.perf_counter() - t0:.1f}s, status {st_dev}", file=sys.stderr, flush=True)
+    g = binding.Graph([S], [u], nsteps=args.steps)
+    g.launch()
+    torch.cuda.synchronize()
+    S.status()
+    S.troubled_stats(reset=True)
+    start = u.clone()
+    time_start = float(S.time()[0])
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    g.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    secs = ev0.elapsed_time(ev1) / 1000.0
+    status = S.status()
+    tot, calls = S.troubled_stats()
+    after = u.clone()
+    u.copy_(start)
+    S.set_time(time_start)
+    ev0.record()
+    for _ in range(args.steps):
+        S.ssprk3_step(u)
+    ev1.record()
+    torch.cuda.synchronize()
+    secs_eager = ev0.elapsed_time(ev1) / 1000.0
+    dof = K * m * Np
+    out = {
+        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P1 Euler, double Mach reflection)",
+        "value": dof * 3 * args.steps / secs,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.steps,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "p1_euler_dmr", "triangles": K, "degree": 1, "dof": dof,
+                   "developed_steps": args.develop, "time_at_timing": round(time_start, 5),
+                   "troubled_fraction": round(tot / max(1, calls * K), 5),
+                   "boundaries": "post-shock inflow, wall, outflow, moving Mach 10 shock on top",
+                   "limiter": "kxrcf+csweno", "positivity": True, "parallelism": "single-gpu"},
+        "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
+                  "graph_equals_eager": bool(torch.equal(u, after))},
+        "status_bits": status,
+        "status_bits_develop": st_dev,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_shock_entropy(args):
     import numpy as np
     import torch
@@ -505,9 +594,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS) + ["c4_batch", "p2_euler_ffstep", "p1_euler_ffstep",
-                                                                  "p1_euler_shock_entropy"])
-    ap.add_argument("--develop", type=int, default=4000,
-                    help="p2_euler_ffstep: untimed steps that develop the flow first")
+                                                                  "p1_euler_shock_entropy", "p1_euler_dmr"])
+    ap.add_argument("--develop", type=int, default=None,
+                    help="p*_euler_ffstep / p1_euler_dmr: untimed steps that develop the flow first "
+                         "(default 4000 / 1000)")
     ap.add_argument("--t-end", type=float, default=None,
                     help="p2/p1_euler_ffstep: also run from the initial flow to this time "
                          "(default: none for P2, the paper's 4 for P1)")
@@ -546,10 +636,17 @@ def main():
         run_batch(args)
         return
     if args.workload in ("p2_euler_ffstep", "p1_euler_ffstep"):
+        if args.develop is None:
+            args.develop = 4000
         run_ffstep(args, degree=int(args.workload[1]))
         return
     if args.workload == "p1_euler_shock_entropy":
         run_shock_entropy(args)
+        return
+    if args.workload == "p1_euler_dmr":
+        if args.develop is None:
+            args.develop = 1000
+        run_dmr(args)
         return
     eq, N, bc, v, t, ic, period = make_problem(args.workload)
     precision = WORKLOADS[args.workload][5]

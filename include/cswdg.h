@@ -41,7 +41,8 @@
  * bits 2-3 / 4-5 the x / y shift code (0 none, 1 add +period, 2 add -period
  * to the neighbour's coordinates to place it next to the element), bit 6 set
  * on a boundary face (neighbour id -1), whose bits 0-1 then hold its kind
- * (cswdg_set_boundary: 0 outflow, the default).
+ * (cswdg_set_boundary: 0 outflow, the default; 1 wall; 2 inflow; 3 moving
+ * shock).
  */
 #ifndef CSWDG_H
 #define CSWDG_H
@@ -150,13 +151,31 @@ int cswdg_instances(const cswdg_solver* s, int32_t* n_inst, int64_t* offsets);
  * trace, the default), 1 reflective wall (interior trace with its normal
  * momentum reversed; for Burgers the same as outflow), 2 inflow (the state
  * inflow, host double [m] of conserved variables, may be NULL to keep the
- * last one; zero after a mesh upload).  The limiter's ghost cell across a
- * boundary face is Delta0's mirror image carrying the same exterior state
- * (the mirrored polynomial, with reversed normal momentum at a wall, or the
- * inflow state on every piece); KXRCF sees the ghost's density.  Adjoint
- * calls reject meshes with wall or inflow faces.  Another kind than 0, 1, 2
- * is CSWDG_EINVAL.  Synchronous. */
+ * last one; zero after a mesh upload), 3 moving shock (Example 5's top
+ * boundary; cswdg_set_moving_shock first).  The limiter's ghost cell across
+ * a boundary face is Delta0's mirror image carrying the same exterior state
+ * (the mirrored polynomial, with reversed normal momentum at a wall, the
+ * inflow state on every piece, the moving shock's state at the face
+ * midpoint on every piece); KXRCF sees the ghost's density.  Adjoint calls
+ * reject meshes with faces of kinds 1-3.  Another kind is CSWDG_EINVAL, and
+ * so is kind 3 before a moving shock is set.  Synchronous. */
 int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* inflow);
+
+/* The moving planar shock of boundary kind 3 (Section 4, Example 5's top
+ * boundary, where the exact Mach 10 shock position is imposed): at a
+ * boundary point x and time t the exterior state is post (host double [4],
+ * conserved variables) where nx x + ny y < d0 + speed t, pre elsewhere.
+ * The residual of an SSP-RK3 stage evaluates it at its input's time (the
+ * step's start t, t + dt, t + dt/2 for u^n, u^(1), u^(2)); KXRCF and the
+ * limiter at the step's start.  Setting it makes cswdg_ssprk3_step (and
+ * graphs of it) advance the solution time by dt.  Euler only (otherwise
+ * CSWDG_EINVAL).  Synchronous. */
+int cswdg_set_moving_shock(cswdg_solver* s, const double* post, const double* pre, double nx, double ny, double d0,
+                           double speed);
+/* Solution time of every instance: set to t (synchronous; zero after a mesh
+ * upload), read into t_host [n_inst] (synchronous). */
+int cswdg_set_time(cswdg_solver* s, double t);
+int cswdg_time(cswdg_solver* s, double* t_host);
 
 /* Number of elements, number of triangles re-oriented by the CCW fix. */
 int cswdg_mesh_info(const cswdg_solver* s, int64_t* n_elements, int64_t* n_flipped);

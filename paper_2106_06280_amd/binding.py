@@ -68,6 +68,10 @@ _SIGS = {
     "cswdg_profile_select": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "cswdg_set_boundary": (ctypes.c_int, [_P, _P, _P]),
     "cswdg_positivity": (ctypes.c_int, [_P, _P]),
+    "cswdg_set_moving_shock": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double]),
+    "cswdg_set_time": (ctypes.c_int, [_P, ctypes.c_double]),
+    "cswdg_time": (ctypes.c_int, [_P, _P]),
     "cswdg_kernel_times": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "cswdg_mesh_upload_batch": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
     "cswdg_instances": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
@@ -221,6 +225,25 @@ class Solver:
                 raise ValueError(f"inflow: expected ({self.m},), got {s.shape}")
         self._c(lib().cswdg_set_boundary(self.h, None if k is None else k.ctypes.data,
                                          None if s is None else s.ctypes.data))
+
+    def set_moving_shock(self, post, pre, n, d0, speed):
+        """The planar shock of boundary kind 3: post where n.x < d0 + speed t
+        (conserved states [4]); see cswdg_set_moving_shock."""
+        a = np.ascontiguousarray(np.asarray(post, dtype=np.float64))
+        b = np.ascontiguousarray(np.asarray(pre, dtype=np.float64))
+        if a.shape != (4,) or b.shape != (4,):
+            raise ValueError("moving shock: post and pre are [4] conserved states")
+        self._c(lib().cswdg_set_moving_shock(self.h, a.ctypes.data, b.ctypes.data, float(n[0]), float(n[1]),
+                                             float(d0), float(speed)))
+
+    def set_time(self, t):
+        self._c(lib().cswdg_set_time(self.h, float(t)))
+
+    def time(self):
+        """Solution time of each instance (numpy float64 [n_inst])."""
+        out = np.zeros(self._n_inst(), np.float64)
+        self._c(lib().cswdg_time(self.h, out.ctypes.data))
+        return out
 
     def instances(self):
         """Instance offsets (numpy int64 [n_inst + 1])."""

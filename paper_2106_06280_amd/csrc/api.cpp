@@ -65,6 +65,9 @@ struct cswdg_solver {
     unsigned long long* d_amax = nullptr;
     double* d_inflow = nullptr;   // [m] state of inflow boundary faces
     double* d_lfa = nullptr;      // [n_inst] global Lax-Friedrichs constants (lf_mode = 1)
+    double* d_time = nullptr;     // [n_inst] solution time (advanced by steps while a moving shock is set)
+    double* d_shock = nullptr;    // moving shock of boundary kind 3: nx, ny, d0, w, post[4], pre[4]
+    bool shock_set = false;
     int64_t n_special = 0;        // boundary faces of wall or inflow kind
     int dt_blocks = 1024;
     int64_t n_rank = 0, n_foot = 0;
@@ -97,7 +100,7 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
                     s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2,
-                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow, s->d_lfa};
+                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow, s->d_lfa, s->d_time, s->d_shock};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -118,6 +121,9 @@ void free_mesh(cswdg_solver* s) {
     s->d_amax = nullptr;
     s->d_inflow = nullptr;
     s->d_lfa = nullptr;
+    s->d_time = nullptr;
+    s->d_shock = nullptr;
+    s->shock_set = false;
     s->n_special = 0;
     s->n_inst = 1;
     s->inst_off.clear();
@@ -399,7 +405,10 @@ int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* infl
         int64_t special = 0;
         for (int64_t i = 0; i < 3 * K; ++i) {
             if (!(s->mesh.info[i] & 0x40)) continue;
-            if (kinds[i] > 2) return fail(s, CSWDG_EINVAL, "boundary kind must be 0 (outflow), 1 (wall) or 2 (inflow)");
+            if (kinds[i] > 3)
+                return fail(s, CSWDG_EINVAL, "boundary kind must be 0 (outflow), 1 (wall), 2 (inflow) or 3 (moving shock)");
+            if (kinds[i] == 3 && !s->shock_set)
+                return fail(s, CSWDG_EINVAL, "boundary kind 3 needs cswdg_set_moving_shock first");
             special += kinds[i] != 0;
         }
         std::vector<uint32_t> info4(K);
@@ -421,6 +430,46 @@ int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* infl
         if (e != hipSuccess) return hipfail(s, e, "set_boundary");
     }
     return CSWDG_OK;
+}
+
+int cswdg_set_moving_shock(cswdg_solver* s, const double* post, const double* pre, double nx, double ny, double d0,
+                           double speed) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (s->p.equation != CSWDG_EQ_EULER) return fail(s, CSWDG_EINVAL, "the moving-shock boundary is an Euler boundary");
+    if (!post || !pre) return fail(s, CSWDG_EINVAL, "null state");
+    if (!std::isfinite(nx) || !std::isfinite(ny) || !std::isfinite(d0) || !std::isfinite(speed))
+        return fail(s, CSWDG_EINVAL, "moving shock: non-finite parameter");
+    double rec[12] = {nx, ny, d0, speed};
+    for (int c = 0; c < 4; ++c) {
+        rec[4 + c] = post[c];
+        rec[8 + c] = pre[c];
+    }
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(s->d_shock, rec, sizeof(rec), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hipfail(s, e, "set_moving_shock");
+    s->shock_set = true;
+    s->dm.shock = s->d_shock;
+    return CSWDG_OK;
+}
+
+int cswdg_set_time(cswdg_solver* s, double t) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!std::isfinite(t)) return fail(s, CSWDG_EINVAL, "non-finite time");
+    std::vector<double> tv((size_t)s->n_inst, t);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(s->d_time, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice);
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "set_time");
+}
+
+int cswdg_time(cswdg_solver* s, double* t) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!t) return fail(s, CSWDG_EINVAL, "null pointer");
+    hipError_t e = hipMemcpyAsync(t, s->d_time, sizeof(double) * s->n_inst, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "time");
 }
 
 int cswdg_mesh_info(const cswdg_solver* s, int64_t* n_elements, int64_t* n_flipped) {
@@ -543,7 +592,10 @@ int cswdg_ssprk3_step(cswdg_solver* s, void* u, const double* dt_dev) {
     if (rc) return rc;
     rc = rk_stage_impl(s, 2, u, s->d_T1, s->d_T2, dt);
     if (rc) return rc;
-    return rk_stage_impl(s, 3, u, s->d_T2, u, dt);
+    rc = rk_stage_impl(s, 3, u, s->d_T2, u, dt);
+    if (rc || !s->shock_set) return rc;
+    hipError_t e = launch_time_advance(s->ctx, s->n_inst, s->d_time, dt);
+    return e == hipSuccess ? CSWDG_OK : hipfail(s, e, "time advance");
 }
 
 int cswdg_positivity(cswdg_solver* s, void* u) {
@@ -978,6 +1030,8 @@ int upload_mesh(cswdg_solver* s) {
         {(void**)&s->d_amax, sizeof(unsigned long long) * s->n_inst},
         {(void**)&s->d_inflow, sizeof(double) * 4},
         {(void**)&s->d_lfa, sizeof(double) * s->n_inst},
+        {(void**)&s->d_time, sizeof(double) * s->n_inst},
+        {(void**)&s->d_shock, sizeof(double) * 12},
         {(void**)&s->d_T1, sizeof(double) * NPM * K},
         {(void**)&s->d_T2, sizeof(double) * NPM * K},
     };
@@ -1005,6 +1059,8 @@ int upload_mesh(cswdg_solver* s) {
     cp(s->d_inst_hmin, s->inst_hmin.data(), sizeof(double) * s->n_inst);
     if (e == hipSuccess) e = hipMemset(s->d_amax, 0, sizeof(unsigned long long) * s->n_inst);
     if (e == hipSuccess) e = hipMemset(s->d_inflow, 0, sizeof(double) * 4);
+    if (e == hipSuccess) e = hipMemset(s->d_time, 0, sizeof(double) * s->n_inst);
+    if (e == hipSuccess) e = hipMemset(s->d_shock, 0, sizeof(double) * 12);
     if (e != hipSuccess) {
         free_mesh(s);
         return hipfail(s, e, "mesh upload");
@@ -1019,6 +1075,9 @@ int upload_mesh(cswdg_solver* s) {
     s->n_special = 0;
     s->dm.inst_off = s->d_inst_off;
     s->dm.lf_alpha = s->p.lf_mode ? s->d_lfa : nullptr;
+    s->dm.time = s->d_time;
+    s->dm.shock = nullptr;
+    s->shock_set = false;
     {
         const char* xt = std::getenv("CSWDG_XCD_TILES");
         s->dm.xcd_tiles = xt ? std::atoi(xt) : 1;

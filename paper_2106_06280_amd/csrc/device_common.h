@@ -150,9 +150,20 @@ __device__ __forceinline__ void append_list_block(bool tr, int e, int32_t* __res
 // interior trace um and up already set to it (outflow): a reflective wall
 // reverses the normal momentum, an inflow face takes the prescribed state.
 // The kind is kept in the face bits of the boundary face's info byte.
+// side of the moving shock of boundary kind 3 at (x, y) and time t: the
+// index of the first component of its post- (behind: n.x < d0 + w t) or
+// pre-shock state in the shock record {nx, ny, d0, w, post[4], pre[4]}
+__device__ __forceinline__ int shock_state_at(const double* __restrict__ shock, double x, double y, double t) {
+    return (shock[0] * x + shock[1] * y < shock[2] + shock[3] * t) ? 4 : 8;
+}
+
+// exterior trace of a boundary point (x, y) at time t (kinds: 0 outflow,
+// 1 reflective wall, 2 inflow state, 3 moving shock; the point and time are
+// read for kind 3 only)
 template <int EQ, typename R>
 __device__ __forceinline__ void boundary_trace(const R* um, R* up, uint32_t inf, R nx, R ny,
-                                               const double* __restrict__ inflow) {
+                                               const double* __restrict__ inflow,
+                                               const double* __restrict__ shock, double x, double y, double t) {
     // selects rather than branches keep up[] in registers
     constexpr int M = (EQ == 1) ? 4 : 1;
     const uint32_t kind = inf & 3u;
@@ -164,7 +175,15 @@ __device__ __forceinline__ void boundary_trace(const R* um, R* up, uint32_t inf,
     }
 #pragma unroll
     for (int c = 0; c < M; ++c) up[c] = (kind == 2u) ? (R)inflow[c] : up[c];
+    if constexpr (EQ == 1) {
+        if (shock != nullptr) {
+            const int o = shock_state_at(shock, x, y, t);
+#pragma unroll
+            for (int c = 0; c < M; ++c) up[c] = (kind == 3u) ? (R)shock[o + c] : up[c];
+        }
+    }
 }
+
 
 // instance holding element e (binary search over the instance offsets)
 __device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
@@ -183,6 +202,18 @@ __device__ __forceinline__ int inst_of(const DevMesh& m, int e) {
 // normal wave speed of the two traces at each point)
 __device__ __forceinline__ double lf_global(const DevMesh& m, int e) {
     return m.lf_alpha ? m.lf_alpha[inst_of(m, e)] : -1.0;
+}
+
+// time of a residual's input for the moving-shock boundary: the step's
+// start for u^n (modes 0, 1), + dt for u^(1) (mode 2), + dt/2 for u^(2)
+// (mode 3)
+template <int MODE>
+__device__ __forceinline__ double stage_time(const DevMesh& m, int e, const double* __restrict__ dtp) {
+    if (m.shock == nullptr) return 0.0;
+    const int i = inst_of(m, e);
+    if constexpr (MODE == 2) return m.time[i] + dtp[i];
+    if constexpr (MODE == 3) return m.time[i] + 0.5 * dtp[i];
+    return m.time[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -194,6 +194,7 @@ void fill_tables(Tab<N>& t) {
         double x = (double)(0.5L * (e.x[g] - e.x[D::NE - 1 - g]));
         double w = (double)(0.5L * (e.w[g] + e.w[D::NE - 1 - g]));
         t.we[g] = w;
+        t.es[g] = 0.5 * (1.0 + x);
         for (int f = 0; f < 3; ++f) {
             double r, s;
             if (f == 0) {

@@ -84,6 +84,8 @@ struct DevMesh {
     int n_inst;            // independent meshes held (1 for a single mesh)
     const int32_t* inst_off;  // [n_inst + 1] first element of each instance
     const double* lf_alpha;   // [n_inst] global Lax-Friedrichs constants, or null (local)
+    const double* time;       // [n_inst] solution time at the start of the step
+    const double* shock;      // moving shock of boundary kind 3: nx, ny, d0, w, post[4], pre[4]; or null
 };
 
 struct LaunchCtx {
@@ -123,6 +125,8 @@ hipError_t launch_zero_u32(const LaunchCtx& c, uint32_t* p, int n);
 // speed of instance i of u (amax_bits [n_inst] zero on entry and exit)
 hipError_t launch_lf_alpha(const LaunchCtx& c, const DevMesh& m, const void* u, unsigned long long* amax_bits,
                            double* alpha, uint32_t* status);
+// time[i] += dt[i] for every instance (the end of a step)
+hipError_t launch_time_advance(const LaunchCtx& c, int n_inst, double* time, const double* dt);
 // positivity-preserving scaling of an Euler state in place (all elements)
 hipError_t launch_positivity(const LaunchCtx& c, const DevMesh& m, void* u, uint32_t* status);
 // limiter over the list; results to the compact buffer

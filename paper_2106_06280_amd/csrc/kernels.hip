@@ -103,7 +103,7 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
         const double sf = 0.5 * L * iJ;
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
-        const int fp = (int)(inf & 3u);
+        const int fp = bnd ? 0 : (int)(inf & 3u);
         const int nb = bnd ? e : msh.nbr[f * K + e];
         double Un[M][NP];
 #pragma unroll
@@ -124,7 +124,9 @@ __device__ __forceinline__ void residual_body(DevMesh msh, const double* __restr
                 um[c] = a;
                 up[c] = bnd ? a : b;
             }
-            if (bnd) boundary_trace<EQ>(um, up, inf, nx, ny, msh.inflow);
+            if (bnd)
+                boundary_trace<EQ>(um, up, inf, nx, ny, msh.inflow, msh.shock, X[f] + tab<N>().es[g] * ex,
+                                   Y[f] + tab<N>().es[g] * ey, stage_time<MODE>(msh, e, dtp));
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(up, nx, ny, gamma, Fp, lp);
@@ -249,7 +251,7 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
         const double sf = 0.5 * L / J;
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
-        const int fp = (int)(inf & 3u);
+        const int fp = bnd ? 0 : (int)(inf & 3u);
         const int nb = bnd ? e : msh.nbr[f * K + e];
         double up[NE][M];
 #pragma unroll
@@ -276,7 +278,9 @@ __device__ __forceinline__ void residual_body_lean(DevMesh msh, const double* __
                 um[c] = a;
                 upg[c] = bnd ? a : up[g][c];
             }
-            if (bnd) boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow);
+            if (bnd)
+                boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow, msh.shock, xa + tab<N>().es[g] * ex,
+                                   ya + tab<N>().es[g] * ey, stage_time<MODE>(msh, e, dtp));
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
@@ -387,7 +391,7 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
         const R sf = (R)(0.5 * L / J);
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
-        const int fp = (int)(inf & 3u);
+        const int fp = bnd ? 0 : (int)(inf & 3u);
         const int nb = bnd ? e : msh.nbr[f * K + e];
         const int gr = NE - 1;
 #pragma unroll 1
@@ -404,7 +408,9 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
                 um[c] = a;
                 upg[c] = bnd ? a : b;
             }
-            if (bnd) boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow);
+            if (bnd)
+                boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow, msh.shock, xa + tab<N>().es[g] * ex,
+                                   ya + tab<N>().es[g] * ey, stage_time<MODE>(msh, e, dtp));
             R Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gm, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gm, Fp, lp);
@@ -538,7 +544,7 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
         const double sf = 0.5 * L / J;
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
-        const int fp = (int)(inf & 3u);
+        const int fp = bnd ? 0 : (int)(inf & 3u);
         const int nb = bnd ? e : msh.nbr[f * K + e];
         asm volatile("" : "+s"(us));
         double up[NE][M], umf[NE][M];
@@ -570,7 +576,9 @@ __device__ __forceinline__ void residual_body_stream(DevMesh msh, const double* 
                 um[c] = umf[g][c];
                 upg[c] = bnd ? umf[g][c] : up[g][c];
             }
-            if (bnd) boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow);
+            if (bnd)
+                boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow, msh.shock, xa + tab<N>().es[g] * ex,
+                                   ya + tab<N>().es[g] * ey, stage_time<MODE>(msh, e, dtp));
             double Fm[M], Fp[M], lm, lp;
             Phys<EQ>::normal_flux(um, nx, ny, gamma, Fm, lm);
             Phys<EQ>::normal_flux(upg, nx, ny, gamma, Fp, lp);
@@ -734,6 +742,12 @@ __global__ __launch_bounds__(256) void k_lf_alpha_final(int n, unsigned long lon
     amax_bits[i] = 0ull;
 }
 
+__global__ __launch_bounds__(64) void k_time_advance(int n, double* __restrict__ time,
+                                                     const double* __restrict__ dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) time[i] += dt[i];
+}
+
 // ---------------------------------------------------------------------------
 // KXRCF indicator + compaction (Section 3.1)
 // ---------------------------------------------------------------------------
@@ -763,6 +777,7 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
         const double Y[3] = {msh.vy[e], msh.vy[K + e], msh.vy[2 * K + e]};
         const double J = 0.25 * ((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]));
         const uint32_t info4 = msh.info[e];
+        const double ts = (msh.shock != nullptr) ? msh.time[inst_of(msh, e)] : 0.0;
         double num = 0.0, len = 0.0, Ls[3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -773,7 +788,7 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
             const double nx = ey / L, ny = -ex / L;
             const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
             const bool bnd = (inf & 0x40u) != 0u;
-            const int fp = (int)(inf & 3u);
+            const int fp = bnd ? 0 : (int)(inf & 3u);
             const int nb = bnd ? e : msh.nbr[f * K + e];
             double Un[NP];
 #pragma unroll
@@ -802,7 +817,13 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
                 if (vn < 0.0) {
                     // boundary faces: the interior trace (outflow, wall) or the
                     // inflow state's indicator variable (inflow)
-                    const double up = bnd ? (((inf & 3u) == 2u) ? msh.inflow[0] : um) : upv;
+                    // boundary faces: the interior trace (outflow, wall), the
+                    // inflow state's indicator variable (inflow), the moving
+                    // shock's at the point and the step's start (moving shock)
+                    double ub = ((inf & 3u) == 2u) ? msh.inflow[0] : um;
+                    if ((inf & 3u) == 3u && msh.shock != nullptr)
+                        ub = msh.shock[shock_state_at(msh.shock, X[f] + T.es[g] * ex, Y[f] + T.es[g] * ey, ts)];
+                    const double up = bnd ? ub : upv;
                     const double ds = 0.5 * L * T.we[g];
                     num += ds * (um - up);
                     len += ds;
@@ -933,11 +954,19 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
                     Lf[2] = -Lr[1] * (2.0 * nx * ny) + Lr[2] * (1.0 - 2.0 * ny * ny);
                 }
             }
-            if (kind == 2u) {
-                // inflow ghost: the prescribed state on every piece
+            if (kind == 2u || kind == 3u) {
+                // inflow ghost: the prescribed state on every piece; moving
+                // shock: its state at the face midpoint and the step's start
+                const double* st = msh.inflow;
+                if (kind == 3u) {
+                    const int f1 = (f == 2) ? 0 : f + 1;
+                    const double xm = 0.5 * (msh.vx[f * K + e] + msh.vx[f1 * K + e]);
+                    const double ym = 0.5 * (msh.vy[f * K + e] + msh.vy[f1 * K + e]);
+                    st = msh.shock + shock_state_at(msh.shock, xm, ym, msh.time[inst_of(msh, e)]);
+                }
                 double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < M; ++c) s += Lr[c] * msh.inflow[c];
+                for (int c = 0; c < M; ++c) s += Lr[c] * st[c];
 #pragma unroll
                 for (int p = 0; p < NPC; ++p) w[f][p] = s;
                 continue;
@@ -1359,6 +1388,11 @@ hipError_t launch_lf_alpha(const LaunchCtx& c, const DevMesh& m, const void* u, 
         k_dt_inst<EQ, N, S><<<g, 256, 0, c.stream>>>(m, (const S*)u, c.gamma, amax_bits, status);
     });
     k_lf_alpha_final<<<grid_for(m.n_inst, 256), 256, 0, c.stream>>>(m.n_inst, amax_bits, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_time_advance(const LaunchCtx& c, int n_inst, double* time, const double* dt) {
+    k_time_advance<<<grid_for(n_inst, 64), 64, 0, c.stream>>>(n_inst, time, dt);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct Tab {
     double PF[3][D::NE][D::NP];  // psi_n at the points of face f
     double wPF[3][D::NE][D::NP]; // w_g psi_n at the points of face f
     double we[D::NE];            // edge weights (sum 2)
+    double es[D::NE];            // position of edge point g along its face, in (0, 1) from vertex f to f+1
     double wmean[D::NP];         // mean of psi_n over the reference triangle
 };
 

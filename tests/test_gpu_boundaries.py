@@ -318,3 +318,98 @@ def test_example4_shock_position_p1(torch):
     exp = 0.125 + inputs.ShockEntropyWave.shock_speed() * t_end
     print(f"shock at {xs:.4f}, jump conditions {exp:.4f}", flush=True)
     assert abs(xs - exp) < 1.0 / n
+
+
+def _dmr_case(N, s, seed, positivity=0):
+    from paper_2106_06280_amd import binding
+    D = inputs.DoubleMachReflection
+    v, t = inputs.dmr_mesh(s, seed=seed)
+    kinds = inputs.dmr_kinds(v, t)
+    M = Mesh(v, t, BC_TRANSMISSIVE)
+    M.set_boundary_kinds(kinds)
+    dg = DG(M, N, 1)
+    sh = D.shock()
+    dg.shock = sh
+    dg.inflow = np.asarray(sh["post"])
+    S = binding.Solver(1, N, positivity=positivity)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (0.0, 0.0))
+    S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
+    S.set_boundary(kinds.astype(np.uint8), sh["post"])
+    return M, dg, S
+
+
+def _dmr_state(M, dg, T):
+    """The exact planar shock of Example 5 at time T, cells the line cuts
+    as cell means."""
+    from oracle.physics import moving_shock_state
+    u = dg.project(lambda x, y: moving_shock_state(dg.shock, x, y, T))
+    side = M.V @ np.array(dg.shock["n"]) - (dg.shock["d0"] + dg.shock["w"] * T)
+    u[~(np.all(side < 0, axis=1) | np.all(side > 0, axis=1)), :, 1:] = 0.0
+    return u
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_moving_shock_operators(torch, N):
+    """Example 5's boundaries (post-shock inflow at x = 0 and on the bottom
+    up to 1/6, wall beyond, outflow at x = 4, the moving Mach 10 shock on
+    the top) at time 0.03, when the shock has moved along the top: residual,
+    KXRCF and the limiter with every cell troubled against the oracle."""
+    M, dg, S = _dmr_case(N, 6, seed=31)
+    T = 0.03
+    dg.time = T
+    S.set_time(T)
+    u = _dmr_state(M, dg, T)
+    ud = S.to_device(u)
+    r = S.to_host(S.dg_residual(ud))
+    assert _relerr(r, dg.residual(u)) < TOL
+    flags, R = S.kxrcf(ud)
+    Ro, fo = kxrcf.indicator(dg, u)
+    assert (np.abs(Ro - 1.0) < 1e-9).sum() == 0
+    assert np.array_equal(flags.cpu().numpy().astype(bool), fo)
+    out, _ = S.csweno_limit(ud, mask=torch.ones(M.K, dtype=torch.uint8))
+    assert _relerr(S.to_host(out), csweno.limit(dg, u, np.ones(M.K, bool))) < TOL
+    # the top faces see both states at this time
+    top = np.nonzero(M.boundary_kind() == 3)
+    mid = 0.5 * (M.V + np.roll(M.V, -1, axis=1))[top] @ np.array(dg.shock["n"])
+    behind = mid < dg.shock["d0"] + dg.shock["w"] * T
+    assert behind.any() and (~behind).any()
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_moving_shock_steps(torch, N):
+    """Four limited steps of Example 5 from t = 0 with the positivity scaling
+    on both sides: the stage residuals see the moving shock at t, t + dt and
+    t + dt/2; the solution time advances by dt per step."""
+    from oracle import positivity
+    M, dg, S = _dmr_case(N, 6, seed=33, positivity=1)
+    u = _dmr_state(M, dg, 0.0)
+    ud = S.to_device(u)
+    lim = lambda w: positivity.scale(dg, csweno.limit(dg, w, kxrcf.indicator(dg, w)[1]))[0]
+    for _ in range(4):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert abs(S.time()[0] - dg.time) <= 1e-15 * dg.time
+    assert S.status() & 0x3 == 0
+
+
+def test_moving_shock_validation(torch):
+    from paper_2106_06280_amd import binding
+    D = inputs.DoubleMachReflection
+    sh = D.shock()
+    v, t = inputs.dmr_mesh(3, seed=1)
+    B = binding.Solver(0, 1)
+    B.mesh_upload(v, t, BC_TRANSMISSIVE, (0.0, 0.0))
+    with pytest.raises(binding.CswdgError):
+        B.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
+    S = binding.Solver(1, 1)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (0.0, 0.0))
+    kinds = inputs.dmr_kinds(v, t).astype(np.uint8)
+    with pytest.raises(binding.CswdgError):
+        S.set_boundary(kinds, sh["post"])
+    S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
+    S.set_boundary(kinds, sh["post"])
+    u = S.project_fn(inputs.DoubleMachReflection())
+    with pytest.raises(binding.CswdgError):
+        S.dg_residual_vjp(u, u.clone())
+    assert S.time()[0] == 0.0
