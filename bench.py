@@ -29,8 +29,9 @@ inflow of the uniform Mach 3 flow (rho 1.4, u 3, v 0, p 1) at x = 0,
 outflow at x = 4, reflective walls elsewhere; initialised with that flow.
 The positivity-preserving scaling (not in the paper) follows the limiter
 of every stage: without it the impulsive start at the step loses
-positivity within two steps.  --workload p1_euler_ffstep: the same with
-P1, whose run to the paper's t = 4 is part of the default line.  The flow first develops for --develop steps
+positivity within two steps; P2 takes the quadratic top member of its
+reconstruction hierarchy (p2_top = 1).  --workload p1_euler_ffstep: the
+same with P1.  Both lines include the run to the paper's t = 4.  The flow first develops for --develop steps
 (default 4000, untimed, in graph launches of 100 steps); then K steps are
 timed as one graph launch (after one untimed launch) and as plain
 launches.  --t-end T adds a run from the initial flow to time T (the
@@ -209,11 +210,14 @@ FFSTEP = {"s": 110, "seed": 1005}
 
 
 def ffstep_solver(degree=2):
+    """Example 6's solver; P2 takes the quadratic top member of its
+    reconstruction hierarchy (p2_top = 1), with which the run is stable."""
     from paper_2106_06280_amd import binding, inputs
     v, t = inputs.forward_step_mesh(FFSTEP["s"], seed=FFSTEP["seed"])
     kinds = inputs.forward_step_kinds(v, t)
     inflow = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
-    S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1)
+    S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1,
+                       p2_top=1 if degree == 2 else 0)
     S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
     S.set_boundary(kinds, inflow.state)
     return S, v, t, kinds, inflow
@@ -326,6 +330,7 @@ def run_ffstep(args, degree=2):
         "config": {"workload": name, "triangles": K, "degree": degree, "dof": dof,
                    "developed_steps": args.develop, "troubled_fraction": round(tot / max(1, calls * K), 5),
                    "boundaries": "inflow x=0, outflow x=4, reflective walls", "limiter": "kxrcf+csweno",
+                   "p2_top": "quadratic" if degree == 2 else None,
                    "parallelism": "single-gpu"},
         "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
                   "graph_equals_eager": same},
@@ -336,7 +341,7 @@ def run_ffstep(args, degree=2):
         "status_bits": status,
         "status_bits_develop": st_dev,
     }
-    t_end = args.t_end if args.t_end is not None else (4.0 if degree == 1 else 0.0)
+    t_end = args.t_end if args.t_end is not None else 4.0
     if t_end > 0:
         u2 = S.project_fn(inflow)
         S.status()
@@ -600,7 +605,7 @@ def main():
                          "(default 4000 / 1000)")
     ap.add_argument("--t-end", type=float, default=None,
                     help="p2/p1_euler_ffstep: also run from the initial flow to this time "
-                         "(default: none for P2, the paper's 4 for P1)")
+                         "(default: the paper's 4; 0 skips it)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)

@@ -103,6 +103,13 @@ typedef struct cswdg_params {
      * constant per residual and instance, the largest cell-mean wave speed
      * of the residual's input state (the bound the time step uses) */
     int lf_mode;
+    /* top member of the N = 2 reconstruction hierarchy (Section 3.2, Steps
+     * 1-2 for P2): 0 the quartic q_5 on the 16-cell stencil T4 (the default
+     * reading); 1 the quadratic q_3, i.e. the hierarchy of N = 1 projected
+     * onto P2 (a third-order reconstruction, the design order of P2; stable
+     * under refinement with every cell limited, where the quartic is not).
+     * N = 1 and N = 3 are unaffected. */
+    int p2_top;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream

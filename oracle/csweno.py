@@ -251,11 +251,14 @@ def _beta_matrix(V0, x0, y0, h0, area0, d):
     return B
 
 
-def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True):
+def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True, quadratic_top=False):
     """New coefficients for the troubled cells elems: [T, m, Np].  Mode 0
     is copied from u.  linear_only: the weights are the linear weights
     (omega = gamma); characteristic=False (Euler): the conserved variables
-    are reconstructed directly instead of the characteristic fields."""
+    are reconstructed directly instead of the characteristic fields.
+    quadratic_top (N = 2 only): the hierarchy of N = 1, {p_1, p_2, p_3}
+    with the quadratic q_3 on top (a third-order reconstruction, the design
+    order of P2), instead of the quartic q_5 of the N >= 2 reading."""
     M = dg.mesh
     E = np.asarray(elems, dtype=np.int64)
     T = len(E)
@@ -341,7 +344,8 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     ntop = len(mono_top)
     pad = lambda c: np.concatenate([c, np.zeros((T, ntop - c.shape[1], F))], axis=1)
     qs = [np.zeros((T, ntop, F)), pad(c2), pad(c3)]
-    if N >= 2:
+    quartic = N >= 3 or (N == 2 and not quadratic_top)
+    if quartic:
         c5 = _solve_ls(rows(names_t4), rhs(names_t4, favg, fbar0))  # [T, 14, F]
         qs.append(c5)
     L = len(qs)
@@ -351,7 +355,7 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     g3 = linear_weights(h0, 3)
     ps = [qs[0], qs[1] / g2[:, 1, None, None]]  # p1 = q1 has zero mean-free part
     ps.append((qs[2] - g3[:, 1, None, None] * ps[1]) / g3[:, 2, None, None])
-    if N >= 2:
+    if quartic:
         g5 = linear_weights(h0, 4)
         ps.append((qs[3] - sum(g5[:, l, None, None] * ps[l] for l in range(3))) / g5[:, 3, None, None])
         gtop = g5
@@ -385,7 +389,7 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     betas[0] = area0[:, None] * np.sum(gmix * gmix, axis=1)
 
     # Step 4: tau and nonlinear weights
-    if N == 1:
+    if not quartic:
         tau = (np.abs(betas[2] - betas[0]) ** 2 + np.abs(betas[2] - betas[1]) ** 2) / 4.0
     else:
         tau = sum(np.abs(betas[3] - betas[l]) ** 2 for l in range(3)) / 16.0
@@ -419,13 +423,14 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     return out
 
 
-def limit(dg: DG, u, mask, linear_only=False, characteristic=True):
+def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False):
     """Apply the limiter to the cells where mask is true (simultaneous
     update: every reconstruction reads the pre-limit u)."""
     E = np.nonzero(np.asarray(mask))[0]
     out = u.copy()
     if len(E):
-        out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic)
+        out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic,
+                             quadratic_top=quadratic_top)
     return out
 
 

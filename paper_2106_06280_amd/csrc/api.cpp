@@ -159,6 +159,7 @@ int check_single(cswdg_solver* s) {
     if (s->n_special != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take meshes without wall or inflow faces");
     if (s->p.positivity != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take solvers without the positivity scaling");
     if (s->p.lf_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the local Lax-Friedrichs flux (lf_mode = 0)");
+    if (s->p.p2_top != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the quartic P2 hierarchy (p2_top = 0)");
     return CSWDG_OK;
 }
 
@@ -280,6 +281,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         return fail(nullptr, CSWDG_EINVAL, "kxrcf_norm, char_mode and weights_mode must be 0 or 1");
     if (p.positivity < 0 || p.positivity > 1) return fail(nullptr, CSWDG_EINVAL, "positivity must be 0 or 1");
     if (p.lf_mode < 0 || p.lf_mode > 1) return fail(nullptr, CSWDG_EINVAL, "lf_mode must be 0 or 1");
+    if (p.p2_top < 0 || p.p2_top > 1) return fail(nullptr, CSWDG_EINVAL, "p2_top must be 0 or 1");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
@@ -318,6 +320,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.kxrcf_rms = p.kxrcf_norm;
     s->ctx.char_comp = p.char_mode;
     s->ctx.weights_linear = p.weights_mode;
+    s->ctx.p2_quadratic_top = p.p2_top;
     *out = s;
     return CSWDG_OK;
 }

@@ -97,6 +97,7 @@ struct LaunchCtx {
     int kxrcf_rms;         // KXRCF norm divided by |Delta|^(1/2)
     int char_comp;         // Euler limiting on the conserved variables
     int weights_linear;    // limiter weights omega = gamma
+    int p2_quadratic_top;  // N = 2: the N = 1 hierarchy (quadratic top member)
 };
 
 int upload_tables_device();   // once per device (both translation units)

@@ -867,7 +867,7 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // ---------------------------------------------------------------------------
 // CSWENO limiter (Section 3.2)
 // ---------------------------------------------------------------------------
-template <int EQ, int N, typename S>
+template <int EQ, int N, typename S, int QTOP = 0>
 __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict__ u,
                                                 const double* __restrict__ ops,
                                                 const int32_t* __restrict__ list,
@@ -1009,7 +1009,9 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
         }
 #pragma unroll
         for (int jj = 0; jj < NM; ++jj) c5[jj] = 0.0;
-        if constexpr (N >= 2) {
+        // N = 2 with QTOP: the hierarchy of N = 1 (quadratic top member)
+        constexpr bool quartic = (N >= 3) || (N == 2 && !QTOP);
+        if constexpr (quartic) {
             constexpr int pl[5] = {0, 3, 4, 5, 6};
 #pragma unroll
             for (int jj = 0; jj < 14; ++jj) {
@@ -1026,7 +1028,7 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
         double beta[4];
         beta[1] = quad_form<NM, 2>(bp, c2);
         beta[2] = quad_form<NM, 5>(bp, c3);
-        beta[3] = (N >= 2) ? quad_form<NM, NM>(bp, c5) : 0.0;
+        beta[3] = quartic ? quad_form<NM, NM>(bp, c5) : 0.0;
         const double area0 = op[LO::AREA0];
         {
             double gx[3], gy[3], b1[3];
@@ -1063,7 +1065,7 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
             const double s2 = 1.0 + ih, s3 = 1.0 + ih + ih * ih;
             const double g22 = ih / s2;
             const double g23 = ih / s3, g33 = ih * ih / s3;
-            if constexpr (N == 1) {
+            if constexpr (!quartic) {
                 const double g13 = 1.0 / s3;
                 const double d31 = fabs(beta[2] - beta[0]), d32 = fabs(beta[2] - beta[1]);
                 // tau = 0 gives the linear weights (omega = gamma)
@@ -1425,8 +1427,12 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
     if (g > 16384u) g = 16384u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        k_limiter<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma, c.eps,
-                                                      c.char_comp, c.weights_linear);
+        if (N == 2 && c.p2_quadratic_top)
+            k_limiter<EQ, N, S, 1><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma,
+                                                             c.eps, c.char_comp, c.weights_linear);
+        else
+            k_limiter<EQ, N, S, 0><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma,
+                                                             c.eps, c.char_comp, c.weights_linear);
     });
     return hipGetLastError();
 }

@@ -392,3 +392,31 @@ def test_global_lax_friedrichs_per_instance(torch):
         assert torch.equal(ub[:, :, off[i]:off[i + 1]], u), i
     with pytest.raises(b.CswdgError):
         sol[0].dg_residual_vjp(us[0], us[0].clone())
+
+
+@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
+@pytest.mark.parametrize("eq", [0, 1])
+def test_limiter_p2_quadratic_top(torch, eq, bc):
+    """p2_top = 1: the N = 2 hierarchy with the quadratic top member, every
+    cell limited, and three KXRCF-limited steps, against the oracle's
+    quadratic_top reading."""
+    b = _binding()
+    v, t = inputs.jittered_mesh(12, seed=171)
+    M = Mesh(v, t, bc, (1.0, 1.0))
+    dg = DG(M, 2, eq)
+    S = b.Solver(eq, 2, p2_top=1)
+    S.mesh_upload(v, t, bc, (1.0, 1.0))
+    for u in (_jump_state(dg, eq, seed=4), _smooth_state(dg, eq, seed=5)):
+        out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+        exp = csweno.limit(dg, u, np.ones(M.K, bool), quadratic_top=True)
+        assert _relerr(S.to_host(out), exp) < TOL
+    u = _jump_state(dg, eq, seed=6)
+    ud = S.to_device(u)
+    lim = lambda w: csweno.limit(dg, w, kxrcf.indicator(dg, w)[1], quadratic_top=True)
+    for _ in range(3):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < 1e-10
+    if eq == 1:
+        with pytest.raises(b.CswdgError):
+            S.dg_residual_vjp(ud, ud.clone())

@@ -166,3 +166,34 @@ def test_forward_step_p1_reaches_the_papers_time(torch):
     assert bool(torch.isfinite(u).all())
     assert means[0].min() > 0 and p.min() > 0
     assert means[0].max() > 3.0
+
+
+def test_forward_step_p2_quadratic_top_reaches_the_papers_time(torch):
+    """The same with P2 and the quadratic top member of the N = 2 hierarchy
+    (p2_top = 1), about 80,000 steps."""
+    import math
+    from paper_2106_06280_amd import binding
+    v, t = inputs.forward_step_mesh(110, seed=1005)
+    kinds = inputs.forward_step_kinds(v, t)
+    ic = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
+    S = binding.Solver(1, 2, positivity=1, p2_top=1)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (0.0, 0.0))
+    S.set_boundary(kinds.astype(np.uint8), ic.state)
+    u = S.project_fn(ic)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.status()
+    steps = 0
+    while float(tt.item()) < 4.0:
+        for _ in range(2000):
+            S.max_dt(u, dt)
+            S.ssprk3_step(u, dt)
+            tt += dt
+        steps += 2000
+        assert S.status() & (binding.STATUS_NONFINITE | binding.STATUS_NEGATIVE) == 0, steps
+        assert steps < 120000
+    means = (u[:, 0, :] / math.sqrt(2.0)).cpu().numpy()
+    p = 0.4 * (means[3] - 0.5 * (means[1] ** 2 + means[2] ** 2) / means[0])
+    print(f"t = {float(tt.item()):.3f} after {steps} steps; rho in [{means[0].min():.3f}, {means[0].max():.3f}]",
+          flush=True)
+    assert bool(torch.isfinite(u).all()) and means[0].min() > 0 and p.min() > 0 and means[0].max() > 3.0

@@ -254,3 +254,35 @@ def test_component_mode_is_the_scalar_limiter_per_variable(N):
         assert np.abs(out[:, c, :] - ref[:, 0, :]).max() < 1e-13
     # and it differs from the characteristic reconstruction on jump data
     assert np.abs(out - csweno.reconstruct(de, U, E)).max() > 1e-6
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_quadratic_top_reproduces_quadratics_and_linear_data(eq):
+    """The N = 2 switch to the quadratic top member (the N = 1 hierarchy
+    projected onto P2): with the linear weights the reconstruction is the
+    quadratic least-squares fit, which reproduces quadratic data exactly;
+    with the nonlinear weights linear data are reproduced (as for every
+    hierarchy); the hierarchy has three members."""
+    M = _mesh(6)
+    d = DG(M, 2, eq)
+    E = _interior(M)
+    if eq == 0:
+        fq = lambda x, y: 0.4 + 0.7 * x - 0.5 * y + 2.0 * x * x - 0.8 * x * y + 0.3 * y * y
+        fl = lambda x, y: 0.4 + 0.7 * x - 0.5 * y
+    else:
+        fq = lambda x, y: np.stack([1.0 + 0.2 * x - 0.1 * y + 0.3 * x * y, 0.3 + 0.1 * x * x, -0.2 + 0.05 * y,
+                                    2.5 + 0.1 * x + 0.2 * y * y], -1)
+        fl = lambda x, y: np.stack([1.0 + 0.2 * x - 0.1 * y, 0.3 + 0.1 * x, -0.2 + 0.05 * y,
+                                    2.5 + 0.1 * x + 0.2 * y], -1)
+    Uq = d.project(fq)
+    out = csweno.reconstruct(d, Uq, E, linear_only=True, characteristic=False, quadratic_top=True)
+    assert np.abs(out - Uq[E]).max() < 1e-11
+    Ul = d.project(fl)
+    out, info = csweno.reconstruct(d, Ul, E, return_info=True, quadratic_top=True)
+    assert np.abs(out - Ul[E]).max() < 1e-11
+    assert len(info["omega"]) == 3
+    # the two hierarchies differ on data beyond their common degree
+    Uc = d.project(lambda x, y: (fq(x, y).T * (1.0 + 0.5 * np.sin(7.0 * x) * np.cos(5.0 * y)).T).T)
+    a = csweno.reconstruct(d, Uc, E, quadratic_top=True)
+    b = csweno.reconstruct(d, Uc, E)
+    assert np.abs(a - b).max() > 1e-6
