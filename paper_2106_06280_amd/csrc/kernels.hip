@@ -1423,8 +1423,10 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
                           int max_cells) {
     const unsigned bs = 64;
     const int lpc = c.eq == 1 ? LimLanes<1>::LPC : LimLanes<0>::LPC;
+    // 2,048 one-wave blocks fill the chip once at the limiter's register
+    // count; more blocks only add empty ones when few cells are troubled
     unsigned g = grid_for(max_cells, bs / lpc);
-    if (g > 16384u) g = 16384u;
+    if (g > 2048u) g = 2048u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
         if (N == 2 && c.p2_quadratic_top)
