@@ -163,6 +163,11 @@ int check_single(cswdg_solver* s) {
     return CSWDG_OK;
 }
 
+// The wide residual schedule (all loops unrolled) needs more than the 512
+// registers of a wave for P3 Euler and spills; that build has produced NaN
+// in some elements, so the schedule is not offered there.
+bool wide_offered(const cswdg_params& p) { return !(p.equation == CSWDG_EQ_EULER && p.degree == 3); }
+
 size_t elem_bytes(const cswdg_solver* s) { return s->p.precision == 1 ? sizeof(float) : sizeof(double); }
 
 // limit `buf` in place: troubled list from mask or KXRCF, limiter reading
@@ -316,6 +321,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     // schedule choice for the residual kernel (a tuning knob; same results)
     const char* rv = std::getenv("CSWDG_RESIDUAL_VARIANT");
     s->ctx.residual_variant = rv ? std::atoi(rv) : 3;
+    if (s->ctx.residual_variant == 1 && !wide_offered(p)) s->ctx.residual_variant = 3;
     s->ctx.residual_block = 128;
     s->ctx.kxrcf_rms = p.kxrcf_norm;
     s->ctx.char_comp = p.char_mode;
@@ -783,6 +789,8 @@ int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched) {
     if (sched[0] < 0 || sched[0] > 3 || (sched[1] != 64 && sched[1] != 128 && sched[1] != 256) ||
         (sched[2] != 0 && sched[2] != 1))
         return fail(s, CSWDG_EINVAL, "schedule: variant 0..3, block 64/128/256, xcd 0/1");
+    if (sched[0] == 1 && !wide_offered(s->p))
+        return fail(s, CSWDG_EINVAL, "schedule: the wide variant is not offered for P3 Euler");
     s->ctx.residual_variant = sched[0];
     s->ctx.residual_block = sched[1];
     s->dm.xcd_tiles = sched[2];
@@ -815,8 +823,8 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
     for (int v : variants)
         for (int b : blocks)
             for (int x : xcds) {
-                if (s->p.precision == 1 && v != 3) {
-                    // FP32-bulk runs the compact schedule only
+                if ((s->p.precision == 1 && v != 3) || (v == 1 && !wide_offered(s->p))) {
+                    // FP32-bulk runs the compact schedule only; P3 Euler has no wide one
                     if (times_us) times_us[k] = INFINITY;
                     ++k;
                     continue;

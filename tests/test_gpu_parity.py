@@ -306,6 +306,11 @@ def test_residual_schedules_parity(torch, eq, N, variant):
     """Every residual schedule (the default compact one is covered above)
     against the oracle, on a mesh with a ragged last block."""
     M, dg, S = _case(eq, N, 12, BC_TRANSMISSIVE, seed=141 + N)
+    if (eq, N, variant) == (1, 3, 1):
+        # the wide schedule is not offered for P3 Euler (its build spills)
+        with pytest.raises(_binding().CswdgError):
+            S.set_schedule(variant, 128, 1)
+        return
     S.set_schedule(variant, 128, 1)
     u = _smooth_state(dg, eq, seed=N)
     r = S.to_host(S.dg_residual(S.to_device(u)))
