@@ -71,6 +71,9 @@ extern "C" {
 #define CSWDG_LIMIT_ALL 1   /* mark every cell troubled (the accuracy tests of Section 4.1) */
 #define CSWDG_LIMIT_NONE 2  /* no limiter */
 
+#define CSWDG_INDICATOR_KXRCF 0 /* params.indicator: KXRCF (Section 3.1) */
+#define CSWDG_INDICATOR_TVB 1   /* params.indicator: TVB minmod test (not in the paper) */
+
 #define CSWDG_STATUS_NONFINITE 0x1u /* a NaN/Inf coefficient was produced */
 #define CSWDG_STATUS_NEGATIVE 0x2u  /* a non-positive Euler cell-mean density or pressure */
 #define CSWDG_STATUS_RANK 0x4u      /* a stencil least-squares system was rank deficient */
@@ -110,6 +113,15 @@ typedef struct cswdg_params {
      * under refinement with every cell limited, where the quartic is not).
      * N = 1 and N = 3 are unaffected. */
     int p2_top;
+    /* troubled-cell indicator (the first step of Section 3; the limiter does
+     * not depend on which one marks the cells): CSWDG_INDICATOR_KXRCF (the
+     * paper's, Section 3.1) or CSWDG_INDICATOR_TVB (not in the paper: the
+     * TVB minmod test of Cockburn and Shu's limiter for triangles, J. Comput.
+     * Phys. 141 (1998); cswdg_kxrcf documents it) */
+    int indicator;
+    /* the TVB constant M of CSWDG_INDICATOR_TVB (>= 0, default 0: the TVD
+     * minmod test); deviations up to M h^2 pass, h the circumradius */
+    double tvb_m;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream
@@ -194,6 +206,18 @@ int cswdg_host_connectivity(int64_t nv, const double* vxy, int64_t nt, const int
                             double period_x, double period_y, int32_t* tri_ccw, int32_t* nbr,
                             uint8_t* info);
 
+/* Host-only builder of the TVB indicator's midpoint decomposition (see
+ * cswdg_kxrcf; no device needed): A [nt][3][3] receives, for element e and
+ * face midpoint i, the coefficients A[e][i][f] with
+ * m_i - b0 = sum_f A[e][i][f] (b_f - b0) (at most two nonzero per i; the
+ * pairs of neighbour faces are tried in the order (i, i+1), (i, i+2),
+ * (i+1, i+2), the first whose coefficients are both >= 0 is used, else the
+ * one whose smaller coefficient is largest); *n_neg (may be NULL) the number
+ * of midpoints without a nonnegative pair.  Same mesh rules as
+ * cswdg_mesh_upload. */
+int cswdg_host_tvb_decomposition(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc,
+                                 double period_x, double period_y, double* A, int64_t* n_neg);
+
 /* Copy the uploaded connectivity to host arrays nbr [nt][3], info [nt][3].
  * Synchronous. */
 int cswdg_connectivity(const cswdg_solver* s, int32_t* nbr, uint8_t* info);
@@ -229,15 +253,33 @@ int cswdg_dg_residual(cswdg_solver* s, const void* u, void* r);
  * max taken over that instance's elements. */
 int cswdg_max_dt(cswdg_solver* s, const void* u, double* dt_dev);
 
-/* KXRCF indicator (Section 3.1, eq. troubledCellIndicator): flags [K]
- * (device uint8, 1 = troubled, R > C_K) and optionally R [K] (device double,
- * may be NULL). */
+/* The troubled-cell indicator of params.indicator.  KXRCF (Section 3.1,
+ * eq. troubledCellIndicator): flags [K] (device uint8, 1 = troubled,
+ * R > C_K) and optionally R [K] (device double, may be NULL).
+ * TVB (CSWDG_INDICATOR_TVB; Cockburn and Shu's limiter for triangles, used
+ * as an indicator as by Zhu, Qiu, Shu and Dumbser, J. Comput. Phys. 227
+ * (2008)): the midpoint m_i of each face is written as
+ * b0 + alpha (b_j - b0) + beta (b_k - b0), alpha, beta >= 0, with b0 the
+ * element's centroid and b_j, b_k two neighbours' centroids (a periodic
+ * neighbour translated, a boundary face's mirror image; built at mesh
+ * upload); per variable (every conserved variable for Euler) the deviation
+ * a = u_h(m_i) - ubar0 is compared with b = alpha (ubar_j - ubar0) +
+ * beta (ubar_k - ubar0) (a boundary face's ghost mean is its boundary
+ * kind's state: ubar0, reversed normal momentum at a wall, the inflow
+ * state, the moving shock's state at the face midpoint); a cell is troubled
+ * when the TVB minmod would change some a: |a| above
+ * max(tvb_m h^2, 1e-12 max_c |ubar0_c|) (h the circumradius) and not
+ * (a b > 0 and |a| <= 1.5 |b|).  R then receives the largest ratio of a
+ * deviation |a| above that threshold to the largest deviation the minmod
+ * leaves alone, max(threshold, 1.5 |b| if a b > 0), over midpoints and
+ * variables (0 when every |a| is at or below the threshold); a cell is
+ * troubled exactly when R > 1. */
 int cswdg_kxrcf(cswdg_solver* s, const void* u, uint8_t* flags, double* R);
 
 /* CSWENO limiter (Section 3.2).  Reads u_in, writes u_out (distinct
  * buffers; every troubled cell reads the pre-limit field).  Troubled cells:
  * mask_in (device uint8 [K], nonzero = troubled) when not NULL, otherwise
- * the KXRCF flags.  Cell means are copied bitwise; untroubled cells are
+ * the flags of params.indicator.  Cell means are copied bitwise; untroubled cells are
  * copied.  flags_out (device uint8 [K]) receives the mask used; may be NULL. */
 int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* flags_out,
                        const uint8_t* mask_in);
@@ -263,7 +305,10 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
  * The limiter is differentiated with its troubled-cell set frozen (the KXRCF
  * indicator is a switch, not differentiated); the Lax-Friedrichs max picks
  * the first argument on ties and d|x|/dx = 0 at x = 0.  Deterministic (no
- * floating-point atomics).  All buffers device, state layout. */
+ * floating-point atomics).  All buffers device, state layout.  These calls
+ * take FP64 single-instance solvers with the default readings (char_mode,
+ * weights_mode, lf_mode, p2_top and positivity 0, the KXRCF indicator) and
+ * no wall, inflow or moving-shock faces; CSWDG_EINVAL otherwise. */
 
 /* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).
  * u_bar must not alias r_bar. */

@@ -92,8 +92,8 @@ def decomposition(dg: DG, elems=None):
             sd = np.where(ok, det, 1.0)
             alpha = (d[:, 0] * bk[:, 1] - d[:, 1] * bk[:, 0]) / sd
             beta = (bj[:, 0] * d[:, 1] - bj[:, 1] * d[:, 0]) / sd
-            coef[:, p, 0] = alpha
-            coef[:, p, 1] = beta
+            coef[:, p, 0] = np.where(ok, alpha, 0.0)
+            coef[:, p, 1] = np.where(ok, beta, 0.0)
             low[:, p] = np.where(ok, np.minimum(alpha, beta), -np.inf)
         nonneg = low >= 0.0
         pick = np.where(nonneg.any(axis=1), nonneg.argmax(axis=1), low.argmax(axis=1))
@@ -122,11 +122,15 @@ def neighbour_means(dg: DG, u, elems=None):
     return out
 
 
-def indicator(dg: DG, u, tvb_m=0.0, elems=None):
-    """Returns (troubled bool [T], margin [T]).  margin is the smallest
-    relative distance of a deciding comparison from its tie (|a| against the
-    threshold; |a| against nu |b| where the signs agree and |a| is above the
-    threshold): decisions with margin below rounding can go either way."""
+def indicator(dg: DG, u, tvb_m=0.0, elems=None, return_ratio=False):
+    """Returns (troubled bool [T], margin [T]), and R [T] with
+    return_ratio.  margin is the smallest relative distance of a deciding
+    comparison from its tie (|a| against the threshold; |a| against nu |b|
+    where the signs agree and |a| is above the threshold): decisions with
+    margin below rounding can go either way.  R is the largest ratio of a
+    deviation above the threshold to the largest deviation the minmod keeps,
+    max(threshold, nu |b| where a b > 0), over midpoints and variables (0 if
+    none is above the threshold): troubled exactly when R > 1."""
     M = dg.mesh
     E = np.arange(M.K) if elems is None else np.asarray(elems)
     ub0 = u[E, :, 0] * PSI0  # [T, m]
@@ -147,4 +151,9 @@ def indicator(dg: DG, u, tvb_m=0.0, elems=None):
     live = (absa > thr) & (a * b > 0.0)
     d2 = np.where(live, np.abs(absa - nub) / np.maximum(np.maximum(absa, nub), tiny), np.inf)
     margin = np.minimum(d1, d2).min(axis=(1, 2))
-    return troubled, margin
+    if not return_ratio:
+        return troubled, margin
+    above = absa > thr
+    keepmax = np.maximum(thr, np.where(a * b > 0.0, nub, 0.0))
+    ratio = np.where(above, absa / np.where(above, keepmax, 1.0), 0.0)
+    return troubled, margin, ratio.max(axis=(1, 2))

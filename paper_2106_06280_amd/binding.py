@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libcswdg.so")
 EQ_BURGERS, EQ_EULER = 0, 1
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 LIMIT_KXRCF, LIMIT_ALL, LIMIT_NONE = 0, 1, 2
+INDICATOR_KXRCF, INDICATOR_TVB = 0, 1
 STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_RANK, STATUS_FOOT, STATUS_SCALED = 1, 2, 4, 8, 16
 
 _lib = None
@@ -33,7 +34,8 @@ class Params(ctypes.Structure):
                 ("limiter_mode", ctypes.c_int), ("gas_gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("c_k", ctypes.c_double), ("eps_weno", ctypes.c_double), ("kxrcf_norm", ctypes.c_int),
                 ("char_mode", ctypes.c_int), ("weights_mode", ctypes.c_int), ("positivity", ctypes.c_int),
-                ("lf_mode", ctypes.c_int), ("p2_top", ctypes.c_int)]
+                ("lf_mode", ctypes.c_int), ("p2_top", ctypes.c_int), ("indicator", ctypes.c_int),
+                ("tvb_m", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -45,6 +47,8 @@ _SIGS = {
     "cswdg_mesh_upload": (ctypes.c_int, [_P, _I64, _P, _I64, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "cswdg_mesh_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "cswdg_host_connectivity": (ctypes.c_int, [_I64, _P, _I64, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "cswdg_host_tvb_decomposition": (ctypes.c_int, [_I64, _P, _I64, _P, ctypes.c_int, ctypes.c_double,
+                                                    ctypes.c_double, _P, ctypes.POINTER(_I64)]),
     "cswdg_connectivity": (ctypes.c_int, [_P, _P, _P]),
     "cswdg_stencil": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int32)]),
     "cswdg_ic_points": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
@@ -127,16 +131,30 @@ def host_connectivity(vxy, tri, bc, period=(0.0, 0.0)):
     return tc, nbr, info
 
 
+def host_tvb_decomposition(vxy, tri, bc, period=(0.0, 0.0)):
+    """Host-only builder of the TVB indicator's midpoint decomposition:
+    (A [K, 3, 3], number of midpoints without a nonnegative pair)."""
+    vxy = np.ascontiguousarray(vxy, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    K = tri.shape[0]
+    A = np.zeros((K, 3, 3), np.float64)
+    neg = _I64(0)
+    rc = lib().cswdg_host_tvb_decomposition(vxy.shape[0], vxy.ctypes.data, K, tri.ctypes.data, bc,
+                                            float(period[0]), float(period[1]), A.ctypes.data, ctypes.byref(neg))
+    _check(rc, None)
+    return A, int(neg.value)
+
+
 class Solver:
     """One solver = one equation, degree and mesh on the current GPU."""
 
     def __init__(self, equation, degree, limiter_mode=LIMIT_KXRCF, precision=0, gamma=1.4, cfl=0.0,
                  c_k=0.0, eps=0.0, stream=None, kxrcf_norm=0, char_mode=0, weights_mode=0, positivity=0,
-                 lf_mode=0, p2_top=0):
+                 lf_mode=0, p2_top=0, indicator=INDICATOR_KXRCF, tvb_m=0.0):
         import torch
         self.torch = torch
         p = Params(equation, degree, precision, limiter_mode, gamma, cfl, c_k, eps, kxrcf_norm, char_mode,
-                   weights_mode, positivity, lf_mode, p2_top)
+                   weights_mode, positivity, lf_mode, p2_top, indicator, tvb_m)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

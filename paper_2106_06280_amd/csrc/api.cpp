@@ -67,6 +67,8 @@ struct cswdg_solver {
     double* d_lfa = nullptr;      // [n_inst] global Lax-Friedrichs constants (lf_mode = 1)
     double* d_time = nullptr;     // [n_inst] solution time (advanced by steps while a moving shock is set)
     double* d_shock = nullptr;    // moving shock of boundary kind 3: nx, ny, d0, w, post[4], pre[4]
+    double* d_tvb = nullptr;      // [9][K] TVB midpoint decomposition (indicator = 1 only)
+    int64_t n_tvb_neg = 0;        // midpoints without a nonnegative decomposition
     bool shock_set = false;
     int64_t n_special = 0;        // boundary faces of wall or inflow kind
     int dt_blocks = 1024;
@@ -100,7 +102,7 @@ int hipfail(cswdg_solver* s, hipError_t e, const char* what) {
 void free_mesh(cswdg_solver* s) {
     void* ptrs[] = {s->d_vx, s->d_vy, s->d_nbr, s->d_info, s->d_ops, s->d_flags, s->d_list, s->d_count,
                     s->d_status, s->d_tstats, s->d_compact, s->d_partial, s->d_dt, s->d_T1, s->d_T2,
-                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow, s->d_lfa, s->d_time, s->d_shock};
+                    s->d_slot, s->d_contrib, s->d_V, s->d_inst_off, s->d_inst_hmin, s->d_amax, s->d_inflow, s->d_lfa, s->d_time, s->d_shock, s->d_tvb};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s->d_vx = s->d_vy = nullptr;
@@ -123,6 +125,7 @@ void free_mesh(cswdg_solver* s) {
     s->d_lfa = nullptr;
     s->d_time = nullptr;
     s->d_shock = nullptr;
+    s->d_tvb = nullptr;
     s->shock_set = false;
     s->n_special = 0;
     s->n_inst = 1;
@@ -160,6 +163,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.positivity != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take solvers without the positivity scaling");
     if (s->p.lf_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the local Lax-Friedrichs flux (lf_mode = 0)");
     if (s->p.p2_top != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the quartic P2 hierarchy (p2_top = 0)");
+    if (s->p.indicator != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the KXRCF indicator (indicator = 0)");
     return CSWDG_OK;
 }
 
@@ -287,6 +291,10 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     if (p.positivity < 0 || p.positivity > 1) return fail(nullptr, CSWDG_EINVAL, "positivity must be 0 or 1");
     if (p.lf_mode < 0 || p.lf_mode > 1) return fail(nullptr, CSWDG_EINVAL, "lf_mode must be 0 or 1");
     if (p.p2_top < 0 || p.p2_top > 1) return fail(nullptr, CSWDG_EINVAL, "p2_top must be 0 or 1");
+    if (p.indicator != CSWDG_INDICATOR_KXRCF && p.indicator != CSWDG_INDICATOR_TVB)
+        return fail(nullptr, CSWDG_EINVAL, "indicator must be CSWDG_INDICATOR_KXRCF or CSWDG_INDICATOR_TVB");
+    if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m))
+        return fail(nullptr, CSWDG_EINVAL, "tvb_m must be finite and >= 0");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
@@ -327,6 +335,8 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.char_comp = p.char_mode;
     s->ctx.weights_linear = p.weights_mode;
     s->ctx.p2_quadratic_top = p.p2_top;
+    s->ctx.indicator = p.indicator;
+    s->ctx.tvb_m = p.tvb_m;
     *out = s;
     return CSWDG_OK;
 }
@@ -353,6 +363,22 @@ int cswdg_host_connectivity(int64_t nv, const double* vxy, int64_t nt, const int
     std::memcpy(tri_ccw, m.tri.data(), sizeof(int32_t) * 3 * nt);
     std::memcpy(nbr, m.nbr.data(), sizeof(int32_t) * 3 * nt);
     std::memcpy(info, m.info.data(), 3 * nt);
+    return CSWDG_OK;
+}
+
+int cswdg_host_tvb_decomposition(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc,
+                                 double px, double py, double* A, int64_t* n_neg) {
+    if (!A) return fail(nullptr, CSWDG_EINVAL, "null output");
+    HostMesh m;
+    std::string msg;
+    int rc = build_mesh(nv, vxy, nt, tri, bc, px, py, m, msg);
+    if (rc != CSWDG_OK) return fail(nullptr, rc, msg);
+    std::vector<double> soa;
+    int64_t neg = 0;
+    build_tvb_ops(m, soa, neg);
+    for (int64_t e = 0; e < nt; ++e)
+        for (int r = 0; r < 9; ++r) A[9 * e + r] = soa[(size_t)r * nt + e];
+    if (n_neg) *n_neg = neg;
     return CSWDG_OK;
 }
 
@@ -1007,6 +1033,9 @@ int upload_mesh(cswdg_solver* s) {
     std::vector<double> ops;
     rc = build_limiter_ops(s->mesh, s->p.degree, ops, s->n_rank, s->n_foot);
     if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
+    std::vector<double> tvbA;
+    s->n_tvb_neg = 0;
+    if (s->p.indicator == CSWDG_INDICATOR_TVB) build_tvb_ops(s->mesh, tvbA, s->n_tvb_neg);
     std::vector<int32_t> nbrT(3 * K);
     std::vector<uint32_t> info4(K);
     for (int64_t e = 0; e < K; ++e) {
@@ -1043,6 +1072,7 @@ int upload_mesh(cswdg_solver* s) {
         {(void**)&s->d_lfa, sizeof(double) * s->n_inst},
         {(void**)&s->d_time, sizeof(double) * s->n_inst},
         {(void**)&s->d_shock, sizeof(double) * 12},
+        {(void**)&s->d_tvb, sizeof(double) * std::max<size_t>(1, tvbA.size())},
         {(void**)&s->d_T1, sizeof(double) * NPM * K},
         {(void**)&s->d_T2, sizeof(double) * NPM * K},
     };
@@ -1061,6 +1091,7 @@ int upload_mesh(cswdg_solver* s) {
     cp(s->d_nbr, nbrT.data(), sizeof(int32_t) * 3 * K);
     cp(s->d_info, info4.data(), sizeof(uint32_t) * K);
     cp(s->d_ops, ops.data(), sizeof(double) * ops.size());
+    if (!tvbA.empty()) cp(s->d_tvb, tvbA.data(), sizeof(double) * tvbA.size());
     std::vector<uint32_t> zeros(kCountWords, 0u);
     cp(s->d_count, zeros.data(), sizeof(uint32_t) * kCountWords);
     cp(s->d_status, zeros.data(), sizeof(uint32_t) * 4);
@@ -1088,6 +1119,7 @@ int upload_mesh(cswdg_solver* s) {
     s->dm.lf_alpha = s->p.lf_mode ? s->d_lfa : nullptr;
     s->dm.time = s->d_time;
     s->dm.shock = nullptr;
+    s->dm.tvb = tvbA.empty() ? nullptr : s->d_tvb;
     s->shock_set = false;
     {
         const char* xt = std::getenv("CSWDG_XCD_TILES");

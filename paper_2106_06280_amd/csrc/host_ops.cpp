@@ -406,6 +406,69 @@ int build_ops_n(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank, in
 
 }  // namespace
 
+// TVB minmod indicator (Cockburn and Shu's limiter for triangles): for each
+// element (centroid b0) and face midpoint m_i, coefficients A[3 i + f] with
+// m_i - b0 = sum_f A[3 i + f] (b_f - b0), b_f the centroid of the neighbour
+// across face f (translated by its periodic shift; across a boundary face
+// the mirror image of b0 in the face line).  The neighbour pairs are tried
+// in the order (i, i+1), (i, i+2), (i+1, i+2); the first whose two
+// coefficients are >= 0 is used, else the one whose smaller coefficient is
+// largest (counted in n_neg).
+void build_tvb_ops(const HostMesh& m, std::vector<double>& A, int64_t& n_neg) {
+    const int64_t K = m.K;
+    A.assign((size_t)9 * K, 0.0);
+    n_neg = 0;
+    for (int64_t e = 0; e < K; ++e) {
+        P2d V[3];
+        for (int k = 0; k < 3; ++k) V[k] = {m.vx[k * K + e], m.vy[k * K + e]};
+        const P2d b0 = (1.0 / 3.0) * (V[0] + V[1] + V[2]);
+        P2d d[3];
+        for (int f = 0; f < 3; ++f) {
+            const uint8_t inf = m.info[3 * e + f];
+            P2d bf;
+            if (inf & 0x40) {
+                const P2d P = V[f], dd = V[(f + 1) % 3] - V[f];
+                const double t = dot(b0 - P, dd) / dot(dd, dd);
+                bf = 2.0 * (P + t * dd) - b0;
+            } else {
+                const int cx = (inf >> 2) & 3, cy = (inf >> 4) & 3;
+                const P2d sh = {cx == 1 ? m.px : (cx == 2 ? -m.px : 0.0), cy == 1 ? m.py : (cy == 2 ? -m.py : 0.0)};
+                const int64_t nb = m.nbr[3 * e + f];
+                P2d W[3];
+                for (int k = 0; k < 3; ++k) W[k] = {m.vx[k * K + nb], m.vy[k * K + nb]};
+                bf = (1.0 / 3.0) * (W[0] + W[1] + W[2]) + sh;
+            }
+            d[f] = bf - b0;
+        }
+        for (int i = 0; i < 3; ++i) {
+            const P2d mi = 0.5 * (V[i] + V[(i + 1) % 3]) - b0;
+            const int pj[3] = {i, i, (i + 1) % 3}, pk[3] = {(i + 1) % 3, (i + 2) % 3, (i + 2) % 3};
+            int best = -1;
+            double blow = -INFINITY, ba = 0.0, bb = 0.0;
+            bool found = false;
+            for (int p = 0; p < 3 && !found; ++p) {
+                const P2d bj = d[pj[p]], bk = d[pk[p]];
+                const double det = bj.x * bk.y - bj.y * bk.x;
+                if (det == 0.0) continue;
+                const double al = (mi.x * bk.y - mi.y * bk.x) / det;
+                const double be = (bj.x * mi.y - bj.y * mi.x) / det;
+                const double lo = std::min(al, be);
+                if (lo >= 0.0) found = true;
+                if (found || lo > blow) {
+                    blow = lo;
+                    best = p;
+                    ba = al;
+                    bb = be;
+                }
+            }
+            if (!found) ++n_neg;
+            if (best < 0) continue;
+            A[(size_t)(3 * i + pj[best]) * K + e] = ba;
+            A[(size_t)(3 * i + pk[best]) * K + e] = bb;
+        }
+    }
+}
+
 int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank,
                       int64_t& n_foot) {
     if (N == 1) return build_ops_n<1>(m, ops, n_rank, n_foot);

@@ -215,6 +215,12 @@ void fill_tables(Tab<N>& t) {
         }
     }
     for (int n = 0; n < D::NP; ++n) t.wmean[n] = (n == 0) ? kPsi0 : 0.0;
+    // face midpoints: (0, -1), (0, 0), (-1, 0)
+    const double mr[3] = {0.0, 0.0, -1.0}, ms[3] = {-1.0, 0.0, 0.0};
+    for (int f = 0; f < 3; ++f) {
+        basis_eval(N, mr[f], ms[f], psi);
+        for (int n = 0; n < D::NP; ++n) t.PMID[f][n] = psi[n];
+    }
 }
 
 template void fill_tables<1>(Tab<1>&);

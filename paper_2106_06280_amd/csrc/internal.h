@@ -64,6 +64,9 @@ int concat_meshes(const std::vector<HostMesh>& parts, HostMesh& out, std::vector
 // rank-deficient elements and perpendicular feet that fell outside
 int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank,
                       int64_t& n_foot);
+// the TVB indicator's midpoint decomposition [9][K] (host_ops.cpp); n_neg
+// counts midpoints with no pair of nonnegative coefficients
+void build_tvb_ops(const HostMesh& m, std::vector<double>& A, int64_t& n_neg);
 
 // ----------------------------------------------------------------------------
 // device views and launchers (kernels.hip)
@@ -86,6 +89,7 @@ struct DevMesh {
     const double* lf_alpha;   // [n_inst] global Lax-Friedrichs constants, or null (local)
     const double* time;       // [n_inst] solution time at the start of the step
     const double* shock;      // moving shock of boundary kind 3: nx, ny, d0, w, post[4], pre[4]; or null
+    const double* tvb;        // [9][K] TVB indicator: midpoint i along neighbour face f at row 3 i + f; or null
 };
 
 struct LaunchCtx {
@@ -98,6 +102,8 @@ struct LaunchCtx {
     int char_comp;         // Euler limiting on the conserved variables
     int weights_linear;    // limiter weights omega = gamma
     int p2_quadratic_top;  // N = 2: the N = 1 hierarchy (quadratic top member)
+    int indicator;         // troubled-cell indicator: 0 KXRCF, 1 TVB minmod
+    double tvb_m;          // TVB constant M
 };
 
 int upload_tables_device();   // once per device (both translation units)
@@ -115,7 +121,8 @@ hipError_t launch_max_dt(const LaunchCtx& c, const DevMesh& m, const void* u, do
 // zero on entry) is left zero for the next call
 hipError_t launch_max_dt_inst(const LaunchCtx& c, const DevMesh& m, const void* u, const double* hmin,
                               double* dt, unsigned long long* amax_bits, uint32_t* status);
-// KXRCF flags (+ optional R) and the compacted list of troubled cells
+// flags of the selected indicator (+ optional R: KXRCF's ratio, or the TVB
+// decision as 0/1) and the compacted list of troubled cells
 hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags,
                         double* R, int32_t* list, uint32_t* count);
 // compact a mask (or all cells when mask == nullptr) into the list

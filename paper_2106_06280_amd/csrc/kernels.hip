@@ -13,6 +13,7 @@
 //   k_dt_*      cell-mean wave speeds -> dt (two-pass reduction).
 //   k_kxrcf     one thread per element: KXRCF indicator, then a wave ballot
 //               and one atomic per wave to append troubled cells to a list.
+//   k_tvb       the same with the TVB minmod test (params.indicator = 1).
 //   k_limiter   one lane per (troubled cell, characteristic direction,
 //               field): subcell averages, the three (four) least-squares
 //               levels, smoothness indicators, WENO-Z weights and the
@@ -815,8 +816,6 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
                 }
                 const double vn = vx * nx + vy * ny;
                 if (vn < 0.0) {
-                    // boundary faces: the interior trace (outflow, wall) or the
-                    // inflow state's indicator variable (inflow)
                     // boundary faces: the interior trace (outflow, wall), the
                     // inflow state's indicator variable (inflow), the moving
                     // shock's at the point and the step's start (moving shock)
@@ -842,6 +841,113 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
         tr = R > ck;
         flags[e] = tr ? 1 : 0;
         if (Rout) Rout[e] = R;
+    }
+    append_list_block(tr, e, list, count, K, blockIdx.x & (kListSegs - 1));
+}
+
+// ---------------------------------------------------------------------------
+// TVB minmod indicator (not in the paper; Cockburn and Shu's limiter for
+// triangles used as a troubled-cell indicator) + compaction
+// ---------------------------------------------------------------------------
+// One thread per element.  For each face midpoint m_i and variable c: the
+// deviation a = u_h(m_i) - ubar0 = sum_{n >= 1} u_n psi_n(m_i) and the
+// neighbour-mean difference b = sum_f A[3 i + f] (ubar_f - ubar0) along the
+// mesh's midpoint decomposition A (two nonnegative coefficients); the cell
+// is troubled when some |a| exceeds max(M h^2, 1e-12 max_c |ubar0_c|) (h the
+// circumradius) without a b > 0 and |a| <= 1.5 |b|.  Across a boundary face
+// the neighbour mean is the ghost's: ubar0 (outflow), ubar0 with its normal
+// momentum reversed (wall), the inflow state, or the moving shock's state
+// at the face midpoint and the step's start.
+template <int EQ, int N, typename S>
+__global__ __launch_bounds__(256) void k_tvb(DevMesh msh, const S* __restrict__ u,
+                                             uint8_t* __restrict__ flags, double* __restrict__ Rout,
+                                             int32_t* __restrict__ list, uint32_t* __restrict__ count,
+                                             double tvb_m) {
+    constexpr int M = Phys<EQ>::M, NP = Dims<N>::NP;
+    const int K = msh.K;
+    const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
+    bool tr = false;
+    if (e < K) {
+        const Tab<N>& T = tab<N>();
+        double ub0[M], db[3][M];
+        double smax = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            ub0[c] = (double)u[(size_t)(c * NP) * K + e] * kPsi0;
+            smax = fmax(smax, fabs(ub0[c]));
+        }
+        const double X[3] = {msh.vx[e], msh.vx[K + e], msh.vx[2 * K + e]};
+        const double Y[3] = {msh.vy[e], msh.vy[K + e], msh.vy[2 * K + e]};
+        const uint32_t info4 = msh.info[e];
+        double Ls[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const int f1 = (f + 1) % 3;
+            const double ex = X[f1] - X[f], ey = Y[f1] - Y[f];
+            Ls[f] = sqrt(ex * ex + ey * ey);
+            const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+            const bool bnd = (inf & 0x40u) != 0u;
+            const uint32_t kind = inf & 3u;
+            double g[M];
+            if (!bnd) {
+                const int nb = msh.nbr[f * K + e];
+#pragma unroll
+                for (int c = 0; c < M; ++c) g[c] = (double)u[(size_t)(c * NP) * K + nb] * kPsi0;
+            } else {
+#pragma unroll
+                for (int c = 0; c < M; ++c) g[c] = ub0[c];
+                if constexpr (EQ == 1) {
+                    if (kind == 1u) {
+                        const double nx = ey / Ls[f], ny = -ex / Ls[f];
+                        const double mn = ub0[1] * nx + ub0[2] * ny;
+                        g[1] = ub0[1] - 2.0 * mn * nx;
+                        g[2] = ub0[2] - 2.0 * mn * ny;
+                    }
+                }
+                if (kind == 2u) {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) g[c] = msh.inflow[c];
+                } else if (kind == 3u && msh.shock != nullptr) {
+                    const double xm = 0.5 * (X[f] + X[f1]), ym = 0.5 * (Y[f] + Y[f1]);
+                    const int o = shock_state_at(msh.shock, xm, ym, msh.time[inst_of(msh, e)]);
+#pragma unroll
+                    for (int c = 0; c < M; ++c) g[c] = msh.shock[o + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) db[f][c] = g[c] - ub0[c];
+        }
+        double A[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) A[i][f] = msh.tvb[(size_t)(3 * i + f) * K + e];
+        const double J2 = (X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]);
+        const double h = Ls[0] * Ls[1] * Ls[2] / (2.0 * J2);
+        const double thr = fmax(tvb_m * h * h, 1e-12 * smax);
+        double rmax = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double U[NP];
+#pragma unroll
+            for (int n = 1; n < NP; ++n) U[n] = (double)u[(size_t)(c * NP + n) * K + e];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double a = 0.0;
+#pragma unroll
+                for (int n = 1; n < NP; ++n) a += T.PMID[i][n] * U[n];
+                const double b = A[i][0] * db[0][c] + A[i][1] * db[1][c] + A[i][2] * db[2][c];
+                const double aa = fabs(a);
+                const bool same = a * b > 0.0;
+                const bool keep = (aa <= thr) || (same && aa <= 1.5 * fabs(b));
+                tr = tr || !keep;
+                // the ratio of the deviation to the largest one the minmod
+                // leaves alone (> 1 exactly for the deviations it changes)
+                if (Rout != nullptr && aa > thr) rmax = fmax(rmax, aa / fmax(thr, same ? 1.5 * fabs(b) : 0.0));
+            }
+        }
+        flags[e] = tr ? 1 : 0;
+        if (Rout) Rout[e] = rmax;
     }
     append_list_block(tr, e, list, count, K, blockIdx.x & (kListSegs - 1));
 }
@@ -1401,9 +1507,16 @@ hipError_t launch_time_advance(const LaunchCtx& c, int n_inst, double* time, con
 hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags, double* R,
                         int32_t* list, uint32_t* count) {
     const unsigned bs = 256, g = grid_for(m.K, bs);
-    CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        k_kxrcf<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, flags, R, list, count, c.c_k, c.kxrcf_rms);
-    });
+    if (c.indicator == 1) {
+        if (m.tvb == nullptr) return hipErrorInvalidValue;
+        CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+            k_tvb<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, flags, R, list, count, c.tvb_m);
+        });
+    } else {
+        CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+            k_kxrcf<EQ, N, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, flags, R, list, count, c.c_k, c.kxrcf_rms);
+        });
+    }
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct Tab {
     double we[D::NE];            // edge weights (sum 2)
     double es[D::NE];            // position of edge point g along its face, in (0, 1) from vertex f to f+1
     double wmean[D::NP];         // mean of psi_n over the reference triangle
+    double PMID[3][D::NP];       // psi_n at the midpoint of face f
 };
 
 // The residual's tables in single precision (FP32-bulk mode).

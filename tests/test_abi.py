@@ -63,3 +63,26 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(ImportError):
         binding.lib()
+
+
+@pytest.mark.parametrize("kind", ["periodic", "transmissive", "oneway", "ffstep"])
+def test_host_tvb_decomposition_matches_the_oracle(kind):
+    """The library's TVB midpoint decomposition (built on the host at mesh
+    upload) against the oracle's: the same pair of neighbours per midpoint
+    and the same coefficients up to rounding."""
+    from oracle import tvb
+    from oracle.dg import DG
+    from oracle.mesh import Mesh
+    if kind == "ffstep":
+        v, t = inputs.forward_step_mesh(10, seed=4)
+        bc, period = BC_TRANSMISSIVE, (0.0, 0.0)
+    else:
+        v, t = inputs.jittered_mesh(9, -1.0, 3.0, 0.0, 2.0, seed=6)
+        bc, period = {"periodic": (BC_PERIODIC, (4.0, 2.0)), "transmissive": (BC_TRANSMISSIVE, (0.0, 0.0)),
+                      "oneway": (BC_PERIODIC, (4.0, 0.0))}[kind]
+    A, neg = binding.host_tvb_decomposition(v, t, bc, period)
+    M = Mesh(v, t, bc, period)
+    Ao = tvb.decomposition(DG(M, 1, 1))
+    assert neg == 0
+    assert np.array_equal(A != 0.0, Ao != 0.0)
+    assert np.abs(A - Ao).max() < 1e-12

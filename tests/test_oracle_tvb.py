@@ -93,9 +93,17 @@ def test_one_cell_slope_scaled(N, eq):
                       (-0.3, True)]:
         u = base.copy()
         u[e, :, 1:] *= s
-        tr, margin = tvb.indicator(dg, u, elems=[e])
+        tr, margin, R = tvb.indicator(dg, u, elems=[e], return_ratio=True)
         assert bool(tr[0]) == expect, s
         assert margin[0] > 0.01
+        # the ratio to the largest deviation kept: s / 1.5 for s > 0, the
+        # deviation over the rounding floor for s < 0
+        if s > 0:
+            assert abs(R[0] - s / 1.5) < 1e-10
+        elif s < 0:
+            assert R[0] > 1e6
+        else:
+            assert R[0] == 0.0
 
 
 def test_threshold_is_m_h_squared_at_the_circumradius():
