@@ -22,7 +22,9 @@ result goes to a new array, so the order of troubled cells is irrelevant):
    least-squares sense (QR), in the scaled monomials ((x-x0)/h0)^a
    ((y-y0)/h0)^b about the centroid of Delta0, h0 its mean side.
 5. Step 2: equivalent polynomials (eqs. equivalentOrder0-2, 4) with linear
-   weights gamma_{l,m} = h^{-(l-1)} / sum (Section 3.2, Step 2).
+   weights gamma_{l,m} = h^{-(l-1)} / sum (Section 3.2, Step 2); the
+   option constant_gamma takes 10^{l-1} / sum instead, the weights of the
+   reference cited there, which the paper replaces by the h-dependent ones.
 6. Step 3: smoothness indicators (eq. smoothnessIndicator) of q_l,
    l >= 2, over all derivative orders 1..deg q_l; beta_1 from the three
    linear functions on each neighbour's centroid subcells (eqs. sigmaEqn,
@@ -207,9 +209,13 @@ def monomial_average(P, x0, y0, h0, d):
 # The limiter
 # ---------------------------------------------------------------------------
 
-def linear_weights(h0, t):
-    """gamma_{l,m}, l = 1..t: (1/h)^{l-1} normalised to sum 1: [T, t]."""
-    g = np.stack([h0 ** (-(l - 1)) for l in range(1, t + 1)], axis=-1)
+def linear_weights(h0, t, constant=False):
+    """gamma_{l,m}, l = 1..t, normalised to sum 1: [T, t].  The paper's
+    gamma_bar = (1/h)^{l-1} (Section 3.2, Step 2), or with constant = True
+    gamma_bar = 10^{l-1}, the choice of the reference it cites there, which
+    the paper replaces by the h-dependent one."""
+    base = np.full_like(h0, 10.0) if constant else 1.0 / h0
+    g = np.stack([base ** (l - 1) for l in range(1, t + 1)], axis=-1)
     return g / np.sum(g, axis=-1, keepdims=True)
 
 
@@ -251,14 +257,16 @@ def _beta_matrix(V0, x0, y0, h0, area0, d):
     return B
 
 
-def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True, quadratic_top=False):
+def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True, quadratic_top=False,
+                constant_gamma=False):
     """New coefficients for the troubled cells elems: [T, m, Np].  Mode 0
     is copied from u.  linear_only: the weights are the linear weights
     (omega = gamma); characteristic=False (Euler): the conserved variables
     are reconstructed directly instead of the characteristic fields.
     quadratic_top (N = 2 only): the hierarchy of N = 1, {p_1, p_2, p_3}
     with the quadratic q_3 on top (a third-order reconstruction, the design
-    order of P2), instead of the quartic q_5 of the N >= 2 reading."""
+    order of P2), instead of the quartic q_5 of the N >= 2 reading.
+    constant_gamma: linear weights from 10^{l-1} instead of (1/h)^{l-1}."""
     M = dg.mesh
     E = np.asarray(elems, dtype=np.int64)
     T = len(E)
@@ -351,12 +359,12 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     L = len(qs)
 
     # Step 2: equivalent polynomials (mean-free parts; all means equal ubar0)
-    g2 = linear_weights(h0, 2)
-    g3 = linear_weights(h0, 3)
+    g2 = linear_weights(h0, 2, constant_gamma)
+    g3 = linear_weights(h0, 3, constant_gamma)
     ps = [qs[0], qs[1] / g2[:, 1, None, None]]  # p1 = q1 has zero mean-free part
     ps.append((qs[2] - g3[:, 1, None, None] * ps[1]) / g3[:, 2, None, None])
     if quartic:
-        g5 = linear_weights(h0, 4)
+        g5 = linear_weights(h0, 4, constant_gamma)
         ps.append((qs[3] - sum(g5[:, l, None, None] * ps[l] for l in range(3))) / g5[:, 3, None, None])
         gtop = g5
     else:
@@ -423,14 +431,14 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     return out
 
 
-def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False):
+def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False, constant_gamma=False):
     """Apply the limiter to the cells where mask is true (simultaneous
     update: every reconstruction reads the pre-limit u)."""
     E = np.nonzero(np.asarray(mask))[0]
     out = u.copy()
     if len(E):
         out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic,
-                             quadratic_top=quadratic_top)
+                             quadratic_top=quadratic_top, constant_gamma=constant_gamma)
     return out
 
 

@@ -286,3 +286,59 @@ def test_quadratic_top_reproduces_quadratics_and_linear_data(eq):
     a = csweno.reconstruct(d, Uc, E, quadratic_top=True)
     b = csweno.reconstruct(d, Uc, E)
     assert np.abs(a - b).max() > 1e-6
+
+
+def test_constant_linear_weights():
+    """gamma_bar = 10^{l-1} (the cited reference's choice that Section 3.2,
+    Step 2 replaces): the same weights for every h."""
+    for h in (0.005, 0.3, 7.0):
+        h0 = np.array([h])
+        assert np.allclose(csweno.linear_weights(h0, 2, True)[0], [1 / 11, 10 / 11], rtol=1e-15)
+        assert np.allclose(csweno.linear_weights(h0, 3, True)[0], [1 / 111, 10 / 111, 100 / 111], rtol=1e-15)
+        assert np.allclose(csweno.linear_weights(h0, 4, True)[0], [1 / 1111, 10 / 1111, 100 / 1111, 1000 / 1111],
+                           rtol=1e-15)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_constant_gamma_reproduction(N):
+    """With the constant linear weights: linear data are reproduced by the
+    nonlinear weights (tau = 0) and degree-N data by the linear weights
+    (the telescoping sum is the top least-squares fit, exact on the
+    neighbours' degree-N polynomials)."""
+    M = _mesh(6)
+    d = DG(M, N, 0)
+    E = _interior(M)
+    U = d.project(lambda x, y: 0.4 + 0.7 * x - 0.5 * y)
+    out, info = csweno.reconstruct(d, U, E, return_info=True, constant_gamma=True)
+    assert np.abs(out - U[E]).max() < 1e-11
+    assert np.allclose(np.stack(info["omega"], 1), info["gamma"][:, :, None], atol=1e-9)
+    assert np.allclose(info["gamma"][0], csweno.linear_weights(np.array([1.0]), info["gamma"].shape[1], True)[0])
+    terms = [lambda x, y: 0.7 * x - 0.5 * y, lambda x, y: 2.0 * x * x - 0.8 * x * y + 0.3 * y * y,
+             lambda x, y: 1.5 * x ** 3 - 0.7 * x * y * y + 0.4 * y ** 3]
+    Uq = d.project(lambda x, y: 0.4 + sum(f(x, y) for f in terms[:N]))
+    out = csweno.reconstruct(d, Uq, E, linear_only=True, constant_gamma=True)
+    assert np.abs(out - Uq[E]).max() < 1e-10
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_constant_gamma_is_scale_free(N):
+    """Every other ingredient of the reconstruction (least-squares fits,
+    beta, tau) is invariant under scaling the domain, so with constant
+    linear weights the limited coefficients of u(x / s) on the mesh scaled
+    by s equal those of u on the original mesh; with (1/h)^{l-1} they do
+    not."""
+    v, t = inputs.jittered_mesh(6, seed=12)
+    s = 7.0
+    f = lambda x, y: 0.3 + 0.5 * np.sin(2 * math.pi * (x + y)) + np.where(x + 0.3 * y > 0.55, 0.8, 0.0)
+    d1 = DG(Mesh(v, t, BC_PERIODIC, (1.0, 1.0)), N, 0)
+    d2 = DG(Mesh(v * s, t, BC_PERIODIC, (s, s)), N, 0)
+    U1 = d1.project(f)
+    U2 = d2.project(lambda x, y: f(x / s, y / s))
+    assert np.abs(U1 - U2).max() < 1e-13
+    mask = np.ones(d1.mesh.K, bool)
+    a = csweno.limit(d1, U1, mask, constant_gamma=True)
+    b = csweno.limit(d2, U2, mask, constant_gamma=True)
+    assert np.abs(a - b).max() < 1e-9
+    a = csweno.limit(d1, U1, mask)
+    b = csweno.limit(d2, U2, mask)
+    assert np.abs(a - b).max() > 1e-4
