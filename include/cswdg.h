@@ -122,6 +122,12 @@ typedef struct cswdg_params {
     /* the TVB constant M of CSWDG_INDICATOR_TVB (>= 0, default 0: the TVD
      * minmod test); deviations up to M h^2 pass, h the circumradius */
     double tvb_m;
+    /* linear weights of the reconstruction hierarchy (Section 3.2, Step 2):
+     * 0 gamma_bar_{l,m} = (1/h)^(l-1), h the mean side (the paper's);
+     * 1 gamma_bar_{l,m} = 10^(l-1), the weights of the reference cited
+     * there, which the paper replaces (the same for every h, so the
+     * reconstruction does not depend on the length scale of the mesh) */
+    int gamma_mode;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream
@@ -307,7 +313,7 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
  * the first argument on ties and d|x|/dx = 0 at x = 0.  Deterministic (no
  * floating-point atomics).  All buffers device, state layout.  These calls
  * take FP64 single-instance solvers with the default readings (char_mode,
- * weights_mode, lf_mode, p2_top and positivity 0, the KXRCF indicator) and
+ * weights_mode, lf_mode, p2_top, gamma_mode and positivity 0, the KXRCF indicator) and
  * no wall, inflow or moving-shock faces; CSWDG_EINVAL otherwise. */
 
 /* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).

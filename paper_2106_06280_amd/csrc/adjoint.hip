@@ -433,7 +433,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             }
             beta[0] = area0 * (mx * mx + my * my);
         }
-        const double ih = 1.0 / op[LO::H0];
+        const double ih = op[LO::GBASE];
         const double s2 = 1.0 + ih, s3 = 1.0 + ih + ih * ih, s5 = 1.0 + ih + ih * ih + ih * ih * ih;
         const double g22 = ih / s2, g23 = ih / s3, g33 = ih * ih / s3;
         const double g15 = 1.0 / s5, g25 = ih / s5, g35 = ih * ih / s5, g45 = ih * ih * ih / s5;

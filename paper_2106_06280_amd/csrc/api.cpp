@@ -164,6 +164,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.lf_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the local Lax-Friedrichs flux (lf_mode = 0)");
     if (s->p.p2_top != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the quartic P2 hierarchy (p2_top = 0)");
     if (s->p.indicator != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the KXRCF indicator (indicator = 0)");
+    if (s->p.gamma_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the linear weights (1/h)^(l-1) (gamma_mode = 0)");
     return CSWDG_OK;
 }
 
@@ -295,6 +296,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         return fail(nullptr, CSWDG_EINVAL, "indicator must be CSWDG_INDICATOR_KXRCF or CSWDG_INDICATOR_TVB");
     if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m))
         return fail(nullptr, CSWDG_EINVAL, "tvb_m must be finite and >= 0");
+    if (p.gamma_mode < 0 || p.gamma_mode > 1) return fail(nullptr, CSWDG_EINVAL, "gamma_mode must be 0 or 1");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
@@ -1031,7 +1033,7 @@ int upload_mesh(cswdg_solver* s) {
     int rc;
     const int64_t K = s->mesh.K;
     std::vector<double> ops;
-    rc = build_limiter_ops(s->mesh, s->p.degree, ops, s->n_rank, s->n_foot);
+    rc = build_limiter_ops(s->mesh, s->p.degree, s->p.gamma_mode == 1, ops, s->n_rank, s->n_foot);
     if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
     std::vector<double> tvbA;
     s->n_tvb_neg = 0;

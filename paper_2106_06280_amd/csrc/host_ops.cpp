@@ -27,6 +27,7 @@
 //                 functions of eq. sigmaEqn.
 //   PM            (1/J) int_e phi_j psi_i for i >= 1: the L2 projection of
 //                 the reconstruction onto the basis.
+//   GBASE         b of the linear weights gamma_bar_l = b^(l-1): 1/h0, or 10.
 #include <algorithm>
 #include <cmath>
 #include <thread>
@@ -131,12 +132,13 @@ struct OpBuilder {
     using D = Dims<N>;
     using L = OpLayout<N>;
     const HostMesh& m;
+    bool constant_gamma;
     std::vector<double> C;  // basis monomial form [NP][NP]
     Rule2D rN, rTop, rBeta, rProj;
     std::vector<double> psiProj;  // [q][NP] on rProj
     MonoList mono{D::DTOP};
 
-    explicit OpBuilder(const HostMesh& mm) : m(mm) {
+    OpBuilder(const HostMesh& mm, bool cg) : m(mm), constant_gamma(cg) {
         basis_monomial_form(N, C);
         rN = triangle_rule((N + 2) / 2);
         rTop = triangle_rule((D::DTOP + 2) / 2);
@@ -375,7 +377,9 @@ struct OpBuilder {
                         op[L::PM + (i - 1) * D::NMONO + j] += rProj.w[q] * tmp[j] * psiProj[q * D::NP + i];
             }
         }
-        op[L::H0] = h0;
+        // linear weights gamma_bar_l = b^(l-1) (Section 3.2, Step 2): b = 1/h0,
+        // or the constant 10 of the reference cited there
+        op[L::GBASE] = constant_gamma ? 10.0 : 1.0 / h0;
         op[L::AREA0] = area0;
         op[L::VALID] = valid ? 1.0 : 0.0;
         return valid;
@@ -383,9 +387,10 @@ struct OpBuilder {
 };
 
 template <int N>
-int build_ops_n(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank, int64_t& n_foot) {
+int build_ops_n(const HostMesh& m, bool constant_gamma, std::vector<double>& ops, int64_t& n_rank,
+                int64_t& n_foot) {
     using L = OpLayout<N>;
-    OpBuilder<N> b(m);
+    OpBuilder<N> b(m, constant_gamma);
     ops.assign((size_t)m.K * L::LEN, 0.0);
     unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
     std::vector<int64_t> rank(nt, 0), foot(nt, 0);
@@ -469,11 +474,11 @@ void build_tvb_ops(const HostMesh& m, std::vector<double>& A, int64_t& n_neg) {
     }
 }
 
-int build_limiter_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank,
+int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, std::vector<double>& ops, int64_t& n_rank,
                       int64_t& n_foot) {
-    if (N == 1) return build_ops_n<1>(m, ops, n_rank, n_foot);
-    if (N == 2) return build_ops_n<2>(m, ops, n_rank, n_foot);
-    if (N == 3) return build_ops_n<3>(m, ops, n_rank, n_foot);
+    if (N == 1) return build_ops_n<1>(m, constant_gamma, ops, n_rank, n_foot);
+    if (N == 2) return build_ops_n<2>(m, constant_gamma, ops, n_rank, n_foot);
+    if (N == 3) return build_ops_n<3>(m, constant_gamma, ops, n_rank, n_foot);
     return CSWDG_EINVAL;
 }
 

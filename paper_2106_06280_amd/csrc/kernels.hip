@@ -1163,9 +1163,11 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
             }
             beta[0] = area0 * (mx * mx + my * my);
         }
-        // Steps 2 and 4: linear weights gamma_{l,t} = h^{-(l-1)} / sum,
-        // WENO-Z weights, R = sum_l omega_l p_l written on c2, c3, c5
-        const double ih = 1.0 / op[LO::H0];
+        // Steps 2 and 4: linear weights gamma_{l,t} = b^{l-1} / sum with
+        // b = 1/h (or the constant b = 10 of the reference cited there; the
+        // operator record holds b), WENO-Z weights, R = sum_l omega_l p_l
+        // written on c2, c3, c5
+        const double ih = op[LO::GBASE];
         double A2, A3, A5;
         {
             const double s2 = 1.0 + ih, s3 = 1.0 + ih + ih * ih;

@@ -65,8 +65,8 @@ struct OpLayout {
     static constexpr int BP = X5 + ((N >= 2) ? 14 * 15 : 0);      // packed upper triangle of the beta matrix
     static constexpr int MINV = BP + D::NBP;                      // [3][2][2] inverse centroid-difference matrices
     static constexpr int PM = MINV + 12;                          // [NP-1][NMONO] projection onto psi_1..
-    static constexpr int H0 = PM + (D::NP - 1) * D::NMONO;         // mean side of Delta0
-    static constexpr int AREA0 = H0 + 1;                           // area of Delta0
+    static constexpr int GBASE = PM + (D::NP - 1) * D::NMONO;      // base b of the linear weights b^(l-1): 1/h0 or 10
+    static constexpr int AREA0 = GBASE + 1;                        // area of Delta0
     static constexpr int VALID = AREA0 + 1;                        // 1 = full-rank stencil
     static constexpr int RAW = VALID + 1;
     static constexpr int LEN = (RAW + 7) / 8 * 8;                  // padded to 64 bytes

@@ -425,3 +425,38 @@ def test_limiter_p2_quadratic_top(torch, eq, bc):
     if eq == 1:
         with pytest.raises(b.CswdgError):
             S.dg_residual_vjp(ud, ud.clone())
+
+
+@pytest.mark.parametrize("eq,N", EQN)
+def test_limiter_constant_gamma(torch, eq, N):
+    """gamma_mode = 1: the linear weights 10^(l-1) of the reference that
+    Section 3.2, Step 2 cites (instead of (1/h)^(l-1)); every cell troubled
+    and the KXRCF cells, against the oracle."""
+    M, dg, S = _case_opts(eq, N, 12, BC_TRANSMISSIVE, seed=131 + N, gamma_mode=1)
+    u = _jump_state(dg, eq, seed=17)
+    ud = S.to_device(u)
+    out, _ = S.csweno_limit(ud, mask=torch.ones(M.K, dtype=torch.uint8))
+    exp = csweno.limit(dg, u, np.ones(M.K, bool), constant_gamma=True)
+    assert _relerr(S.to_host(out), exp) < TOL
+    assert np.abs(exp - csweno.limit(dg, u, np.ones(M.K, bool))).max() > 1e-6
+    out, flags = S.csweno_limit(ud)
+    fo = kxrcf.indicator(dg, u)[1]
+    assert np.array_equal(flags.cpu().numpy().astype(bool), fo)
+    assert _relerr(S.to_host(out), csweno.limit(dg, u, fo, constant_gamma=True)) < TOL
+
+
+@pytest.mark.parametrize("N,top", [(1, 0), (2, 0), (2, 1), (3, 0)])
+def test_steps_constant_gamma(torch, N, top):
+    M, dg, S = _case_opts(1, N, 14, BC_TRANSMISSIVE, seed=141, gamma_mode=1, p2_top=top)
+    u = _jump_state(dg, 1, seed=19)
+    ud = S.to_device(u)
+    lim = lambda v: csweno.limit(dg, v, kxrcf.indicator(dg, v)[1], quadratic_top=bool(top), constant_gamma=True)
+    for _ in range(3):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < 1e-10
+    b = _binding()
+    with pytest.raises(b.CswdgError):
+        b.Solver(1, N, gamma_mode=2)
+    with pytest.raises(b.CswdgError):
+        S.dg_residual_vjp(ud, ud.clone())
