@@ -1,0 +1,121 @@
+"""Section 4's Examples 4-6 at P2 and P3 run to the paper's end times with
+the linear weights 10^(l-1) of the reference that Section 3.2, Step 2
+cites (gamma_mode = 1), on meshes of half the paper's resolution (GPU).
+
+With the paper's (1/h)^(l-1), at the paper's resolutions, these problems
+lose positivity at P2/P3 long before the end time (Example 4 in the first
+step): at h = 1/200 the linear weights of the four members are in the
+ratio 1 : 200 : 4e4 : 8e6, the nonlinear weights cannot move off the top
+member at a strong shock, and its least-squares fit across the jump
+undershoots to negative densities.  Example 4 also takes the TVB indicator: KXRCF
+sees no inflow faces ahead of a shock moving into gas at rest."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2106_06280_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _clip_run(torch, S, u, t_end, chunk):
+    """Whole chunks while they fit, then single steps with the last dt
+    clipped to t_end."""
+    from paper_2106_06280_amd import binding
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    S.status()
+    steps = 0
+    while True:
+        S.max_dt(u, dt)
+        if float(t.item()) + 1.5 * chunk * float(dt.item()) > t_end:
+            break
+        for _ in range(chunk):
+            S.max_dt(u, dt)
+            S.ssprk3_step(u, dt)
+            t += dt
+        steps += chunk
+        st = S.status()
+        assert st & (binding.STATUS_NONFINITE | binding.STATUS_NEGATIVE) == 0, (steps, float(t.item()))
+        assert steps < 200000
+    while float(t.item()) < t_end - 1e-14:
+        S.max_dt(u, dt)
+        dt.clamp_(max=t_end - float(t.item()))
+        S.ssprk3_step(u, dt)
+        t += dt
+        steps += 1
+    assert S.status() & (binding.STATUS_NONFINITE | binding.STATUS_NEGATIVE) == 0
+    means = (u[:, 0, :] / math.sqrt(2.0)).cpu().numpy()
+    p = 0.4 * (means[3] - 0.5 * (means[1] ** 2 + means[2] ** 2) / means[0])
+    assert bool(torch.isfinite(u).all()) and means[0].min() > 0 and p.min() > 0
+    return float(t.item()), means, p, steps
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_example4_shock_entropy_p2_p3(torch, N):
+    """Example 4 at h = 1/100 to t = 0.178 (TVB indicator, constant linear
+    weights, cell means in the cells the initial shock cuts): the shock
+    sits where the jump conditions put it, within a mesh width."""
+    from paper_2106_06280_amd import binding
+    n = 100
+    v, t = inputs.jittered_mesh(n, seed=1006)
+    S = binding.Solver(1, N, positivity=1, indicator=binding.INDICATOR_TVB, gamma_mode=1)
+    S.mesh_upload(v, t, binding.BC_PERIODIC, (0.0, 1.0))
+    u = S.project_fn(inputs.ShockEntropyWave())
+    cx = v[t].mean(axis=1)[:, 0]
+    u[:, 1:, torch.from_numpy(np.abs(cx - 0.125) < 1.0 / n).cuda()] = 0.0
+    tt, means, p, steps = _clip_run(torch, S, u, 0.178, 200)
+    assert abs(tt - 0.178) < 1e-12
+    xs = cx[p > 5.5].max()
+    exp = 0.125 + inputs.ShockEntropyWave.shock_speed() * 0.178
+    print(f"Example 4 P{N}: {steps} steps, shock at {xs:.4f} (jump conditions {exp:.4f})", flush=True)
+    assert abs(xs - exp) < 1.0 / n
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_example5_double_mach_p2_p3(torch, N):
+    """Example 5 at h = 1/100 to t = 0.2 (KXRCF, constant linear weights):
+    the Mach stem compresses the gas to several times the post-shock
+    density 8."""
+    from paper_2106_06280_amd import binding
+    D = inputs.DoubleMachReflection
+    sh = D.shock()
+    v, t = inputs.dmr_mesh(100, seed=1007)
+    S = binding.Solver(1, N, positivity=1, gamma_mode=1)
+    S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
+    S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
+    S.set_boundary(inputs.dmr_kinds(v, t), sh["post"])
+    u = S.project_fn(D())
+    side = v[t] @ np.array(sh["n"]) - sh["d0"]
+    cut = ~(np.all(side < 0, axis=1) | np.all(side > 0, axis=1))
+    u[:, 1:, torch.from_numpy(cut).cuda()] = 0.0
+    tt, means, p, steps = _clip_run(torch, S, u, 0.2, 1000)
+    assert abs(S.time()[0] - 0.2) < 1e-12
+    print(f"Example 5 P{N}: {steps} steps, rho in [{means[0].min():.3f}, {means[0].max():.3f}]", flush=True)
+    assert means[0].min() > 1.3 and 15.0 < means[0].max() < 40.0
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_example6_forward_step_p2_p3(torch, N):
+    """Example 6 at h = 1/50 to t = 4 (KXRCF, constant linear weights): the
+    reflected shocks compress the gas well above the inflow density 1.4."""
+    from paper_2106_06280_amd import binding
+    v, t = inputs.forward_step_mesh(50, seed=1005)
+    kinds = inputs.forward_step_kinds(v, t)
+    ic = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
+    S = binding.Solver(1, N, positivity=1, gamma_mode=1)
+    S.mesh_upload(v, t, binding.BC_TRANSMISSIVE, (0.0, 0.0))
+    S.set_boundary(kinds.astype(np.uint8), ic.state)
+    u = S.project_fn(ic)
+    tt, means, p, steps = _clip_run(torch, S, u, 4.0, 2000)
+    print(f"Example 6 P{N}: {steps} steps, rho in [{means[0].min():.3f}, {means[0].max():.3f}]", flush=True)
+    assert abs(tt - 4.0) < 1e-12 and means[0].max() > 3.0
