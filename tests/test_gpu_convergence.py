@@ -33,7 +33,7 @@ def torch():
     return t
 
 
-def _run(torch, problem, N, n, limit_all, p2_top=0):
+def _run(torch, problem, N, n, limit_all, p2_top=0, gamma_mode=0):
     from paper_2106_06280_amd import binding
     if problem == "burgers":
         v, t = inputs.jittered_mesh(n, -2, 2, -2, 2, seed=7)
@@ -41,7 +41,8 @@ def _run(torch, problem, N, n, limit_all, p2_top=0):
     else:
         v, t = inputs.jittered_mesh(n, 0, 2, 0, 2, seed=7)
         per, ic, eq, t_end = (2.0, 2.0), inputs.EntropyWave(), 1, 0.2
-    S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_ALL if limit_all else binding.LIMIT_NONE, p2_top=p2_top)
+    S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_ALL if limit_all else binding.LIMIT_NONE, p2_top=p2_top,
+                       gamma_mode=gamma_mode)
     S.mesh_upload(v, t, BC_PERIODIC, per)
     u = S.project_fn(ic)
     nsteps = int(math.ceil(t_end / S.max_dt(u).item()))
@@ -67,5 +68,21 @@ def test_convergence_order(torch, problem, table, N, limit_all):
     order = math.log(errs[1] / errs[2]) / math.log(2.0)
     printed = ORDERS[(table, N)][1 if limit_all else 0]
     print(f"{problem} P{N} limiter={limit_all}: errors {errs}, order {order:.3f} (paper {printed})", flush=True)
+    assert order >= min(printed, N + 1) - 0.25
+    assert errs[0] > errs[1] > errs[2]
+
+
+@pytest.mark.parametrize("problem,table,N", [("burgers", 1, 1), ("burgers", 1, 3), ("entropy", 2, 1),
+                                             ("entropy", 2, 2), ("entropy", 2, 3)])
+def test_convergence_order_constant_gamma(torch, problem, table, N):
+    """The 'with limiter' orders with the linear weights 10^(l-1)
+    (gamma_mode = 1) instead of (1/h)^(l-1): the design order is kept (the
+    weights that Section 3.2, Step 2 replaces for the sake of the order
+    estimate)."""
+    p2_top = 1 if N == 2 else 0
+    errs = [_run(torch, problem, N, n, True, p2_top, gamma_mode=1) for n in (20, 40, 80)]
+    order = math.log(errs[1] / errs[2]) / math.log(2.0)
+    printed = ORDERS[(table, N)][1]
+    print(f"{problem} P{N} limiter, constant gamma: errors {errs}, order {order:.3f} (paper {printed})", flush=True)
     assert order >= min(printed, N + 1) - 0.25
     assert errs[0] > errs[1] > errs[2]
