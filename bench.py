@@ -47,6 +47,14 @@ top; initial data the planar shock (cell means in the cells it cuts).
 --develop steps (default 1000) first, then K steps timed as one graph
 launch and as plain launches.
 
+The example workloads exist at P1, P2 and P3 (p1_/p2_/p3_euler_ffstep,
+_dmr, _shock_entropy); --gamma-mode 1 takes the linear weights 10^(l-1)
+of the reference that Section 3.2, Step 2 cites, with which the P2/P3 runs
+reach the paper's end times, --indicator tvb the TVB minmod indicator
+(Example 4 at P2/P3 needs it: KXRCF flags nothing ahead of a shock moving
+into gas at rest).  Example 4 at P2/P3 starts with cell means in the cells
+the initial shock cuts.
+
 --workload p1_euler_shock_entropy: Example 4 (Section 4) at the paper's
 h = 1/200: 80,000 jittered triangles on [0,1]^2 (seed 1006), periodic in y,
 outflow sides at x = 0 and 1, P1, FP64, the positivity scaling on; the
@@ -209,18 +217,35 @@ def run_batch(args):
 FFSTEP = {"s": 110, "seed": 1005}
 
 
-def ffstep_solver(degree=2):
-    """Example 6's solver; P2 takes the quadratic top member of its
-    reconstruction hierarchy (p2_top = 1), with which the run is stable."""
+def limiter_options(args, degree, default_p2_top=0):
+    """Solver keywords of the example workloads: --gamma-mode, --indicator,
+    --tvb-m, --p2-top (None: the workload's default)."""
+    from paper_2106_06280_amd import binding
+    p2_top = default_p2_top if args.p2_top is None else args.p2_top
+    return {"gamma_mode": args.gamma_mode, "tvb_m": args.tvb_m, "p2_top": p2_top if degree == 2 else 0,
+            "indicator": binding.INDICATOR_TVB if args.indicator == "tvb" else binding.INDICATOR_KXRCF}
+
+
+def limiter_config(opts):
+    return {"indicator": "tvb" if opts["indicator"] == 1 else "kxrcf", "tvb_m": opts["tvb_m"],
+            "linear_weights": "10^(l-1)" if opts["gamma_mode"] == 1 else "(1/h)^(l-1)",
+            "p2_top": "quadratic" if opts["p2_top"] == 1 else None}
+
+
+def ffstep_solver(args, degree=2):
+    """Example 6's solver.  With the paper's linear weights P2 takes the
+    quadratic top member of its reconstruction hierarchy (p2_top = 1), with
+    which the run is stable; with the constant weights (--gamma-mode 1)
+    the default quartic one."""
     from paper_2106_06280_amd import binding, inputs
     v, t = inputs.forward_step_mesh(FFSTEP["s"], seed=FFSTEP["seed"])
     kinds = inputs.forward_step_kinds(v, t)
     inflow = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
-    S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1,
-                       p2_top=1 if degree == 2 else 0)
+    opts = limiter_options(args, degree, default_p2_top=0 if args.gamma_mode == 1 else 1)
+    S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1, **opts)
     S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
     S.set_boundary(kinds, inflow.state)
-    return S, v, t, kinds, inflow
+    return S, v, t, kinds, inflow, opts
 
 
 def run_to_time(S, u, t_end, check_every=1000):
@@ -267,7 +292,7 @@ def run_ffstep(args, degree=2):
 
     name = f"p{degree}_euler_ffstep"
     t0 = time.perf_counter()
-    S, _, _, _, inflow = ffstep_solver(degree)
+    S, _, _, _, inflow, opts = ffstep_solver(args, degree)
     u = S.project_fn(inflow)
     K, m, Np = S.K, S.m, S.Np
     chunk = 100
@@ -329,9 +354,8 @@ def run_ffstep(args, degree=2):
         "data": "synthetic",
         "config": {"workload": name, "triangles": K, "degree": degree, "dof": dof,
                    "developed_steps": args.develop, "troubled_fraction": round(tot / max(1, calls * K), 5),
-                   "boundaries": "inflow x=0, outflow x=4, reflective walls", "limiter": "kxrcf+csweno",
-                   "p2_top": "quadratic" if degree == 2 else None,
-                   "parallelism": "single-gpu"},
+                   "boundaries": "inflow x=0, outflow x=4, reflective walls", "limiter": "csweno",
+                   **limiter_config(opts), "parallelism": "single-gpu"},
         "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
                   "graph_equals_eager": same},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -354,7 +378,7 @@ def run_ffstep(args, degree=2):
     print(json.dumps(out), flush=True)
 
 
-def run_dmr(args):
+def run_dmr(args, degree=1):
     import numpy as np
     import torch
 
@@ -362,15 +386,22 @@ def run_dmr(args):
 
     D = inputs.DoubleMachReflection
     sh = D.shock()
+    name = f"p{degree}_euler_dmr"
     v, t = inputs.dmr_mesh(200, seed=1007)
-    S = binding.Solver(binding.EQ_EULER, 1, limiter_mode=binding.LIMIT_KXRCF, positivity=1)
-    S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
-    S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
-    S.set_boundary(inputs.dmr_kinds(v, t), sh["post"])
-    u = S.project_fn(D())
-    side = v[t] @ np.array(sh["n"]) - sh["d0"]
-    cut = torch.from_numpy(~(np.all(side < 0, axis=1) | np.all(side > 0, axis=1))).cuda()
-    u[:, 1:, cut] = 0.0
+    opts = limiter_options(args, degree)
+
+    def fresh():
+        S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1, **opts)
+        S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
+        S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
+        S.set_boundary(inputs.dmr_kinds(v, t), sh["post"])
+        u = S.project_fn(D())
+        side = v[t] @ np.array(sh["n"]) - sh["d0"]
+        cut = torch.from_numpy(~(np.all(side < 0, axis=1) | np.all(side > 0, axis=1))).cuda()
+        u[:, 1:, cut] = 0.0
+        return S, u
+
+    S, u = fresh()
     K, m, Np = S.K, S.m, S.Np
     t0 = time.perf_counter()
     chunk = 100
@@ -380,7 +411,7 @@ def run_dmr(args):
     torch.cuda.synchronize()
     st_dev = S.status()
     t_dev = float(S.time()[0])
-    print(f"[bench] p1_euler_dmr: K={K}, developed {args.develop} steps to t = {t_dev:.4f} in "
+    print(f"[bench] {name}: K={K}, developed {args.develop} steps to t = {t_dev:.4f} in "
           f"{time.perf_counter() - t0:.1f}s, status {st_dev}", file=sys.stderr, flush=True)
     g = binding.Graph([S], [u], nsteps=args.steps)
     g.launch()
@@ -409,7 +440,7 @@ def run_dmr(args):
     secs_eager = ev0.elapsed_time(ev1) / 1000.0
     dof = K * m * Np
     out = {
-        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P1 Euler, double Mach reflection)",
+        "metric": f"DOF-updates/s per SSP-RK stage incl. CSWENO (P{degree} Euler, double Mach reflection)",
         "value": dof * 3 * args.steps / secs,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
@@ -421,30 +452,46 @@ def run_dmr(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "p1_euler_dmr", "triangles": K, "degree": 1, "dof": dof,
+        "config": {"workload": name, "triangles": K, "degree": degree, "dof": dof,
                    "developed_steps": args.develop, "time_at_timing": round(time_start, 5),
                    "troubled_fraction": round(tot / max(1, calls * K), 5),
                    "boundaries": "post-shock inflow, wall, outflow, moving Mach 10 shock on top",
-                   "limiter": "kxrcf+csweno", "positivity": True, "parallelism": "single-gpu"},
+                   "limiter": "csweno", **limiter_config(opts), "positivity": True, "parallelism": "single-gpu"},
         "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
                   "graph_equals_eager": bool(torch.equal(u, after))},
         "status_bits": status,
         "status_bits_develop": st_dev,
     }
+    if args.t_end is not None and args.t_end > 0:
+        S2, u2 = fresh()
+        S2.status()
+        run = run_to_time(S2, u2, args.t_end)
+        run["status_bits"] = S2.status()
+        run["finite"] = bool(torch.isfinite(u2).all())
+        means = u2[:, 0, :] / math.sqrt(2.0)
+        run["rho_range"] = [round(float(means[0].min()), 4), round(float(means[0].max()), 4)]
+        out["t_end_run"] = run
     print(json.dumps(out), flush=True)
 
 
-def run_shock_entropy(args):
+def run_shock_entropy(args, degree=1):
     import numpy as np
     import torch
 
     from paper_2106_06280_amd import binding, inputs
 
     n, t_end = 200, 0.178
+    name = f"p{degree}_euler_shock_entropy"
     v, t = inputs.jittered_mesh(n, seed=1006)
-    S = binding.Solver(binding.EQ_EULER, 1, limiter_mode=binding.LIMIT_KXRCF, positivity=1)
+    opts = limiter_options(args, degree)
+    S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1, **opts)
     S.mesh_upload(v, t, binding.BC_PERIODIC, (0.0, 1.0))
     u = S.project_fn(inputs.ShockEntropyWave())
+    if degree >= 2:
+        # cell means in the cells the initial shock cuts (the projection has
+        # points of negative pressure there)
+        cx = torch.from_numpy(v[t].mean(axis=1)[:, 0]).cuda()
+        u[:, 1:, (cx - 0.125).abs() < 1.0 / n] = 0.0
     K, m, Np = S.K, S.m, S.Np
     torch.cuda.synchronize()
     S.status()
@@ -469,7 +516,7 @@ def run_shock_entropy(args):
     torch.cuda.synchronize()
     secs = ev0.elapsed_time(ev1) / 1000.0
     out = {
-        "metric": "DOF-updates/s per SSP-RK stage incl. CSWENO (P1 Euler, shock / entropy waves)",
+        "metric": f"DOF-updates/s per SSP-RK stage incl. CSWENO (P{degree} Euler, shock / entropy waves)",
         "value": K * m * Np * 3 * args.steps / secs,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
@@ -481,8 +528,8 @@ def run_shock_entropy(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "p1_euler_shock_entropy", "triangles": K, "degree": 1, "dof": K * m * Np,
-                   "boundaries": "periodic in y, outflow at x = 0 and 1", "limiter": "kxrcf+csweno",
+        "config": {"workload": name, "triangles": K, "degree": degree, "dof": K * m * Np,
+                   "boundaries": "periodic in y, outflow at x = 0 and 1", "limiter": "csweno", **limiter_config(opts),
                    "positivity": True, "parallelism": "single-gpu"},
         "t_end_run": run,
         "status_bits": S.status(),
@@ -598,14 +645,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS) + ["c4_batch", "p2_euler_ffstep", "p1_euler_ffstep",
-                                                                  "p1_euler_shock_entropy", "p1_euler_dmr"])
+    examples = [f"p{d}_euler_{x}" for x in ("ffstep", "dmr", "shock_entropy") for d in (1, 2, 3)]
+    ap.add_argument("--workload", default="p2_euler_1m", choices=sorted(WORKLOADS) + ["c4_batch"] + examples)
     ap.add_argument("--develop", type=int, default=None,
-                    help="p*_euler_ffstep / p1_euler_dmr: untimed steps that develop the flow first "
+                    help="p*_euler_ffstep / p*_euler_dmr: untimed steps that develop the flow first "
                          "(default 4000 / 1000)")
     ap.add_argument("--t-end", type=float, default=None,
-                    help="p2/p1_euler_ffstep: also run from the initial flow to this time "
-                         "(default: the paper's 4; 0 skips it)")
+                    help="p*_euler_ffstep: also run from the initial flow to this time (default: the "
+                         "paper's 4; 0 skips it); p*_euler_dmr: the same when given (the paper's is 0.2)")
+    ap.add_argument("--gamma-mode", type=int, default=0, choices=(0, 1),
+                    help="example workloads: linear weights (1/h)^(l-1) (0, the paper's) or 10^(l-1) (1)")
+    ap.add_argument("--indicator", default="kxrcf", choices=("kxrcf", "tvb"),
+                    help="example workloads: troubled-cell indicator")
+    ap.add_argument("--tvb-m", type=float, default=0.0, help="TVB constant M of --indicator tvb")
+    ap.add_argument("--p2-top", type=int, default=None, choices=(0, 1),
+                    help="example workloads at P2: 1 the quadratic top member (default: 1 for the forward "
+                         "step with the paper's weights, else 0)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -640,18 +695,18 @@ def main():
     if args.workload == "c4_batch":
         run_batch(args)
         return
-    if args.workload in ("p2_euler_ffstep", "p1_euler_ffstep"):
+    if args.workload.endswith("_euler_ffstep"):
         if args.develop is None:
             args.develop = 4000
         run_ffstep(args, degree=int(args.workload[1]))
         return
-    if args.workload == "p1_euler_shock_entropy":
-        run_shock_entropy(args)
+    if args.workload.endswith("_euler_shock_entropy"):
+        run_shock_entropy(args, degree=int(args.workload[1]))
         return
-    if args.workload == "p1_euler_dmr":
+    if args.workload.endswith("_euler_dmr"):
         if args.develop is None:
             args.develop = 1000
-        run_dmr(args)
+        run_dmr(args, degree=int(args.workload[1]))
         return
     eq, N, bc, v, t, ic, period = make_problem(args.workload)
     precision = WORKLOADS[args.workload][5]
