@@ -298,8 +298,9 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
         double ub0[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) ub0[c] = u[(size_t)(c * NP) * K + e] * kPsi0;
-        // row k of L_d, column k of R_d, and their derivatives in ub0
-        double Lr[M], Rc[M], dLr[M][M], dRc[M][M];
+        // row k of L_d and column k of R_d (their derivatives in ub0 are
+        // formed at the end, where they are used)
+        double Lr[M], Rc[M];
         if constexpr (EQ == 1) {
             const double nx = d == 0 ? 1.0 : 0.0, ny = d == 0 ? 0.0 : 1.0;
             double Lm[4][4], Rm[4][4];
@@ -315,29 +316,9 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                 Lr[c] = a;
                 Rc[c] = bb;
             }
-#pragma unroll 1
-            for (int cc = 0; cc < 4; ++cc) {
-                Dual U4[4], Ld[4][4], Rd[4][4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) U4[c] = Dual(ub0[c], c == cc ? 1.0 : 0.0);
-                euler_eigen<Dual>(U4, nx, ny, gamma, Ld, Rd);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double a = Ld[0][c].d, bb = Rd[c][0].d;
-#pragma unroll
-                    for (int kk = 1; kk < 4; ++kk) {
-                        a = (k == kk) ? Ld[kk][c].d : a;
-                        bb = (k == kk) ? Rd[c][kk].d : bb;
-                    }
-                    dLr[c][cc] = a;
-                    dRc[c][cc] = bb;
-                }
-            }
         } else {
             Lr[0] = 1.0;
             Rc[0] = 1.0;
-            dLr[0][0] = 0.0;
-            dRc[0][0] = 0.0;
         }
         double w0 = 0.0;
 #pragma unroll
@@ -673,14 +654,20 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             ub0b[c] = Lr[c] * w0b;
         }
         double* rec = contrib + (size_t)t * (4 * M * NP);
-#pragma unroll
+#pragma unroll 1
         for (int f = 0; f < 3; ++f) {
+            // this face's row of wb and its source, by selects (a register
+            // array indexed by the loop counter would live in scratch)
+            double wbf[NPC];
+#pragma unroll
+            for (int p = 0; p < NPC; ++p) wbf[p] = (f == 0) ? wb[0][p] : ((f == 1) ? wb[1][p] : wb[2][p]);
+            const int srcf = (f == 0) ? srcs[0] : ((f == 1) ? srcs[1] : srcs[2]);
             double wsb[NP];
 #pragma unroll
             for (int n = 0; n < NP; ++n) {
                 double s = 0.0;
 #pragma unroll
-                for (int p = 0; p < NPC; ++p) s += op[LO::AVG + (f * NPC + p) * NP + n] * wb[f][p];
+                for (int p = 0; p < NPC; ++p) s += op[LO::AVG + (f * NPC + p) * NP + n] * wbf[p];
                 wsb[n] = s;
             }
             double Usb[M][NP];
@@ -690,7 +677,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
 #pragma unroll
                 for (int n = 0; n < NP; ++n) {
                     Usb[c][n] = Lr[c] * wsb[n];
-                    s += u[(size_t)(c * NP + n) * K + srcs[f]] * wsb[n];
+                    s += u[(size_t)(c * NP + n) * K + srcf] * wsb[n];
                 }
                 Lrb[c] += s;
             }
@@ -711,13 +698,28 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                 }
             }
         }
-        // characteristic matrices depend on the cell mean
+        // characteristic matrices depend on the cell mean: one forward-mode
+        // pass per component of ub0 gives d(row k of L_d)/d ub0[cc] and
+        // d(column k of R_d)/d ub0[cc]
         if constexpr (EQ == 1) {
+            const double nx = d == 0 ? 1.0 : 0.0, ny = d == 0 ? 0.0 : 1.0;
+#pragma unroll 1
+            for (int cc = 0; cc < 4; ++cc) {
+                Dual U4[4], Ld[4][4], Rd[4][4];
 #pragma unroll
-            for (int cc = 0; cc < M; ++cc) {
+                for (int c = 0; c < 4; ++c) U4[c] = Dual(ub0[c], c == cc ? 1.0 : 0.0);
+                euler_eigen<Dual>(U4, nx, ny, gamma, Ld, Rd);
                 double s = 0.0;
 #pragma unroll
-                for (int c = 0; c < M; ++c) s += Lrb[c] * dLr[c][cc] + Rcb[c] * dRc[c][cc];
+                for (int c = 0; c < 4; ++c) {
+                    double a = Ld[0][c].d, bb = Rd[c][0].d;
+#pragma unroll
+                    for (int kk = 1; kk < 4; ++kk) {
+                        a = (k == kk) ? Ld[kk][c].d : a;
+                        bb = (k == kk) ? Rd[c][kk].d : bb;
+                    }
+                    s += Lrb[c] * a + Rcb[c] * bb;
+                }
                 ub0b[cc] += s;
             }
         }
