@@ -83,8 +83,10 @@ extern "C" {
 typedef struct cswdg_solver cswdg_solver;
 typedef struct cswdg_graph cswdg_graph;
 
-/* Parameters.  Zero-initialise and set what you need; a zero/negative value
- * selects the default shown. */
+/* Parameters.  Zero-initialise and set what you need: for gas_gamma, cfl,
+ * c_k and eps_weno a zero/negative value selects the default shown; the
+ * integer switches and tvb_m take only the values listed (CSWDG_EINVAL
+ * otherwise), zero being the default. */
 typedef struct cswdg_params {
     int equation;     /* CSWDG_EQ_BURGERS (eq. 2dBurgers) or CSWDG_EQ_EULER (eq. 2dEulerEquations) */
     int degree;       /* N = 1, 2 or 3 (Section 2, eq. modalForm2D) */
