@@ -228,16 +228,17 @@ def _solve_ls(A, b):
     return np.linalg.solve(R, np.einsum("trc,trf->tcf", Q, b))
 
 
-def _beta_matrix(V0, x0, y0, h0, area0, d):
-    """B [T, n, n] with c^T B c = sum_{1<=|alpha|<=d} |D0|^{|alpha|-1}
-    int_D0 (D^alpha q)^2 dA for q = sum_j c_j phi_j (physical derivatives)."""
+def _beta_matrix(V0, x0, y0, h0, area0, d, orders=None):
+    """B [T, n, n] with c^T B c = sum_{1<=|alpha|<=orders} |D0|^{|alpha|-1}
+    int_D0 (D^alpha q)^2 dA for q = sum_j c_j phi_j of degree d (physical
+    derivatives; orders = d unless given)."""
     mono = monomials(d)
     x, y, w = quadrature.physical_rule_on_triangle(V0, max(1, (2 * d + 2) // 2))
     xi = (x - x0[:, None]) / h0[:, None]
     eta = (y - y0[:, None]) / h0[:, None]
     T = V0.shape[0]
     B = np.zeros((T, len(mono), len(mono)))
-    for s in range(1, d + 1):
+    for s in range(1, (d if orders is None else min(d, orders)) + 1):
         for a1 in range(s + 1):
             a2 = s - a1
             # D^alpha phi_j = a!/(a-a1)! b!/(b-a2)! h0^{-s} xi^{a-a1} eta^{b-a2}
@@ -258,7 +259,7 @@ def _beta_matrix(V0, x0, y0, h0, area0, d):
 
 
 def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True, quadratic_top=False,
-                constant_gamma=False):
+                constant_gamma=False, beta_literal=False):
     """New coefficients for the troubled cells elems: [T, m, Np].  Mode 0
     is copied from u.  linear_only: the weights are the linear weights
     (omega = gamma); characteristic=False (Euler): the conserved variables
@@ -266,7 +267,11 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     quadratic_top (N = 2 only): the hierarchy of N = 1, {p_1, p_2, p_3}
     with the quadratic q_3 on top (a third-order reconstruction, the design
     order of P2), instead of the quartic q_5 of the N >= 2 reading.
-    constant_gamma: linear weights from 10^{l-1} instead of (1/h)^{l-1}."""
+    constant_gamma: linear weights from 10^{l-1} instead of (1/h)^{l-1}.
+    beta_literal: the smoothness indicators of eq. smoothnessIndicator
+    read literally, of the equivalent polynomials p_l over derivative orders
+    1..N, instead of q_l over orders 1..deg q_l (a study of the reading; the
+    library has no such switch)."""
     M = dg.mesh
     E = np.asarray(elems, dtype=np.int64)
     T = len(E)
@@ -376,8 +381,12 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     for l in range(1, L):
         d = degs[l]
         nd = len(monomials(d))
-        c = qs[l][:, :nd, :]
-        Bl = _beta_matrix(V0, x0, y0, h0, area0, d)
+        if beta_literal:
+            c = ps[l][:, :nd, :]
+            Bl = _beta_matrix(V0, x0, y0, h0, area0, d, orders=N)
+        else:
+            c = qs[l][:, :nd, :]
+            Bl = _beta_matrix(V0, x0, y0, h0, area0, d)
         betas.append(np.einsum("tif,tij,tjf->tf", c, Bl, c))
     # beta_1 from linear functions on each neighbour's centroid subcells
     cen = {nm: pcs[nm].mean(axis=2) for nm in names_t3}  # [T,3,2]
@@ -431,14 +440,15 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     return out
 
 
-def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False, constant_gamma=False):
+def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False, constant_gamma=False,
+          beta_literal=False):
     """Apply the limiter to the cells where mask is true (simultaneous
     update: every reconstruction reads the pre-limit u)."""
     E = np.nonzero(np.asarray(mask))[0]
     out = u.copy()
     if len(E):
         out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic,
-                             quadratic_top=quadratic_top, constant_gamma=constant_gamma)
+                             quadratic_top=quadratic_top, constant_gamma=constant_gamma, beta_literal=beta_literal)
     return out
 
 

@@ -342,3 +342,28 @@ def test_constant_gamma_is_scale_free(N):
     a = csweno.limit(d1, U1, mask)
     b = csweno.limit(d2, U2, mask)
     assert np.abs(a - b).max() > 1e-4
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_literal_smoothness_indicators(N):
+    """Study of eq. smoothnessIndicator read literally (beta of the
+    equivalent polynomials p_l over derivative orders 1..N): linear data are
+    no longer reproduced (tau > 0 although every member is exact), which is
+    why the default takes beta of q_l; a single application on smooth data
+    still converges at the design order."""
+    M = _mesh(6)
+    d = DG(M, N, 0)
+    E = _interior(M)
+    U = d.project(lambda x, y: 0.4 + 0.7 * x - 0.5 * y)
+    out, info = csweno.reconstruct(d, U, E, beta_literal=True, return_info=True)
+    assert np.all(info["tau"] > 0)
+    assert np.abs(out - U[E]).max() > 1e-9
+    assert np.abs(csweno.reconstruct(d, U, E) - U[E]).max() < 1e-11
+    ic = inputs.BurgersSine()
+    errs = []
+    for n in ((16, 32) if N == 1 else (32, 64)):
+        v, t = inputs.jittered_mesh(n, -2, 2, -2, 2, seed=7)
+        dd = DG(Mesh(v, t, BC_PERIODIC, (4.0, 4.0)), N, 0)
+        Ui = dd.project(ic)
+        errs.append(dd.errors(csweno.limit(dd, Ui, np.ones(dd.mesh.K, bool), beta_literal=True), ic)[0])
+    assert math.log2(errs[0] / errs[1]) > N + 1 - 0.3, errs
