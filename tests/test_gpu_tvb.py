@@ -258,3 +258,26 @@ def test_tvb_validation(torch):
     u = S.project_fn(inputs.IsentropicVortex(beta=2.0, x0=0.5, y0=0.5, period_x=1.0, period_y=1.0))
     with pytest.raises(binding.CswdgError):
         S.dg_residual_vjp(u, u.clone())
+
+
+def test_tvb_and_constant_gamma_in_a_graph(torch):
+    """Steps with the TVB indicator and the constant linear weights captured
+    in a HIP graph: every replay equals the same steps launched eagerly, bit
+    for bit (eager work and synchronisations between the replays)."""
+    from paper_2106_06280_amd import binding
+    v, t = inputs.jittered_mesh(14, seed=491)
+    S = binding.Solver(1, 2, indicator=binding.INDICATOR_TVB, gamma_mode=1, positivity=1)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    u0 = S.project_fn(inputs.FourQuadrant(seed=31, xc=0.45, yc=0.55, rho_range=(0.6, 1.4),
+                                          p_range=(0.6, 1.4), vel_range=(-0.5, 0.5)))
+    ug = u0.clone()
+    ue = u0.clone()
+    g = binding.Graph([S], [ug], nsteps=2)
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        for _ in range(2):
+            S.ssprk3_step(ue)
+        torch.cuda.synchronize()
+        assert torch.equal(ug, ue), rep
+    assert S.status() & 0x3 == 0
