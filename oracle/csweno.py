@@ -168,9 +168,11 @@ def tri_area(P):
 # Averages
 # ---------------------------------------------------------------------------
 
-def neighbour_average(dg: DG, u, E, nid, shift, face, P):
+def neighbour_average(dg: DG, u, E, nid, shift, face, P, extrapolate=None):
     """Average of the neighbour-across-face polynomial over triangles
-    P [T,3,2] (placed frame), all components: [T, m]."""
+    P [T,3,2] (placed frame), all components: [T, m].  extrapolate [T]
+    (boundary faces only): the ghost carries Delta0's own polynomial
+    continued across the face instead of its mirror image."""
     M = dg.mesh
     x, y, w = quadrature.physical_rule_on_triangle(P, max(1, (dg.N + 2) // 2))
     real = nid[:, face] >= 0
@@ -184,11 +186,25 @@ def neighbour_average(dg: DG, u, E, nid, shift, face, P):
     Qf = V0[:, (face + 1) % 3]
     X = np.stack([x, y], axis=-1)
     Xm = _reflect(Pf[:, None, :], Qf[:, None, :], X)
+    if extrapolate is not None:
+        Xm = np.where(np.asarray(extrapolate)[:, None, None], X, Xm)
     xe = np.where(real[:, None], xr, Xm[..., 0])
     ye = np.where(real[:, None], yr, Xm[..., 1])
     r, s = M.reference_coords(nb, xe, ye)
     Vh = basis.vandermonde(dg.N, r, s)  # [T, q, Np]
     vals = np.einsum("tqn,tcn->tqc", Vh, u[nb])
+    if extrapolate is not None and np.any(extrapolate):
+        # outside the reference triangle the collapsed coordinates of the
+        # basis are singular on the line s = 1: write Delta0's polynomial in
+        # the monomials r^a s^b (interpolating it at the volume points) and
+        # evaluate those
+        ex = np.asarray(extrapolate)
+        mono = [(a, b) for d in range(dg.N + 1) for b in range(d + 1) for a in [d - b]]
+        Vm = np.stack([dg.vr ** a * dg.vs ** b for a, b in mono], axis=-1)  # [q, Np]
+        coef = np.linalg.lstsq(Vm, dg.V, rcond=None)[0]  # psi_n = sum_k coef[k, n] r^a_k s^b_k
+        Mo = np.stack([r ** a * s ** b for a, b in mono], axis=-1)  # [T, q, Np]
+        vm = np.einsum("tqk,kn,tcn->tqc", Mo, coef, u[nb])
+        vals = np.where(ex[:, None, None], vm, vals)
     return np.einsum("tq,tqc->tc", w, vals) / np.sum(w, axis=1)[:, None]
 
 
@@ -259,7 +275,7 @@ def _beta_matrix(V0, x0, y0, h0, area0, d, orders=None):
 
 
 def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True, quadratic_top=False,
-                constant_gamma=False, beta_literal=False):
+                constant_gamma=False, beta_literal=False, ghost_extrapolate=False):
     """New coefficients for the troubled cells elems: [T, m, Np].  Mode 0
     is copied from u.  linear_only: the weights are the linear weights
     (omega = gamma); characteristic=False (Euler): the conserved variables
@@ -271,7 +287,10 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     beta_literal: the smoothness indicators of eq. smoothnessIndicator
     read literally, of the equivalent polynomials p_l over derivative orders
     1..N, instead of q_l over orders 1..deg q_l (a study of the reading; the
-    library has no such switch)."""
+    library has no such switch).
+    ghost_extrapolate: across an outflow face the ghost cell (the mirror
+    image of Delta0's triangle) carries Delta0's polynomial continued across
+    the face instead of its mirror image (walls keep the mirror image)."""
     M = dg.mesh
     E = np.asarray(elems, dtype=np.int64)
     T = len(E)
@@ -295,7 +314,11 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     # cell averages of u (all components) on the pieces: avg[name] [T, 3, m]
     avg = {}
     for name in pcs:
-        avg[name] = np.stack([neighbour_average(dg, u, E, nid, shift, f, pcs[name][:, f]) for f in range(3)], axis=1)
+        avg[name] = np.stack([neighbour_average(dg, u, E, nid, shift, f, pcs[name][:, f],
+                                                extrapolate=(ghost_extrapolate
+                                                             & ((M.info[E, f] & INFO_BOUNDARY) != 0)
+                                                             & ((M.info[E, f] & 3) == 0)))
+                              for f in range(3)], axis=1)
     # ghost cells of boundary faces carry the boundary's ghost state: the
     # mirrored polynomial (outflow), the same with its normal momentum
     # reversed (reflective wall), the inflow state on every piece (inflow),
@@ -441,14 +464,15 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
 
 
 def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False, constant_gamma=False,
-          beta_literal=False):
+          beta_literal=False, ghost_extrapolate=False):
     """Apply the limiter to the cells where mask is true (simultaneous
     update: every reconstruction reads the pre-limit u)."""
     E = np.nonzero(np.asarray(mask))[0]
     out = u.copy()
     if len(E):
         out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic,
-                             quadratic_top=quadratic_top, constant_gamma=constant_gamma, beta_literal=beta_literal)
+                             quadratic_top=quadratic_top, constant_gamma=constant_gamma, beta_literal=beta_literal,
+                             ghost_extrapolate=ghost_extrapolate)
     return out
 
 

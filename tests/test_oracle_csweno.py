@@ -367,3 +367,30 @@ def test_literal_smoothness_indicators(N):
         Ui = dd.project(ic)
         errs.append(dd.errors(csweno.limit(dd, Ui, np.ones(dd.mesh.K, bool), beta_literal=True), ic)[0])
     assert math.log2(errs[0] / errs[1]) > N + 1 - 0.3, errs
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_extrapolated_ghosts_reproduce_linear_data_at_the_boundary(N, eq):
+    """ghost_extrapolate: across outflow faces the ghost carries Delta0's own
+    polynomial continued, so every cell, boundary cells included, sees one
+    linear function on its whole stencil and reproduces it (the nonlinear
+    weights) - and degree-N data with the linear weights; the mirror image
+    does not (the normal gradient changes sign across the face)."""
+    M = _mesh(6)
+    d = DG(M, N, eq)
+    bcell = np.nonzero(((M.info & INFO_BOUNDARY) != 0).any(axis=1))[0]
+    if eq == 0:
+        U = d.project(lambda x, y: 0.4 + 0.7 * x - 0.5 * y)
+    else:
+        U = d.project(lambda x, y: np.stack([1.0 + 0.2 * x - 0.1 * y, 0.3 + 0.1 * x, -0.2 + 0.05 * y,
+                                             2.5 + 0.1 * x + 0.2 * y], -1))
+    out = csweno.reconstruct(d, U, bcell, ghost_extrapolate=True)
+    assert np.abs(out - U[bcell]).max() < 1e-11
+    assert np.abs(csweno.reconstruct(d, U, bcell) - U[bcell]).max() > 1e-6
+    if eq == 0:
+        terms = [lambda x, y: 0.7 * x - 0.5 * y, lambda x, y: 2.0 * x * x - 0.8 * x * y + 0.3 * y * y,
+                 lambda x, y: 1.5 * x ** 3 - 0.7 * x * y * y + 0.4 * y ** 3]
+        Uq = d.project(lambda x, y: 0.4 + sum(f(x, y) for f in terms[:N]))
+        out = csweno.reconstruct(d, Uq, bcell, linear_only=True, ghost_extrapolate=True)
+        assert np.abs(out - Uq[bcell]).max() < 1e-9
