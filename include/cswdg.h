@@ -130,6 +130,14 @@ typedef struct cswdg_params {
      * there, which the paper replaces (the same for every h, so the
      * reconstruction does not depend on the length scale of the mesh) */
     int gamma_mode;
+    /* the limiter's ghost cell across an outflow face (the paper is silent
+     * on boundaries): 0 the mirror image of Delta0 carrying its reflected
+     * polynomial; 1 the same triangle carrying Delta0's polynomial continued
+     * across the face (linear data then reproduced in boundary cells too).
+     * Wall faces keep the mirror image, inflow and moving-shock faces their
+     * states.  With 1, cswdg_set_boundary rebuilds the stencil operators
+     * (synchronous, host work proportional to K). */
+    int ghost_mode;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream
@@ -315,7 +323,7 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
  * the first argument on ties and d|x|/dx = 0 at x = 0.  Deterministic (no
  * floating-point atomics).  All buffers device, state layout.  These calls
  * take FP64 single-instance solvers with the default readings (char_mode,
- * weights_mode, lf_mode, p2_top, gamma_mode and positivity 0, the KXRCF indicator) and
+ * weights_mode, lf_mode, p2_top, gamma_mode, ghost_mode and positivity 0, the KXRCF indicator) and
  * no wall, inflow or moving-shock faces; CSWDG_EINVAL otherwise. */
 
 /* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).

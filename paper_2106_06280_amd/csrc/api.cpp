@@ -165,6 +165,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.p2_top != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the quartic P2 hierarchy (p2_top = 0)");
     if (s->p.indicator != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the KXRCF indicator (indicator = 0)");
     if (s->p.gamma_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the linear weights (1/h)^(l-1) (gamma_mode = 0)");
+    if (s->p.ghost_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the mirror ghost (ghost_mode = 0)");
     return CSWDG_OK;
 }
 
@@ -297,6 +298,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m))
         return fail(nullptr, CSWDG_EINVAL, "tvb_m must be finite and >= 0");
     if (p.gamma_mode < 0 || p.gamma_mode > 1) return fail(nullptr, CSWDG_EINVAL, "gamma_mode must be 0 or 1");
+    if (p.ghost_mode < 0 || p.ghost_mode > 1) return fail(nullptr, CSWDG_EINVAL, "ghost_mode must be 0 or 1");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
@@ -461,6 +463,15 @@ int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* infl
         e = hipMemcpy(s->d_info, info4.data(), sizeof(uint32_t) * K, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hipfail(s, e, "set_boundary");
         s->n_special = special;
+        if (s->p.ghost_mode == 1) {
+            // the outflow faces' ghosts differ from the walls': rebuild the
+            // stencil operators for the new kinds
+            std::vector<double> ops;
+            rc = build_limiter_ops(s->mesh, s->p.degree, s->p.gamma_mode == 1, true, ops, s->n_rank, s->n_foot);
+            if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
+            e = hipMemcpy(s->d_ops, ops.data(), sizeof(double) * ops.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hipfail(s, e, "set_boundary");
+        }
     }
     if (inflow) {
         e = hipMemcpy(s->d_inflow, inflow, sizeof(double) * s->M, hipMemcpyHostToDevice);
@@ -1033,7 +1044,8 @@ int upload_mesh(cswdg_solver* s) {
     int rc;
     const int64_t K = s->mesh.K;
     std::vector<double> ops;
-    rc = build_limiter_ops(s->mesh, s->p.degree, s->p.gamma_mode == 1, ops, s->n_rank, s->n_foot);
+    rc = build_limiter_ops(s->mesh, s->p.degree, s->p.gamma_mode == 1, s->p.ghost_mode == 1, ops, s->n_rank,
+                           s->n_foot);
     if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
     std::vector<double> tvbA;
     s->n_tvb_neg = 0;

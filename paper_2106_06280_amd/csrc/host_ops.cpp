@@ -133,12 +133,13 @@ struct OpBuilder {
     using L = OpLayout<N>;
     const HostMesh& m;
     bool constant_gamma;
+    bool ghost_extrapolate;  // outflow faces: Delta0's polynomial continued, not mirrored
     std::vector<double> C;  // basis monomial form [NP][NP]
     Rule2D rN, rTop, rBeta, rProj;
     std::vector<double> psiProj;  // [q][NP] on rProj
     MonoList mono{D::DTOP};
 
-    OpBuilder(const HostMesh& mm, bool cg) : m(mm), constant_gamma(cg) {
+    OpBuilder(const HostMesh& mm, bool cg, bool ge) : m(mm), constant_gamma(cg), ghost_extrapolate(ge) {
         basis_monomial_form(N, C);
         rN = triangle_rule((N + 2) / 2);
         rTop = triangle_rule((D::DTOP + 2) / 2);
@@ -236,6 +237,12 @@ struct OpBuilder {
                 W[2] = R;
                 fp = 0;
                 src = e;
+                if (ghost_extrapolate && (inf & 3) == 0) {
+                    // outflow: the ghost triangle carries Delta0's own
+                    // polynomial at its points (no reflection)
+                    fr.mirror = false;
+                    fr.shift = {0.0, 0.0};
+                }
             } else {
                 int cx = (inf >> 2) & 3, cy = (inf >> 4) & 3;
                 double sx = cx == 1 ? m.px : (cx == 2 ? -m.px : 0.0);
@@ -387,10 +394,10 @@ struct OpBuilder {
 };
 
 template <int N>
-int build_ops_n(const HostMesh& m, bool constant_gamma, std::vector<double>& ops, int64_t& n_rank,
-                int64_t& n_foot) {
+int build_ops_n(const HostMesh& m, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
+                int64_t& n_rank, int64_t& n_foot) {
     using L = OpLayout<N>;
-    OpBuilder<N> b(m, constant_gamma);
+    OpBuilder<N> b(m, constant_gamma, ghost_extrapolate);
     ops.assign((size_t)m.K * L::LEN, 0.0);
     unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
     std::vector<int64_t> rank(nt, 0), foot(nt, 0);
@@ -474,11 +481,11 @@ void build_tvb_ops(const HostMesh& m, std::vector<double>& A, int64_t& n_neg) {
     }
 }
 
-int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, std::vector<double>& ops, int64_t& n_rank,
-                      int64_t& n_foot) {
-    if (N == 1) return build_ops_n<1>(m, constant_gamma, ops, n_rank, n_foot);
-    if (N == 2) return build_ops_n<2>(m, constant_gamma, ops, n_rank, n_foot);
-    if (N == 3) return build_ops_n<3>(m, constant_gamma, ops, n_rank, n_foot);
+int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
+                      int64_t& n_rank, int64_t& n_foot) {
+    if (N == 1) return build_ops_n<1>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+    if (N == 2) return build_ops_n<2>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+    if (N == 3) return build_ops_n<3>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
     return CSWDG_EINVAL;
 }
 

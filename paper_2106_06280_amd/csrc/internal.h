@@ -62,8 +62,8 @@ int concat_meshes(const std::vector<HostMesh>& parts, HostMesh& out, std::vector
 
 // per-element limiter operators (host_ops.cpp); returns number of
 // rank-deficient elements and perpendicular feet that fell outside
-int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, std::vector<double>& ops, int64_t& n_rank,
-                      int64_t& n_foot);
+int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
+                      int64_t& n_rank, int64_t& n_foot);
 // the TVB indicator's midpoint decomposition [9][K] (host_ops.cpp); n_neg
 // counts midpoints with no pair of nonnegative coefficients
 void build_tvb_ops(const HostMesh& m, std::vector<double>& A, int64_t& n_neg);

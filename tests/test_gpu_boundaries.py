@@ -413,3 +413,48 @@ def test_moving_shock_validation(torch):
     with pytest.raises(binding.CswdgError):
         S.dg_residual_vjp(u, u.clone())
     assert S.time()[0] == 0.0
+
+
+@pytest.mark.parametrize("eq,N", [(0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3)])
+def test_extrapolated_ghost_limiter(torch, eq, N):
+    """ghost_mode = 1: across outflow faces the limiter's ghost carries
+    Delta0's polynomial continued (the oracle's ghost_extrapolate); every
+    cell troubled, against the oracle, and different from the mirror ghost."""
+    from paper_2106_06280_amd import binding
+    v, t = inputs.jittered_mesh(10, seed=500 + N)
+    M = Mesh(v, t, BC_TRANSMISSIVE)
+    dg = DG(M, N, eq)
+    S = binding.Solver(eq, N, ghost_mode=1)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    if eq == 0:
+        u = dg.project(lambda x, y: 0.3 + 0.5 * np.sin(2 * math.pi * (x + y)) + np.where(x + 0.3 * y > 0.55, 0.8, 0.0))
+    else:
+        u = dg.project(inputs.FourQuadrant(seed=5, xc=0.47, yc=0.53, rho_range=(0.6, 1.4), p_range=(0.6, 1.4),
+                                           vel_range=(-0.5, 0.5)))
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    exp = csweno.limit(dg, u, np.ones(M.K, bool), ghost_extrapolate=True)
+    assert _relerr(S.to_host(out), exp) < TOL
+    assert np.abs(exp - csweno.limit(dg, u, np.ones(M.K, bool))).max() > 1e-6
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_extrapolated_ghost_with_walls_and_steps(torch, N):
+    """The operators rebuilt by cswdg_set_boundary: walls keep the mirror
+    image, outflow faces extrapolate, the inflow face its state; the limiter
+    with every cell troubled and three KXRCF-limited steps against the
+    oracle."""
+    inflow = [1.2, 0.4, 0.1, 2.8]
+    M, dg, S = _case(1, N, 10, 511, (BKIND_INFLOW, BKIND_OUTFLOW, BKIND_WALL, BKIND_OUTFLOW), inflow, ghost_mode=1)
+    u = dg.project(inputs.FourQuadrant(seed=9, xc=0.47, yc=0.53, rho_range=(0.6, 1.4), p_range=(0.6, 1.4),
+                                       vel_range=(-0.5, 0.5)))
+    ud = S.to_device(u)
+    out, _ = S.csweno_limit(ud, mask=torch.ones(M.K, dtype=torch.uint8))
+    assert _relerr(S.to_host(out), csweno.limit(dg, u, np.ones(M.K, bool), ghost_extrapolate=True)) < TOL
+    lim = lambda w: csweno.limit(dg, w, kxrcf.indicator(dg, w)[1], ghost_extrapolate=True)
+    for _ in range(3):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < 1e-10
+    from paper_2106_06280_amd import binding
+    with pytest.raises(binding.CswdgError):
+        binding.Solver(1, N, ghost_mode=2)
