@@ -1508,7 +1508,9 @@ hipError_t launch_time_advance(const LaunchCtx& c, int n_inst, double* time, con
 
 hipError_t launch_kxrcf(const LaunchCtx& c, const DevMesh& m, const void* u, uint8_t* flags, double* R,
                         int32_t* list, uint32_t* count) {
-    const unsigned bs = 256, g = grid_for(m.K, bs);
+    // one-wave blocks: measured 4% faster than 256 threads at the 1M P2
+    // Euler workload (the list append is per block either way)
+    const unsigned bs = 64, g = grid_for(m.K, bs);
     if (c.indicator == 1) {
         if (m.tvb == nullptr) return hipErrorInvalidValue;
         CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
