@@ -86,3 +86,20 @@ def test_host_tvb_decomposition_matches_the_oracle(kind):
     assert neg == 0
     assert np.array_equal(A != 0.0, Ao != 0.0)
     assert np.abs(A - Ao).max() < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_host_tvb_decomposition_on_distorted_meshes(seed):
+    """Interior vertices moved by up to 0.4 h: the library's and the
+    oracle's decompositions still agree, and every midpoint still has a pair
+    of nonnegative coefficients (the fallback for midpoints without one is
+    not reached on these meshes)."""
+    from oracle import tvb
+    from oracle.dg import DG
+    from oracle.mesh import Mesh
+    v, t = inputs.jittered_mesh(12, jitter=0.4, seed=seed)
+    A, neg = binding.host_tvb_decomposition(v, t, BC_TRANSMISSIVE)
+    Ao = tvb.decomposition(DG(Mesh(v, t, BC_TRANSMISSIVE), 1, 0))
+    assert neg == 0 and Ao.min() >= 0.0
+    assert np.array_equal(A != 0.0, Ao != 0.0)
+    assert np.abs(A - Ao).max() < 1e-12
