@@ -1,6 +1,7 @@
 """Convergence orders of the library against the paper's accuracy tables
 (Section 4.1: Table 1, Example 1, 2D Burgers; Table 2, Example 2, Euler
-entropy wave; L1 error of u or of the density), on jittered periodic
+entropy wave; Table 3, Example 3, isentropic vortex at t = 2; L1 error of u
+or of the density), on jittered periodic
 meshes with 20, 40 and 80 squares per side, with and without the limiter
 on every cell (the paper's 'with limiter' columns).  The state is stepped
 on the GPU; the oracle only measures the error against the exact solution.
@@ -38,6 +39,11 @@ def _run(torch, problem, N, n, limit_all, p2_top=0, gamma_mode=0):
     if problem == "burgers":
         v, t = inputs.jittered_mesh(n, -2, 2, -2, 2, seed=7)
         per, ic, eq, t_end = (4.0, 4.0), inputs.BurgersSine(), 0, 0.5 / math.pi
+    elif problem == "vortex":
+        # Example 3: [0,10] x [-5,5], periodic, beta = 5, errors at t = 2
+        v, t = inputs.jittered_mesh(n, 0, 10, -5, 5, seed=7)
+        per, eq, t_end = (10.0, 10.0), 1, 2.0
+        ic = inputs.IsentropicVortex(beta=5.0, x0=5.0, y0=0.0, period_x=10.0, period_y=10.0)
     else:
         v, t = inputs.jittered_mesh(n, 0, 2, 0, 2, seed=7)
         per, ic, eq, t_end = (2.0, 2.0), inputs.EntropyWave(), 1, 0.2
@@ -58,13 +64,17 @@ def _run(torch, problem, N, n, limit_all, p2_top=0, gamma_mode=0):
 
 
 CASES = [("burgers", 1, N, lim) for N in (1, 2, 3) for lim in (False, True)] + \
-        [("entropy", 2, N, False) for N in (1, 2, 3)] + [("entropy", 2, N, True) for N in (1, 2, 3)]
+        [("entropy", 2, N, False) for N in (1, 2, 3)] + [("entropy", 2, N, True) for N in (1, 2, 3)] + \
+        [("vortex", 3, N, lim) for N in (1, 2, 3) for lim in (False, True)]
 
 
 @pytest.mark.parametrize("problem,table,N,limit_all", CASES)
 def test_convergence_order(torch, problem, table, N, limit_all):
-    p2_top = 1 if (problem == "entropy" and N == 2 and limit_all) else 0
-    errs = [_run(torch, problem, N, n, limit_all, p2_top) for n in (20, 40, 80)]
+    p2_top = 1 if (problem in ("entropy", "vortex") and N == 2 and limit_all) else 0
+    # the vortex (core radius about 1 on a domain of 10) needs the paper's
+    # finer pair, 10/80 and 10/160
+    sizes = (40, 80, 160) if problem == "vortex" else (20, 40, 80)
+    errs = [_run(torch, problem, N, n, limit_all, p2_top) for n in sizes]
     order = math.log(errs[1] / errs[2]) / math.log(2.0)
     printed = ORDERS[(table, N)][1 if limit_all else 0]
     print(f"{problem} P{N} limiter={limit_all}: errors {errs}, order {order:.3f} (paper {printed})", flush=True)
