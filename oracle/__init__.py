@@ -10,7 +10,6 @@ The oracle follows the paper step by step in plain numpy float64,
 vectorised over elements (residual, indicator) and over troubled cells
 (limiter).  Every function cites the section / equation it follows.
 
-Parity status per function is stated in each module header; the readings
-taken where the paper is silent or garbled are collected in the design doc of
-the repository.
+Parity status per function is stated in each module header, as are the
+readings taken where the paper is silent or garbled.
 """

@@ -38,7 +38,7 @@ result goes to a new array, so the order of troubled cells is irrelevant):
    the eigenvectors of the x- and of the y-Jacobian at the mean of Delta0;
    the two results are averaged.
 
-Readings where the paper is ambiguous (each listed in the design doc):
+Readings where the paper is ambiguous:
 the members of the N >= 2 hierarchy are {p_1, p_2, p_3, p_top} with p_top
 from the quartic q_5 and weights gamma_{.,5} (the text's 'p_4'/'beta_4'
 denote this fourth member); T2, T3 and beta_1 use the whole centroid

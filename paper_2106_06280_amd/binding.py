@@ -93,8 +93,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                              "(python paper_2106_06280_amd/build.py)")
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "python paper_2106_06280_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
