@@ -10,7 +10,7 @@ order N + 1 where the printed one is higher, within 0.25.
 
 Euler P2 with every cell limited is run with the quadratic top member of
 the N = 2 hierarchy (p2_top = 1): with the quartic top of the default
-reading its error grows under refinement (see the design notes)."""
+reading its error grows under refinement."""
 import math
 
 import numpy as np
