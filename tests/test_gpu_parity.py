@@ -460,3 +460,26 @@ def test_steps_constant_gamma(torch, N, top):
         b.Solver(1, N, gamma_mode=2)
     with pytest.raises(b.CswdgError):
         S.dg_residual_vjp(ud, ud.clone())
+
+
+@pytest.mark.parametrize("eq,N", [(0, 1), (1, 2), (1, 3)])
+def test_limiter_with_no_troubled_cell(torch, eq, N):
+    """An empty troubled set (a mask of zeros; smooth data under KXRCF with
+    a huge C_K): the limiter launches on an empty list and copies the state
+    bit for bit, and a limited step equals the unlimited one."""
+    M, dg, S = _case(eq, N, 9, BC_PERIODIC, seed=151)
+    u = _smooth_state(dg, eq, seed=21)
+    ud = S.to_device(u)
+    out, flags = S.csweno_limit(ud, mask=torch.zeros(M.K, dtype=torch.uint8))
+    assert not flags.cpu().numpy().any()
+    assert torch.equal(out, ud)
+    b = _binding()
+    Sk = b.Solver(eq, N, c_k=1e30)
+    Sk.mesh_upload(*inputs.jittered_mesh(9, 0.0, 1.0, 0.0, 1.0, seed=151), BC_PERIODIC, (1.0, 1.0))
+    Sn = b.Solver(eq, N, limiter_mode=b.LIMIT_NONE)
+    Sn.mesh_upload(*inputs.jittered_mesh(9, 0.0, 1.0, 0.0, 1.0, seed=151), BC_PERIODIC, (1.0, 1.0))
+    uk, un = Sk.to_device(u), Sn.to_device(u)
+    Sk.ssprk3_step(uk)
+    Sn.ssprk3_step(un)
+    assert Sk.troubled_count() == 0
+    assert torch.equal(uk, un)
