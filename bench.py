@@ -759,6 +759,18 @@ def main():
         S.profile(False)
     print(f"[bench] {args.steps} steps in {secs*1e3:.2f} ms; status {status}", file=sys.stderr, flush=True)
 
+    # the same K steps captured as one HIP graph (launch gaps removed; what a
+    # latency-bound small mesh gains), timed after one untimed launch
+    g = binding.Graph([S], [u], nsteps=args.steps)
+    g.launch()
+    torch.cuda.synchronize()
+    ev0.record()
+    g.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    secs_graph = ev0.elapsed_time(ev1) / 1000.0
+    del g
+
     stages = 3 * args.steps
     dof = K * m * Np
     value = dof * stages / secs
@@ -801,6 +813,7 @@ def main():
                    **({} if (opts["indicator"] == 0 and opts["gamma_mode"] == 0) else limiter_config(opts)),
                    "parallelism": "single-gpu"},
         "roofline": roof,
+        "us_per_stage": {"plain": round(secs * 1e6 / stages, 2), "graph": round(secs_graph * 1e6 / stages, 2)},
         "adjoint": adj,
         "kernel_ms_per_step": {k: round(a / 3, 4) for k, (a, b) in breakdown.items() if b},
         "status_bits": status,
