@@ -761,7 +761,9 @@ def main():
 
     # the same K steps captured as one HIP graph (launch gaps removed; what a
     # latency-bound small mesh gains), timed after one untimed launch
-    g = binding.Graph([S], [u], nsteps=args.steps)
+    # (on a copy of the state, so that the adjoint below sees the same one)
+    ug = u.clone()
+    g = binding.Graph([S], [ug], nsteps=args.steps)
     g.launch()
     torch.cuda.synchronize()
     ev0.record()
@@ -769,7 +771,7 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     secs_graph = ev0.elapsed_time(ev1) / 1000.0
-    del g
+    del g, ug
 
     stages = 3 * args.steps
     dof = K * m * Np
