@@ -103,3 +103,18 @@ def test_host_tvb_decomposition_on_distorted_meshes(seed):
     assert neg == 0 and Ao.min() >= 0.0
     assert np.array_equal(A != 0.0, Ao != 0.0)
     assert np.abs(A - Ao).max() < 1e-12
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/cswdg.h compiles as strict C99 (no C++ or torch types cross
+    the boundary)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "cswdg.h"\nint main(void) { cswdg_params p = {0}; (void)p; return 0; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
