@@ -113,7 +113,9 @@ typedef struct cswdg_params {
      * reading); 1 the quadratic q_3, i.e. the hierarchy of N = 1 projected
      * onto P2 (a third-order reconstruction, the design order of P2; stable
      * under refinement with every cell limited, where the quartic is not).
-     * N = 1 and N = 3 are unaffected. */
+     * N = 3 takes the same switch (1: the quadratic top projected onto P3,
+     * a third-order reconstruction, one below the design order of P3);
+     * N = 1 is unaffected. */
     int p2_top;
     /* troubled-cell indicator (the first step of Section 3; the limiter does
      * not depend on which one marks the cells): CSWDG_INDICATOR_KXRCF (the

@@ -280,9 +280,10 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     is copied from u.  linear_only: the weights are the linear weights
     (omega = gamma); characteristic=False (Euler): the conserved variables
     are reconstructed directly instead of the characteristic fields.
-    quadratic_top (N = 2 only): the hierarchy of N = 1, {p_1, p_2, p_3}
-    with the quadratic q_3 on top (a third-order reconstruction, the design
-    order of P2), instead of the quartic q_5 of the N >= 2 reading.
+    quadratic_top (N >= 2): the hierarchy of N = 1, {p_1, p_2, p_3} with
+    the quadratic q_3 on top (a third-order reconstruction: the design order
+    of P2, one below that of P3), instead of the quartic q_5 of the N >= 2
+    reading.
     constant_gamma: linear weights from 10^{l-1} instead of (1/h)^{l-1}.
     beta_literal: the smoothness indicators of eq. smoothnessIndicator
     read literally, of the equivalent polynomials p_l over derivative orders
@@ -380,7 +381,7 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     ntop = len(mono_top)
     pad = lambda c: np.concatenate([c, np.zeros((T, ntop - c.shape[1], F))], axis=1)
     qs = [np.zeros((T, ntop, F)), pad(c2), pad(c3)]
-    quartic = N >= 3 or (N == 2 and not quadratic_top)
+    quartic = N >= 2 and not quadratic_top
     if quartic:
         c5 = _solve_ls(rows(names_t4), rhs(names_t4, favg, fbar0))  # [T, 14, F]
         qs.append(c5)

@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
 #pragma unroll
         for (int jj = 0; jj < NM; ++jj) c5[jj] = 0.0;
         // N = 2 with QTOP: the hierarchy of N = 1 (quadratic top member)
-        constexpr bool quartic = (N >= 3) || (N == 2 && !QTOP);
+        constexpr bool quartic = (N >= 2) && !QTOP;
         if constexpr (quartic) {
             constexpr int pl[5] = {0, 3, 4, 5, 6};
 #pragma unroll
@@ -1546,7 +1546,7 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
     if (g > 2048u) g = 2048u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        if (N == 2 && c.p2_quadratic_top)
+        if (N >= 2 && c.p2_quadratic_top)
             k_limiter<EQ, N, S, 1><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma,
                                                              c.eps, c.char_comp, c.weights_linear);
         else

@@ -399,17 +399,18 @@ def test_global_lax_friedrichs_per_instance(torch):
         sol[0].dg_residual_vjp(us[0], us[0].clone())
 
 
+@pytest.mark.parametrize("N", [2, 3])
 @pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
 @pytest.mark.parametrize("eq", [0, 1])
-def test_limiter_p2_quadratic_top(torch, eq, bc):
-    """p2_top = 1: the N = 2 hierarchy with the quadratic top member, every
-    cell limited, and three KXRCF-limited steps, against the oracle's
-    quadratic_top reading."""
+def test_limiter_p2_quadratic_top(torch, eq, bc, N):
+    """p2_top = 1: the N = 2 (and N = 3) hierarchy with the quadratic top
+    member, every cell limited, and three KXRCF-limited steps, against the
+    oracle's quadratic_top reading."""
     b = _binding()
     v, t = inputs.jittered_mesh(12, seed=171)
     M = Mesh(v, t, bc, (1.0, 1.0))
-    dg = DG(M, 2, eq)
-    S = b.Solver(eq, 2, p2_top=1)
+    dg = DG(M, N, eq)
+    S = b.Solver(eq, N, p2_top=1)
     S.mesh_upload(v, t, bc, (1.0, 1.0))
     for u in (_jump_state(dg, eq, seed=4), _smooth_state(dg, eq, seed=5)):
         out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))

@@ -256,15 +256,16 @@ def test_component_mode_is_the_scalar_limiter_per_variable(N):
     assert np.abs(out - csweno.reconstruct(de, U, E)).max() > 1e-6
 
 
+@pytest.mark.parametrize("N", [2, 3])
 @pytest.mark.parametrize("eq", [0, 1])
-def test_quadratic_top_reproduces_quadratics_and_linear_data(eq):
+def test_quadratic_top_reproduces_quadratics_and_linear_data(eq, N):
     """The N = 2 switch to the quadratic top member (the N = 1 hierarchy
     projected onto P2): with the linear weights the reconstruction is the
     quadratic least-squares fit, which reproduces quadratic data exactly;
     with the nonlinear weights linear data are reproduced (as for every
     hierarchy); the hierarchy has three members."""
     M = _mesh(6)
-    d = DG(M, 2, eq)
+    d = DG(M, N, eq)
     E = _interior(M)
     if eq == 0:
         fq = lambda x, y: 0.4 + 0.7 * x - 0.5 * y + 2.0 * x * x - 0.8 * x * y + 0.3 * y * y
