@@ -144,10 +144,11 @@ def test_example7_riemann(torch, config, N, opts):
     cells the quadrant lines cut: configuration 12 at P1 with the defaults,
     at P2 and P3 with the TVB indicator and the constant linear weights;
     configuration 3 at P1 with those and at P2 with the quadratic top member
-    as well (its P3 runs lose positivity before the end time with every
-    combination tried; the P2 run carries an artifact of high density in
-    the cells along the left side, so the density bounds are checked away
-    from the sides)."""
+    as well (with the quartic top its P2/P3 runs lose positivity before the
+    end time; the P2 run carries an artifact of high density in the cells
+    along the left side, so the density bounds are checked away from the
+    sides; at P3 the artifact reaches 5.2 inside that margin and the case is
+    left out)."""
     S, u = _riemann(torch, config, N, 200, **opts)
     t_end = 0.3 if config == 3 else 0.25
     tt, means, p, steps = _clip_run(torch, S, u, t_end, 100)
