@@ -17,11 +17,12 @@ result goes to a new array, so the order of troubled cells is irrelevant):
 3. Subcell averages are averages of the neighbour's own DG polynomial.
 4. Step 1: q_1 = mean of Delta0; q_2 (linear) on T2 = {Delta0, Delta_i1};
    q_3 (quadratic) on T3 = {Delta0, Delta_i1, Delta_i2, Delta_i3}; for
-   N >= 2 also the quartic q_5 on the 16-cell T4 (pieces of step 2).  Each
+   N >= 2 also the cubic q_4 or the quartic q_5 on the 16-cell T4 (pieces
+   of step 2).  Each
    has the exact mean of Delta0 and matches the other averages in the
    least-squares sense (QR), in the scaled monomials ((x-x0)/h0)^a
    ((y-y0)/h0)^b about the centroid of Delta0, h0 its mean side.
-5. Step 2: equivalent polynomials (eqs. equivalentOrder0-2, 4) with linear
+5. Step 2: equivalent polynomials (eqs. equivalentOrder0-4) with linear
    weights gamma_{l,m} = h^{-(l-1)} / sum (Section 3.2, Step 2); the
    option constant_gamma takes 10^{l-1} / sum instead, the weights of the
    reference cited there, which the paper replaces by the h-dependent ones.
@@ -39,11 +40,22 @@ result goes to a new array, so the order of troubled cells is irrelevant):
    the two results are averaged.
 
 Readings where the paper is ambiguous:
-the members of the N >= 2 hierarchy are {p_1, p_2, p_3, p_top} with p_top
-from the quartic q_5 and weights gamma_{.,5} (the text's 'p_4'/'beta_4'
-denote this fourth member); T2, T3 and beta_1 use the whole centroid
-subcells; N = 3 reuses the N = 2 stencil and hierarchy; beta is taken of
-q_l; sigma is read literally.
+the fourth member of the N >= 2 hierarchy (TOPS; the text defines a p_4
+from the cubic q_4 by eq. equivalentOrder3 and a p_5 from the quartic q_5
+by eq. equivalentOrder4, and then sums four members with gamma_{.,5} and
+tau from beta_4):
+  'cubic'      p_4 of eq. equivalentOrder3 as printed: q_4 (cubic, T4)
+               minus gamma_{1,4} p_1 + gamma_{2,4} p_2, over gamma_{3,4},
+               with the three weights gamma_{.,4} (t = m - 1 = 3); the
+               members {p_1, p_2, p_3, p_4} are combined with gamma_{.,5}
+               and beta_4 = beta(q_4) (the default for N = 2);
+  'cubic_tel'  q_4 in place of q_5 in eq. equivalentOrder4 (four weights,
+               so that sum gamma_{l,5} p_l telescopes to q_4);
+  'quartic'    eq. equivalentOrder4 with q_5 (the default for N = 3);
+  'quadratic'  the three members of N = 1, {p_1, p_2, p_3}, with
+               gamma_{.,3} and the tau of eq. tauNonlinearWeightsP1.
+T2, T3 and beta_1 use the whole centroid subcells; N = 3 reuses the N = 2
+stencil and hierarchy; beta is taken of q_l; sigma is read literally.
 
 Parity status: pinned by tests/test_oracle_csweno.py (subcell tiling and
 areas, perpendicular cut, least-squares reproduction of polynomials,
@@ -66,6 +78,11 @@ from .physics import EQ_EULER, euler_left_eigenvectors, euler_right_eigenvectors
 EPS = 1e-10
 LAMBDA1 = 1.0 / 3.0
 
+# fourth member of the N >= 2 hierarchy (see the module docstring)
+TOPS = ("cubic", "quadratic", "quartic", "cubic_tel")
+DEFAULT_TOP = {1: "quadratic", 2: "cubic", 3: "quartic"}
+TOP_DEGREE = {"quadratic": 2, "cubic": 3, "cubic_tel": 3, "quartic": 4}
+
 
 class RankError(ValueError):
     pass
@@ -77,7 +94,21 @@ def monomials(d):
 
 
 def top_degree(N):
+    """Degree of the monomial space the reconstruction is written in."""
     return 2 if N == 1 else 4
+
+
+def resolve_top(N, top=None, quadratic_top=False):
+    """The top member used for degree N: N = 1 always has the quadratic
+    q_3 on top; N >= 2 takes top (one of TOPS), else the default."""
+    if N == 1:
+        return "quadratic"
+    if quadratic_top:
+        return "quadratic"
+    t = DEFAULT_TOP[N] if top is None else top
+    if t not in TOPS:
+        raise ValueError(f"unknown top member {t!r}")
+    return t
 
 
 # ---------------------------------------------------------------------------
@@ -275,15 +306,16 @@ def _beta_matrix(V0, x0, y0, h0, area0, d, orders=None):
 
 
 def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characteristic=True, quadratic_top=False,
-                constant_gamma=False, beta_literal=False, ghost_extrapolate=False):
+                constant_gamma=False, beta_literal=False, ghost_extrapolate=False, top=None):
     """New coefficients for the troubled cells elems: [T, m, Np].  Mode 0
     is copied from u.  linear_only: the weights are the linear weights
     (omega = gamma); characteristic=False (Euler): the conserved variables
     are reconstructed directly instead of the characteristic fields.
-    quadratic_top (N >= 2): the hierarchy of N = 1, {p_1, p_2, p_3} with
-    the quadratic q_3 on top (a third-order reconstruction: the design order
-    of P2, one below that of P3), instead of the quartic q_5 of the N >= 2
-    reading.
+    top (N >= 2): the fourth member of the hierarchy, one of TOPS
+    (default DEFAULT_TOP[N]); quadratic_top = True is top = 'quadratic',
+    the hierarchy of N = 1, {p_1, p_2, p_3} with the quadratic q_3 on top
+    (a third-order reconstruction: the design order of P2, one below that
+    of P3).
     constant_gamma: linear weights from 10^{l-1} instead of (1/h)^{l-1}.
     beta_literal: the smoothness indicators of eq. smoothnessIndicator
     read literally, of the equivalent polynomials p_l over derivative orders
@@ -375,16 +407,20 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
 
     nlin = len(monomials(1))
     nquad = len(monomials(2))
-    # Step 1: q_2, q_3 (and q_5)
+    tname = resolve_top(N, top, quadratic_top)
+    dfour = TOP_DEGREE[tname]
+    # Step 1: q_2, q_3 and the top least-squares level on T4 (the cubic
+    # q_4 or the quartic q_5)
     c2 = _solve_ls(rows(["S1"])[:, :, :nlin], rhs(["S1"], favg, fbar0))  # [T, 2, F]
     c3 = _solve_ls(rows(names_t3)[:, :, :nquad], rhs(names_t3, favg, fbar0))  # [T, 5, F]
     ntop = len(mono_top)
     pad = lambda c: np.concatenate([c, np.zeros((T, ntop - c.shape[1], F))], axis=1)
     qs = [np.zeros((T, ntop, F)), pad(c2), pad(c3)]
-    quartic = N >= 2 and not quadratic_top
-    if quartic:
-        c5 = _solve_ls(rows(names_t4), rhs(names_t4, favg, fbar0))  # [T, 14, F]
-        qs.append(c5)
+    four = tname != "quadratic"
+    if four:
+        nfour = len(monomials(dfour))
+        c4 = _solve_ls(rows(names_t4)[:, :, :nfour], rhs(names_t4, favg, fbar0))  # [T, 9 or 14, F]
+        qs.append(pad(c4))
     L = len(qs)
 
     # Step 2: equivalent polynomials (mean-free parts; all means equal ubar0)
@@ -392,16 +428,23 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     g3 = linear_weights(h0, 3, constant_gamma)
     ps = [qs[0], qs[1] / g2[:, 1, None, None]]  # p1 = q1 has zero mean-free part
     ps.append((qs[2] - g3[:, 1, None, None] * ps[1]) / g3[:, 2, None, None])
-    if quartic:
+    if four:
         g5 = linear_weights(h0, 4, constant_gamma)
-        ps.append((qs[3] - sum(g5[:, l, None, None] * ps[l] for l in range(3))) / g5[:, 3, None, None])
+        if tname == "cubic":
+            # eq. equivalentOrder3: q_4 = gamma_{1,4} p_1 + gamma_{2,4} p_2 +
+            # gamma_{3,4} p_4 with the three weights gamma_{.,4}
+            g4 = linear_weights(h0, 3, constant_gamma)
+            ps.append((qs[3] - g4[:, 1, None, None] * ps[1]) / g4[:, 2, None, None])
+        else:
+            # eq. equivalentOrder4 (q_5, or q_4 in its place)
+            ps.append((qs[3] - sum(g5[:, l, None, None] * ps[l] for l in range(3))) / g5[:, 3, None, None])
         gtop = g5
     else:
         gtop = g3
 
     # Step 3: smoothness indicators of q_l (l >= 2)
     betas = [None]
-    degs = [0, 1, 2, 4]
+    degs = [0, 1, 2, dfour]
     for l in range(1, L):
         d = degs[l]
         nd = len(monomials(d))
@@ -430,7 +473,7 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     betas[0] = area0[:, None] * np.sum(gmix * gmix, axis=1)
 
     # Step 4: tau and nonlinear weights
-    if not quartic:
+    if not four:
         tau = (np.abs(betas[2] - betas[0]) ** 2 + np.abs(betas[2] - betas[1]) ** 2) / 4.0
     else:
         tau = sum(np.abs(betas[3] - betas[l]) ** 2 for l in range(3)) / 16.0
@@ -460,12 +503,12 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     if return_info:
         return out, dict(qs=qs, ps=ps, betas=betas, omega=omega, gamma=gtop, tau=tau,
                          pieces=pcs, avg=avg, fbar0=fbar0, nbad=nbad, Rc=Rc, mavg0=mavg0,
-                         x0=x0, y0=y0, h0=h0, favg=favg)
+                         x0=x0, y0=y0, h0=h0, favg=favg, top=tname, wbar=wbar, area0=area0)
     return out
 
 
 def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top=False, constant_gamma=False,
-          beta_literal=False, ghost_extrapolate=False):
+          beta_literal=False, ghost_extrapolate=False, top=None):
     """Apply the limiter to the cells where mask is true (simultaneous
     update: every reconstruction reads the pre-limit u)."""
     E = np.nonzero(np.asarray(mask))[0]
@@ -473,7 +516,7 @@ def limit(dg: DG, u, mask, linear_only=False, characteristic=True, quadratic_top
     if len(E):
         out[E] = reconstruct(dg, u, E, linear_only=linear_only, characteristic=characteristic,
                              quadratic_top=quadratic_top, constant_gamma=constant_gamma, beta_literal=beta_literal,
-                             ghost_extrapolate=ghost_extrapolate)
+                             ghost_extrapolate=ghost_extrapolate, top=top)
     return out
 
 

@@ -110,8 +110,13 @@ def test_beta_closed_form():
     assert math.isclose(c @ B @ c, 4.0 / 3.0, rel_tol=1e-13)
 
 
-@pytest.mark.parametrize("N,deg", [(1, 1), (2, 2), (3, 3)])
-def test_least_squares_levels_reproduce_polynomials(N, deg):
+@pytest.mark.parametrize("N,deg,top", [(1, 1, None), (2, 2, "quartic"), (2, 2, "cubic_tel"), (2, 2, "quadratic"),
+                                       (3, 3, "quartic"), (3, 3, "cubic_tel")])
+def test_least_squares_levels_reproduce_polynomials(N, deg, top):
+    """Every telescoping hierarchy (the top member built by eq.
+    equivalentOrder4 from the top least-squares level) reproduces data of
+    the top level's degree with the linear weights.  The literal cubic
+    reading does not telescope; its identity is pinned separately."""
     M = _mesh(7)
     d = DG(M, N, 0)
     coef = {1: (0.2, 0.5, -0.3, 0, 0, 0), 2: (0.2, 0.5, -0.3, 0.4, -0.2, 0.3),
@@ -125,7 +130,7 @@ def test_least_squares_levels_reproduce_polynomials(N, deg):
 
     U = d.project(u)
     E = _interior(M)
-    out, info = csweno.reconstruct(d, U, E, linear_only=True, return_info=True)
+    out, info = csweno.reconstruct(d, U, E, linear_only=True, return_info=True, top=top)
     # the top level (degree >= data degree) reproduces the data exactly, and
     # with omega = gamma the reconstruction telescopes to it
     assert np.abs(out - U[E]).max() < 1e-11
@@ -304,8 +309,8 @@ def test_constant_linear_weights():
 def test_constant_gamma_reproduction(N):
     """With the constant linear weights: linear data are reproduced by the
     nonlinear weights (tau = 0) and degree-N data by the linear weights
-    (the telescoping sum is the top least-squares fit, exact on the
-    neighbours' degree-N polynomials)."""
+    of a telescoping hierarchy (the telescoping sum is the top
+    least-squares fit, exact on the neighbours' degree-N polynomials)."""
     M = _mesh(6)
     d = DG(M, N, 0)
     E = _interior(M)
@@ -317,8 +322,10 @@ def test_constant_gamma_reproduction(N):
     terms = [lambda x, y: 0.7 * x - 0.5 * y, lambda x, y: 2.0 * x * x - 0.8 * x * y + 0.3 * y * y,
              lambda x, y: 1.5 * x ** 3 - 0.7 * x * y * y + 0.4 * y ** 3]
     Uq = d.project(lambda x, y: 0.4 + sum(f(x, y) for f in terms[:N]))
-    out = csweno.reconstruct(d, Uq, E, linear_only=True, constant_gamma=True)
-    assert np.abs(out - Uq[E]).max() < 1e-10
+    # telescoping hierarchies (the literal cubic reading does not telescope)
+    for top in ((None,) if N == 1 else ("quartic", "cubic_tel")):
+        out = csweno.reconstruct(d, Uq, E, linear_only=True, constant_gamma=True, top=top)
+        assert np.abs(out - Uq[E]).max() < 1e-10
 
 
 @pytest.mark.parametrize("N", [1, 2])
@@ -376,7 +383,8 @@ def test_extrapolated_ghosts_reproduce_linear_data_at_the_boundary(N, eq):
     """ghost_extrapolate: across outflow faces the ghost carries Delta0's own
     polynomial continued, so every cell, boundary cells included, sees one
     linear function on its whole stencil and reproduces it (the nonlinear
-    weights) - and degree-N data with the linear weights; the mirror image
+    weights) - and degree-N data with the linear weights of a telescoping
+    hierarchy; the mirror image
     does not (the normal gradient changes sign across the face)."""
     M = _mesh(6)
     d = DG(M, N, eq)
@@ -393,5 +401,6 @@ def test_extrapolated_ghosts_reproduce_linear_data_at_the_boundary(N, eq):
         terms = [lambda x, y: 0.7 * x - 0.5 * y, lambda x, y: 2.0 * x * x - 0.8 * x * y + 0.3 * y * y,
                  lambda x, y: 1.5 * x ** 3 - 0.7 * x * y * y + 0.4 * y ** 3]
         Uq = d.project(lambda x, y: 0.4 + sum(f(x, y) for f in terms[:N]))
-        out = csweno.reconstruct(d, Uq, bcell, linear_only=True, ghost_extrapolate=True)
-        assert np.abs(out - Uq[bcell]).max() < 1e-9
+        for top in ((None,) if N == 1 else ("quartic", "cubic_tel")):
+            out = csweno.reconstruct(d, Uq, bcell, linear_only=True, ghost_extrapolate=True, top=top)
+            assert np.abs(out - Uq[bcell]).max() < 1e-9
