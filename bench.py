@@ -30,7 +30,7 @@ outflow at x = 4, reflective walls elsewhere; initialised with that flow.
 The positivity-preserving scaling (not in the paper) follows the limiter
 of every stage: without it the impulsive start at the step loses
 positivity within two steps; P2 takes the quadratic top member of its
-reconstruction hierarchy (p2_top = 1).  --workload p1_euler_ffstep: the
+reconstruction hierarchy (the default reading).  --workload p1_euler_ffstep: the
 same with P1.  Both lines include the run to the paper's t = 4.  The flow first develops for --develop steps
 (default 4000, untimed, in graph launches of 100 steps); then K steps are
 timed as one graph launch (after one untimed launch) and as plain
@@ -218,30 +218,29 @@ FFSTEP = {"s": 110, "seed": 1005}
 
 
 def limiter_options(args, degree, default_p2_top=0):
-    """Solver keywords of the example workloads: --gamma-mode, --indicator,
-    --tvb-m, --p2-top (None: the workload's default)."""
+    """Solver keywords of the workloads: --gamma-mode, --indicator, --tvb-m,
+    --p2-top (None: the workload's default)."""
     from paper_2106_06280_amd import binding
     p2_top = default_p2_top if args.p2_top is None else args.p2_top
-    return {"gamma_mode": args.gamma_mode, "tvb_m": args.tvb_m, "p2_top": p2_top if degree == 2 else 0,
+    return {"gamma_mode": args.gamma_mode, "tvb_m": args.tvb_m, "p2_top": p2_top if degree >= 2 else 0,
             "indicator": binding.INDICATOR_TVB if args.indicator == "tvb" else binding.INDICATOR_KXRCF}
 
 
-def limiter_config(opts):
+def limiter_config(opts, degree):
+    from paper_2106_06280_amd import binding
     return {"indicator": "tvb" if opts["indicator"] == 1 else "kxrcf", "tvb_m": opts["tvb_m"],
             "linear_weights": "10^(l-1)" if opts["gamma_mode"] == 1 else "(1/h)^(l-1)",
-            "p2_top": "quadratic" if opts["p2_top"] == 1 else None}
+            "top_member": binding.top_name(degree, opts["p2_top"])}
 
 
 def ffstep_solver(args, degree=2):
-    """Example 6's solver.  With the paper's linear weights P2 takes the
-    quadratic top member of its reconstruction hierarchy (p2_top = 1), with
-    which the run is stable; with the constant weights (--gamma-mode 1)
-    the default quartic one."""
+    """Example 6's solver (the default reading of the top member: quadratic
+    for P2, quartic for P3)."""
     from paper_2106_06280_amd import binding, inputs
     v, t = inputs.forward_step_mesh(FFSTEP["s"], seed=FFSTEP["seed"])
     kinds = inputs.forward_step_kinds(v, t)
     inflow = inputs.UniformFlow(*inputs.FFSTEP_PRIMITIVE)
-    opts = limiter_options(args, degree, default_p2_top=0 if args.gamma_mode == 1 else 1)
+    opts = limiter_options(args, degree)
     S = binding.Solver(binding.EQ_EULER, degree, limiter_mode=binding.LIMIT_KXRCF, positivity=1, **opts)
     S.mesh_upload(v, t, binding.BC_TRANSMISSIVE)
     S.set_boundary(kinds, inflow.state)
@@ -355,7 +354,7 @@ def run_ffstep(args, degree=2):
         "config": {"workload": name, "triangles": K, "degree": degree, "dof": dof,
                    "developed_steps": args.develop, "troubled_fraction": round(tot / max(1, calls * K), 5),
                    "boundaries": "inflow x=0, outflow x=4, reflective walls", "limiter": "csweno",
-                   **limiter_config(opts), "parallelism": "single-gpu"},
+                   **limiter_config(opts, degree), "parallelism": "single-gpu"},
         "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
                   "graph_equals_eager": same},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -456,7 +455,7 @@ def run_dmr(args, degree=1):
                    "developed_steps": args.develop, "time_at_timing": round(time_start, 5),
                    "troubled_fraction": round(tot / max(1, calls * K), 5),
                    "boundaries": "post-shock inflow, wall, outflow, moving Mach 10 shock on top",
-                   "limiter": "csweno", **limiter_config(opts), "positivity": True, "parallelism": "single-gpu"},
+                   "limiter": "csweno", **limiter_config(opts, degree), "positivity": True, "parallelism": "single-gpu"},
         "eager": {"value": dof * 3 * args.steps / secs_eager, "ms_per_step": secs_eager * 1e3 / args.steps,
                   "graph_equals_eager": bool(torch.equal(u, after))},
         "status_bits": status,
@@ -529,7 +528,7 @@ def run_shock_entropy(args, degree=1):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": name, "triangles": K, "degree": degree, "dof": K * m * Np,
-                   "boundaries": "periodic in y, outflow at x = 0 and 1", "limiter": "csweno", **limiter_config(opts),
+                   "boundaries": "periodic in y, outflow at x = 0 and 1", "limiter": "csweno", **limiter_config(opts, degree),
                    "positivity": True, "parallelism": "single-gpu"},
         "t_end_run": run,
         "status_bits": S.status(),
@@ -658,9 +657,9 @@ def main():
     ap.add_argument("--indicator", default="kxrcf", choices=("kxrcf", "tvb"),
                     help="troubled-cell indicator; not the batch")
     ap.add_argument("--tvb-m", type=float, default=0.0, help="TVB constant M of --indicator tvb")
-    ap.add_argument("--p2-top", type=int, default=None, choices=(0, 1),
-                    help="example workloads at P2: 1 the quadratic top member (default: 1 for the forward "
-                         "step with the paper's weights, else 0)")
+    ap.add_argument("--p2-top", type=int, default=None, choices=(0, 1, 2, 3, 4),
+                    help="top member of the N >= 2 hierarchy: 0 the default reading (quadratic for P2, quartic "
+                         "for P3), 1 quadratic, 2 quartic, 3 telescoping cubic, 4 the printed cubic p_4")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -812,7 +811,7 @@ def main():
                    "equation": "euler" if eq == 1 else "burgers", "dof": dof,
                    "troubled_fraction": round(f, 5),
                    "limiter": "kxrcf+csweno" if opts["indicator"] == 0 else "tvb+csweno",
-                   **({} if (opts["indicator"] == 0 and opts["gamma_mode"] == 0) else limiter_config(opts)),
+                   **limiter_config(opts, N),
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "us_per_stage": {"plain": round(secs * 1e6 / stages, 2), "graph": round(secs_graph * 1e6 / stages, 2)},

@@ -108,14 +108,23 @@ typedef struct cswdg_params {
      * constant per residual and instance, the largest cell-mean wave speed
      * of the residual's input state (the bound the time step uses) */
     int lf_mode;
-    /* top member of the N = 2 reconstruction hierarchy (Section 3.2, Steps
-     * 1-2 for P2): 0 the quartic q_5 on the 16-cell stencil T4 (the default
-     * reading); 1 the quadratic q_3, i.e. the hierarchy of N = 1 projected
-     * onto P2 (a third-order reconstruction, the design order of P2; stable
-     * under refinement with every cell limited, where the quartic is not).
-     * N = 3 takes the same switch (1: the quadratic top projected onto P3,
-     * a third-order reconstruction, one below the design order of P3);
-     * N = 1 is unaffected. */
+    /* fourth member of the N >= 2 reconstruction hierarchy (Section 3.2,
+     * Steps 1-2 for P2; the text defines p_4 from the cubic q_4 by eq.
+     * equivalentOrder3 and p_5 from the quartic q_5 by eq.
+     * equivalentOrder4, then combines four members with gamma_{.,5}):
+     *   0 the default reading of the degree: for N = 2 the quadratic top
+     *     (value 1: with every cell limited the readings that build a fourth
+     *     member on T4 diverge under refinement for the Euler equations),
+     *     for N = 3 the quartic (value 2);
+     *   1 the quadratic q_3 on top: the three members of N = 1 projected
+     *     onto P_N (a third-order reconstruction);
+     *   2 the quartic q_5 on the 16-cell stencil T4 by eq. equivalentOrder4;
+     *   3 the cubic q_4 in place of q_5 in eq. equivalentOrder4 (so that
+     *     the linear weights telescope to q_4);
+     *   4 p_4 = (q_4 - gamma_{1,4} p_1 - gamma_{2,4} p_2) / gamma_{3,4} with
+     *     the three weights gamma_{.,4} (eq. equivalentOrder3 as printed),
+     *     the members p_1..p_4 combined with gamma_{.,5}.
+     * N = 1 is unaffected.  Values outside 0..4: CSWDG_EINVAL. */
     int p2_top;
     /* troubled-cell indicator (the first step of Section 3; the limiter does
      * not depend on which one marks the cells): CSWDG_INDICATOR_KXRCF (the
@@ -325,8 +334,9 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
  * the first argument on ties and d|x|/dx = 0 at x = 0.  Deterministic (no
  * floating-point atomics).  All buffers device, state layout.  These calls
  * take FP64 single-instance solvers with the default readings (char_mode,
- * weights_mode, lf_mode, p2_top, gamma_mode, ghost_mode and positivity 0, the KXRCF indicator) and
- * no wall, inflow or moving-shock faces; CSWDG_EINVAL otherwise. */
+ * weights_mode, lf_mode, gamma_mode, ghost_mode and positivity 0, the KXRCF
+ * indicator; any p2_top) and no wall, inflow or moving-shock faces;
+ * CSWDG_EINVAL otherwise. */
 
 /* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).
  * u_bar must not alias r_bar. */

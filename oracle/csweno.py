@@ -48,12 +48,16 @@ tau from beta_4):
                minus gamma_{1,4} p_1 + gamma_{2,4} p_2, over gamma_{3,4},
                with the three weights gamma_{.,4} (t = m - 1 = 3); the
                members {p_1, p_2, p_3, p_4} are combined with gamma_{.,5}
-               and beta_4 = beta(q_4) (the default for N = 2);
+               and beta_4 = beta(q_4);
   'cubic_tel'  q_4 in place of q_5 in eq. equivalentOrder4 (four weights,
                so that sum gamma_{l,5} p_l telescopes to q_4);
   'quartic'    eq. equivalentOrder4 with q_5 (the default for N = 3);
   'quadratic'  the three members of N = 1, {p_1, p_2, p_3}, with
-               gamma_{.,3} and the tau of eq. tauNonlinearWeightsP1.
+               gamma_{.,3} and the tau of eq. tauNonlinearWeightsP1 (the
+               default for N = 2: with every cell limited it is the only
+               one of these readings whose errors fall at the order of
+               Tables 1-3 under refinement; the three that build the fourth
+               member on T4 diverge for Euler P2).
 T2, T3 and beta_1 use the whole centroid subcells; N = 3 reuses the N = 2
 stencil and hierarchy; beta is taken of q_l; sigma is read literally.
 
@@ -80,7 +84,7 @@ LAMBDA1 = 1.0 / 3.0
 
 # fourth member of the N >= 2 hierarchy (see the module docstring)
 TOPS = ("cubic", "quadratic", "quartic", "cubic_tel")
-DEFAULT_TOP = {1: "quadratic", 2: "cubic", 3: "quartic"}
+DEFAULT_TOP = {1: "quadratic", 2: "quadratic", 3: "quartic"}
 TOP_DEGREE = {"quadratic": 2, "cubic": 3, "cubic_tel": 3, "quartic": 4}
 
 

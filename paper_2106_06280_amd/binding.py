@@ -145,6 +145,22 @@ def host_tvb_decomposition(vxy, tri, bc, period=(0.0, 0.0)):
     return A, int(neg.value)
 
 
+# p2_top values (Section 3.2, Steps 1-2 for P2: the fourth member of the
+# N >= 2 hierarchy) and the oracle's name of each reading
+TOP_DEFAULT, TOP_QUADRATIC, TOP_QUARTIC, TOP_CUBIC_TEL, TOP_CUBIC = 0, 1, 2, 3, 4
+TOP_NAMES = {TOP_QUADRATIC: "quadratic", TOP_QUARTIC: "quartic", TOP_CUBIC_TEL: "cubic_tel", TOP_CUBIC: "cubic"}
+
+
+def top_name(degree, p2_top):
+    """The reading a p2_top value selects for degree N (None: N = 1, whose
+    hierarchy has the quadratic q_3 on top)."""
+    if degree == 1:
+        return None
+    if p2_top == TOP_DEFAULT:
+        return "quadratic" if degree == 2 else "quartic"
+    return TOP_NAMES[p2_top]
+
+
 class Solver:
     """One solver = one equation, degree and mesh on the current GPU."""
 

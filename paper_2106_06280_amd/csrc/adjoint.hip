@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_compact_slots(int K, const uint8_t* __r
     }
 }
 
-template <int EQ, int N>
+template <int EQ, int N, int QTOP>
 __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* __restrict__ u,
                                                     const double* __restrict__ ops,
                                                     const int32_t* __restrict__ list,
@@ -277,8 +277,10 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                                                     double* __restrict__ contrib, double gamma,
                                                     double eps) {
     using D = Dims<N>;
-    using LO = OpLayout<N>;
-    constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = D::NPIECE, NM = D::NMONO;
+    using LO = OpLayout<N, QTOP>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = LO::NPC, NM = LO::NM;
+    constexpr bool FOUR = LO::FOUR;  // a fourth member on T4
+    constexpr int NT = LO::NT > 0 ? LO::NT : 1;
     constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
     constexpr int CPB = 64 / LPC;
     const int K = msh.K;
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             }
         }
         constexpr int pl[5] = {0, 3, 4, 5, 6};
-        double c2[2], c3[5], c5[NM];
+        double c2[2], c3[5], c5[NT];
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
             double s = 0.0;
@@ -368,10 +370,10 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             c3[jj] = s;
         }
 #pragma unroll
-        for (int jj = 0; jj < NM; ++jj) c5[jj] = 0.0;
-        if constexpr (N >= 2) {
+        for (int jj = 0; jj < NT; ++jj) c5[jj] = 0.0;
+        if constexpr (FOUR) {
 #pragma unroll 1
-            for (int jj = 0; jj < 14; ++jj) {
+            for (int jj = 0; jj < NT; ++jj) {
                 double s = 0.0;
 #pragma unroll
                 for (int kk = 0; kk < 5; ++kk)
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
         double beta[4];
         beta[1] = quad_form<NM, 2>(bp, c2);
         beta[2] = quad_form<NM, 5>(bp, c3);
-        beta[3] = (N >= 2) ? quad_form<NM, NM>(bp, c5) : 0.0;
+        beta[3] = FOUR ? quad_form<NM, NT>(bp, c5) : 0.0;
         const double area0 = op[LO::AREA0];
         double gx[3], gy[3], b1[3], sg[3], ssum, mx, my, num, mm;
         {
@@ -419,9 +421,9 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
         const double g22 = ih / s2, g23 = ih / s3, g33 = ih * ih / s3;
         const double g15 = 1.0 / s5, g25 = ih / s5, g35 = ih * ih / s5, g45 = ih * ih * ih / s5;
         const double g13 = 1.0 / s3;
-        constexpr int NL = (N == 1) ? 3 : 4;
+        constexpr int NL = FOUR ? 4 : 3;
         double gl[4], om[4], ob[4], tau, os;
-        if constexpr (N == 1) {
+        if constexpr (!FOUR) {
             gl[0] = g13;
             gl[1] = g23;
             gl[2] = g33;
@@ -445,10 +447,15 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
 #pragma unroll
         for (int l = 0; l < NL; ++l) om[l] = ob[l] / os;
         double A2, A3, A5;
-        if constexpr (N == 1) {
+        if constexpr (!FOUR) {
             A3 = om[2] / g33;
             A2 = om[1] / g22 - A3 * g23 / g22;
             A5 = 0.0;
+        } else if constexpr (QTOP == kTopCubic) {
+            // eq. equivalentOrder3: p4 = (c4 - g24 p2)/g34, gamma_{.,4} = gamma_{.,3}
+            A5 = om[3] / g33;
+            A3 = om[2] / g33;
+            A2 = (om[1] - (om[2] + om[3]) * (g23 / g33)) / g22;
         } else {
             A5 = om[3] / g45;
             A3 = (om[2] - A5 * g35) / g33;
@@ -457,7 +464,8 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
         double Rcoef[NM];
 #pragma unroll
         for (int jj = 0; jj < NM; ++jj) {
-            double r = A5 * c5[jj];
+            double r = 0.0;
+            if constexpr (FOUR) r = A5 * c5[jj];
             if (jj < 5) r += A3 * c3[jj];
             if (jj < 2) r += A2 * c2[jj];
             Rcoef[jj] = r;
@@ -500,12 +508,16 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             for (int i = 0; i < NP - 1; ++i) s += op[LO::PM + i * NM + jj] * momb[i];
             Rcoefb[jj] = s;
         }
-        double c2b[2], c3b[5], c5b[NM];
+        double c2b[2], c3b[5], c5b[NT];
         double A2b = 0.0, A3b = 0.0, A5b = 0.0;
 #pragma unroll
-        for (int jj = 0; jj < NM; ++jj) {
-            c5b[jj] = A5 * Rcoefb[jj];
-            A5b += c5[jj] * Rcoefb[jj];
+        for (int jj = 0; jj < NT; ++jj) c5b[jj] = 0.0;
+        if constexpr (FOUR) {
+#pragma unroll
+            for (int jj = 0; jj < NT; ++jj) {
+                c5b[jj] = A5 * Rcoefb[jj];
+                A5b += c5[jj] * Rcoefb[jj];
+            }
         }
 #pragma unroll
         for (int jj = 0; jj < 5; ++jj) {
@@ -518,10 +530,15 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             A2b += c2[jj] * Rcoefb[jj];
         }
         double omb[4] = {0.0, 0.0, 0.0, 0.0};
-        if constexpr (N == 1) {
+        if constexpr (!FOUR) {
             omb[1] = A2b / g22;
             A3b -= A2b * g23 / g22;
             omb[2] = A3b / g33;
+        } else if constexpr (QTOP == kTopCubic) {
+            omb[1] = A2b / g22;
+            const double tb = A2b * (g23 / g33) / g22;
+            omb[2] = A3b / g33 - tb;
+            omb[3] = A5b / g33 - tb;
         } else {
             omb[1] = A2b / g22;
             A5b -= A2b * g25 / g22;
@@ -541,7 +558,7 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             taub += obar * gl[l] * ie;
             betab[l] -= obar * gl[l] * tau * ie * ie;
         }
-        if constexpr (N == 1) {
+        if constexpr (!FOUR) {
             betab[2] += taub * 0.5 * ((beta[2] - beta[0]) + (beta[2] - beta[1]));
             betab[0] -= taub * 0.5 * (beta[2] - beta[0]);
             betab[1] -= taub * 0.5 * (beta[2] - beta[1]);
@@ -561,11 +578,11 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
             for (int jj = 0; jj < NM; ++jj) {
                 const int r0 = i < jj ? i : jj, r1 = i < jj ? jj : i;
                 const double Bij = bp[r0 * NM - (r0 * (r0 - 1)) / 2 + (r1 - r0)];
-                s5 += Bij * c5[jj];
+                if constexpr (FOUR) s5 += Bij * c5[jj];
                 if (i < 5 && jj < 5) s3v += Bij * c3[jj];
                 if (i < 2 && jj < 2) s2v += Bij * c2[jj];
             }
-            if (N >= 2) c5b[i] += 2.0 * betab[3] * s5;
+            if constexpr (FOUR) c5b[i] += 2.0 * betab[3] * s5;
             if (i < 5) c3b[i] += 2.0 * betab[2] * s3v;
             if (i < 2) c2b[i] += 2.0 * betab[1] * s2v;
         }
@@ -631,14 +648,14 @@ __global__ __launch_bounds__(64) void k_limiter_vjp(DevMesh msh, const double* _
                 wb[f][p] += s;
                 w0b -= s;
             }
-        if constexpr (N >= 2) {
+        if constexpr (FOUR) {
 #pragma unroll 1
             for (int kk = 0; kk < 5; ++kk)
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
                     double s = 0.0;
 #pragma unroll
-                    for (int jj = 0; jj < 14; ++jj) s += op[LO::X5 + jj * 15 + kk * 3 + f] * c5b[jj];
+                    for (int jj = 0; jj < NT; ++jj) s += op[LO::X5 + jj * 15 + kk * 3 + f] * c5b[jj];
                     wb[f][pl[kk]] += s;
                     w0b -= s;
                 }
@@ -829,8 +846,19 @@ hipError_t launch_limiter_vjp(const LaunchCtx& c, const DevMesh& m, const void* 
     if (g > 16384u) g = 16384u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_EN(c.eq, c.N, {
-        k_limiter_vjp<EQ, N><<<g, bs, 0, c.stream>>>(m, (const double*)w, ops, list, count, (const double*)ybar,
-                                                     contrib, c.gamma, c.eps);
+        const int qt = N >= 2 ? c.qtop : kTopQuadratic;
+        if (N == 1 || qt == kTopQuadratic)
+            k_limiter_vjp<EQ, N, kTopQuadratic><<<g, bs, 0, c.stream>>>(m, (const double*)w, ops, list, count,
+                                                                        (const double*)ybar, contrib, c.gamma, c.eps);
+        else if (qt == kTopCubic)
+            k_limiter_vjp<EQ, N, kTopCubic><<<g, bs, 0, c.stream>>>(m, (const double*)w, ops, list, count,
+                                                                    (const double*)ybar, contrib, c.gamma, c.eps);
+        else if (qt == kTopCubicTel)
+            k_limiter_vjp<EQ, N, kTopCubicTel><<<g, bs, 0, c.stream>>>(m, (const double*)w, ops, list, count,
+                                                                       (const double*)ybar, contrib, c.gamma, c.eps);
+        else
+            k_limiter_vjp<EQ, N, kTopQuartic><<<g, bs, 0, c.stream>>>(m, (const double*)w, ops, list, count,
+                                                                      (const double*)ybar, contrib, c.gamma, c.eps);
     });
     return hipGetLastError();
 }

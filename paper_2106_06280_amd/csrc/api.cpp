@@ -162,7 +162,6 @@ int check_single(cswdg_solver* s) {
     if (s->n_special != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take meshes without wall or inflow faces");
     if (s->p.positivity != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take solvers without the positivity scaling");
     if (s->p.lf_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the local Lax-Friedrichs flux (lf_mode = 0)");
-    if (s->p.p2_top != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the quartic P2 hierarchy (p2_top = 0)");
     if (s->p.indicator != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the KXRCF indicator (indicator = 0)");
     if (s->p.gamma_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the linear weights (1/h)^(l-1) (gamma_mode = 0)");
     if (s->p.ghost_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the mirror ghost (ghost_mode = 0)");
@@ -292,7 +291,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         return fail(nullptr, CSWDG_EINVAL, "kxrcf_norm, char_mode and weights_mode must be 0 or 1");
     if (p.positivity < 0 || p.positivity > 1) return fail(nullptr, CSWDG_EINVAL, "positivity must be 0 or 1");
     if (p.lf_mode < 0 || p.lf_mode > 1) return fail(nullptr, CSWDG_EINVAL, "lf_mode must be 0 or 1");
-    if (p.p2_top < 0 || p.p2_top > 1) return fail(nullptr, CSWDG_EINVAL, "p2_top must be 0 or 1");
+    if (p.p2_top < 0 || p.p2_top > 4) return fail(nullptr, CSWDG_EINVAL, "p2_top must be 0..4");
     if (p.indicator != CSWDG_INDICATOR_KXRCF && p.indicator != CSWDG_INDICATOR_TVB)
         return fail(nullptr, CSWDG_EINVAL, "indicator must be CSWDG_INDICATOR_KXRCF or CSWDG_INDICATOR_TVB");
     if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m))
@@ -338,7 +337,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.kxrcf_rms = p.kxrcf_norm;
     s->ctx.char_comp = p.char_mode;
     s->ctx.weights_linear = p.weights_mode;
-    s->ctx.p2_quadratic_top = p.p2_top;
+    s->ctx.qtop = top_for(p.degree, p.p2_top);
     s->ctx.indicator = p.indicator;
     s->ctx.tvb_m = p.tvb_m;
     *out = s;
@@ -467,7 +466,7 @@ int cswdg_set_boundary(cswdg_solver* s, const uint8_t* kinds, const double* infl
             // the outflow faces' ghosts differ from the walls': rebuild the
             // stencil operators for the new kinds
             std::vector<double> ops;
-            rc = build_limiter_ops(s->mesh, s->p.degree, s->p.gamma_mode == 1, true, ops, s->n_rank, s->n_foot);
+            rc = build_limiter_ops(s->mesh, s->p.degree, s->ctx.qtop, s->p.gamma_mode == 1, true, ops, s->n_rank, s->n_foot);
             if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
             e = hipMemcpy(s->d_ops, ops.data(), sizeof(double) * ops.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) return hipfail(s, e, "set_boundary");
@@ -1044,7 +1043,7 @@ int upload_mesh(cswdg_solver* s) {
     int rc;
     const int64_t K = s->mesh.K;
     std::vector<double> ops;
-    rc = build_limiter_ops(s->mesh, s->p.degree, s->p.gamma_mode == 1, s->p.ghost_mode == 1, ops, s->n_rank,
+    rc = build_limiter_ops(s->mesh, s->p.degree, s->ctx.qtop, s->p.gamma_mode == 1, s->p.ghost_mode == 1, ops, s->n_rank,
                            s->n_foot);
     if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
     std::vector<double> tvbA;

@@ -14,8 +14,10 @@
 //                 neighbour's centroid G to its outer sides (Fig. 2).
 //   X2, X3, X5    least-squares pseudo-inverses (Householder QR) of the
 //                 constrained fits q_2 (linear, rows S1 x 3 faces), q_3
-//                 (quadratic, rows S1, S2, S3 x 3) and q_5 (quartic, rows
-//                 S1, S2', S21, S3', S31 x 3) in the scaled monomials
+//                 (quadratic, rows S1, S2, S3 x 3) and the top level on T4
+//                 (rows S1, S2', S21, S3', S31 x 3): the quartic q_5, or
+//                 for the cubic readings the cubic q_4 in X5's first nine
+//                 rows, in the scaled monomials
 //                 ((x-x0)/h0)^a ((y-y0)/h0)^b, 1 <= a+b, minus their mean
 //                 over e; the right-hand side is (piece average - mean of e).
 //   BP            the smoothness-indicator matrix of eq. smoothnessIndicator:
@@ -31,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <thread>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -127,24 +130,24 @@ struct MonoList {
     }
 };
 
-template <int N>
+template <int N, int QT>
 struct OpBuilder {
     using D = Dims<N>;
-    using L = OpLayout<N>;
+    using L = OpLayout<N, QT>;
     const HostMesh& m;
     bool constant_gamma;
     bool ghost_extrapolate;  // outflow faces: Delta0's polynomial continued, not mirrored
     std::vector<double> C;  // basis monomial form [NP][NP]
     Rule2D rN, rTop, rBeta, rProj;
     std::vector<double> psiProj;  // [q][NP] on rProj
-    MonoList mono{D::DTOP};
+    MonoList mono{L::DR};
 
     OpBuilder(const HostMesh& mm, bool cg, bool ge) : m(mm), constant_gamma(cg), ghost_extrapolate(ge) {
         basis_monomial_form(N, C);
         rN = triangle_rule((N + 2) / 2);
-        rTop = triangle_rule((D::DTOP + 2) / 2);
-        rBeta = triangle_rule(D::DTOP);
-        rProj = triangle_rule((D::DTOP + N + 2) / 2);
+        rTop = triangle_rule((L::DR + 2) / 2);
+        rBeta = triangle_rule(L::DR);
+        rProj = triangle_rule((L::DR + N + 2) / 2);
         psiProj.resize(rProj.w.size() * D::NP);
         for (size_t q = 0; q < rProj.w.size(); ++q) basis_eval(N, rProj.r[q], rProj.s[q], &psiProj[q * D::NP]);
     }
@@ -256,7 +259,7 @@ struct OpBuilder {
             P2d G = (1.0 / 3.0) * (W[0] + W[1] + W[2]);
             P2d wa = W[fp], wb = W[(fp + 1) % 3], wc = W[(fp + 2) % 3];
             P2d pcs[7][3] = {{G, wa, wb}, {G, wb, wc}, {G, wc, wa}};
-            if (N >= 2) {
+            if (L::NPC == 7) {
                 auto foot = [&](P2d p, P2d q) {
                     P2d d = q - p;
                     double t = dot(G - p, d) / dot(d, d);
@@ -272,7 +275,7 @@ struct OpBuilder {
                     for (int k = 0; k < 3; ++k) pcs[3 + p][k] = extra[p][k];
             }
             for (int p = 0; p < 3; ++p) cen[f][p] = (1.0 / 3.0) * (pcs[p][0] + pcs[p][1] + pcs[p][2]);
-            for (int p = 0; p < D::NPIECE; ++p) {
+            for (int p = 0; p < L::NPC; ++p) {
                 // average of psi_n of the source element
                 double acc[D::NP] = {0};
                 double wsum = 0, psi[D::NP];
@@ -284,7 +287,7 @@ struct OpBuilder {
                     for (int n = 0; n < D::NP; ++n) acc[n] += rN.w[q] * psi[n];
                     wsum += rN.w[q];
                 }
-                for (int n = 0; n < D::NP; ++n) op[L::AVG + (f * D::NPIECE + p) * D::NP + n] = acc[n] / wsum;
+                for (int n = 0; n < D::NP; ++n) op[L::AVG + (f * L::NPC + p) * D::NP + n] = acc[n] / wsum;
                 // scaled-monomial averages
                 double ma[14] = {0}, tmp[14];
                 wsum = 0;
@@ -322,24 +325,26 @@ struct OpBuilder {
                     for (int j = 0; j < 5; ++j) A[(p * 3 + f) * 5 + j] = mavg[f][p][j];
             valid &= pinv(9, 5, A, op + L::X3);
         }
-        if (N >= 2) {
-            // quartic level: rows S1, S2', S21, S3', S31 (pieces 0, 3, 4, 5, 6) x faces
+        if (L::FOUR) {
+            // top level on T4: rows S1, S2', S21, S3', S31 (pieces 0, 3, 4,
+            // 5, 6) x faces; columns the 14 quartic or the 9 cubic monomials
             const int pl[5] = {0, 3, 4, 5, 6};
+            const int nc = L::NT;
             double A[15 * 14];
             for (int k = 0; k < 5; ++k)
                 for (int f = 0; f < 3; ++f)
-                    for (int j = 0; j < 14; ++j) A[(k * 3 + f) * 14 + j] = mavg[f][pl[k]][j];
-            valid &= pinv(15, 14, A, op + L::X5);
+                    for (int j = 0; j < nc; ++j) A[(k * 3 + f) * nc + j] = mavg[f][pl[k]][j];
+            valid &= pinv(15, nc, A, op + L::X5);
         }
 
         // smoothness-indicator matrix
         {
             const int nm = mono.n;
             double B[14][14] = {{0}};
-            double ihp[D::DTOP + 1], ap[D::DTOP + 1];
+            double ihp[L::DR + 1], ap[L::DR + 1];
             ihp[0] = 1.0;
             ap[0] = 1.0 / area0;
-            for (int s = 1; s <= D::DTOP; ++s) {
+            for (int s = 1; s <= L::DR; ++s) {
                 ihp[s] = ihp[s - 1] / h0;
                 ap[s] = ap[s - 1] * area0;
             }
@@ -347,7 +352,7 @@ struct OpBuilder {
                 P2d x = map_tri(V0, rBeta.r[q], rBeta.s[q]);
                 double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
                 double wq = J0 * rBeta.w[q];
-                for (int s = 1; s <= D::DTOP; ++s)
+                for (int s = 1; s <= L::DR; ++s)
                     for (int a1 = 0; a1 <= s; ++a1) {
                         int a2 = s - a1;
                         double Dv[14];
@@ -381,7 +386,7 @@ struct OpBuilder {
                 mono_eval(map_tri(V0, rProj.r[q], rProj.s[q]), c0, h0, tmp);
                 for (int i = 1; i < D::NP; ++i)
                     for (int j = 0; j < mono.n; ++j)
-                        op[L::PM + (i - 1) * D::NMONO + j] += rProj.w[q] * tmp[j] * psiProj[q * D::NP + i];
+                        op[L::PM + (i - 1) * L::NM + j] += rProj.w[q] * tmp[j] * psiProj[q * D::NP + i];
             }
         }
         // linear weights gamma_bar_l = b^(l-1) (Section 3.2, Step 2): b = 1/h0,
@@ -393,11 +398,11 @@ struct OpBuilder {
     }
 };
 
-template <int N>
+template <int N, int QT>
 int build_ops_n(const HostMesh& m, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
                 int64_t& n_rank, int64_t& n_foot) {
-    using L = OpLayout<N>;
-    OpBuilder<N> b(m, constant_gamma, ghost_extrapolate);
+    using L = OpLayout<N, QT>;
+    OpBuilder<N, QT> b(m, constant_gamma, ghost_extrapolate);
     ops.assign((size_t)m.K * L::LEN, 0.0);
     unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
     std::vector<int64_t> rank(nt, 0), foot(nt, 0);
@@ -481,11 +486,20 @@ void build_tvb_ops(const HostMesh& m, std::vector<double>& A, int64_t& n_neg) {
     }
 }
 
-int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
+int build_limiter_ops(const HostMesh& m, int N, int qtop, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
                       int64_t& n_rank, int64_t& n_foot) {
-    if (N == 1) return build_ops_n<1>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
-    if (N == 2) return build_ops_n<2>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
-    if (N == 3) return build_ops_n<3>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+    auto by_top = [&](auto nc) {
+        constexpr int NN = decltype(nc)::value;
+        switch (qtop) {
+            case kTopQuadratic: return build_ops_n<NN, kTopQuadratic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+            case kTopCubic: return build_ops_n<NN, kTopCubic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+            case kTopCubicTel: return build_ops_n<NN, kTopCubicTel>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+            default: return build_ops_n<NN, kTopQuartic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+        }
+    };
+    if (N == 1) return build_ops_n<1, kTopQuadratic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+    if (N == 2) return by_top(std::integral_constant<int, 2>{});
+    if (N == 3) return by_top(std::integral_constant<int, 3>{});
     return CSWDG_EINVAL;
 }
 

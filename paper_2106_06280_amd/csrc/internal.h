@@ -62,7 +62,21 @@ int concat_meshes(const std::vector<HostMesh>& parts, HostMesh& out, std::vector
 
 // per-element limiter operators (host_ops.cpp); returns number of
 // rank-deficient elements and perpendicular feet that fell outside
-int build_limiter_ops(const HostMesh& m, int N, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
+// kTop* for degree N from the p2_top parameter: 0 the default reading of N
+// (the quadratic top for N = 2, the quartic for N = 3), 1 quadratic, 2
+// quartic, 3 the telescoping cubic, 4 the printed cubic
+inline int top_for(int N, int p2_top) {
+    if (N < 2) return kTopQuadratic;
+    switch (p2_top) {
+        case 1: return kTopQuadratic;
+        case 2: return kTopQuartic;
+        case 3: return kTopCubicTel;
+        case 4: return kTopCubic;
+        default: return N == 2 ? kTopQuadratic : kTopQuartic;
+    }
+}
+
+int build_limiter_ops(const HostMesh& m, int N, int qtop, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
                       int64_t& n_rank, int64_t& n_foot);
 // the TVB indicator's midpoint decomposition [9][K] (host_ops.cpp); n_neg
 // counts midpoints with no pair of nonnegative coefficients
@@ -101,7 +115,7 @@ struct LaunchCtx {
     int kxrcf_rms;         // KXRCF norm divided by |Delta|^(1/2)
     int char_comp;         // Euler limiting on the conserved variables
     int weights_linear;    // limiter weights omega = gamma
-    int p2_quadratic_top;  // N = 2: the N = 1 hierarchy (quadratic top member)
+    int qtop;  // N >= 2: top member of the hierarchy (kTop* below)
     int indicator;         // troubled-cell indicator: 0 KXRCF, 1 TVB minmod
     double tvb_m;          // TVB constant M
 };

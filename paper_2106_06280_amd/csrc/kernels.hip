@@ -973,7 +973,7 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // ---------------------------------------------------------------------------
 // CSWENO limiter (Section 3.2)
 // ---------------------------------------------------------------------------
-template <int EQ, int N, typename S, int QTOP = 0>
+template <int EQ, int N, typename S, int QTOP>
 __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict__ u,
                                                 const double* __restrict__ ops,
                                                 const int32_t* __restrict__ list,
@@ -982,8 +982,8 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
                                                 uint32_t* __restrict__ status, double gamma,
                                                 double eps, int comp, int lin) {
     using D = Dims<N>;
-    using LO = OpLayout<N>;
-    constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = D::NPIECE, NM = D::NMONO;
+    using LO = OpLayout<N, QTOP>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = LO::NPC, NM = LO::NM;
     constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
     constexpr int CPB = 64 / LPC;  // cells per block
     const int K = msh.K;
@@ -1096,7 +1096,9 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
         }
         // Step 1: least-squares levels (pseudo-inverses applied to
         // piece average - mean of Delta0)
-        double c2[2], c3[5], c5[NM];
+        constexpr bool quartic = LO::FOUR;  // a fourth member on T4
+        constexpr int NT = LO::NT > 0 ? LO::NT : 1;
+        double c2[2], c3[5], c5[NT];
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
             double s = 0.0;
@@ -1114,13 +1116,14 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
             c3[jj] = s;
         }
 #pragma unroll
-        for (int jj = 0; jj < NM; ++jj) c5[jj] = 0.0;
-        // N = 2 with QTOP: the hierarchy of N = 1 (quadratic top member)
-        constexpr bool quartic = (N >= 2) && !QTOP;
+        for (int jj = 0; jj < NT; ++jj) c5[jj] = 0.0;
+        // the top level on T4 for N >= 2 (QTOP = kTopQuadratic: the
+        // hierarchy of N = 1); the cubic readings fit 9 monomials, the
+        // quartic 14
         if constexpr (quartic) {
             constexpr int pl[5] = {0, 3, 4, 5, 6};
 #pragma unroll
-            for (int jj = 0; jj < 14; ++jj) {
+            for (int jj = 0; jj < NT; ++jj) {
                 double s = 0.0;
 #pragma unroll
                 for (int kk = 0; kk < 5; ++kk)
@@ -1134,7 +1137,7 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
         double beta[4];
         beta[1] = quad_form<NM, 2>(bp, c2);
         beta[2] = quad_form<NM, 5>(bp, c3);
-        beta[3] = quartic ? quad_form<NM, NM>(bp, c5) : 0.0;
+        beta[3] = quartic ? quad_form<NM, NT>(bp, c5) : 0.0;
         const double area0 = op[LO::AREA0];
         {
             double gx[3], gy[3], b1[3];
@@ -1198,12 +1201,20 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
                 const double o4 = g45 * (1.0 + tau / (eps + beta[3]));
                 const double os = o1 + o2 + o3 + o4;
                 const double w2 = o2 / os, w3 = o3 / os, w4 = o4 / os;
-                // p4 = (c5 - g25 p2 - g35 p3)/g45; collect the factors of c5, c3, c2
-                A5 = w4 / g45;
-                const double P3 = w3 - A5 * g35;  // factor of p3
-                A3 = P3 / g33;
-                const double P2 = w2 - A5 * g25 - A3 * g23;  // factor of p2
-                A2 = P2 / g22;
+                if constexpr (QTOP == kTopCubic) {
+                    // eq. equivalentOrder3: p4 = (c4 - g24 p2)/g34 with the
+                    // three weights gamma_{.,4} (equal to gamma_{.,3})
+                    A5 = w4 / g33;
+                    A3 = w3 / g33;
+                    A2 = (w2 - (w3 + w4) * (g23 / g33)) / g22;
+                } else {
+                    // p4 = (c5 - g25 p2 - g35 p3)/g45; collect the factors of c5, c3, c2
+                    A5 = w4 / g45;
+                    const double P3 = w3 - A5 * g35;  // factor of p3
+                    A3 = P3 / g33;
+                    const double P2 = w2 - A5 * g25 - A3 * g23;  // factor of p2
+                    A2 = P2 / g22;
+                }
             }
         }
         // Step 5: projection of R onto psi_1..psi_{Np-1}
@@ -1214,7 +1225,10 @@ __global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict
             double s = 0.0;
 #pragma unroll
             for (int jj = 0; jj < NM; ++jj) {
-                double r = A5 * c5[jj];
+                double r = 0.0;
+                if constexpr (quartic) {
+                    if (jj < NT) r = A5 * c5[jj];
+                }
                 if (jj < 5) r += A3 * c3[jj];
                 if (jj < 2) r += A2 * c2[jj];
                 s += pm[jj] * r;
@@ -1546,12 +1560,22 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
     if (g > 2048u) g = 2048u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        if (N >= 2 && c.p2_quadratic_top)
-            k_limiter<EQ, N, S, 1><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma,
-                                                             c.eps, c.char_comp, c.weights_linear);
+        const int qt = N >= 2 ? c.qtop : kTopQuartic;
+        if (N == 1)
+            k_limiter<EQ, N, S, kTopQuartic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                                       c.gamma, c.eps, c.char_comp, c.weights_linear);
+        else if (qt == kTopQuadratic)
+            k_limiter<EQ, N, S, kTopQuadratic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                                         c.gamma, c.eps, c.char_comp, c.weights_linear);
+        else if (qt == kTopCubic)
+            k_limiter<EQ, N, S, kTopCubic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                                     c.gamma, c.eps, c.char_comp, c.weights_linear);
+        else if (qt == kTopCubicTel)
+            k_limiter<EQ, N, S, kTopCubicTel><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                                        c.gamma, c.eps, c.char_comp, c.weights_linear);
         else
-            k_limiter<EQ, N, S, 0><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma,
-                                                             c.eps, c.char_comp, c.weights_linear);
+            k_limiter<EQ, N, S, kTopQuartic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                                       c.gamma, c.eps, c.char_comp, c.weights_linear);
     });
     return hipGetLastError();
 }

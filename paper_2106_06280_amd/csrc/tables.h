@@ -10,6 +10,17 @@
 
 namespace cswdg {
 
+// Top member of the N >= 2 reconstruction hierarchy (Section 3.2, Steps
+// 1-2 for P2).  The text builds p_4 from the cubic q_4 (eq.
+// equivalentOrder3, three weights gamma_{.,4}) and p_5 from the quartic q_5
+// (eq. equivalentOrder4) and then combines four members with gamma_{.,5}:
+//   kTopQuartic    p_top from q_5 by eq. equivalentOrder4 (four weights);
+//   kTopQuadratic  the three members of N = 1 (q_3 on top, gamma_{.,3});
+//   kTopCubic      p_4 from q_4 by eq. equivalentOrder3 as printed, the
+//                  members {p_1, p_2, p_3, p_4} combined with gamma_{.,5};
+//   kTopCubicTel   q_4 in place of q_5 in eq. equivalentOrder4.
+constexpr int kTopQuartic = 0, kTopQuadratic = 1, kTopCubic = 2, kTopCubicTel = 3;
+
 template <int N>
 struct Dims {
     static constexpr int NP = (N + 1) * (N + 2) / 2;
@@ -18,14 +29,6 @@ struct Dims {
     static constexpr int NE = (3 * N + 2) / 2;
     static constexpr int NI1 = N + 4;
     static constexpr int NQI = NI1 * NI1;
-    // limiter: degree of the top least-squares polynomial (quadratic for
-    // N = 1, quartic for N = 2, 3), number of scaled monomials of degree
-    // 1..DTOP, pieces per neighbour
-    static constexpr int DTOP = (N == 1) ? 2 : 4;
-    static constexpr int NMONO = (DTOP == 2) ? 5 : 14;
-    static constexpr int NPIECE = (N == 1) ? 3 : 7;
-    static constexpr int NTOPROWS = (N == 1) ? 9 : 15;
-    static constexpr int NBP = NMONO * (NMONO + 1) / 2;
 };
 
 // Per-degree device tables (constant memory).
@@ -54,22 +57,34 @@ struct TabF {
     float wPF[3][D::NE][D::NP];
 };
 
-// Layout of the per-element limiter operator record (doubles).
-template <int N>
+// Layout of the per-element limiter operator record (doubles) for degree N
+// and top member QT.  A hierarchy with a fourth member (N >= 2, QT not
+// kTopQuadratic) reads all seven pieces per neighbour (S1, S2, S3 and the
+// cut pieces S2', S21, S3', S31) and writes its reconstruction in the NT
+// monomials of the top level (9 cubic or 14 quartic); the three-member
+// hierarchy (N = 1, or kTopQuadratic) reads the three centroid pieces and
+// writes the reconstruction in the 5 monomials of degree 1..2.
+template <int N, int QT>
 struct OpLayout {
     using D = Dims<N>;
-    static constexpr int AVG = 0;                                  // [3][NPIECE][NP] subcell-average functionals
-    static constexpr int X2 = AVG + 3 * D::NPIECE * D::NP;         // [2][3]   pinv, linear level
-    static constexpr int X3 = X2 + 2 * 3;                          // [5][9]   pinv, quadratic level
-    static constexpr int X5 = X3 + 5 * 9;                          // [14][15] pinv, quartic level (N >= 2)
-    static constexpr int BP = X5 + ((N >= 2) ? 14 * 15 : 0);      // packed upper triangle of the beta matrix
-    static constexpr int MINV = BP + D::NBP;                      // [3][2][2] inverse centroid-difference matrices
-    static constexpr int PM = MINV + 12;                          // [NP-1][NMONO] projection onto psi_1..
-    static constexpr int GBASE = PM + (D::NP - 1) * D::NMONO;      // base b of the linear weights b^(l-1): 1/h0 or 10
-    static constexpr int AREA0 = GBASE + 1;                        // area of Delta0
-    static constexpr int VALID = AREA0 + 1;                        // 1 = full-rank stencil
+    static constexpr bool FOUR = (N >= 2) && QT != kTopQuadratic;
+    static constexpr int NT = !FOUR ? 0 : ((QT == kTopCubic || QT == kTopCubicTel) ? 9 : 14);
+    static constexpr int DR = !FOUR ? 2 : (NT == 9 ? 3 : 4);        // degree of the reconstruction
+    static constexpr int NPC = FOUR ? 7 : 3;                        // pieces per neighbour
+    static constexpr int NM = FOUR ? NT : 5;                        // monomials of the reconstruction
+    static constexpr int NBP = NM * (NM + 1) / 2;
+    static constexpr int AVG = 0;                                   // [3][NPC][NP] subcell-average functionals
+    static constexpr int X2 = AVG + 3 * NPC * D::NP;                // [2][3]   pinv, linear level
+    static constexpr int X3 = X2 + 2 * 3;                           // [5][9]   pinv, quadratic level
+    static constexpr int X5 = X3 + 5 * 9;                           // [NT][15] pinv, top level on T4
+    static constexpr int BP = X5 + NT * 15;                         // packed upper triangle of the beta matrix
+    static constexpr int MINV = BP + NBP;                           // [3][2][2] inverse centroid-difference matrices
+    static constexpr int PM = MINV + 12;                            // [NP-1][NM] projection onto psi_1..
+    static constexpr int GBASE = PM + (D::NP - 1) * NM;             // base b of the linear weights b^(l-1): 1/h0 or 10
+    static constexpr int AREA0 = GBASE + 1;                         // area of Delta0
+    static constexpr int VALID = AREA0 + 1;                         // 1 = full-rank stencil
     static constexpr int RAW = VALID + 1;
-    static constexpr int LEN = (RAW + 7) / 8 * 8;                  // padded to 64 bytes
+    static constexpr int LEN = (RAW + 7) / 8 * 8;                   // padded to 64 bytes
 };
 
 }  // namespace cswdg

@@ -6,11 +6,11 @@ meshes with 20, 40 and 80 squares per side, with and without the limiter
 on every cell (the paper's 'with limiter' columns).  The state is stepped
 on the GPU; the oracle only measures the error against the exact solution.
 The order of the finest pair must reach the printed order, or the design
-order N + 1 where the printed one is higher, within 0.25.
-
-Euler P2 with every cell limited is run with the quadratic top member of
-the N = 2 hierarchy (p2_top = 1): with the quartic top of the default
-reading its error grows under refinement."""
+order N + 1 where the printed one is higher, within 0.25.  Every case runs
+the library's default reading; P2 with every cell limited is refined to 160
+squares (320 for the vortex), where readings of the N = 2 hierarchy with a
+fourth member on the 16-piece stencil T4 diverge (kept visible below as
+expected failures)."""
 import math
 
 import numpy as np
@@ -68,18 +68,36 @@ CASES = [("burgers", 1, N, lim) for N in (1, 2, 3) for lim in (False, True)] + \
         [("vortex", 3, N, lim) for N in (1, 2, 3) for lim in (False, True)]
 
 
+def _sizes(problem, N, limit_all):
+    # the vortex (core radius about 1 on a domain of 10) needs the paper's
+    # finer pair, 10/80 and 10/160; P2 with every cell limited goes one
+    # refinement further
+    base = (40, 80, 160) if problem == "vortex" else (20, 40, 80)
+    if N == 2 and limit_all:
+        base = base + (2 * base[-1],)
+    return base
+
+
 @pytest.mark.parametrize("problem,table,N,limit_all", CASES)
 def test_convergence_order(torch, problem, table, N, limit_all):
-    p2_top = 1 if (problem in ("entropy", "vortex") and N == 2 and limit_all) else 0
-    # the vortex (core radius about 1 on a domain of 10) needs the paper's
-    # finer pair, 10/80 and 10/160
-    sizes = (40, 80, 160) if problem == "vortex" else (20, 40, 80)
-    errs = [_run(torch, problem, N, n, limit_all, p2_top) for n in sizes]
-    order = math.log(errs[1] / errs[2]) / math.log(2.0)
+    sizes = _sizes(problem, N, limit_all)
+    errs = [_run(torch, problem, N, n, limit_all) for n in sizes]
+    order = math.log(errs[-2] / errs[-1]) / math.log(2.0)
     printed = ORDERS[(table, N)][1 if limit_all else 0]
     print(f"{problem} P{N} limiter={limit_all}: errors {errs}, order {order:.3f} (paper {printed})", flush=True)
     assert order >= min(printed, N + 1) - 0.25
-    assert errs[0] > errs[1] > errs[2]
+    assert all(errs[i] > errs[i + 1] for i in range(len(errs) - 1))
+
+
+@pytest.mark.xfail(strict=True, reason="with every cell limited, the N = 2 readings that build a fourth member "
+                   "on the 16-piece stencil T4 (quartic q_5, the printed cubic p_4, the telescoping cubic) "
+                   "diverge under refinement for the Euler entropy wave (errors grow from 40 to 160 squares)")
+@pytest.mark.parametrize("p2_top", [2, 3, 4])
+def test_entropy_wave_p2_with_fourth_member_on_t4(torch, p2_top):
+    errs = [_run(torch, "entropy", 2, n, True, p2_top) for n in (20, 40, 80, 160)]
+    print(f"entropy P2 limiter p2_top={p2_top}: errors {errs}", flush=True)
+    assert all(np.isfinite(errs)) and errs[1] > errs[2] > errs[3]
+    assert math.log(errs[2] / errs[3]) / math.log(2.0) >= 2.65
 
 
 @pytest.mark.parametrize("problem,table,N", [("burgers", 1, 1), ("burgers", 1, 3), ("entropy", 2, 1),
@@ -89,8 +107,7 @@ def test_convergence_order_constant_gamma(torch, problem, table, N):
     (gamma_mode = 1) instead of (1/h)^(l-1): the design order is kept (the
     weights that Section 3.2, Step 2 replaces for the sake of the order
     estimate)."""
-    p2_top = 1 if N == 2 else 0
-    errs = [_run(torch, problem, N, n, True, p2_top, gamma_mode=1) for n in (20, 40, 80)]
+    errs = [_run(torch, problem, N, n, True, gamma_mode=1) for n in (20, 40, 80)]
     order = math.log(errs[1] / errs[2]) / math.log(2.0)
     printed = ORDERS[(table, N)][1]
     print(f"{problem} P{N} limiter, constant gamma: errors {errs}, order {order:.3f} (paper {printed})", flush=True)

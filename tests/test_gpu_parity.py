@@ -399,33 +399,41 @@ def test_global_lax_friedrichs_per_instance(torch):
         sol[0].dg_residual_vjp(us[0], us[0].clone())
 
 
+@pytest.mark.parametrize("p2_top", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("N", [2, 3])
 @pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
 @pytest.mark.parametrize("eq", [0, 1])
-def test_limiter_p2_quadratic_top(torch, eq, bc, N):
-    """p2_top = 1: the N = 2 (and N = 3) hierarchy with the quadratic top
-    member, every cell limited, and three KXRCF-limited steps, against the
-    oracle's quadratic_top reading."""
+def test_limiter_top_members(torch, eq, bc, N, p2_top):
+    """Every reading of the fourth member of the N >= 2 hierarchy (p2_top:
+    the default, the quadratic top, the quartic q_5, the telescoping cubic,
+    the printed cubic p_4 of eq. equivalentOrder3), every cell limited, and
+    three KXRCF-limited steps, against the oracle's reading of the same
+    name."""
     b = _binding()
+    top = b.top_name(N, p2_top)
     v, t = inputs.jittered_mesh(12, seed=171)
     M = Mesh(v, t, bc, (1.0, 1.0))
     dg = DG(M, N, eq)
-    S = b.Solver(eq, N, p2_top=1)
+    S = b.Solver(eq, N, p2_top=p2_top)
     S.mesh_upload(v, t, bc, (1.0, 1.0))
     for u in (_jump_state(dg, eq, seed=4), _smooth_state(dg, eq, seed=5)):
         out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
-        exp = csweno.limit(dg, u, np.ones(M.K, bool), quadratic_top=True)
+        exp = csweno.limit(dg, u, np.ones(M.K, bool), top=top)
         assert _relerr(S.to_host(out), exp) < TOL
     u = _jump_state(dg, eq, seed=6)
     ud = S.to_device(u)
-    lim = lambda w: csweno.limit(dg, w, kxrcf.indicator(dg, w)[1], quadratic_top=True)
+    lim = lambda w: csweno.limit(dg, w, kxrcf.indicator(dg, w)[1], top=top)
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
     assert _relerr(S.to_host(ud), u) < 1e-10
-    if eq == 1:
+
+
+def test_top_member_switch_rejects_bad_values(torch):
+    b = _binding()
+    for bad in (-1, 5):
         with pytest.raises(b.CswdgError):
-            S.dg_residual_vjp(ud, ud.clone())
+            b.Solver(1, 2, p2_top=bad)
 
 
 @pytest.mark.parametrize("eq,N", EQN)
@@ -451,7 +459,8 @@ def test_steps_constant_gamma(torch, N, top):
     M, dg, S = _case_opts(1, N, 14, BC_TRANSMISSIVE, seed=141, gamma_mode=1, p2_top=top)
     u = _jump_state(dg, 1, seed=19)
     ud = S.to_device(u)
-    lim = lambda v: csweno.limit(dg, v, kxrcf.indicator(dg, v)[1], quadratic_top=bool(top), constant_gamma=True)
+    lim = lambda v: csweno.limit(dg, v, kxrcf.indicator(dg, v)[1], top=_binding().top_name(N, top),
+                                 constant_gamma=True)
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
