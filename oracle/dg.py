@@ -179,6 +179,24 @@ class DG:
         self.time = t0 + dt
         return stages[-1]
 
+    def ssprk3_step_decisions(self, u, dt, indicator, limit):
+        """One step with the limiter limit(w, mask) applied to the cells
+        indicator(w) marks at each stage; returns (u^{n+1}, masks), the three
+        stages' troubled sets (the step's decisions, with dt)."""
+        masks = []
+
+        def lim(w):
+            m = np.asarray(indicator(w), dtype=bool)
+            masks.append(m)
+            return limit(w, m)
+        return self.ssprk3_step(u, dt, lim), masks
+
+    def ssprk3_step_frozen(self, u, dt, masks, limit):
+        """One step with dt and the three stages' troubled sets fixed: the map
+        whose derivative an adjoint with frozen decisions differentiates."""
+        it = iter(masks)
+        return self.ssprk3_step(u, dt, lambda w: limit(w, next(it)))
+
     # ------------------------------------------------------------------
     def errors(self, u, exact_fn, component=0, degree=None):
         """(L1, Linf) of u_h - exact over the domain (L1 divided by |D|)."""

@@ -50,18 +50,49 @@ def _state(dg, eq, jump, seed):
     return u
 
 
+class _Background:
+    """Four-quadrant jumps (rho, p in [0.6, 1.4], velocities in [-0.5, 0.5])
+    on a smooth background, so that no region is flat: a flat region's
+    smoothness indicators decay towards eps_WENO = 1e-10 within a few steps,
+    and there the weights switch on a scale below any difference step."""
+
+    def __init__(self, seed):
+        self.fq = inputs.FourQuadrant(seed=seed, xc=0.47, yc=0.53, rho_range=(0.6, 1.4), p_range=(0.6, 1.4),
+                                      vel_range=(-0.5, 0.5))
+
+    def __call__(self, x, y):
+        U = np.asarray(self.fq(x, y))
+        s = np.sin(2 * math.pi * x + 0.3) * np.cos(2 * math.pi * y + 0.7)
+        c = np.cos(2 * math.pi * (x + 2 * y))
+        rho = U[..., 0] * (1 + 0.2 * s)
+        return np.stack([rho, U[..., 1] + 0.1 * c * rho, U[..., 2] + 0.1 * s * rho, U[..., 3] * (1 + 0.2 * c)], -1)
+
+
 def _rel(a, b):
     return abs(a - b) / max(abs(a), abs(b), 1e-300)
 
 
-# The maps are piecewise smooth (the Lax-Friedrichs max, the WENO weights'
-# strong curvature): a central difference of step eps carries an O(eps^2)
-# truncation and is wrong whenever the step straddles a kink. Directions are
-# normalised to the state's norm and the check passes when the analytic value
-# agrees with the difference at one of a decreasing list of steps.
-# Each step also gives a Richardson value (4 D(e) - D(2e)) / 3, whose
-# truncation is O(eps^4).
-EPS = (1e-6, 1e-7, 1e-8, 1e-9)
+# Directional derivatives by central differences with Richardson
+# extrapolation at ONE fixed step: D(e) = (F(u + e v) - F(u - e v)) / 2e and
+# (4 D(e) - D(2e)) / 3, whose truncation is O(e^4).  Directions are
+# normalised to the state's norm, so e is relative.  The WENO weights and
+# sigma carry high powers of the smoothness indicators in ratios with small
+# denominators, so the maps curve strongly on the scale of the smallest
+# indicators: measured on these meshes, the plain difference's error falls
+# 100-fold per decade of e from about 1e-4 at e = 1e-6, and rounding takes
+# over below e = 1e-8; e = 1e-7 with Richardson lands between the two
+# (errors of 1e-9 to 1e-7 on smooth-background data).  The remaining kinks
+# (the Lax-Friedrichs max at edge points of nearly continuous data) each
+# move a difference by a relative amount of the order of the trace jump over
+# the number of edge points.
+EPS_FD = 1e-7
+
+
+def _fd(f, e=EPS_FD):
+    """f(e) = <w, F(u + e v) - F(u - e v)> (a difference, not two values)."""
+    d1 = f(e) / (2 * e)
+    d2 = f(2 * e) / (4 * e)
+    return (4 * d1 - d2) / 3
 
 
 def _direction(rng, u):
@@ -69,98 +100,132 @@ def _direction(rng, u):
     return v * (np.linalg.norm(u) / np.linalg.norm(v))
 
 
-def _best(lhs, f, eps_list=EPS):
-    errs = []
-    for e in eps_list:
-        d1 = f(e) / (2 * e)
-        d2 = f(2 * e) / (4 * e)
-        errs += [_rel(lhs, d1), _rel(lhs, (4 * d1 - d2) / 3)]
-    return min(errs), errs
-
-
 EQN = [(0, 1), (0, 2), (1, 1), (1, 2), (1, 3)]
 
 
 @pytest.mark.parametrize("eq,N", EQN)
 def test_residual_vjp(torch, eq, N):
+    """<L'(u)^T w, v> of the library against the oracle's directional
+    derivative of its residual (and the library's own), 4 directions."""
     M, dg, S = _case(eq, N, 10, BC_TRANSMISSIVE, seed=5)
     u = _state(dg, eq, True, seed=1)
     rng = np.random.default_rng(2)
-    v = _direction(rng, u)
-    w = rng.standard_normal(u.shape)
-    ud, vd, wd = S.to_device(u), S.to_device(v), S.to_device(w)
-    ub = S.to_host(S.dg_residual_vjp(ud, wd))
-    lhs = float(np.sum(ub * v))
-    # GPU forward
-    e_gpu = _best(lhs, lambda e: float(np.sum(w * (S.to_host(S.dg_residual(ud + e * vd))
-                                                   - S.to_host(S.dg_residual(ud - e * vd))))))
-    # oracle forward
-    e_orc = _best(lhs, lambda e: float(np.sum(w * (dg.residual(u + e * v) - dg.residual(u - e * v)))))
-    assert e_gpu[0] < 1e-6, e_gpu
-    assert e_orc[0] < 1e-6, e_orc
+    ud = S.to_device(u)
+    errs = []
+    for _ in range(4):
+        v = _direction(rng, u)
+        w = rng.standard_normal(u.shape)
+        vd, wd = S.to_device(v), S.to_device(w)
+        lhs = float(np.sum(S.to_host(S.dg_residual_vjp(ud, wd)) * v))
+        orc = _fd(lambda e: float(np.sum(w * (dg.residual(u + e * v) - dg.residual(u - e * v)))))
+        gpu = _fd(lambda e: float(np.sum(w * (S.to_host(S.dg_residual(ud + e * vd))
+                                              - S.to_host(S.dg_residual(ud - e * vd))))))
+        errs.append((_rel(lhs, orc), _rel(lhs, gpu)))
+    print(f"residual VJP eq={eq} N={N}: rel. err. against oracle / library differences {errs}", flush=True)
+    assert max(e for e, _ in errs) < 1e-6 and max(e for _, e in errs) < 1e-6, errs
 
 
 @pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
 @pytest.mark.parametrize("eq,N", EQN)
 def test_limiter_vjp(torch, eq, N, bc):
+    """<Lambda'(u)^T w, v> with the troubled set frozen against the oracle's
+    directional derivative of its limiter with that set (and the
+    library's), 4 directions."""
     M, dg, S = _case(eq, N, 10, bc, seed=7)
     u = _state(dg, eq, True, seed=3)
     mask = kxrcf.indicator(dg, u)[1]
     mask[::5] = True  # more troubled cells, some next to each other
-    rng = np.random.default_rng(4)
-    v = _direction(rng, u)
-    w = rng.standard_normal(u.shape)
     md = torch.from_numpy(mask.astype(np.uint8))
-    ud, vd, wd = S.to_device(u), S.to_device(v), S.to_device(w)
-    ub = S.to_host(S.csweno_limit_vjp(ud, wd, mask=md))
-    lhs = float(np.sum(ub * v))
+    rng = np.random.default_rng(4)
+    ud = S.to_device(u)
+    errs = []
+    for _ in range(4):
+        v = _direction(rng, u)
+        w = rng.standard_normal(u.shape)
+        vd, wd = S.to_device(v), S.to_device(w)
+        lhs = float(np.sum(S.to_host(S.csweno_limit_vjp(ud, wd, mask=md)) * v))
 
-    def gpu(e):
-        yp = S.to_host(S.csweno_limit(ud + e * vd, mask=md)[0])
-        ym = S.to_host(S.csweno_limit(ud - e * vd, mask=md)[0])
-        return float(np.sum(w * (yp - ym)))
+        def gpu(e):
+            yp = S.to_host(S.csweno_limit(ud + e * vd, mask=md)[0])
+            ym = S.to_host(S.csweno_limit(ud - e * vd, mask=md)[0])
+            return float(np.sum(w * (yp - ym)))
 
-    e_gpu = _best(lhs, gpu)
-    e_orc = _best(lhs, lambda e: float(np.sum(w * (csweno.limit(dg, u + e * v, mask)
-                                                   - csweno.limit(dg, u - e * v, mask)))))
-    assert e_gpu[0] < 1e-6, e_gpu
-    assert e_orc[0] < 1e-6, e_orc
+        orc = _fd(lambda e: float(np.sum(w * (csweno.limit(dg, u + e * v, mask) - csweno.limit(dg, u - e * v, mask)))))
+        errs.append((_rel(lhs, orc), _rel(lhs, _fd(gpu))))
+    print(f"limiter VJP eq={eq} N={N} bc={bc}: rel. err. against oracle / library differences {errs}", flush=True)
+    assert max(e for e, _ in errs) < 1e-6 and max(e for _, e in errs) < 1e-6, errs
 
 
-@pytest.mark.parametrize("eq,N", [(0, 1), (1, 2)])
-def test_step_vjp(torch, eq, N):
+def _oracle_trajectory(dg, u0, dts, masks):
+    """The oracle's steps with every step's dt and troubled sets fixed."""
+    lim = lambda w, m: csweno.limit(dg, w, m)
+    u = u0
+    for dt, ms in zip(dts, masks):
+        u = dg.ssprk3_step_frozen(u, dt, ms, lim)
+    return u
+
+
+def _oracle_decisions(dg, u0, nsteps):
+    """dt and the troubled sets of an unperturbed oracle trajectory."""
+    ind = lambda w: kxrcf.indicator(dg, w)[1]
+    lim = lambda w, m: csweno.limit(dg, w, m)
+    u, dts, masks = u0, [], []
+    for _ in range(nsteps):
+        dt = dg.max_dt(u)
+        u, ms = dg.ssprk3_step_decisions(u, dt, ind, lim)
+        dts.append(dt)
+        masks.append(ms)
+    return u, dts, masks
+
+
+@pytest.mark.parametrize("eq,N", EQN)
+def test_step_vjp_against_oracle(torch, eq, N):
+    """One SSP-RK3 step with KXRCF + CSWENO: the library's step VJP (tape of
+    its own decisions) against the oracle's directional derivative of its
+    step with the same dt and troubled sets frozen (the oracle's decisions
+    on the unperturbed state, equal to the library's: flags are bit-exact),
+    8 directions."""
     from paper_2106_06280_amd import adjoint
     M, dg, S = _case(eq, N, 12, BC_TRANSMISSIVE, seed=9)
     u = _state(dg, eq, True, seed=5)
-    rng = np.random.default_rng(6)
-    v = _direction(rng, u)
-    w = rng.standard_normal(u.shape)
-    ud, vd, wd = S.to_device(u), S.to_device(v), S.to_device(w)
+    uo, dts, masks = _oracle_decisions(dg, u, 1)
+    ud = S.to_device(u)
     uT, tapes = adjoint.record(S, ud, 1)
-    ub = S.to_host(S.ssprk3_step_vjp(tapes[0], wd))
-    lhs = float(np.sum(ub * v))
-
-    def gpu(e):
-        yp = S.to_host(adjoint.replay(S, ud + e * vd, tapes))
-        ym = S.to_host(adjoint.replay(S, ud - e * vd, tapes))
-        return float(np.sum(w * (yp - ym)))
-
-    err = _best(lhs, gpu)
-    assert err[0] < 1e-6, err
+    assert _rel_state(S.to_host(uT), uo) < 1e-10
+    assert sum(int(m.sum()) for m in masks[0]) > 0
+    rng = np.random.default_rng(6)
+    errs = []
+    for _ in range(8):
+        v = _direction(rng, u)
+        w = rng.standard_normal(u.shape)
+        lhs = float(np.sum(S.to_host(S.ssprk3_step_vjp(tapes[0], S.to_device(w))) * v))
+        orc = _fd(lambda e: float(np.sum(w * (_oracle_trajectory(dg, u + e * v, dts, masks)
+                                              - _oracle_trajectory(dg, u - e * v, dts, masks)))))
+        errs.append(_rel(lhs, orc))
+    print(f"step VJP eq={eq} N={N}: rel. err. against the oracle's frozen step {sorted(errs)}", flush=True)
+    assert max(errs) < 1e-6, errs
     # the recorded step equals the plain step bit for bit
     u2 = ud.clone()
     S.ssprk3_step(u2)
     assert torch.equal(u2, uT)
 
 
-def test_trajectory_gradient_against_finite_differences(torch):
-    """Loss = 1/2 int (rho_h(T) - rho*)^2 over a 6-step trajectory with
-    checkpoints every 2 steps; directional derivatives along 8 normalised
-    random directions against central differences with the recorded dt and
-    troubled sets."""
+def _rel_state(a, b):
+    return max(np.abs(a[:, c] - b[:, c]).max() / max(np.abs(b[:, c]).max(), 1e-300) for c in range(b.shape[1]))
+
+
+@pytest.mark.parametrize("nsteps", [6, 20])
+def test_trajectory_gradient_against_oracle(torch, nsteps):
+    """Loss = 1/2 int (rho_h(T) - rho*)^2 after nsteps steps of P2 Euler
+    (KXRCF + CSWENO, the default reading; four-quadrant jumps on a smooth
+    background, 288 elements) with checkpoints every 2 steps
+    (every 10 for 20 steps): the library's gradient along 16 (6 for 20
+    steps) normalised random directions against the oracle's directional derivative of the
+    same trajectory with its dt and troubled sets frozen (the oracle's own
+    decisions on the unperturbed run)."""
     from paper_2106_06280_amd import adjoint
     M, dg, S = _case(1, 2, 12, BC_TRANSMISSIVE, seed=11)
-    u0 = _state(dg, 1, True, seed=7)
+    u0 = dg.project(_Background(7))
     target = dg.project(lambda x, y: 1.0 + 0.3 * np.sin(2 * math.pi * (x + 2 * y) + 0.4))[:, 0, :]
     Jd = torch.from_numpy(M.J).cuda()
     tgt = torch.from_numpy(np.ascontiguousarray(target.T)).cuda()  # [Np, K]
@@ -169,49 +234,54 @@ def test_trajectory_gradient_against_finite_differences(torch):
         return 0.5 * torch.sum(Jd * (uT[0] - tgt) ** 2)
 
     ud = S.to_device(u0).requires_grad_(True)
-    uT = adjoint.trajectory(S, ud, 6, checkpoint_every=2)
-    L = loss(uT)
-    L.backward()
-    g = ud.grad.detach()
-    _, tapes = adjoint.record(S, ud.detach(), 6)
-    scale = float(torch.linalg.norm(ud.detach()))
+    uT = adjoint.trajectory(S, ud, nsteps, checkpoint_every=2 if nsteps <= 6 else 10)
+    loss(uT).backward()
+    g = S.to_host(ud.grad)  # [K, m, Np]
+    uo, dts, masks = _oracle_decisions(dg, u0, nsteps)
+    assert _rel_state(S.to_host(uT.detach()), uo) < 1e-9
+
+    def dloss(up, um):
+        # L(+) - L(-) in factored form, rho rows of the [K, m, Np] states
+        a, b = up[:, 0, :], um[:, 0, :]
+        return float(0.5 * np.sum(M.J[:, None] * (a - b) * (a + b - 2.0 * target)))
+
     rng = np.random.default_rng(8)
-    worst = 0.0
-    for _ in range(8):
-        d = torch.from_numpy(rng.standard_normal(tuple(ud.shape))).cuda()
-        d *= scale / torch.linalg.norm(d)
-        an = float(torch.sum(g * d))
-
-        def fd(e):
-            return float(loss(adjoint.replay(S, ud.detach() + e * d, tapes))) - \
-                float(loss(adjoint.replay(S, ud.detach() - e * d, tapes)))
-
-        worst = max(worst, _best(an, fd)[0])
-    assert worst < 1e-6, worst
+    errs = []
+    for _ in range(16 if nsteps <= 6 else 6):
+        d = _direction(rng, u0)
+        an = float(np.sum(g * d))
+        orc = _fd(lambda e: dloss(_oracle_trajectory(dg, u0 + e * d, dts, masks),
+                                  _oracle_trajectory(dg, u0 - e * d, dts, masks)))
+        errs.append(_rel(an, orc))
+    errs = sorted(errs)
+    print(f"trajectory gradient, {nsteps} steps: rel. err. against the oracle, all directions {errs}", flush=True)
+    assert errs[-1] < 1e-6, errs
 
 
 def test_gradient_full_size_p2_euler_100k(torch):
-    """P2 Euler on 100,352 triangles (n = 224), four-quadrant data projected
-    on the basis (rho, p in [0.6, 1.4], velocities in [-0.5, 0.5]; the
-    full-range draw of this seed gives negative pressure at face points where
-    a quadrant line meets the transmissive boundary within the first step, in
-    the oracle as in the library, and the method has no positivity limiter),
-    KXRCF + CSWENO after every stage. Loss = 1/2 int (rho_h(T) - rho*)^2 with
-    a seeded smooth target.
+    """The differentiation workload's mesh: P2 Euler on 100,352 triangles
+    (n = 224), KXRCF + CSWENO after every stage, loss = 1/2 int (rho_h(T) -
+    rho*)^2 with a seeded smooth target.
 
-    * 50 steps, state checkpointed every 10: the gradient equals the plain
-      chain of 50 step VJPs over recorded tapes bit for bit.
-    * 2 steps, a checkpoint every step: the gradient along 32 normalised
-      random directions against central differences of the replayed
-      trajectory (recorded dt and troubled sets). The differences' own error
-      falls as eps^2 with a large constant (the WENO weights switch on the
-      scale of eps_WENO = 1e-10 in the smoothness indicators) until it meets
-      the rounding floor near 1e-6 at eps = 1e-10 of the state's norm, so the
-      bar is 1e-6 on the median direction and 1e-5 on every direction (with
-      Richardson extrapolation). Longer horizons are not checkable this way:
-      the derivative of the frozen-decision map grows with the number of
-      steps (gradient norm 7e-3, 1e-1 and 3e2 after 5, 20 and 50 steps
-      here) while the neighbourhood in which it is linear shrinks."""
+    * Four-quadrant data projected on the basis (rho, p in [0.6, 1.4],
+      velocities in [-0.5, 0.5]; the full-range draw of this seed gives
+      negative pressure at face points where a quadrant line meets the
+      transmissive boundary within the first step, and the method has no
+      positivity limiter): 50 steps with the state checkpointed every 10
+      give the gradient of the plain chain of 50 step VJPs over recorded
+      tapes bit for bit (each step VJP is checked against the oracle's
+      frozen step above).
+    * The same jumps on a smooth background (no flat region): the gradient
+      along 32 normalised random directions against central differences with
+      Richardson extrapolation at one fixed step (1e-8 of the state's
+      norm) of the library's replayed trajectory (recorded dt and troubled sets;
+      the oracle is too slow at this size, its check is the 288-element
+      trajectory test), after 2 and 10 steps; every direction reported; the
+      bar of 1e-6 on every direction holds after 2 steps (after 10, 25 of
+      32 directions are within it and the rest within 1e-5).  After 50 steps the map is no longer linear on the scale
+      of any resolvable step (the differences' error still falls 100-fold
+      per decade of the step at 1e-8, where rounding begins), so the 50-step
+      gradient rests on the bitwise chain above."""
     from paper_2106_06280_amd import adjoint, binding
     n, seed = 224, 1005
     v, t = inputs.jittered_mesh(n, seed=seed)
@@ -247,26 +317,42 @@ def test_gradient_full_size_p2_euler_100k(torch):
     assert torch.equal(yb, g50)
     del tapes
 
-    # 2 steps against central differences
-    ud = u0.clone().requires_grad_(True)
-    loss(adjoint.trajectory(S, ud, 2, checkpoint_every=1)).backward()
-    g = ud.grad.detach()
-    _, tapes = adjoint.record(S, u0, 2)
-    scale = float(torch.linalg.norm(u0))
-    rng = np.random.default_rng(seed + 1)
-    errs = []
-    for _ in range(32):
-        d = torch.from_numpy(rng.standard_normal(tuple(u0.shape))).cuda()
-        d *= scale / torch.linalg.norm(d)
-        an = float(torch.sum(g * d))
+    u0 = S.project_fn(_Background(seed))
+    # the step of the differences: at this size the map curves more
+    # strongly than on the 288-element mesh (smaller cells, smaller
+    # smoothness indicators), and with more edge points a step of 1e-7 more
+    # often straddles a Lax-Friedrichs kink; 1e-8 is still above the
+    # rounding floor of the factored loss difference (measured)
+    STEP = {2: 1e-8, 10: 1e-8}
+    worst = {}
+    for H in (2, 10):
+        ud = u0.clone().requires_grad_(True)
+        loss(adjoint.trajectory(S, ud, H, checkpoint_every=min(H, 10))).backward()
+        g = ud.grad.detach()
+        _, tapes = adjoint.record(S, u0, H)
+        scale = float(torch.linalg.norm(u0))
+        rng = np.random.default_rng(seed + 1)
+        errs = []
+        for _ in range(32):
+            d = torch.from_numpy(rng.standard_normal(tuple(u0.shape))).cuda()
+            d *= scale / torch.linalg.norm(d)
+            an = float(torch.sum(g * d))
 
-        def fd(e):
-            # L(+) - L(-) in factored form, free of the cancellation of two
-            # nearly equal sums over 2.4 M terms
-            a = adjoint.replay(S, u0 + e * d, tapes)[0]
-            b = adjoint.replay(S, u0 - e * d, tapes)[0]
-            return float(0.5 * torch.sum(Jd * torch.sum((a - b) * (a + b - 2.0 * tgt), dim=0)))
+            def fd(e):
+                # L(+) - L(-) in factored form, free of the cancellation of
+                # two nearly equal sums over 2.4 M terms
+                pa = adjoint.replay(S, u0 + e * d, tapes)[0]
+                pb = adjoint.replay(S, u0 - e * d, tapes)[0]
+                return float(0.5 * torch.sum(Jd * torch.sum((pa - pb) * (pa + pb - 2.0 * tgt), dim=0)))
 
-        errs.append(_best(an, fd, (1e-7, 1e-8, 1e-9, 1e-10))[0])
-    errs = sorted(errs)
-    assert errs[16] < 1e-6 and errs[-1] < 1e-5, (errs[16], errs[-4:])
+            errs.append(_rel(an, _fd(fd, STEP[H])))
+        del tapes
+        errs = sorted(errs)
+        worst[H] = errs[-1]
+        print(f"100k trajectory gradient, {H} steps: |grad| {float(torch.linalg.norm(g)):.3e}, rel. err. "
+              f"of 32 directions {['%.1e' % x for x in errs]}", flush=True)
+    # the bar (1e-6 on every direction) holds after 2 steps; after 10 steps
+    # a quarter of the directions lie between 1e-6 and 1e-5 (the curvature
+    # and the kinks at this size), which is recorded and guarded, not the bar
+    assert worst[2] < 1e-6, worst
+    assert worst[10] < 2e-5, worst
