@@ -247,13 +247,35 @@ TapeView tape_view(const cswdg_solver* s, void* tape) {
     return v;
 }
 
+// Test hook: CSWDG_FAIL_ADJOINT_ALLOC=i (1..3) makes the allocation of the
+// i-th adjoint buffer fail, so that the recovery below can be exercised.
+bool adjoint_alloc_fails(int i) {
+    const char* v = std::getenv("CSWDG_FAIL_ADJOINT_ALLOC");
+    return v != nullptr && std::atoi(v) == i + 1;
+}
+
+// The three adjoint buffers are allocated together: on any failure the ones
+// that were allocated are freed and all three reset, so a later call retries
+// from scratch instead of launching with a missing buffer.
 int ensure_adjoint_scratch(cswdg_solver* s) {
-    if (s->d_slot) return CSWDG_OK;
+    if (s->d_slot && s->d_contrib && s->d_V) return CSWDG_OK;
     const size_t K = (size_t)s->mesh.K;
-    if (hipMalloc((void**)&s->d_slot, sizeof(int32_t) * K) != hipSuccess ||
-        hipMalloc((void**)&s->d_contrib, sizeof(double) * 4 * s->state_elems) != hipSuccess ||
-        hipMalloc(&s->d_V, sizeof(double) * s->state_elems) != hipSuccess)
+    void** bufs[3] = {(void**)&s->d_slot, (void**)&s->d_contrib, (void**)&s->d_V};
+    const size_t bytes[3] = {sizeof(int32_t) * K, sizeof(double) * 4 * s->state_elems,
+                             sizeof(double) * s->state_elems};
+    bool ok = true;
+    for (int i = 0; i < 3 && ok; ++i) {
+        if (*bufs[i]) continue;
+        ok = !adjoint_alloc_fails(i) && hipMalloc(bufs[i], bytes[i]) == hipSuccess;
+        if (!ok) *bufs[i] = nullptr;
+    }
+    if (!ok) {
+        for (int i = 0; i < 3; ++i) {
+            if (*bufs[i]) (void)hipFree(*bufs[i]);
+            *bufs[i] = nullptr;
+        }
         return fail(s, CSWDG_ENOMEM, "adjoint scratch allocation failed");
+    }
     return CSWDG_OK;
 }
 

@@ -356,3 +356,28 @@ def test_gradient_full_size_p2_euler_100k(torch):
     # and the kinks at this size), which is recorded and guarded, not the bar
     assert worst[2] < 1e-6, worst
     assert worst[10] < 2e-5, worst
+
+
+@pytest.mark.parametrize("which", [1, 2, 3])
+def test_adjoint_scratch_allocation_failure_recovers(torch, which, monkeypatch):
+    """The limiter VJP's three scratch buffers are allocated together: when
+    the allocation of one fails (forced from the host through the library's
+    CSWDG_FAIL_ADJOINT_ALLOC hook, before any kernel is launched) the call
+    returns CSWDG_ENOMEM, and the next call allocates all three and gives the
+    result of a solver that never failed."""
+    from paper_2106_06280_amd import binding
+    M, dg, S = _case(1, 2, 8, BC_PERIODIC, seed=13)
+    u = _state(dg, 1, True, seed=2)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(u.shape)
+    ud, wd = S.to_device(u), S.to_device(w)
+    mask = torch.ones(M.K, dtype=torch.uint8, device="cuda")
+    monkeypatch.setenv("CSWDG_FAIL_ADJOINT_ALLOC", str(which))
+    with pytest.raises(binding.CswdgError) as ei:
+        S.csweno_limit_vjp(ud, wd, mask=mask)
+    assert "allocation" in str(ei.value)
+    monkeypatch.delenv("CSWDG_FAIL_ADJOINT_ALLOC")
+    got = S.csweno_limit_vjp(ud, wd, mask=mask)
+    _, _, S2 = _case(1, 2, 8, BC_PERIODIC, seed=13)
+    ref = S2.csweno_limit_vjp(S2.to_device(u), S2.to_device(w), mask=mask)
+    assert torch.equal(got, ref)
