@@ -311,6 +311,21 @@ int cswdg_kxrcf(cswdg_solver* s, const void* u, uint8_t* flags, double* R);
 int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* flags_out,
                        const uint8_t* mask_in);
 
+/* cswdg_csweno_limit for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but the call's
+ * scratch (troubled-list counters, troubled list, compact limiter results)
+ * is a static device array of 64 MiB that every GPU the library runs on
+ * holds until the process ends, instead of the solver's buffers; no
+ * allocation of any kind.  Limit: 1024 + 32 K (rounded up to 256 bytes) +
+ * 8 K m Np bytes must fit in 64 MiB (K <= 299,000 elements for P2 Euler,
+ * 1.2 M for P1 Burgers); larger meshes: CSWDG_EINVAL with a message.  The
+ * counters are cleared by a kernel at every call.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from different solvers) race. */
+int cswdg_csweno_limit_noalloc(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* flags_out,
+                               const uint8_t* mask_in);
+
 /* One stage of the table:tvd third-order RK (end of Section 3) followed by
  * the limiter: out = a u_n + b (u_prev + dt L(u_prev)) with
  * (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 1, 2, 3, then limited

@@ -57,6 +57,7 @@ _SIGS = {
     "cswdg_max_dt": (ctypes.c_int, [_P, _P, _P]),
     "cswdg_kxrcf": (ctypes.c_int, [_P, _P, _P, _P]),
     "cswdg_csweno_limit": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "cswdg_csweno_limit_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "cswdg_rk_stage": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P]),
     "cswdg_ssprk3_step": (ctypes.c_int, [_P, _P, _P]),
     "cswdg_last_dt": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
@@ -378,6 +379,16 @@ class Solver:
         self._st(u_in, "u_in")
         self._st(u_out, "u_out")
         self._c(lib().cswdg_csweno_limit(self.h, _ptr(u_in), _ptr(u_out), _ptr(flags), _ptr(m)))
+        return u_out, flags
+
+    def csweno_limit_noalloc(self, u_in, u_out, flags, mask=None):
+        """cswdg_csweno_limit_noalloc: u_out and flags (device uint8 [K])
+        are the caller's; the library allocates nothing."""
+        m = self._mask(mask)
+        self._st(u_in, "u_in")
+        self._st(u_out, "u_out")
+        self._dev(flags, "flags", (self.K,), self.torch.uint8)
+        self._c(lib().cswdg_csweno_limit_noalloc(self.h, _ptr(u_in), _ptr(u_out), _ptr(flags), _ptr(m)))
         return u_out, flags
 
     def rk_stage(self, stage, u_n, u_prev, out, dt):

@@ -177,29 +177,49 @@ size_t elem_bytes(const cswdg_solver* s) { return s->p.precision == 1 ? sizeof(f
 
 // limit `buf` in place: troubled list from mask or KXRCF, limiter reading
 // `src` (the pre-limit field), scatter into buf
-int limit_into(cswdg_solver* s, const void* src, void* buf, uint8_t* flags_out, const uint8_t* mask,
-               int mode, bool count_zeroed) {
+// The limiter's per-call scratch: troubled-list counters, list, compact
+// results (the solver's own buffers, or the static array of the
+// allocation-free entry point).
+struct LimScratch {
+    uint32_t* count;
+    int32_t* list;
+    double* compact;
+};
+
+LimScratch solver_scratch(cswdg_solver* s) { return {s->d_count, s->d_list, s->d_compact}; }
+
+// limit `buf` in place: troubled list from mask or KXRCF, limiter reading
+// `src` (the pre-limit field), scatter into buf.  Launches are timed through
+// the solver's event pool unless untimed is set (the allocation-free path).
+int limit_into_with(cswdg_solver* s, const LimScratch& w, const void* src, void* buf, uint8_t* flags_out,
+                    const uint8_t* mask, int mode, bool count_zeroed, bool untimed) {
     hipError_t e;
     const int K = (int)s->mesh.K;
     if (mode == CSWDG_LIMIT_NONE) return CSWDG_OK;
     uint8_t* flags = flags_out ? flags_out : s->d_flags;
+    auto run = [&](int kid, auto&& f) { return untimed ? f() : timed(s, kid, f); };
     if (!count_zeroed) {
-        e = timed(s, KID_ZERO, [&] { return launch_zero_u32(s->ctx, s->d_count, kCountWords); });
+        e = run(KID_ZERO, [&] { return launch_zero_u32(s->ctx, w.count, kCountWords); });
         if (e != hipSuccess) return hipfail(s, e, "zero");
     }
     if (mask || mode == CSWDG_LIMIT_ALL) {
-        e = timed(s, KID_COMPACT, [&] { return launch_compact_mask(s->ctx, K, mask, flags, s->d_list, s->d_count); });
+        e = run(KID_COMPACT, [&] { return launch_compact_mask(s->ctx, K, mask, flags, w.list, w.count); });
     } else {
-        e = timed(s, KID_KXRCF, [&] { return launch_kxrcf(s->ctx, s->dm, src, flags, nullptr, s->d_list, s->d_count); });
+        e = run(KID_KXRCF, [&] { return launch_kxrcf(s->ctx, s->dm, src, flags, nullptr, w.list, w.count); });
     }
     if (e != hipSuccess) return hipfail(s, e, "troubled-cell list");
-    e = timed(s, KID_LIMITER, [&] {
-        return launch_limiter(s->ctx, s->dm, src, s->d_ops, s->d_list, s->d_count, s->d_compact, s->d_status, K);
+    e = run(KID_LIMITER, [&] {
+        return launch_limiter(s->ctx, s->dm, src, s->d_ops, w.list, w.count, w.compact, s->d_status, K);
     });
     if (e != hipSuccess) return hipfail(s, e, "limiter");
-    e = timed(s, KID_SCATTER, [&] { return launch_scatter(s->ctx, K, buf, s->d_list, s->d_count, s->d_compact, K, s->d_tstats); });
+    e = run(KID_SCATTER, [&] { return launch_scatter(s->ctx, K, buf, w.list, w.count, w.compact, K, s->d_tstats); });
     if (e != hipSuccess) return hipfail(s, e, "scatter");
     return CSWDG_OK;
+}
+
+int limit_into(cswdg_solver* s, const void* src, void* buf, uint8_t* flags_out, const uint8_t* mask,
+               int mode, bool count_zeroed) {
+    return limit_into_with(s, solver_scratch(s), src, buf, flags_out, mask, mode, count_zeroed, false);
 }
 
 // the global Lax-Friedrichs constants of u, for a residual of u (lf_mode = 1)
@@ -333,6 +353,8 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         if (std::find(g_dev_tables.begin(), g_dev_tables.end(), dev) == g_dev_tables.end()) {
             int rc = upload_tables_device();
             if (rc != CSWDG_OK) return fail(nullptr, rc, "constant table upload failed");
+            rc = init_noalloc_scratch();
+            if (rc != CSWDG_OK) return fail(nullptr, rc, "address of the allocation-free scratch not available");
             g_dev_tables.push_back(dev);
         }
     }
@@ -636,6 +658,30 @@ int cswdg_csweno_limit(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* 
     if (e != hipSuccess) return hipfail(s, e, "copy");
     int mode = mask_in ? CSWDG_LIMIT_KXRCF : (s->p.limiter_mode == CSWDG_LIMIT_ALL ? CSWDG_LIMIT_ALL : CSWDG_LIMIT_KXRCF);
     return limit_into(s, u_in, u_out, flags_out, mask_in, mode, false);
+}
+
+int cswdg_csweno_limit_noalloc(cswdg_solver* s, const void* u_in, void* u_out, uint8_t* flags_out,
+                               const uint8_t* mask_in) {
+    int rc = check_ready(s);
+    if (rc) return rc;
+    if (!u_in || !u_out || u_in == u_out) return fail(s, CSWDG_EINVAL, "u_in and u_out must be distinct non-null buffers");
+    const size_t K = (size_t)s->mesh.K;
+    // the troubled list has kListSegs segments of capacity K (as the
+    // solver's own list), the compact results one row per element
+    const size_t compact_off = (kNoAllocListOffset + sizeof(int32_t) * K * kListSegs + 255) / 256 * 256;
+    const size_t need = compact_off + sizeof(double) * K * (size_t)s->M * (size_t)s->NP;
+    if (need > kNoAllocScratchBytes)
+        return fail(s, CSWDG_EINVAL,
+                    "mesh too large for the allocation-free limiter: it needs " + std::to_string(need) +
+                        " bytes of scratch, the static array holds " + std::to_string(kNoAllocScratchBytes));
+    unsigned char* base = (unsigned char*)noalloc_scratch(s->device);
+    if (!base) return fail(s, CSWDG_ESTATE, "allocation-free scratch not initialised on this device");
+    const LimScratch w = {(uint32_t*)base, (int32_t*)(base + kNoAllocListOffset), (double*)(base + compact_off)};
+    const size_t bytes = elem_bytes(s) * s->state_elems;
+    hipError_t e = hipMemcpyAsync(u_out, u_in, bytes, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hipfail(s, e, "copy");
+    int mode = mask_in ? CSWDG_LIMIT_KXRCF : (s->p.limiter_mode == CSWDG_LIMIT_ALL ? CSWDG_LIMIT_ALL : CSWDG_LIMIT_KXRCF);
+    return limit_into_with(s, w, u_in, u_out, flags_out, mask_in, mode, false, true);
 }
 
 int cswdg_rk_stage(cswdg_solver* s, int stage, const void* u_n, const void* u_prev, void* out, const double* dt_dev) {

@@ -121,6 +121,19 @@ struct LaunchCtx {
 };
 
 int upload_tables_device();   // once per device (both translation units)
+
+// Scratch of cswdg_csweno_limit_noalloc (a static device array in
+// kernels.hip): init_noalloc_scratch() takes its address on the current
+// device (once per device, at solver creation); noalloc_scratch(device)
+// returns that address (nullptr before).  Layout: the troubled-list counters
+// (kCountWords u32) at 0, the list (int32 [kListSegs][K], as the solver's
+// own) at kNoAllocListOffset, the compact results (double [K][m][Np]) at the
+// next 256-byte boundary.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr size_t kNoAllocListOffset = 1024;
+constexpr int kMaxDevices = 64;
+int init_noalloc_scratch();
+void* noalloc_scratch(int device);
 int upload_tables_adjoint();  // the adjoint unit's copy of the tables
 
 // residual (mode 0) or RK stage 1..3; dt read from device; reset (may be

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <mutex>
 
 #include "device_common.h"
 
@@ -1431,6 +1432,38 @@ __global__ __launch_bounds__(256) void k_project(int K, int m, const double* __r
 
 int ic_points_per_element(int N) {
     return N == 1 ? Dims<1>::NQI : (N == 2 ? Dims<2>::NQI : Dims<3>::NQI);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free limiter entry point: the troubled-list
+// counters, the troubled list and the compact limiter results live in one
+// static device array (each device the library runs on holds its own copy
+// for the life of the process).  Host code never names the array in a launch:
+// init_noalloc_scratch() takes its device address once per device (with that
+// device current) and the entry point passes that address to the kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int init_noalloc_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CSWDG_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (g_scratch_ptr[dev] != nullptr) return CSWDG_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return CSWDG_EHIP;
+    g_scratch_ptr[dev] = ptr;
+    return CSWDG_OK;
+}
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    return g_scratch_ptr[device];
 }
 
 int upload_tables_device() {
