@@ -16,6 +16,17 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
+def steps_tol(nsteps):
+    """Bar of free-running multi-step comparisons: every stage reproduces the
+    oracle's stage from the same input within TOL (tested separately), and
+    from the second stage on each side starts from its own rounding of the
+    previous one; the step maps are stable (no measured amplification above
+    O(1) per stage), so the differences add up to at most the number of
+    stages times TOL."""
+    return 3 * nsteps * TOL
+
+
+
 @pytest.fixture(scope="module")
 def torch():
     t = pytest.importorskip("torch")
@@ -146,7 +157,7 @@ def test_steps_with_boundary_kinds(torch):
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
     assert S.status() & 0x7 == 0
 
 
@@ -229,7 +240,7 @@ def test_forward_step_steps(torch, N):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
     assert flagged > 0
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(6), _relerr(S.to_host(ud), u)
     assert S.status() & 0x3 == 0
 
 
@@ -286,7 +297,7 @@ def test_periodic_in_y_only_steps(torch, N):
     for _ in range(4):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(4), _relerr(S.to_host(ud), u)
     assert S.status() & 0x3 == 0
 
 
@@ -388,7 +399,7 @@ def test_moving_shock_steps(torch, N):
     for _ in range(4):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(4), _relerr(S.to_host(ud), u)
     assert abs(S.time()[0] - dg.time) <= 1e-15 * dg.time
     assert S.status() & 0x3 == 0
 
@@ -454,7 +465,7 @@ def test_extrapolated_ghost_with_walls_and_steps(torch, N):
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
     from paper_2106_06280_amd import binding
     with pytest.raises(binding.CswdgError):
         binding.Solver(1, N, ghost_mode=2)

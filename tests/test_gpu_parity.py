@@ -19,6 +19,17 @@ from paper_2106_06280_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+
+
+def steps_tol(nsteps):
+    """Bar of free-running multi-step comparisons: every stage reproduces the
+    oracle's stage from the same input within TOL (tested separately), and
+    from the second stage on each side starts from its own rounding of the
+    previous one; the step maps are stable (no measured amplification above
+    O(1) per stage), so the differences add up to at most the number of
+    stages times TOL."""
+    return 3 * nsteps * TOL
+
 TIE = 1e-9
 
 
@@ -187,7 +198,7 @@ def test_rk_stages_parity(torch, eq, N):
         out = S.empty_state()
         S.rk_stage(i, d_stages[0], S.to_device(stages[-1]), out, dtd)
         got = S.to_host(out)
-        assert _relerr(got, exp) < 1e-11, i
+        assert _relerr(got, exp) < TOL, (i, _relerr(got, exp))
         stages.append(exp)
 
 
@@ -201,7 +212,7 @@ def test_ssprk3_steps_euler_p2(torch):
         u = dg.ssprk3_step(u, dt, lim)
         S.ssprk3_step(ud)
     got = S.to_host(ud)
-    assert _relerr(got, u) < 1e-10
+    assert _relerr(got, u) < steps_tol(3), _relerr(got, u)
     assert S.status() & 0x7 == 0
 
 
@@ -368,7 +379,7 @@ def test_steps_global_lax_friedrichs(torch, eq, N):
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
     assert S.status() & 0x7 == 0
 
 
@@ -426,7 +437,7 @@ def test_limiter_top_members(torch, eq, bc, N, p2_top):
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
 
 
 def test_top_member_switch_rejects_bad_values(torch):
@@ -464,7 +475,7 @@ def test_steps_constant_gamma(torch, N, top):
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
     b = _binding()
     with pytest.raises(b.CswdgError):
         b.Solver(1, N, gamma_mode=2)

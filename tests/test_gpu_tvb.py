@@ -15,6 +15,19 @@ from oracle.dg import DG
 from oracle.mesh import BC_PERIODIC, BC_TRANSMISSIVE, Mesh
 from paper_2106_06280_amd import inputs
 
+TOL = 1e-12
+
+
+def steps_tol(nsteps):
+    """Bar of free-running multi-step comparisons: every stage reproduces the
+    oracle's stage from the same input within TOL (tested separately), and
+    from the second stage on each side starts from its own rounding of the
+    previous one; the step maps are stable (no measured amplification above
+    O(1) per stage), so the differences add up to at most the number of
+    stages times TOL."""
+    return 3 * nsteps * TOL
+
+
 pytestmark = pytest.mark.gpu
 
 TIE = 1e-9
@@ -123,7 +136,7 @@ def test_steps_with_tvb_indicator(torch, eq, N):
     for _ in range(3):
         u = dg.ssprk3_step(u, dg.max_dt(u), lim)
         S.ssprk3_step(ud)
-    assert _relerr(S.to_host(ud), u) < 1e-10
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
     assert S.status() & 0x3 == 0
 
 
