@@ -429,6 +429,8 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
 
     R dt = R(0);
     if (MODE != 0) dt = (R)dtp[inst_of(msh, e)];
+    // u^n and the output are streamed once: non-temporal accesses keep them
+    // from evicting the u^(i-1) lines that neighbouring elements re-read
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
@@ -440,11 +442,11 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
             } else if (MODE == 1) {
                 v = U[c][i] + dt * acc[c][i];
             } else if (MODE == 2) {
-                v = R(0.75) * un[idx] + R(0.25) * (U[c][i] + dt * acc[c][i]);
+                v = R(0.75) * __builtin_nontemporal_load(&un[idx]) + R(0.25) * (U[c][i] + dt * acc[c][i]);
             } else {
-                v = R(1.0 / 3.0) * un[idx] + R(2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
+                v = R(1.0 / 3.0) * __builtin_nontemporal_load(&un[idx]) + R(2.0 / 3.0) * (U[c][i] + dt * acc[c][i]);
             }
-            out[idx] = v;
+            __builtin_nontemporal_store(v, &out[idx]);
         }
 }
 
@@ -974,8 +976,16 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // ---------------------------------------------------------------------------
 // CSWENO limiter (Section 3.2)
 // ---------------------------------------------------------------------------
+// waves per SIMD the limiter is compiled for: four for the three-member
+// hierarchies (no spills beyond a few bytes), two for a fourth member on T4
+// (its quartic least-squares level needs more registers)
+template <int N, int QTOP>
+struct LimWaves {
+    static constexpr int value = OpLayout<N, QTOP>::FOUR ? 2 : 4;
+};
+
 template <int EQ, int N, typename S, int QTOP>
-__global__ __launch_bounds__(64) void k_limiter(DevMesh msh, const S* __restrict__ u,
+__global__ __launch_bounds__(64, (LimWaves<N, QTOP>::value)) void k_limiter(DevMesh msh, const S* __restrict__ u,
                                                 const double* __restrict__ ops,
                                                 const int32_t* __restrict__ list,
                                                 const uint32_t* __restrict__ count,
@@ -1587,10 +1597,12 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
                           int max_cells) {
     const unsigned bs = 64;
     const int lpc = c.eq == 1 ? LimLanes<1>::LPC : LimLanes<0>::LPC;
-    // 2,048 one-wave blocks fill the chip once at the limiter's register
-    // count; more blocks only add empty ones when few cells are troubled
+    // at four waves per SIMD, 4,096 one-wave blocks are resident at once;
+    // up to 16,384 blocks so that every troubled cell's wave is in flight
+    // (each wave's cells form one chain of dependent loads); blocks beyond
+    // the troubled count exit at once
     unsigned g = grid_for(max_cells, bs / lpc);
-    if (g > 2048u) g = 2048u;
+    if (g > 16384u) g = 16384u;
     if (g == 0) g = 1;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
         const int qt = N >= 2 ? c.qtop : kTopQuartic;
