@@ -19,8 +19,9 @@ periodic; half Euler, transmissive), triangle counts log-uniform in
 [2000, 60000] (seed 1004), smooth-plus-jump initial data; each equation's
 instances form one disjoint-union mesh; the residual schedule is autotuned;
 K steps of both solvers are captured into one HIP graph and timed as one
-graph launch (after one untimed launch), then checked bit for bit against
-the same steps run eagerly.
+graph launch (after one untimed launch; each equation's solver is one
+branch of the graph, so the two advance concurrently), then checked bit for
+bit against the same steps run eagerly.
 
 --workload p2_euler_ffstep: the flow over a forward-facing step (Section 4,
 Example 6): tunnel [0,4] x [0,1], step of height 0.2 from x = 1, 82,280
@@ -211,6 +212,14 @@ def run_batch(args):
     torch.cuda.synchronize()
     secs_eager = ev0.elapsed_time(ev1) / 1000.0
     same = all(torch.equal(a, b) for a, b in zip(eager, states))
+    # per-kernel breakdown of each equation's solver: 3 more eager steps with
+    # every launch timed (outside the timed region)
+    for S, u, d in zip(solvers, eager, info):
+        S.profile(True)
+        for _ in range(3):
+            S.ssprk3_step(u)
+        d["kernel_ms_per_step"] = {k: round(a / 3, 4) for k, (a, b) in S.kernel_times().items() if b}
+        S.profile(False)
     dof = sum(d["dof"] for d in info)
     value = dof * 3 * args.steps / secs
     for d, fr in zip(info, f):

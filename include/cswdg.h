@@ -398,10 +398,12 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
                    int32_t* n_cand);
 /* Record nsteps SSP-RK3 steps (cswdg_ssprk3_step with dt computed per step)
  * of each of n solvers on its state states[i] (device, state layout, fixed
- * for the life of the graph), in the order step-major then solver, into one
- * HIP graph.  Capture runs on a private stream after waiting for the
- * solvers' streams; nothing is computed.  The schedule and limiter mode in
- * force at capture are used by every launch. */
+ * for the life of the graph) into one HIP graph: each solver's steps form
+ * one branch (captured on a private stream of default priority, forked from
+ * and joined to the first by events), so the solvers advance concurrently.
+ * Solvers and states must be distinct (CSWDG_EINVAL otherwise).  Capture
+ * waits for the solvers' streams; nothing is computed.  The schedule and
+ * limiter mode in force at capture are used by every launch. */
 int cswdg_graph_capture(int32_t n, cswdg_solver* const* solvers, void* const* states, int32_t nsteps,
                         cswdg_graph** out);
 /* Enqueue the recorded steps on hip_stream (NULL = default stream): each

@@ -978,29 +978,55 @@ int cswdg_graph_capture(int32_t n, cswdg_solver* const* solvers, void* const* st
         int rc = check_ready(solvers[i]);
         if (rc) return rc;
         if (solvers[i]->device != solvers[0]->device) return fail(nullptr, CSWDG_EINVAL, "solvers on different devices");
+        for (int j = 0; j < i; ++j)
+            if (solvers[j] == solvers[i] || states[j] == states[i])
+                return fail(nullptr, CSWDG_EINVAL, "the solvers and their states must be distinct (their branches run concurrently)");
     }
-    // capture on a private stream of default priority; the members' work is
-    // ordered before the capture by a full device wait
-    hipStream_t cs = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) return fail(nullptr, CSWDG_EHIP, "capture stream");
+    // capture on private streams of default priority, one per solver: the
+    // solvers are independent (own state, own scratch), so each one's steps
+    // form a branch of the graph (forked from and joined to the first
+    // stream by events) and the branches run concurrently; the members'
+    // earlier work is ordered before the capture by a full wait
+    std::vector<hipStream_t> cs(n, nullptr);
+    std::vector<hipEvent_t> ev(n, nullptr);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&cs[i], hipStreamNonBlocking);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    auto release = [&]() {
+        for (int i = 0; i < n; ++i) {
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+            if (cs[i]) (void)hipStreamDestroy(cs[i]);
+        }
+    };
+    if (e != hipSuccess) {
+        release();
+        return fail(nullptr, CSWDG_EHIP, "capture streams");
+    }
     for (int i = 0; i < n && e == hipSuccess; ++i) e = hipStreamSynchronize(solvers[i]->stream);
     std::vector<hipStream_t> saved(n);
     std::vector<bool> prof(n);
     for (int i = 0; i < n; ++i) {
         saved[i] = solvers[i]->stream;
         prof[i] = solvers[i]->prof;
-        solvers[i]->stream = cs;
-        solvers[i]->ctx.stream = cs;
+        solvers[i]->stream = cs[i];
+        solvers[i]->ctx.stream = cs[i];
         solvers[i]->prof = false;
     }
     int rc = CSWDG_OK;
     hipGraph_t graph = nullptr;
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int t = 0; t < nsteps && rc == CSWDG_OK; ++t)
-            for (int i = 0; i < n && rc == CSWDG_OK; ++i) rc = cswdg_ssprk3_step(solvers[i], states[i], nullptr);
-        hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        // fork: every other stream joins the capture behind an event of the first
+        if (n > 1) e = hipEventRecord(ev[0], cs[0]);
+        for (int i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs[i], ev[0], 0);
+        for (int i = 0; i < n && rc == CSWDG_OK && e == hipSuccess; ++i)
+            for (int t = 0; t < nsteps && rc == CSWDG_OK; ++t) rc = cswdg_ssprk3_step(solvers[i], states[i], nullptr);
+        // join: the first stream waits for every branch
+        for (int i = 1; i < n && e == hipSuccess; ++i) {
+            e = hipEventRecord(ev[i], cs[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs[0], ev[i], 0);
+        }
+        hipError_t e2 = hipStreamEndCapture(cs[0], &graph);
         if (e == hipSuccess) e = e2;
     }
     for (int i = 0; i < n; ++i) {
@@ -1013,7 +1039,7 @@ int cswdg_graph_capture(int32_t n, cswdg_solver* const* solvers, void* const* st
     size_t nodes = 0;
     if (rc == CSWDG_OK && e == hipSuccess) e = hipGraphGetNodes(graph, nullptr, &nodes);
     if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cs);
+    release();
     if (rc != CSWDG_OK) {
         if (exec) (void)hipGraphExecDestroy(exec);
         return rc;
