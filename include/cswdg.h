@@ -149,6 +149,18 @@ typedef struct cswdg_params {
      * states.  With 1, cswdg_set_boundary rebuilds the stencil operators
      * (synchronous, host work proportional to K). */
     int ghost_mode;
+    /* the reconstruction on the subcell stencils (the paper's stencils work
+     * with any WENO reconstruction, Sections 1 and 5): 0 the Zhu-Shu
+     * hierarchical reconstruction of Section 3.2 (the paper's); 1 a type-I
+     * WENO reconstruction (N = 1, 2 only): degree-N least-squares fits on a
+     * central stencil (the nine centroid subcells of the three neighbours)
+     * and on three sectors (the six of two neighbours), each with the mean
+     * of Delta0 exact, combined with weights lambda_k / (1e-14 + beta_k)^4
+     * (lambda 1e5 central, 1 sectors; beta of eq. smoothnessIndicator);
+     * the boundary ghosts are those of the hierarchical one (the mirror image
+     * and the boundary kinds, ghost_mode 0).  N = 3, ghost_mode 1 or the
+     * adjoint calls with 1: CSWDG_EINVAL. */
+    int reconstruction;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream

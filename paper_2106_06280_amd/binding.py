@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("c_k", ctypes.c_double), ("eps_weno", ctypes.c_double), ("kxrcf_norm", ctypes.c_int),
                 ("char_mode", ctypes.c_int), ("weights_mode", ctypes.c_int), ("positivity", ctypes.c_int),
                 ("lf_mode", ctypes.c_int), ("p2_top", ctypes.c_int), ("indicator", ctypes.c_int),
-                ("tvb_m", ctypes.c_double), ("gamma_mode", ctypes.c_int), ("ghost_mode", ctypes.c_int)]
+                ("tvb_m", ctypes.c_double), ("gamma_mode", ctypes.c_int), ("ghost_mode", ctypes.c_int),
+                ("reconstruction", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -149,6 +150,8 @@ def host_tvb_decomposition(vxy, tri, bc, period=(0.0, 0.0)):
 # p2_top values (Section 3.2, Steps 1-2 for P2: the fourth member of the
 # N >= 2 hierarchy) and the oracle's name of each reading
 TOP_DEFAULT, TOP_QUADRATIC, TOP_QUARTIC, TOP_CUBIC_TEL, TOP_CUBIC = 0, 1, 2, 3, 4
+# reconstruction values: the paper's hierarchical WENO, or type-I WENO
+RECON_HIERARCHICAL, RECON_TYPE1 = 0, 1
 TOP_NAMES = {TOP_QUADRATIC: "quadratic", TOP_QUARTIC: "quartic", TOP_CUBIC_TEL: "cubic_tel", TOP_CUBIC: "cubic"}
 
 
@@ -167,11 +170,12 @@ class Solver:
 
     def __init__(self, equation, degree, limiter_mode=LIMIT_KXRCF, precision=0, gamma=1.4, cfl=0.0,
                  c_k=0.0, eps=0.0, stream=None, kxrcf_norm=0, char_mode=0, weights_mode=0, positivity=0,
-                 lf_mode=0, p2_top=0, indicator=INDICATOR_KXRCF, tvb_m=0.0, gamma_mode=0, ghost_mode=0):
+                 lf_mode=0, p2_top=0, indicator=INDICATOR_KXRCF, tvb_m=0.0, gamma_mode=0, ghost_mode=0,
+                 reconstruction=0):
         import torch
         self.torch = torch
         p = Params(equation, degree, precision, limiter_mode, gamma, cfl, c_k, eps, kxrcf_norm, char_mode,
-                   weights_mode, positivity, lf_mode, p2_top, indicator, tvb_m, gamma_mode, ghost_mode)
+                   weights_mode, positivity, lf_mode, p2_top, indicator, tvb_m, gamma_mode, ghost_mode, reconstruction)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -165,6 +165,8 @@ int check_single(cswdg_solver* s) {
     if (s->p.indicator != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the KXRCF indicator (indicator = 0)");
     if (s->p.gamma_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the linear weights (1/h)^(l-1) (gamma_mode = 0)");
     if (s->p.ghost_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the mirror ghost (ghost_mode = 0)");
+    if (s->p.reconstruction != 0)
+        return fail(s, CSWDG_EINVAL, "adjoint calls take the hierarchical reconstruction (reconstruction = 0)");
     return CSWDG_OK;
 }
 
@@ -340,6 +342,9 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         return fail(nullptr, CSWDG_EINVAL, "tvb_m must be finite and >= 0");
     if (p.gamma_mode < 0 || p.gamma_mode > 1) return fail(nullptr, CSWDG_EINVAL, "gamma_mode must be 0 or 1");
     if (p.ghost_mode < 0 || p.ghost_mode > 1) return fail(nullptr, CSWDG_EINVAL, "ghost_mode must be 0 or 1");
+    if (p.reconstruction < 0 || p.reconstruction > 1) return fail(nullptr, CSWDG_EINVAL, "reconstruction must be 0 or 1");
+    if (p.reconstruction == 1 && (p.degree > 2 || p.ghost_mode != 0))
+        return fail(nullptr, CSWDG_EINVAL, "the type-I reconstruction takes N = 1, 2 and the mirror ghost (ghost_mode = 0)");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
         return fail(nullptr, CSWDG_EINVAL, "the positivity scaling is defined for the Euler equations");
     if (!(p.gas_gamma > 0)) p.gas_gamma = 1.4;
@@ -382,6 +387,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.char_comp = p.char_mode;
     s->ctx.weights_linear = p.weights_mode;
     s->ctx.qtop = top_for(p.degree, p.p2_top);
+    s->ctx.recon = p.reconstruction;
     s->ctx.indicator = p.indicator;
     s->ctx.tvb_m = p.tvb_m;
     *out = s;
@@ -1137,7 +1143,9 @@ int upload_mesh(cswdg_solver* s) {
     int rc;
     const int64_t K = s->mesh.K;
     std::vector<double> ops;
-    rc = build_limiter_ops(s->mesh, s->p.degree, s->ctx.qtop, s->p.gamma_mode == 1, s->p.ghost_mode == 1, ops, s->n_rank,
+    rc = s->p.reconstruction == 1
+             ? build_type1_ops(s->mesh, s->p.degree, ops, s->n_rank)
+             : build_limiter_ops(s->mesh, s->p.degree, s->ctx.qtop, s->p.gamma_mode == 1, s->p.ghost_mode == 1, ops, s->n_rank,
                            s->n_foot);
     if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");
     std::vector<double> tvbA;

@@ -421,7 +421,240 @@ int build_ops_n(const HostMesh& m, bool constant_gamma, bool ghost_extrapolate, 
     return CSWDG_OK;
 }
 
+// The record of the type-I reconstruction (OpLayoutT1): the same stencil
+// geometry as the hierarchical one (centroid subcells only), least-squares
+// pseudo-inverses of degree N on the central stencil and the three sectors.
+template <int N>
+struct OpBuilderT1 {
+    using D = Dims<N>;
+    using L = OpLayoutT1<N>;
+    const HostMesh& m;
+    std::vector<double> C;
+    Rule2D rN, rTop, rBeta, rProj;
+    std::vector<double> psiProj;
+    MonoList mono{N};
+
+    explicit OpBuilderT1(const HostMesh& mm) : m(mm) {
+        basis_monomial_form(N, C);
+        rN = triangle_rule((N + 2) / 2);
+        rTop = triangle_rule((N + 2) / 2);
+        rBeta = triangle_rule(N > 1 ? N : 1);
+        rProj = triangle_rule(N + 1);
+        psiProj.resize(rProj.w.size() * D::NP);
+        for (size_t q = 0; q < rProj.w.size(); ++q) basis_eval(N, rProj.r[q], rProj.s[q], &psiProj[q * D::NP]);
+    }
+
+    P2d vert(int64_t e, int k) const { return {m.vx[k * m.K + e], m.vy[k * m.K + e]}; }
+
+    void psi_mono(double r, double s, double* psi) const {
+        double pw[D::NP];
+        int k = 0;
+        for (int d = 0; d <= N; ++d)
+            for (int bb = 0; bb <= d; ++bb) {
+                double v = 1.0;
+                for (int t = 0; t < d - bb; ++t) v *= r;
+                for (int t = 0; t < bb; ++t) v *= s;
+                pw[k++] = v;
+            }
+        for (int n = 0; n < D::NP; ++n) {
+            double acc = 0;
+            for (int kk = 0; kk < D::NP; ++kk) acc += C[n * D::NP + kk] * pw[kk];
+            psi[n] = acc;
+        }
+    }
+
+    void to_ref(int64_t src, P2d x, double& r, double& s) const {
+        P2d v0 = vert(src, 0), v1 = vert(src, 1), v2 = vert(src, 2);
+        double xr = 0.5 * (v1.x - v0.x), xs = 0.5 * (v2.x - v0.x);
+        double yr = 0.5 * (v1.y - v0.y), ys = 0.5 * (v2.y - v0.y);
+        double J = xr * ys - xs * yr;
+        double dx = x.x - v0.x, dy = x.y - v0.y;
+        r = -1.0 + (ys * dx - xs * dy) / J;
+        s = -1.0 + (-yr * dx + xr * dy) / J;
+    }
+
+    static P2d map_tri(const P2d* T, double r, double s) {
+        return T[0] + (0.5 * (1.0 + r)) * (T[1] - T[0]) + (0.5 * (1.0 + s)) * (T[2] - T[0]);
+    }
+
+    void mono_eval(P2d x, P2d c0, double h0, double* out) const {
+        double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
+        for (int j = 0; j < mono.n; ++j) {
+            double v = 1.0;
+            for (int t = 0; t < mono.a[j]; ++t) v *= xi;
+            for (int t = 0; t < mono.b[j]; ++t) v *= eta;
+            out[j] = v;
+        }
+    }
+
+    bool build(int64_t e, double* op) const {
+        constexpr int NM = L::NM;
+        for (int i = 0; i < L::LEN; ++i) op[i] = 0.0;
+        P2d V0[3] = {vert(e, 0), vert(e, 1), vert(e, 2)};
+        P2d c0 = (1.0 / 3.0) * (V0[0] + V0[1] + V0[2]);
+        double h0 = (std::sqrt(dot(V0[1] - V0[0], V0[1] - V0[0])) + std::sqrt(dot(V0[2] - V0[1], V0[2] - V0[1])) +
+                     std::sqrt(dot(V0[0] - V0[2], V0[0] - V0[2]))) / 3.0;
+        double area0 = tri_area(V0[0], V0[1], V0[2]);
+        double J0 = 0.5 * area0;
+        double mavg0[5] = {0}, tmp[5];
+        {
+            double wsum = 0;
+            for (size_t q = 0; q < rTop.w.size(); ++q) {
+                mono_eval(map_tri(V0, rTop.r[q], rTop.s[q]), c0, h0, tmp);
+                for (int j = 0; j < NM; ++j) mavg0[j] += rTop.w[q] * tmp[j];
+                wsum += rTop.w[q];
+            }
+            for (int j = 0; j < NM; ++j) mavg0[j] /= wsum;
+        }
+        double mavg[3][3][5];
+        for (int f = 0; f < 3; ++f) {
+            uint8_t inf = m.info[3 * e + f];
+            bool mirror = false;
+            P2d shift{0.0, 0.0}, P{0, 0}, Q{0, 0}, W[3];
+            int fp;
+            int64_t src;
+            if (inf & 0x40) {
+                mirror = true;
+                P = V0[f];
+                Q = V0[(f + 1) % 3];
+                P2d d = Q - P;
+                P2d X = V0[(f + 2) % 3];
+                P2d F = P + (dot(X - P, d) / dot(d, d)) * d;
+                W[0] = Q;
+                W[1] = P;
+                W[2] = 2.0 * F - X;
+                fp = 0;
+                src = e;
+            } else {
+                int cx = (inf >> 2) & 3, cy = (inf >> 4) & 3;
+                shift = {cx == 1 ? m.px : (cx == 2 ? -m.px : 0.0), cy == 1 ? m.py : (cy == 2 ? -m.py : 0.0)};
+                src = m.nbr[3 * e + f];
+                for (int k = 0; k < 3; ++k) W[k] = vert(src, k) + shift;
+                fp = inf & 3;
+            }
+            auto back = [&](P2d x) {
+                if (!mirror) return x - shift;
+                P2d d = Q - P;
+                P2d F = P + (dot(x - P, d) / dot(d, d)) * d;
+                return 2.0 * F - x;
+            };
+            P2d G = (1.0 / 3.0) * (W[0] + W[1] + W[2]);
+            P2d wa = W[fp], wb = W[(fp + 1) % 3], wc = W[(fp + 2) % 3];
+            P2d pcs[3][3] = {{G, wa, wb}, {G, wb, wc}, {G, wc, wa}};
+            for (int p = 0; p < 3; ++p) {
+                double acc[D::NP] = {0}, psi[D::NP], wsum = 0;
+                for (size_t q = 0; q < rN.w.size(); ++q) {
+                    double r, s;
+                    to_ref(src, back(map_tri(pcs[p], rN.r[q], rN.s[q])), r, s);
+                    psi_mono(r, s, psi);
+                    for (int n = 0; n < D::NP; ++n) acc[n] += rN.w[q] * psi[n];
+                    wsum += rN.w[q];
+                }
+                for (int n = 0; n < D::NP; ++n) op[L::AVG + (f * 3 + p) * D::NP + n] = acc[n] / wsum;
+                double ma[5] = {0};
+                wsum = 0;
+                for (size_t q = 0; q < rTop.w.size(); ++q) {
+                    mono_eval(map_tri(pcs[p], rTop.r[q], rTop.s[q]), c0, h0, tmp);
+                    for (int j = 0; j < NM; ++j) ma[j] += rTop.w[q] * tmp[j];
+                    wsum += rTop.w[q];
+                }
+                for (int j = 0; j < NM; ++j) mavg[f][p][j] = ma[j] / wsum - mavg0[j];
+            }
+        }
+        bool valid = true;
+        {
+            double A[9 * 5];
+            for (int p = 0; p < 3; ++p)
+                for (int f = 0; f < 3; ++f)
+                    for (int j = 0; j < NM; ++j) A[(p * 3 + f) * NM + j] = mavg[f][p][j];
+            valid &= pinv(9, NM, A, op + L::XC);
+        }
+        for (int k = 0; k < 3; ++k) {
+            const int fa[2] = {k, (k + 1) % 3};
+            double A[6 * 5];
+            for (int p = 0; p < 3; ++p)
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < NM; ++j) A[(p * 2 + i) * NM + j] = mavg[fa[i]][p][j];
+            valid &= pinv(6, NM, A, op + L::XS + k * NM * 6);
+        }
+        // smoothness matrix over derivative orders 1..N
+        {
+            double B[5][5] = {{0}};
+            double ihp[N + 1], ap[N + 1];
+            ihp[0] = 1.0;
+            ap[0] = 1.0 / area0;
+            for (int sd = 1; sd <= N; ++sd) {
+                ihp[sd] = ihp[sd - 1] / h0;
+                ap[sd] = ap[sd - 1] * area0;
+            }
+            for (size_t q = 0; q < rBeta.w.size(); ++q) {
+                P2d x = map_tri(V0, rBeta.r[q], rBeta.s[q]);
+                double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
+                double wq = J0 * rBeta.w[q];
+                for (int sd = 1; sd <= N; ++sd)
+                    for (int a1 = 0; a1 <= sd; ++a1) {
+                        int a2 = sd - a1;
+                        double Dv[5];
+                        for (int j = 0; j < NM; ++j) {
+                            int a = mono.a[j], b = mono.b[j];
+                            if (a < a1 || b < a2) {
+                                Dv[j] = 0;
+                                continue;
+                            }
+                            double coef = 1.0;
+                            for (int t = 0; t < a1; ++t) coef *= (a - t);
+                            for (int t = 0; t < a2; ++t) coef *= (b - t);
+                            double v = coef * ihp[sd];
+                            for (int t = 0; t < a - a1; ++t) v *= xi;
+                            for (int t = 0; t < b - a2; ++t) v *= eta;
+                            Dv[j] = v;
+                        }
+                        double sc = ap[sd] * wq;
+                        for (int i = 0; i < NM; ++i)
+                            for (int j = 0; j < NM; ++j) B[i][j] += sc * Dv[i] * Dv[j];
+                    }
+            }
+            int k = 0;
+            for (int i = 0; i < NM; ++i)
+                for (int j = i; j < NM; ++j) op[L::BP + k++] = B[i][j];
+        }
+        for (size_t q = 0; q < rProj.w.size(); ++q) {
+            mono_eval(map_tri(V0, rProj.r[q], rProj.s[q]), c0, h0, tmp);
+            for (int i = 1; i < D::NP; ++i)
+                for (int j = 0; j < NM; ++j) op[L::PM + (i - 1) * NM + j] += rProj.w[q] * tmp[j] * psiProj[q * D::NP + i];
+        }
+        op[L::AREA0] = area0;
+        op[L::VALID] = valid ? 1.0 : 0.0;
+        return valid;
+    }
+};
+
+template <int N>
+int build_ops_t1(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank) {
+    using L = OpLayoutT1<N>;
+    OpBuilderT1<N> b(m);
+    ops.assign((size_t)m.K * L::LEN, 0.0);
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<int64_t> rank(nt, 0);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int64_t e = t; e < m.K; e += nt)
+                if (!b.build(e, &ops[(size_t)e * L::LEN])) ++rank[t];
+        });
+    for (auto& x : th) x.join();
+    n_rank = 0;
+    for (unsigned t = 0; t < nt; ++t) n_rank += rank[t];
+    return CSWDG_OK;
+}
+
 }  // namespace
+
+int build_type1_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank) {
+    if (N == 1) return build_ops_t1<1>(m, ops, n_rank);
+    if (N == 2) return build_ops_t1<2>(m, ops, n_rank);
+    return CSWDG_EINVAL;
+}
 
 // TVB minmod indicator (Cockburn and Shu's limiter for triangles): for each
 // element (centroid b0) and face midpoint m_i, coefficients A[3 i + f] with

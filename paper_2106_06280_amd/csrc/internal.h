@@ -76,6 +76,9 @@ inline int top_for(int N, int p2_top) {
     }
 }
 
+// the per-element record of the type-I reconstruction (OpLayoutT1, N = 1, 2)
+int build_type1_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank);
+
 int build_limiter_ops(const HostMesh& m, int N, int qtop, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
                       int64_t& n_rank, int64_t& n_foot);
 // the TVB indicator's midpoint decomposition [9][K] (host_ops.cpp); n_neg
@@ -116,6 +119,7 @@ struct LaunchCtx {
     int char_comp;         // Euler limiting on the conserved variables
     int weights_linear;    // limiter weights omega = gamma
     int qtop;  // N >= 2: top member of the hierarchy (kTop* below)
+    int recon; // 0 the hierarchical reconstruction, 1 type-I WENO
     int indicator;         // troubled-cell indicator: 0 KXRCF, 1 TVB minmod
     double tvb_m;          // TVB constant M
 };

@@ -87,4 +87,25 @@ struct OpLayout {
     static constexpr int LEN = (RAW + 7) / 8 * 8;                   // padded to 64 bytes
 };
 
+// Layout of the per-element record of the type-I reconstruction (N = 1, 2):
+// the centroid-subcell average functionals, the pseudo-inverses of the
+// central stencil (rows piece-major, then face: 9) and of the three sectors
+// (faces k, k+1; rows piece-major, then the two faces: 6), the smoothness
+// matrix and the projection, in the NM monomials of degree 1..N.
+template <int N>
+struct OpLayoutT1 {
+    using D = Dims<N>;
+    static constexpr int NM = N == 1 ? 2 : 5;
+    static constexpr int NBP = NM * (NM + 1) / 2;
+    static constexpr int AVG = 0;                         // [3][3][NP]
+    static constexpr int XC = AVG + 9 * D::NP;            // [NM][9]
+    static constexpr int XS = XC + NM * 9;                // [3][NM][6]
+    static constexpr int BP = XS + 3 * NM * 6;            // packed upper triangle
+    static constexpr int PM = BP + NBP;                   // [NP-1][NM]
+    static constexpr int AREA0 = PM + (D::NP - 1) * NM;
+    static constexpr int VALID = AREA0 + 1;
+    static constexpr int RAW = VALID + 1;
+    static constexpr int LEN = (RAW + 7) / 8 * 8;
+};
+
 }  // namespace cswdg
