@@ -390,18 +390,22 @@ int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_
  * A schedule is int32 [3]: the residual kernel's variant (0 "lean": one
  * face's neighbour data live at a time, 1 "wide": all three faces live,
  * 2 "stream": own coefficients re-read per face, 3 "compact": quadrature
- * point loops rolled; the default is {3, 128, 1}), its threads per block
+ * point loops rolled, 4 "matrix": the evaluations at the quadrature points
+ * and the projections onto the test functions as FP64 matrix-core products
+ * over tiles of 16 elements per wave; the default is {3, 128, 1}), its
+ * threads per block
  * (64, 128 or 256) and the XCD-contiguous block order (0 off, 1 on).  All
  * schedules compute the same quantities; variants may differ in the last
  * bits (summation order), block size and block order do not change results.
  * The wide variant is not offered for P3 Euler (its build exceeds a wave's
- * registers and spills; CSWDG_EINVAL) and FP32-bulk solvers run the compact
+ * registers and spills; CSWDG_EINVAL), the matrix one is offered for P2 in
+ * FP64 only (CSWDG_EINVAL otherwise), and FP32-bulk solvers run the compact
  * one. */
 int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched);
 int cswdg_get_schedule(const cswdg_solver* s, int32_t* sched);
 /* Time every schedule on the residual of the state u (device, reps timed
  * launches each after one untimed launch), keep the fastest and return it
- * in sched (may be NULL); times_us (host, may be NULL, 24 entries) receives
+ * in sched (may be NULL); times_us (host, may be NULL, 30 entries) receives
  * the mean microseconds per launch in the order variant-major, then block,
  * then XCD order (infinity for schedules not offered to the solver);
  * *n_cand (may be NULL) the number of schedules timed.

@@ -504,11 +504,11 @@ class Solver:
         """Time every residual schedule on u; keep the fastest.  Returns
         (schedule, {schedule: microseconds})."""
         a = np.zeros(3, np.int32)
-        t = np.zeros(24, np.float64)
+        t = np.zeros(30, np.float64)
         n = ctypes.c_int32()
         self._st(u, "u")
         self._c(lib().cswdg_autotune(self.h, _ptr(u), int(reps), a.ctypes.data, t.ctypes.data, ctypes.byref(n)))
-        cands = [(v, b, x) for v in (0, 1, 2, 3) for b in (64, 128, 256) for x in (0, 1)]
+        cands = [(v, b, x) for v in (0, 1, 2, 3, 4) for b in (64, 128, 256) for x in (0, 1)]
         return tuple(int(x) for x in a), {c: float(t[i]) for i, c in enumerate(cands[: n.value])}
 
     KERNEL_CLASSES = ("residual_rk", "max_dt", "kxrcf", "compact_mask", "limiter", "scatter", "copy", "zero",

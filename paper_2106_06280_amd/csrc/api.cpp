@@ -174,6 +174,8 @@ int check_single(cswdg_solver* s) {
 // registers of a wave for P3 Euler and spills; that build has produced NaN
 // in some elements, so the schedule is not offered there.
 bool wide_offered(const cswdg_params& p) { return !(p.equation == CSWDG_EQ_EULER && p.degree == 3); }
+// the matrix-core residual is laid out for the P2 rules in FP64
+bool matrix_offered(const cswdg_params& p) { return p.degree == 2 && p.precision == 0; }
 
 size_t elem_bytes(const cswdg_solver* s) { return s->p.precision == 1 ? sizeof(float) : sizeof(double); }
 
@@ -382,6 +384,8 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     const char* rv = std::getenv("CSWDG_RESIDUAL_VARIANT");
     s->ctx.residual_variant = rv ? std::atoi(rv) : 3;
     if (s->ctx.residual_variant == 1 && !wide_offered(p)) s->ctx.residual_variant = 3;
+    if (s->ctx.residual_variant == 4 && !matrix_offered(p)) s->ctx.residual_variant = 3;
+    if (s->ctx.residual_variant < 0 || s->ctx.residual_variant > 4) s->ctx.residual_variant = 3;
     s->ctx.residual_block = 128;
     s->ctx.kxrcf_rms = p.kxrcf_norm;
     s->ctx.char_comp = p.char_mode;
@@ -898,11 +902,13 @@ int cswdg_ssprk3_step_vjp(cswdg_solver* s, const void* tape, const void* u_next_
 
 int cswdg_set_schedule(cswdg_solver* s, const int32_t* sched) {
     if (!s || !sched) return fail(s, CSWDG_EINVAL, "null argument");
-    if (sched[0] < 0 || sched[0] > 3 || (sched[1] != 64 && sched[1] != 128 && sched[1] != 256) ||
+    if (sched[0] < 0 || sched[0] > 4 || (sched[1] != 64 && sched[1] != 128 && sched[1] != 256) ||
         (sched[2] != 0 && sched[2] != 1))
-        return fail(s, CSWDG_EINVAL, "schedule: variant 0..3, block 64/128/256, xcd 0/1");
+        return fail(s, CSWDG_EINVAL, "schedule: variant 0..4, block 64/128/256, xcd 0/1");
     if (sched[0] == 1 && !wide_offered(s->p))
         return fail(s, CSWDG_EINVAL, "schedule: the wide variant is not offered for P3 Euler");
+    if (sched[0] == 4 && !matrix_offered(s->p))
+        return fail(s, CSWDG_EINVAL, "schedule: the matrix-core variant is offered for P2 in FP64 only");
     s->ctx.residual_variant = sched[0];
     s->ctx.residual_block = sched[1];
     s->dm.xcd_tiles = sched[2];
@@ -921,7 +927,7 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
     int rc = check_ready(s);
     if (rc) return rc;
     if (!u || reps < 1) return fail(s, CSWDG_EINVAL, "autotune needs a state and reps >= 1");
-    const int variants[4] = {0, 1, 2, 3}, blocks[3] = {64, 128, 256}, xcds[2] = {0, 1};
+    const int variants[5] = {0, 1, 2, 3, 4}, blocks[3] = {64, 128, 256}, xcds[2] = {0, 1};
     hipEvent_t ev[2];
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
         return fail(s, CSWDG_EHIP, "hipEventCreate failed");
@@ -935,8 +941,10 @@ int cswdg_autotune(cswdg_solver* s, const void* u, int32_t reps, int32_t* sched,
     for (int v : variants)
         for (int b : blocks)
             for (int x : xcds) {
-                if ((s->p.precision == 1 && v != 3) || (v == 1 && !wide_offered(s->p))) {
-                    // FP32-bulk runs the compact schedule only; P3 Euler has no wide one
+                if ((s->p.precision == 1 && v != 3) || (v == 1 && !wide_offered(s->p)) ||
+                    (v == 4 && !matrix_offered(s->p))) {
+                    // FP32-bulk runs the compact schedule only; P3 Euler has no
+                    // wide one; the matrix-core one is P2 FP64
                     if (times_us) times_us[k] = INFINITY;
                     ++k;
                     continue;

@@ -466,6 +466,215 @@ __global__ __launch_bounds__(256) void k_residual_compact_d(DevMesh msh, const d
     residual_body_compact<EQ, N, MODE, double>(msh, u, un, out, dtp, gamma, cnt_reset);
 }
 
+// ---------------------------------------------------------------------------
+// Residual on the matrix cores (P2, FP64): the evaluation of the state at the
+// quadrature points and the projections onto the test functions are dense
+// contractions with the reference-element matrices, batched over elements,
+// so they run as v_mfma_f64_16x16x4 products; the fluxes stay on the vector
+// ALU.  One wave takes a tile of 16 elements: lane (a = lane / 16,
+// r = lane % 16) works on element r of the tile.  Operand layouts of the
+// 16x16x4 product D = A B + C: lane (a, r) holds A[r][a] and B[a][r] (k = a)
+// and the four entries D[4 i + a][r], i = 0..3.
+//   evaluation: A = a table [16 points x 4 basis functions] (two k-steps for
+//     the six P2 functions), B = the tile's coefficients of one variable, so
+//     register i of lane (a, r) receives the value at row 4 i + a;
+//     volume rows: lane group a holds two points of the 9-point rule (the
+//     last group three), face rows: lane group a < 3 holds the four points
+//     of face a;
+//   projection and lift: each lane's flux values are the B operand of one
+//     k-step (k = a: the four lane groups' values enter one product), A holds
+//     the matching test-function weights (row = output coefficient), and the
+//     products accumulate every variable's right-hand side over 6 volume
+//     k-steps and 4 face k-steps into D (output coefficient 4 i + a in
+//     register i).
+// Same quadrature and flux as the other schedules; the sums run in another
+// order.
+// ---------------------------------------------------------------------------
+typedef double mf_v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf_v4d mf_mma(double a, double b, mf_v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// point of the 9-point volume rule in slot i of lane group a (-1: padding)
+__device__ __forceinline__ int mf_vol_point(int a, int i) {
+    if (a < 3) return (i < 2) ? 2 * a + i : -1;
+    return (i < 3) ? 6 + i : -1;
+}
+
+template <int EQ, int MODE>
+__global__ __launch_bounds__(256) void k_residual_mfma(DevMesh msh, const double* __restrict__ u,
+                                                       const double* __restrict__ un, double* __restrict__ out,
+                                                       const double* __restrict__ dtp, double gamma,
+                                                       uint32_t* __restrict__ cnt_reset) {
+    constexpr int N = 2;
+    using D = Dims<N>;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
+    static_assert(NP == 6 && NE == 4 && NQ == 9, "tile layout of the P2 rules");
+    const int K = msh.K;
+    if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
+    if (K <= 0) return;
+    const int lane = threadIdx.x & 63, a = lane >> 4, r = lane & 15;
+    const int tile = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    const int e_raw = tile * 16 + r;
+    const bool live = e_raw < K;
+    const int e = live ? e_raw : K - 1;  // the tail's lanes compute on a copy and store nothing
+    const auto& T = TabOf<N, double>::get();
+    const double ag = lf_global(msh, e);  // < 0: local Lax-Friedrichs
+
+    const double X0 = msh.vx[e], X1 = msh.vx[K + e], X2 = msh.vx[2 * K + e];
+    const double Y0 = msh.vy[e], Y1 = msh.vy[K + e], Y2 = msh.vy[2 * K + e];
+
+    mf_v4d acc[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc[c] = mf_v4d{0.0, 0.0, 0.0, 0.0};
+
+    // B operands of both evaluations: coefficient n = 4 s + a of element r
+    double bu[2][M];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int n = 4 * s + a;
+        const int nc = n < NP ? n : 0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) bu[s][c] = (n < NP) ? u[(size_t)(c * NP + nc) * K + e] : 0.0;
+    }
+
+    // ---- volume term ----
+    {
+        mf_v4d dv[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) dv[c] = mf_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int n = 4 * s + a;  // basis function of k = a in k-step s
+            const bool nok = n < NP;
+            const int nc = nok ? n : 0;
+            const int qa = mf_vol_point(r & 3, r >> 2);  // point of A's row r
+            const double av = (nok && qa >= 0) ? T.V[qa >= 0 ? qa : 0][nc] : 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) dv[c] = mf_mma(av, bu[s][c], dv[c]);
+        }
+        const double xr = 0.5 * (X1 - X0), xs = 0.5 * (X2 - X0);
+        const double yr = 0.5 * (Y1 - Y0), ys = 0.5 * (Y2 - Y0);
+        const double iJ = 1.0 / (xr * ys - xs * yr);
+        const double rx = ys * iJ, ry = -xs * iJ, sx = -yr * iJ, sy = xr * iJ;
+        const double gm = gamma;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int q = mf_vol_point(a, i);
+            const bool ok = q >= 0;
+            const int qc = ok ? q : 0;
+            double uq[M], F[M], G[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) uq[c] = ok ? dv[c][i] : (c == 0 ? 1.0 : 0.0);  // padding: a harmless state
+            Phys<EQ>::flux(uq, gm, F, G);
+            const bool rok = r < NP;
+            const int rc = rok ? r : 0;
+            const double wr = (ok && rok) ? T.wDr[qc][rc] : 0.0;
+            const double ws = (ok && rok) ? T.wDs[qc][rc] : 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double fr = ok ? rx * F[c] + ry * G[c] : 0.0;
+                const double fs = ok ? sx * F[c] + sy * G[c] : 0.0;
+                acc[c] = mf_mma(wr, fr, acc[c]);
+                acc[c] = mf_mma(ws, fs, acc[c]);
+            }
+        }
+    }
+
+    // ---- surface term: lane group a < 3 takes face a ----
+    {
+        mf_v4d df[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) df[c] = mf_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int n = 4 * s + a;
+            const bool nok = n < NP;
+            const int nc = nok ? n : 0;
+            const int fa = r & 3, ga = r >> 2;  // face and point of A's row r
+            const double af = (nok && fa < 3) ? T.PF[fa < 3 ? fa : 0][ga][nc] : 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) df[c] = mf_mma(af, bu[s][c], df[c]);
+        }
+        const bool fok = a < 3;
+        const int f = fok ? a : 0;
+        const int f1 = (f == 2) ? 0 : f + 1;
+        const double xa = (f == 0) ? X0 : ((f == 1) ? X1 : X2), ya = (f == 0) ? Y0 : ((f == 1) ? Y1 : Y2);
+        const double xb = (f1 == 0) ? X0 : ((f1 == 1) ? X1 : X2), yb = (f1 == 0) ? Y0 : ((f1 == 1) ? Y1 : Y2);
+        const double ex = xb - xa, ey = yb - ya;
+        const double L = sqrt(ex * ex + ey * ey);
+        const double iL = 1.0 / L;
+        const double nx = ey * iL, ny = -ex * iL;
+        const double J = 0.25 * ((X1 - X0) * (Y2 - Y0) - (X2 - X0) * (Y1 - Y0));
+        const double sf = 0.5 * L / J;
+        const uint32_t inf = (msh.info[e] >> (8 * f)) & 0xffu;
+        const bool bnd = (inf & 0x40u) != 0u;
+        const int fp = bnd ? 0 : (int)(inf & 3u);
+        const int nb = bnd ? e : msh.nbr[f * K + e];
+        double Un[M][NP];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int n = 0; n < NP; ++n) Un[c][n] = u[(size_t)(c * NP + n) * K + nb];
+        const double gm = gamma;
+        const bool rok = r < NP;
+        const int rc = rok ? r : 0;
+#pragma unroll
+        for (int g = 0; g < NE; ++g) {
+            // own trace from the evaluation product, the neighbour's at the
+            // same point (its face fp, points in reverse order)
+            double um[M], upg[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double b = 0.0;
+#pragma unroll
+                for (int n = 0; n < NP; ++n) b += T.PF[fp][NE - 1 - g][n] * Un[c][n];
+                um[c] = fok ? df[c][g] : (c == 0 ? 1.0 : 0.0);  // lane group 3: a harmless state
+                upg[c] = (bnd || !fok) ? um[c] : b;
+            }
+            if (bnd && fok)
+                boundary_trace<EQ>(um, upg, inf, nx, ny, msh.inflow, msh.shock, xa + tab<N>().es[g] * ex,
+                                   ya + tab<N>().es[g] * ey, stage_time<MODE>(msh, e, dtp));
+            double Fm[M], Fp[M], lm, lp;
+            Phys<EQ>::normal_flux(um, nx, ny, gm, Fm, lm);
+            Phys<EQ>::normal_flux(upg, nx, ny, gm, Fp, lp);
+            const double alpha = (ag >= 0.0) ? ag : fmax(lm, lp);
+            const double w = (fok && rok) ? -T.wPF[f][g][rc] : 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Fs = 0.5 * (Fm[c] + Fp[c]) - 0.5 * alpha * (upg[c] - um[c]);
+                acc[c] = mf_mma(w, fok ? sf * Fs : 0.0, acc[c]);
+            }
+        }
+    }
+
+    // ---- 1/J is in the weights' metric terms; RK combine of the coefficients 4 i + a ----
+    double dt = 0.0;
+    if (MODE != 0) dt = dtp[inst_of(msh, e)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int ip = 4 * i + a;
+        if (!live || ip >= NP) continue;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const size_t idx = (size_t)(c * NP + ip) * K + e;
+            const double rhs = acc[c][i];
+            double v;
+            if (MODE == 0) {
+                v = rhs;
+            } else if (MODE == 1) {
+                v = u[idx] + dt * rhs;
+            } else if (MODE == 2) {
+                v = 0.75 * __builtin_nontemporal_load(&un[idx]) + 0.25 * (u[idx] + dt * rhs);
+            } else {
+                v = (1.0 / 3.0) * __builtin_nontemporal_load(&un[idx]) + (2.0 / 3.0) * (u[idx] + dt * rhs);
+            }
+            __builtin_nontemporal_store(v, &out[idx]);
+        }
+    }
+}
+
 template <int EQ, int N, int MODE>
 __global__ __launch_bounds__(256) void k_residual_lean(DevMesh msh, const double* __restrict__ u,
                                                        const double* __restrict__ un, double* __restrict__ out,
@@ -1737,6 +1946,20 @@ hipError_t launch_residual_reset(const LaunchCtx& c, const DevMesh& m, int mode,
             CSWDG_RES_LAUNCH(k_residual_stream)
         } else if (c.residual_variant == 3) {
             CSWDG_RES_LAUNCH(k_residual_compact_d)
+        } else if (c.residual_variant == 4) {
+            // matrix cores: P2 only, 16 elements per wave
+            if constexpr (N == 2) {
+                const unsigned gm = grid_for(m.K, bs / 4);
+switch (mode) {
+                    case 0: k_residual_mfma<EQ, 0><<<gm, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+                    case 1: k_residual_mfma<EQ, 1><<<gm, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+                    case 2: k_residual_mfma<EQ, 2><<<gm, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+                    case 3: k_residual_mfma<EQ, 3><<<gm, bs, 0, c.stream>>>(m, U, UN, O, dt, c.gamma, reset); break;
+                    default: return hipErrorInvalidValue;
+                }
+            } else {
+                return hipErrorInvalidValue;
+            }
         } else {
             CSWDG_RES_LAUNCH(k_residual_lean)
         }

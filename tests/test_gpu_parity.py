@@ -311,14 +311,15 @@ def test_limiter_linear_weights(torch, eq, N):
     assert np.abs(got[inner] - u[inner]).max() < 1e-10
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 4])
 @pytest.mark.parametrize("eq,N", EQN)
 def test_residual_schedules_parity(torch, eq, N, variant):
     """Every residual schedule (the default compact one is covered above)
     against the oracle, on a mesh with a ragged last block."""
     M, dg, S = _case(eq, N, 12, BC_TRANSMISSIVE, seed=141 + N)
-    if (eq, N, variant) == (1, 3, 1):
-        # the wide schedule is not offered for P3 Euler (its build spills)
+    if (eq, N, variant) == (1, 3, 1) or (variant == 4 and N != 2):
+        # the wide schedule is not offered for P3 Euler (its build spills),
+        # the matrix-core one is laid out for P2
         with pytest.raises(_binding().CswdgError):
             S.set_schedule(variant, 128, 1)
         return
@@ -353,12 +354,14 @@ def _lf_case(eq, N, n, bc, seed, **kw):
     return M, dg, S
 
 
-@pytest.mark.parametrize("variant", [3, 0, 2])
+@pytest.mark.parametrize("variant", [3, 0, 2, 4])
 @pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
 @pytest.mark.parametrize("eq,N", EQN)
 def test_residual_global_lax_friedrichs(torch, eq, N, bc, variant):
     """lf_mode = 1: one Lax-Friedrichs constant per residual, the largest
     cell-mean wave speed of the input, in every residual schedule."""
+    if variant == 4 and N != 2:
+        pytest.skip("the matrix-core schedule is laid out for P2")
     M, dg, S = _lf_case(eq, N, 12, bc, seed=151 + N)
     S.set_schedule(variant, 128, 1)
     for u in (_smooth_state(dg, eq, seed=N), _jump_state(dg, eq, seed=N)):
