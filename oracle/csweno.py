@@ -57,9 +57,22 @@ tau from beta_4):
                default for N = 2: with every cell limited it is the only
                one of these readings whose errors fall at the order of
                Tables 1-3 under refinement; the three that build the fourth
-               member on T4 diverge for Euler P2).
-T2, T3 and beta_1 use the whole centroid subcells; N = 3 reuses the N = 2
-stencil and hierarchy; beta is taken of q_l; sigma is read literally.
+               member on T4 diverge for Euler P2);
+  'sextic'     N = 3 only: the P3 hierarchy built "in the same way" one
+               level finer (Section 3.2, the remark on P3): the fourth
+               member from a degree-6 least-squares level q_7 (27 scaled
+               monomials) on the 30-piece stencil T5, by eq.
+               equivalentOrder4 with the four weights gamma_{.,5}, beta of
+               q_7 over derivative orders 1..6 and the tau of eq.
+               tauNonlinearWeightsP2.  T5 cuts each neighbour into ten
+               triangles fanned from its centroid G over its boundary
+               divided at its vertices, at the feet F2, F3 of the N = 2 cut
+               and at the midpoints of the five segments these make: each
+               piece of T4 is halved by the segment from G to the midpoint
+               of its outer side.
+T2, T3 and beta_1 use the whole centroid subcells; by default N = 3 reuses
+the N = 2 stencil and hierarchy with the quartic top; beta is taken of q_l;
+sigma is read literally.
 
 Parity status: pinned by tests/test_oracle_csweno.py (subcell tiling and
 areas, perpendicular cut, least-squares reproduction of polynomials,
@@ -83,9 +96,11 @@ EPS = 1e-10
 LAMBDA1 = 1.0 / 3.0
 
 # fourth member of the N >= 2 hierarchy (see the module docstring)
-TOPS = ("cubic", "quadratic", "quartic", "cubic_tel")
+TOPS = ("cubic", "quadratic", "quartic", "cubic_tel", "sextic")
 DEFAULT_TOP = {1: "quadratic", 2: "quadratic", 3: "quartic"}
-TOP_DEGREE = {"quadratic": 2, "cubic": 3, "cubic_tel": 3, "quartic": 4}
+TOP_DEGREE = {"quadratic": 2, "cubic": 3, "cubic_tel": 3, "quartic": 4, "sextic": 6}
+# the ten pieces per neighbour of the stencil T5 of the sextic top
+NAMES_T5 = [f"T5_{k}" for k in range(10)]
 
 
 class RankError(ValueError):
@@ -112,6 +127,8 @@ def resolve_top(N, top=None, quadratic_top=False):
     t = DEFAULT_TOP[N] if top is None else top
     if t not in TOPS:
         raise ValueError(f"unknown top member {t!r}")
+    if t == "sextic" and N != 3:
+        raise ValueError("the sextic top member is defined for N = 3")
     return t
 
 
@@ -158,12 +175,13 @@ def neighbour_frames(dg: DG, elems):
     return W, fp, nid, shift
 
 
-def pieces(W, fp, N):
+def pieces(W, fp, N, fine=False):
     """Subcell triangles of each placed neighbour.
 
     Returns dict name -> [T,3,3,2] for 'S1','S2','S3' and, for N >= 2,
-    'S2p','S21','S3p','S31'; also the number of feet that fell outside
-    their side (split at the midpoint instead)."""
+    'S2p','S21','S3p','S31' and with fine = True the ten pieces of T5
+    (NAMES_T5, in order around the neighbour from w_f'); also the number of
+    feet that fell outside their side (split at the midpoint instead)."""
     T = W.shape[0]
     idx = np.arange(T)[:, None]
     fidx = np.arange(3)[None, :]
@@ -191,6 +209,16 @@ def pieces(W, fp, N):
         out["S21"] = np.stack([G, F2, wc], axis=2)
         out["S3p"] = np.stack([G, wc, F3], axis=2)
         out["S31"] = np.stack([G, F3, wa], axis=2)
+        if fine:
+            # the boundary of the neighbour, divided at its vertices and the
+            # feet, then at the midpoints of the five segments
+            ring = [wa, wb, F2, wc, F3]
+            pts = []
+            for k in range(5):
+                p, q = ring[k], ring[(k + 1) % 5]
+                pts += [p, 0.5 * (p + q)]
+            for k in range(10):
+                out[NAMES_T5[k]] = np.stack([G, pts[k], pts[(k + 1) % 10]], axis=2)
     return out, bad
 
 
@@ -336,7 +364,8 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     Np = dg.Np
     if T == 0:
         return np.zeros((0, m, Np))
-    dtop = top_degree(N)
+    tname = resolve_top(N, top, quadratic_top)
+    dtop = max(top_degree(N), TOP_DEGREE[tname])
     V0 = M.V[E]
     x0 = V0[:, :, 0].mean(axis=1)
     y0 = V0[:, :, 1].mean(axis=1)
@@ -344,9 +373,9 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     area0 = M.area[E]
 
     W, fp, nid, shift = neighbour_frames(dg, E)
-    pcs, nbad = pieces(W, fp, N)
+    pcs, nbad = pieces(W, fp, N, fine=tname == "sextic")
     names_t3 = ["S1", "S2", "S3"]
-    names_t4 = ["S1", "S2p", "S21", "S3p", "S31"]
+    names_t4 = NAMES_T5 if tname == "sextic" else ["S1", "S2p", "S21", "S3p", "S31"]
 
     # cell averages of u (all components) on the pieces: avg[name] [T, 3, m]
     avg = {}
@@ -411,10 +440,9 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
 
     nlin = len(monomials(1))
     nquad = len(monomials(2))
-    tname = resolve_top(N, top, quadratic_top)
     dfour = TOP_DEGREE[tname]
     # Step 1: q_2, q_3 and the top least-squares level on T4 (the cubic
-    # q_4 or the quartic q_5)
+    # q_4 or the quartic q_5), or on T5 (the sextic q_7)
     c2 = _solve_ls(rows(["S1"])[:, :, :nlin], rhs(["S1"], favg, fbar0))  # [T, 2, F]
     c3 = _solve_ls(rows(names_t3)[:, :, :nquad], rhs(names_t3, favg, fbar0))  # [T, 5, F]
     ntop = len(mono_top)
@@ -423,7 +451,7 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
     four = tname != "quadratic"
     if four:
         nfour = len(monomials(dfour))
-        c4 = _solve_ls(rows(names_t4)[:, :, :nfour], rhs(names_t4, favg, fbar0))  # [T, 9 or 14, F]
+        c4 = _solve_ls(rows(names_t4)[:, :, :nfour], rhs(names_t4, favg, fbar0))  # [T, 9, 14 or 27, F]
         qs.append(pad(c4))
     L = len(qs)
 
@@ -440,7 +468,7 @@ def reconstruct(dg: DG, u, elems, linear_only=False, return_info=False, characte
             g4 = linear_weights(h0, 3, constant_gamma)
             ps.append((qs[3] - g4[:, 1, None, None] * ps[1]) / g4[:, 2, None, None])
         else:
-            # eq. equivalentOrder4 (q_5, or q_4 in its place)
+            # eq. equivalentOrder4 (q_5, q_4 in its place, or q_7)
             ps.append((qs[3] - sum(g5[:, l, None, None] * ps[l] for l in range(3))) / g5[:, 3, None, None])
         gtop = g5
     else:

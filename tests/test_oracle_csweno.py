@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle_runs
-from oracle import csweno
+from oracle import csweno, quadrature
 from oracle.dg import DG
 from oracle.mesh import BC_PERIODIC, BC_TRANSMISSIVE, INFO_BOUNDARY, Mesh, connectivity_bruteforce
 from paper_2106_06280_amd import inputs
@@ -49,6 +49,63 @@ def test_pieces_tile_neighbours(N):
         for f in range(3):
             s1 = pcs["S1"][:, f]
             assert np.allclose(s1[:, 1], V0[:, (f + 1) % 3]) and np.allclose(s1[:, 2], V0[:, f])
+
+
+def test_t5_pieces_halve_the_t4_pieces():
+    """The ten pieces of T5 (sextic top): positive areas, consecutive
+    pairs tile the T4 pieces S1, S2', S21, S3', S31, the two halves of each
+    have equal areas (the cut from G to the midpoint of the outer side is a
+    median), and the ten tile the neighbour."""
+    M = _mesh()
+    d = DG(M, 3, 0)
+    E = np.arange(M.K)
+    W, fp, nid, shift = csweno.neighbour_frames(d, E)
+    pcs, nbad = csweno.pieces(W, fp, 3, fine=True)
+    assert nbad == 0
+    a = {nm: csweno.tri_area(pcs[nm]) for nm in pcs}
+    t5 = [a[nm] for nm in csweno.NAMES_T5]
+    assert np.all(np.stack(t5) > 0)
+    for k, nm in enumerate(("S1", "S2p", "S21", "S3p", "S31")):
+        assert np.allclose(t5[2 * k] + t5[2 * k + 1], a[nm], rtol=1e-13)
+        assert np.allclose(t5[2 * k], t5[2 * k + 1], rtol=1e-12)
+    assert np.allclose(sum(t5), csweno.tri_area(W), rtol=1e-13)
+    # every piece has the neighbour's centroid as its first vertex, and the
+    # pieces follow each other around the neighbour
+    G = W.mean(axis=2)
+    for k, nm in enumerate(csweno.NAMES_T5):
+        assert np.allclose(pcs[nm][..., 0, :], G)
+        assert np.allclose(pcs[nm][..., 2, :], pcs[csweno.NAMES_T5[(k + 1) % 10]][..., 1, :])
+
+
+def test_sextic_level_reproduces_degree_six_polynomials():
+    """The degree-6 least-squares level on T5, fed the exact piece
+    averages of a degree-6 polynomial (and Delta0's exact mean), returns its
+    27 scaled-monomial coefficients; a degree-7 term breaks it."""
+    M = _mesh(7)
+    d = DG(M, 3, 0)
+    E = _interior(M)
+    W, fp, nid, shift = csweno.neighbour_frames(d, E)
+    pcs, _ = csweno.pieces(W, fp, 3, fine=True)
+    V0 = M.V[E]
+    x0, y0, h0 = V0[:, :, 0].mean(axis=1), V0[:, :, 1].mean(axis=1), M.mean_side[E]
+    rng = np.random.default_rng(5)
+    mono = csweno.monomials(6)
+    c = rng.normal(size=len(mono))
+    m0 = csweno.monomial_average(V0, x0, y0, h0, 6)
+    A = np.concatenate([csweno.monomial_average(pcs[nm], x0, y0, h0, 6) for nm in csweno.NAMES_T5], axis=1)
+    A = A - m0[:, None, :]
+    b = (A @ c)[..., None]  # piece averages minus Delta0's mean, of sum_j c_j phi_j
+    got = csweno._solve_ls(A, b)[..., 0]
+    assert np.abs(got - c[None, :]).max() < 1e-8 * np.abs(c).max()
+    # a degree-7 term is not reproduced (the level has degree 6 exactly)
+    def avg7(P):
+        x, y, w = quadrature.physical_rule_on_triangle(P, 5)
+        sh = (slice(None),) + (None,) * (x.ndim - 1)
+        xi, eta = (x - x0[sh]) / h0[sh], (y - y0[sh]) / h0[sh]
+        return np.sum(w * xi ** 7, axis=-1) / np.sum(w, axis=-1)
+    b7 = np.concatenate([avg7(pcs[nm]) for nm in csweno.NAMES_T5], axis=1) - avg7(V0[:, None])[:, :1]
+    res = b7 - np.einsum("trc,tc->tr", A, csweno._solve_ls(A, b7[..., None])[..., 0])
+    assert np.abs(res).max() > 1e-6
 
 
 def test_mirror_ghost_is_reflection():
@@ -111,7 +168,7 @@ def test_beta_closed_form():
 
 
 @pytest.mark.parametrize("N,deg,top", [(1, 1, None), (2, 2, "quartic"), (2, 2, "cubic_tel"), (2, 2, "quadratic"),
-                                       (3, 3, "quartic"), (3, 3, "cubic_tel")])
+                                       (3, 3, "quartic"), (3, 3, "cubic_tel"), (3, 3, "sextic")])
 def test_least_squares_levels_reproduce_polynomials(N, deg, top):
     """Every telescoping hierarchy (the top member built by eq.
     equivalentOrder4 from the top least-squares level) reproduces data of
@@ -143,9 +200,9 @@ def test_least_squares_levels_reproduce_polynomials(N, deg, top):
             assert np.abs(info["qs"][l] - info["qs"][-1]).max() < 1e-12
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N,top", [(1, None), (2, None), (3, None), (3, "sextic")])
 @pytest.mark.parametrize("eq", [0, 1])
-def test_linear_data_reproduced_by_nonlinear_weights(N, eq):
+def test_linear_data_reproduced_by_nonlinear_weights(N, top, eq):
     """Linear data: all smoothness indicators coincide, tau = 0, omega =
     gamma and the reconstruction returns the data (the identity on linear
     states is what fixes beta to be taken of q_l)."""
@@ -157,7 +214,7 @@ def test_linear_data_reproduced_by_nonlinear_weights(N, eq):
         U = d.project(lambda x, y: np.stack([1.0 + 0.2 * x - 0.1 * y, 0.3 + 0.1 * x, -0.2 + 0.05 * y,
                                              2.5 + 0.1 * x + 0.2 * y], -1))
     E = _interior(M)
-    out, info = csweno.reconstruct(d, U, E, return_info=True)
+    out, info = csweno.reconstruct(d, U, E, return_info=True, top=top)
     assert np.abs(out - U[E]).max() < 1e-11
     om = np.stack(info["omega"], 1)
     assert np.allclose(om.sum(1), 1.0, atol=1e-15)
@@ -192,8 +249,9 @@ def test_mean_retained_and_untroubled_cells_untouched():
         assert not np.array_equal(out[mask], U[mask])
 
 
-@pytest.mark.parametrize("N,ns", [(1, (16, 32)), (2, (32, 64)), (3, (32, 64))])
-def test_single_application_keeps_design_order(N, ns):
+@pytest.mark.parametrize("N,ns,top", [(1, (16, 32), None), (2, (32, 64), None), (3, (32, 64), None),
+                                      (3, (16, 32), "sextic")])
+def test_single_application_keeps_design_order(N, ns, top):
     """Smooth data, every cell troubled: the limited field stays within
     O(h^{N+1}) of the exact solution (the accuracy claim of Section 4.1)."""
     ic = inputs.BurgersSine()
@@ -203,7 +261,7 @@ def test_single_application_keeps_design_order(N, ns):
         M = Mesh(v, t, BC_PERIODIC, (4.0, 4.0))
         d = DG(M, N, 0)
         U = d.project(ic)
-        out = csweno.limit(d, U, np.ones(M.K, bool))
+        out = csweno.limit(d, U, np.ones(M.K, bool), top=top)
         errs.append(d.errors(out, ic)[0])
     order = math.log2(errs[0] / errs[1])
     assert order > N + 1 - 0.3, (errs, order)
