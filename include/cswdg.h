@@ -123,8 +123,13 @@ typedef struct cswdg_params {
      *     the linear weights telescope to q_4);
      *   4 p_4 = (q_4 - gamma_{1,4} p_1 - gamma_{2,4} p_2) / gamma_{3,4} with
      *     the three weights gamma_{.,4} (eq. equivalentOrder3 as printed),
-     *     the members p_1..p_4 combined with gamma_{.,5}.
-     * N = 1 is unaffected.  Values outside 0..4: CSWDG_EINVAL. */
+     *     the members p_1..p_4 combined with gamma_{.,5};
+     *   5 (N = 3 only: the P3 hierarchy built the same way one level finer,
+     *     Section 3.2) the degree-6 q_7 on the 30-piece stencil T5 by eq.
+     *     equivalentOrder4, T5 halving each T4 piece by the median from the
+     *     neighbour's centroid; no adjoint (CSWDG_EINVAL from the VJP calls).
+     * N = 1 is unaffected.  Values outside 0..5, or 5 with N != 3:
+     * CSWDG_EINVAL. */
     int p2_top;
     /* troubled-cell indicator (the first step of Section 3; the limiter does
      * not depend on which one marks the cells): CSWDG_INDICATOR_KXRCF (the
@@ -362,7 +367,7 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
  * floating-point atomics).  All buffers device, state layout.  These calls
  * take FP64 single-instance solvers with the default readings (char_mode,
  * weights_mode, lf_mode, gamma_mode, ghost_mode and positivity 0, the KXRCF
- * indicator; any p2_top) and no wall, inflow or moving-shock faces;
+ * indicator; any p2_top but 5) and no wall, inflow or moving-shock faces;
  * CSWDG_EINVAL otherwise. */
 
 /* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).

@@ -847,6 +847,7 @@ hipError_t launch_limiter_vjp(const LaunchCtx& c, const DevMesh& m, const void* 
     if (g == 0) g = 1;
     CSWDG_DISPATCH_EN(c.eq, c.N, {
         const int qt = N >= 2 ? c.qtop : kTopQuadratic;
+        if (qt == kTopSextic) return hipErrorInvalidValue;  // no adjoint of the sextic top
         if (N == 1 || qt == kTopQuadratic)
             k_limiter_vjp<EQ, N, kTopQuadratic><<<g, bs, 0, c.stream>>>(m, (const double*)w, ops, list, count,
                                                                         (const double*)ybar, contrib, c.gamma, c.eps);

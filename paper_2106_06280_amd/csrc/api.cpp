@@ -167,6 +167,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.ghost_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the mirror ghost (ghost_mode = 0)");
     if (s->p.reconstruction != 0)
         return fail(s, CSWDG_EINVAL, "adjoint calls take the hierarchical reconstruction (reconstruction = 0)");
+    if (s->ctx.qtop == kTopSextic) return fail(s, CSWDG_EINVAL, "adjoint calls do not take the sextic top (p2_top = 5)");
     return CSWDG_OK;
 }
 
@@ -337,7 +338,8 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         return fail(nullptr, CSWDG_EINVAL, "kxrcf_norm, char_mode and weights_mode must be 0 or 1");
     if (p.positivity < 0 || p.positivity > 1) return fail(nullptr, CSWDG_EINVAL, "positivity must be 0 or 1");
     if (p.lf_mode < 0 || p.lf_mode > 1) return fail(nullptr, CSWDG_EINVAL, "lf_mode must be 0 or 1");
-    if (p.p2_top < 0 || p.p2_top > 4) return fail(nullptr, CSWDG_EINVAL, "p2_top must be 0..4");
+    if (p.p2_top < 0 || p.p2_top > 5) return fail(nullptr, CSWDG_EINVAL, "p2_top must be 0..5");
+    if (p.p2_top == 5 && p.degree != 3) return fail(nullptr, CSWDG_EINVAL, "p2_top = 5 (the sextic top) is for degree 3");
     if (p.indicator != CSWDG_INDICATOR_KXRCF && p.indicator != CSWDG_INDICATOR_TVB)
         return fail(nullptr, CSWDG_EINVAL, "indicator must be CSWDG_INDICATOR_KXRCF or CSWDG_INDICATOR_TVB");
     if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m))

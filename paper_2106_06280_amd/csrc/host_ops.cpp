@@ -66,9 +66,11 @@ struct Frame {  // maps placed coordinates to the source element's physical fram
     }
 };
 
-// Householder QR pseudo-inverse X (c x r) of A (r x c).
+// Householder QR pseudo-inverse X (c x r) of A (r x c), r <= 32.
 bool pinv(int r, int c, const double* A, double* X) {
-    double R[16][16], QT[16][16];
+    constexpr int NMAX = 32;
+    if (r > NMAX || c > r) return false;
+    double R[NMAX][NMAX], QT[NMAX][NMAX];
     for (int i = 0; i < r; ++i)
         for (int j = 0; j < c; ++j) R[i][j] = A[i * c + j];
     for (int i = 0; i < r; ++i)
@@ -79,7 +81,7 @@ bool pinv(int r, int c, const double* A, double* X) {
         nrm = std::sqrt(nrm);
         if (nrm == 0) continue;
         double alpha = R[k][k] > 0 ? -nrm : nrm;
-        double v[16];
+        double v[NMAX];
         for (int i = 0; i < r; ++i) v[i] = 0;
         for (int i = k; i < r; ++i) v[i] = R[i][k];
         v[k] -= alpha;
@@ -107,7 +109,7 @@ bool pinv(int r, int c, const double* A, double* X) {
     if (!(dmin > 1e-12 * dmax)) return false;
     // X = R^{-1} QT[0:c, :]
     for (int col = 0; col < r; ++col) {
-        double y[16];
+        double y[NMAX];
         for (int i = c - 1; i >= 0; --i) {
             double s = QT[i][col];
             for (int j = i + 1; j < c; ++j) s -= R[i][j] * y[j];
@@ -118,8 +120,10 @@ bool pinv(int r, int c, const double* A, double* X) {
     return true;
 }
 
+constexpr int kMonoMax = 27;  // monomials of degree 1..6
+
 struct MonoList {
-    int a[14], b[14], n;
+    int a[kMonoMax], b[kMonoMax], n;
     explicit MonoList(int d) : n(0) {
         for (int s = 1; s <= d; ++s)
             for (int bb = 0; bb <= s; ++bb) {
@@ -210,9 +214,9 @@ struct OpBuilder {
         double J0 = 0.5 * area0;
 
         // monomial means over e
-        double mavg0[14] = {0};
+        double mavg0[kMonoMax] = {0};
         {
-            double tmp[14];
+            double tmp[kMonoMax];
             double wsum = 0;
             for (size_t q = 0; q < rTop.w.size(); ++q) {
                 mono_eval(map_tri(V0, rTop.r[q], rTop.s[q]), c0, h0, tmp);
@@ -222,7 +226,7 @@ struct OpBuilder {
             for (int j = 0; j < mono.n; ++j) mavg0[j] /= wsum;
         }
 
-        double mavg[3][7][14];
+        double mavg[3][L::NPC][kMonoMax];
         P2d cen[3][3];
         for (int f = 0; f < 3; ++f) {
             uint8_t inf = m.info[3 * e + f];
@@ -258,8 +262,8 @@ struct OpBuilder {
             }
             P2d G = (1.0 / 3.0) * (W[0] + W[1] + W[2]);
             P2d wa = W[fp], wb = W[(fp + 1) % 3], wc = W[(fp + 2) % 3];
-            P2d pcs[7][3] = {{G, wa, wb}, {G, wb, wc}, {G, wc, wa}};
-            if (L::NPC == 7) {
+            P2d pcs[L::NPC][3] = {{G, wa, wb}, {G, wb, wc}, {G, wc, wa}};
+            if (L::NPC >= 7) {
                 auto foot = [&](P2d p, P2d q) {
                     P2d d = q - p;
                     double t = dot(G - p, d) / dot(d, d);
@@ -273,6 +277,21 @@ struct OpBuilder {
                 P2d extra[4][3] = {{G, wb, F2}, {G, F2, wc}, {G, wc, F3}, {G, F3, wa}};
                 for (int p = 0; p < 4; ++p)
                     for (int k = 0; k < 3; ++k) pcs[3 + p][k] = extra[p][k];
+                if (L::SEXT) {
+                    // T5: the boundary divided at the vertices, the feet and
+                    // the midpoints of the five segments; fan from G
+                    const P2d ring[5] = {wa, wb, F2, wc, F3};
+                    P2d pts[10];
+                    for (int k = 0; k < 5; ++k) {
+                        pts[2 * k] = ring[k];
+                        pts[2 * k + 1] = 0.5 * (ring[k] + ring[(k + 1) % 5]);
+                    }
+                    for (int k = 0; k < 10; ++k) {
+                        pcs[7 + k][0] = G;
+                        pcs[7 + k][1] = pts[k];
+                        pcs[7 + k][2] = pts[(k + 1) % 10];
+                    }
+                }
             }
             for (int p = 0; p < 3; ++p) cen[f][p] = (1.0 / 3.0) * (pcs[p][0] + pcs[p][1] + pcs[p][2]);
             for (int p = 0; p < L::NPC; ++p) {
@@ -289,7 +308,7 @@ struct OpBuilder {
                 }
                 for (int n = 0; n < D::NP; ++n) op[L::AVG + (f * L::NPC + p) * D::NP + n] = acc[n] / wsum;
                 // scaled-monomial averages
-                double ma[14] = {0}, tmp[14];
+                double ma[kMonoMax] = {0}, tmp[kMonoMax];
                 wsum = 0;
                 for (size_t q = 0; q < rTop.w.size(); ++q) {
                     mono_eval(map_tri(pcs[p], rTop.r[q], rTop.s[q]), c0, h0, tmp);
@@ -327,20 +346,21 @@ struct OpBuilder {
         }
         if (L::FOUR) {
             // top level on T4: rows S1, S2', S21, S3', S31 (pieces 0, 3, 4,
-            // 5, 6) x faces; columns the 14 quartic or the 9 cubic monomials
+            // 5, 6) x faces; columns the 14 quartic or the 9 cubic monomials;
+            // the sextic: rows the ten T5 pieces (7..16) x faces, 27 columns
             const int pl[5] = {0, 3, 4, 5, 6};
-            const int nc = L::NT;
-            double A[15 * 14];
-            for (int k = 0; k < 5; ++k)
+            constexpr int nc = L::NT > 0 ? L::NT : 1, nk = L::NROW / 3;
+            double A[L::NROW * nc];
+            for (int k = 0; k < nk; ++k)
                 for (int f = 0; f < 3; ++f)
-                    for (int j = 0; j < nc; ++j) A[(k * 3 + f) * nc + j] = mavg[f][pl[k]][j];
-            valid &= pinv(15, nc, A, op + L::X5);
+                    for (int j = 0; j < nc; ++j) A[(k * 3 + f) * nc + j] = mavg[f][L::SEXT ? 7 + k : pl[k]][j];
+            valid &= pinv(L::NROW, nc, A, op + L::X5);
         }
 
         // smoothness-indicator matrix
         {
             const int nm = mono.n;
-            double B[14][14] = {{0}};
+            double B[kMonoMax][kMonoMax] = {{0}};
             double ihp[L::DR + 1], ap[L::DR + 1];
             ihp[0] = 1.0;
             ap[0] = 1.0 / area0;
@@ -355,7 +375,7 @@ struct OpBuilder {
                 for (int s = 1; s <= L::DR; ++s)
                     for (int a1 = 0; a1 <= s; ++a1) {
                         int a2 = s - a1;
-                        double Dv[14];
+                        double Dv[kMonoMax];
                         for (int j = 0; j < nm; ++j) {
                             int a = mono.a[j], b = mono.b[j];
                             if (a < a1 || b < a2) {
@@ -381,7 +401,7 @@ struct OpBuilder {
         }
         // projection onto psi_1..psi_{NP-1}
         {
-            double tmp[14];
+            double tmp[kMonoMax];
             for (size_t q = 0; q < rProj.w.size(); ++q) {
                 mono_eval(map_tri(V0, rProj.r[q], rProj.s[q]), c0, h0, tmp);
                 for (int i = 1; i < D::NP; ++i)
@@ -727,6 +747,10 @@ int build_limiter_ops(const HostMesh& m, int N, int qtop, bool constant_gamma, b
             case kTopQuadratic: return build_ops_n<NN, kTopQuadratic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
             case kTopCubic: return build_ops_n<NN, kTopCubic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
             case kTopCubicTel: return build_ops_n<NN, kTopCubicTel>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+            case kTopSextic:
+                if constexpr (NN == 3)
+                    return build_ops_n<NN, kTopSextic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
+                return CSWDG_EINVAL;
             default: return build_ops_n<NN, kTopQuartic>(m, constant_gamma, ghost_extrapolate, ops, n_rank, n_foot);
         }
     };

@@ -72,6 +72,7 @@ inline int top_for(int N, int p2_top) {
         case 2: return kTopQuartic;
         case 3: return kTopCubicTel;
         case 4: return kTopCubic;
+        case 5: return kTopSextic;  // N = 3 only (the API checks)
         default: return N == 2 ? kTopQuadratic : kTopQuartic;
     }
 }

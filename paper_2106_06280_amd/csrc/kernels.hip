@@ -1190,7 +1190,7 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 // (its quartic least-squares level needs more registers)
 template <int N, int QTOP>
 struct LimWaves {
-    static constexpr int value = OpLayout<N, QTOP>::FOUR ? 2 : 4;
+    static constexpr int value = OpLayout<N, QTOP>::SEXT ? 1 : (OpLayout<N, QTOP>::FOUR ? 2 : 4);
 };
 
 template <int EQ, int N, typename S, int QTOP>
@@ -1339,16 +1339,18 @@ __global__ __launch_bounds__(64, (LimWaves<N, QTOP>::value)) void k_limiter(DevM
         for (int jj = 0; jj < NT; ++jj) c5[jj] = 0.0;
         // the top level on T4 for N >= 2 (QTOP = kTopQuadratic: the
         // hierarchy of N = 1); the cubic readings fit 9 monomials, the
-        // quartic 14
+        // quartic 14; the sextic (N = 3) 27 on the ten T5 pieces
         if constexpr (quartic) {
             constexpr int pl[5] = {0, 3, 4, 5, 6};
+            constexpr int NK = LO::NROW / 3;
 #pragma unroll
             for (int jj = 0; jj < NT; ++jj) {
                 double s = 0.0;
 #pragma unroll
-                for (int kk = 0; kk < 5; ++kk)
+                for (int kk = 0; kk < NK; ++kk)
 #pragma unroll
-                    for (int f = 0; f < 3; ++f) s += op[LO::X5 + jj * 15 + kk * 3 + f] * (w[f][pl[kk]] - w0);
+                    for (int f = 0; f < 3; ++f)
+                        s += op[LO::X5 + jj * LO::NROW + kk * 3 + f] * (w[f][LO::SEXT ? 7 + kk : pl[kk]] - w0);
                 c5[jj] = s;
             }
         }
@@ -2062,7 +2064,14 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
         else if (qt == kTopCubicTel)
             k_limiter<EQ, N, S, kTopCubicTel><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
                                                                         c.gamma, c.eps, c.char_comp, c.weights_linear);
-        else
+        else if (qt == kTopSextic) {
+            if constexpr (N == 3)
+                k_limiter<EQ, N, S, kTopSextic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact,
+                                                                          status, c.gamma, c.eps, c.char_comp,
+                                                                          c.weights_linear);
+            else
+                return hipErrorInvalidValue;
+        } else
             k_limiter<EQ, N, S, kTopQuartic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
                                                                        c.gamma, c.eps, c.char_comp, c.weights_linear);
     });

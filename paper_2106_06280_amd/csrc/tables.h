@@ -19,7 +19,7 @@ namespace cswdg {
 //   kTopCubic      p_4 from q_4 by eq. equivalentOrder3 as printed, the
 //                  members {p_1, p_2, p_3, p_4} combined with gamma_{.,5};
 //   kTopCubicTel   q_4 in place of q_5 in eq. equivalentOrder4.
-constexpr int kTopQuartic = 0, kTopQuadratic = 1, kTopCubic = 2, kTopCubicTel = 3;
+constexpr int kTopQuartic = 0, kTopQuadratic = 1, kTopCubic = 2, kTopCubicTel = 3, kTopSextic = 4;
 
 template <int N>
 struct Dims {
@@ -61,23 +61,28 @@ struct TabF {
 // and top member QT.  A hierarchy with a fourth member (N >= 2, QT not
 // kTopQuadratic) reads all seven pieces per neighbour (S1, S2, S3 and the
 // cut pieces S2', S21, S3', S31) and writes its reconstruction in the NT
-// monomials of the top level (9 cubic or 14 quartic); the three-member
-// hierarchy (N = 1, or kTopQuadratic) reads the three centroid pieces and
-// writes the reconstruction in the 5 monomials of degree 1..2.
+// monomials of the top level (9 cubic or 14 quartic); the sextic top (N = 3)
+// also reads the ten pieces of T5 per neighbour (each T4 piece halved by the
+// median from the neighbour's centroid) and writes 27 monomials of degree
+// 1..6; the three-member hierarchy (N = 1, or kTopQuadratic) reads the
+// three centroid pieces and writes the reconstruction in the 5 monomials of
+// degree 1..2.
 template <int N, int QT>
 struct OpLayout {
     using D = Dims<N>;
     static constexpr bool FOUR = (N >= 2) && QT != kTopQuadratic;
-    static constexpr int NT = !FOUR ? 0 : ((QT == kTopCubic || QT == kTopCubicTel) ? 9 : 14);
-    static constexpr int DR = !FOUR ? 2 : (NT == 9 ? 3 : 4);        // degree of the reconstruction
-    static constexpr int NPC = FOUR ? 7 : 3;                        // pieces per neighbour
+    static constexpr bool SEXT = (N == 3) && QT == kTopSextic;
+    static constexpr int NT = !FOUR ? 0 : (SEXT ? 27 : ((QT == kTopCubic || QT == kTopCubicTel) ? 9 : 14));
+    static constexpr int DR = !FOUR ? 2 : (SEXT ? 6 : (NT == 9 ? 3 : 4));  // degree of the reconstruction
+    static constexpr int NPC = SEXT ? 17 : (FOUR ? 7 : 3);            // pieces per neighbour
+    static constexpr int NROW = SEXT ? 30 : 15;                       // rows of the top level (T5 or T4)
     static constexpr int NM = FOUR ? NT : 5;                        // monomials of the reconstruction
     static constexpr int NBP = NM * (NM + 1) / 2;
     static constexpr int AVG = 0;                                   // [3][NPC][NP] subcell-average functionals
     static constexpr int X2 = AVG + 3 * NPC * D::NP;                // [2][3]   pinv, linear level
     static constexpr int X3 = X2 + 2 * 3;                           // [5][9]   pinv, quadratic level
-    static constexpr int X5 = X3 + 5 * 9;                           // [NT][15] pinv, top level on T4
-    static constexpr int BP = X5 + NT * 15;                         // packed upper triangle of the beta matrix
+    static constexpr int X5 = X3 + 5 * 9;                           // [NT][NROW] pinv, top level on T4 or T5
+    static constexpr int BP = X5 + NT * NROW;                       // packed upper triangle of the beta matrix
     static constexpr int MINV = BP + NBP;                           // [3][2][2] inverse centroid-difference matrices
     static constexpr int PM = MINV + 12;                            // [NP-1][NM] projection onto psi_1..
     static constexpr int GBASE = PM + (D::NP - 1) * NM;             // base b of the linear weights b^(l-1): 1/h0 or 10

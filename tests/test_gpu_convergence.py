@@ -113,3 +113,17 @@ def test_convergence_order_constant_gamma(torch, problem, table, N):
     print(f"{problem} P{N} limiter, constant gamma: errors {errs}, order {order:.3f} (paper {printed})", flush=True)
     assert order >= min(printed, N + 1) - 0.25
     assert errs[0] > errs[1] > errs[2]
+
+
+@pytest.mark.xfail(strict=True, reason="with every cell limited, the sextic top for P3 (degree-6 q_7 on the 30-piece "
+                   "stencil T5) falls short of the design order 4 (measured: Burgers 2.8, entropy wave 1.6, vortex "
+                   "3.3 on the finest pair, errors 5-400 times the quartic top's); the quartic top stays the N = 3 "
+                   "default")
+@pytest.mark.parametrize("problem,table", [("burgers", 1), ("entropy", 2), ("vortex", 3)])
+def test_p3_sextic_top_with_every_cell_limited(torch, problem, table):
+    sizes = _sizes(problem, 3, True)
+    errs = [_run(torch, problem, 3, n, True, p2_top=5) for n in sizes]
+    order = math.log(errs[-2] / errs[-1]) / math.log(2.0)
+    print(f"{problem} P3 limiter, sextic top: errors {errs}, order {order:.3f}", flush=True)
+    assert all(np.isfinite(errs)) and errs[0] > errs[1] > errs[2]
+    assert order >= min(ORDERS[(table, 3)][1], 4) - 0.25

@@ -413,17 +413,21 @@ def test_global_lax_friedrichs_per_instance(torch):
         sol[0].dg_residual_vjp(us[0], us[0].clone())
 
 
-@pytest.mark.parametrize("p2_top", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("p2_top", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("N", [2, 3])
 @pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
 @pytest.mark.parametrize("eq", [0, 1])
 def test_limiter_top_members(torch, eq, bc, N, p2_top):
     """Every reading of the fourth member of the N >= 2 hierarchy (p2_top:
     the default, the quadratic top, the quartic q_5, the telescoping cubic,
-    the printed cubic p_4 of eq. equivalentOrder3), every cell limited, and
-    three KXRCF-limited steps, against the oracle's reading of the same
-    name."""
+    the printed cubic p_4 of eq. equivalentOrder3, and for N = 3 the sextic
+    q_7 on T5), every cell limited, and three KXRCF-limited steps, against
+    the oracle's reading of the same name."""
     b = _binding()
+    if p2_top == 5 and N != 3:
+        with pytest.raises(b.CswdgError):
+            b.Solver(eq, N, p2_top=p2_top)
+        return
     top = b.top_name(N, p2_top)
     v, t = inputs.jittered_mesh(12, seed=171)
     M = Mesh(v, t, bc, (1.0, 1.0))
@@ -445,9 +449,18 @@ def test_limiter_top_members(torch, eq, bc, N, p2_top):
 
 def test_top_member_switch_rejects_bad_values(torch):
     b = _binding()
-    for bad in (-1, 5):
+    for bad in (-1, 5, 6):
         with pytest.raises(b.CswdgError):
             b.Solver(1, 2, p2_top=bad)
+    with pytest.raises(b.CswdgError):
+        b.Solver(1, 3, p2_top=6)
+    # the sextic top has no adjoint
+    v, t = inputs.jittered_mesh(4, seed=3)
+    S = b.Solver(1, 3, p2_top=5)
+    S.mesh_upload(v, t, BC_PERIODIC, (1.0, 1.0))
+    u = S.project_fn(inputs.IsentropicVortex(beta=1.0, x0=0.5, y0=0.5, period_x=1.0, period_y=1.0))
+    with pytest.raises(b.CswdgError):
+        S.csweno_limit_vjp(u, u.clone())
 
 
 @pytest.mark.parametrize("eq,N", EQN)
