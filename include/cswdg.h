@@ -166,6 +166,15 @@ typedef struct cswdg_params {
      * and the boundary kinds, ghost_mode 0).  N = 3, ghost_mode 1 or the
      * adjoint calls with 1: CSWDG_EINVAL. */
     int reconstruction;
+    /* the smoothness indicators beta_l, l >= 2, of the hierarchical
+     * reconstruction (Section 3.2, Step 3, eq. smoothnessIndicator):
+     * 0 of the least-squares levels q_l over derivative orders 1..deg q_l
+     * (the default: only then are linear data reproduced, every beta being
+     * |Delta0| |grad u|^2); 1 as the equation is printed, of the equivalent
+     * polynomials p_l over derivative orders 1..N.  beta_1 (eqs. sigmaEqn,
+     * smoothnessIndicatorT1) is the same in both.  1 with reconstruction 1
+     * or in the adjoint calls: CSWDG_EINVAL. */
+    int beta_mode;
 } cswdg_params;
 
 /* Create a solver bound to the current HIP device and to hip_stream
@@ -367,7 +376,7 @@ int cswdg_last_dt(cswdg_solver* s, double** dt_dev);
  * floating-point atomics).  All buffers device, state layout.  These calls
  * take FP64 single-instance solvers with the default readings (char_mode,
  * weights_mode, lf_mode, gamma_mode, ghost_mode and positivity 0, the KXRCF
- * indicator; any p2_top but 5) and no wall, inflow or moving-shock faces;
+ * indicator; any p2_top but 5; beta_mode 0) and no wall, inflow or moving-shock faces;
  * CSWDG_EINVAL otherwise. */
 
 /* u_bar = L'(u)^T r_bar (the transpose of cswdg_dg_residual linearised at u).

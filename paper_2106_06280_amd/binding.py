@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
                 ("char_mode", ctypes.c_int), ("weights_mode", ctypes.c_int), ("positivity", ctypes.c_int),
                 ("lf_mode", ctypes.c_int), ("p2_top", ctypes.c_int), ("indicator", ctypes.c_int),
                 ("tvb_m", ctypes.c_double), ("gamma_mode", ctypes.c_int), ("ghost_mode", ctypes.c_int),
-                ("reconstruction", ctypes.c_int)]
+                ("reconstruction", ctypes.c_int), ("beta_mode", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -172,11 +172,12 @@ class Solver:
     def __init__(self, equation, degree, limiter_mode=LIMIT_KXRCF, precision=0, gamma=1.4, cfl=0.0,
                  c_k=0.0, eps=0.0, stream=None, kxrcf_norm=0, char_mode=0, weights_mode=0, positivity=0,
                  lf_mode=0, p2_top=0, indicator=INDICATOR_KXRCF, tvb_m=0.0, gamma_mode=0, ghost_mode=0,
-                 reconstruction=0):
+                 reconstruction=0, beta_mode=0):
         import torch
         self.torch = torch
         p = Params(equation, degree, precision, limiter_mode, gamma, cfl, c_k, eps, kxrcf_norm, char_mode,
-                   weights_mode, positivity, lf_mode, p2_top, indicator, tvb_m, gamma_mode, ghost_mode, reconstruction)
+                   weights_mode, positivity, lf_mode, p2_top, indicator, tvb_m, gamma_mode, ghost_mode, reconstruction,
+                   beta_mode)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -168,6 +168,7 @@ int check_single(cswdg_solver* s) {
     if (s->p.reconstruction != 0)
         return fail(s, CSWDG_EINVAL, "adjoint calls take the hierarchical reconstruction (reconstruction = 0)");
     if (s->ctx.qtop == kTopSextic) return fail(s, CSWDG_EINVAL, "adjoint calls do not take the sextic top (p2_top = 5)");
+    if (s->p.beta_mode != 0) return fail(s, CSWDG_EINVAL, "adjoint calls take the smoothness indicators of q_l (beta_mode = 0)");
     return CSWDG_OK;
 }
 
@@ -347,6 +348,9 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     if (p.gamma_mode < 0 || p.gamma_mode > 1) return fail(nullptr, CSWDG_EINVAL, "gamma_mode must be 0 or 1");
     if (p.ghost_mode < 0 || p.ghost_mode > 1) return fail(nullptr, CSWDG_EINVAL, "ghost_mode must be 0 or 1");
     if (p.reconstruction < 0 || p.reconstruction > 1) return fail(nullptr, CSWDG_EINVAL, "reconstruction must be 0 or 1");
+    if (p.beta_mode < 0 || p.beta_mode > 1) return fail(nullptr, CSWDG_EINVAL, "beta_mode must be 0 or 1");
+    if (p.beta_mode == 1 && p.reconstruction != 0)
+        return fail(nullptr, CSWDG_EINVAL, "beta_mode = 1 is a reading of the hierarchical reconstruction (reconstruction = 0)");
     if (p.reconstruction == 1 && (p.degree > 2 || p.ghost_mode != 0))
         return fail(nullptr, CSWDG_EINVAL, "the type-I reconstruction takes N = 1, 2 and the mirror ghost (ghost_mode = 0)");
     if (p.positivity && p.equation != CSWDG_EQ_EULER)
@@ -394,6 +398,7 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
     s->ctx.weights_linear = p.weights_mode;
     s->ctx.qtop = top_for(p.degree, p.p2_top);
     s->ctx.recon = p.reconstruction;
+    s->ctx.beta_lit = p.beta_mode;
     s->ctx.indicator = p.indicator;
     s->ctx.tvb_m = p.tvb_m;
     *out = s;

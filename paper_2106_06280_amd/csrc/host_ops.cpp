@@ -357,10 +357,12 @@ struct OpBuilder {
             valid &= pinv(L::NROW, nc, A, op + L::X5);
         }
 
-        // smoothness-indicator matrix
+        // smoothness-indicator matrix (all derivative orders of the
+        // monomials, and orders 1..N only for the literal reading)
         {
             const int nm = mono.n;
             double B[kMonoMax][kMonoMax] = {{0}};
+            double BL[kMonoMax][kMonoMax] = {{0}};
             double ihp[L::DR + 1], ap[L::DR + 1];
             ihp[0] = 1.0;
             ap[0] = 1.0 / area0;
@@ -393,11 +395,18 @@ struct OpBuilder {
                         double sc = ap[s] * wq;
                         for (int i = 0; i < nm; ++i)
                             for (int j = 0; j < nm; ++j) B[i][j] += sc * Dv[i] * Dv[j];
+                        if (s <= N)
+                            for (int i = 0; i < nm; ++i)
+                                for (int j = 0; j < nm; ++j) BL[i][j] += sc * Dv[i] * Dv[j];
                     }
             }
             int k = 0;
             for (int i = 0; i < nm; ++i)
-                for (int j = i; j < nm; ++j) op[L::BP + k++] = B[i][j];
+                for (int j = i; j < nm; ++j) {
+                    op[L::BP + k] = B[i][j];
+                    op[L::BPL + k] = BL[i][j];
+                    ++k;
+                }
         }
         // projection onto psi_1..psi_{NP-1}
         {

@@ -121,6 +121,7 @@ struct LaunchCtx {
     int weights_linear;    // limiter weights omega = gamma
     int qtop;  // N >= 2: top member of the hierarchy (kTop* below)
     int recon; // 0 the hierarchical reconstruction, 1 type-I WENO
+    int beta_lit;  // 1: smoothness indicators of p_l over orders 1..N (eq. smoothnessIndicator as printed)
     int indicator;         // troubled-cell indicator: 0 KXRCF, 1 TVB minmod
     double tvb_m;          // TVB constant M
 };

@@ -1193,7 +1193,7 @@ struct LimWaves {
     static constexpr int value = OpLayout<N, QTOP>::SEXT ? 1 : (OpLayout<N, QTOP>::FOUR ? 2 : 4);
 };
 
-template <int EQ, int N, typename S, int QTOP>
+template <int EQ, int N, typename S, int QTOP, bool BLIT>
 __global__ __launch_bounds__(64, (LimWaves<N, QTOP>::value)) void k_limiter(DevMesh msh, const S* __restrict__ u,
                                                 const double* __restrict__ ops,
                                                 const int32_t* __restrict__ list,
@@ -1354,12 +1354,43 @@ __global__ __launch_bounds__(64, (LimWaves<N, QTOP>::value)) void k_limiter(DevM
                 c5[jj] = s;
             }
         }
-        // Step 3: smoothness indicators of q_2, q_3 (and q_5)
-        const double* bp = op + LO::BP;
+        // Step 3: smoothness indicators of q_2, q_3 (and the top level), or
+        // (BLIT) of the equivalent polynomials p_2, p_3, p_top over derivative
+        // orders 1..N (eq. smoothnessIndicator as printed)
         double beta[4];
-        beta[1] = quad_form<NM, 2>(bp, c2);
-        beta[2] = quad_form<NM, 5>(bp, c3);
-        beta[3] = quartic ? quad_form<NM, NT>(bp, c5) : 0.0;
+        if constexpr (!BLIT) {
+            const double* bp = op + LO::BP;
+            beta[1] = quad_form<NM, 2>(bp, c2);
+            beta[2] = quad_form<NM, 5>(bp, c3);
+            beta[3] = quartic ? quad_form<NM, NT>(bp, c5) : 0.0;
+        } else {
+            const double* bpl = op + LO::BPL;
+            const double ih = op[LO::GBASE];
+            const double s2 = 1.0 + ih, s3 = 1.0 + ih + ih * ih;
+            const double g22 = ih / s2, g23 = ih / s3, g33 = ih * ih / s3;
+            double p2[2], p3[5], pt[NT];
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) p2[jj] = c2[jj] / g22;
+#pragma unroll
+            for (int jj = 0; jj < 5; ++jj) p3[jj] = (c3[jj] - (jj < 2 ? g23 * p2[jj] : 0.0)) / g33;
+            beta[1] = quad_form<NM, 2>(bpl, p2);
+            beta[2] = quad_form<NM, 5>(bpl, p3);
+            beta[3] = 0.0;
+            if constexpr (quartic) {
+                if constexpr (QTOP == kTopCubic) {
+                    // eq. equivalentOrder3: p_4 = (q_4 - g24 p_2) / g34, weights gamma_{.,4} = gamma_{.,3}
+#pragma unroll
+                    for (int jj = 0; jj < NT; ++jj) pt[jj] = (c5[jj] - (jj < 2 ? g23 * p2[jj] : 0.0)) / g33;
+                } else {
+                    const double s5 = 1.0 + ih + ih * ih + ih * ih * ih;
+                    const double g25 = ih / s5, g35 = ih * ih / s5, g45 = ih * ih * ih / s5;
+#pragma unroll
+                    for (int jj = 0; jj < NT; ++jj)
+                        pt[jj] = (c5[jj] - (jj < 2 ? g25 * p2[jj] : 0.0) - (jj < 5 ? g35 * p3[jj] : 0.0)) / g45;
+                }
+                beta[3] = quad_form<NM, NT>(bpl, pt);
+            }
+        }
         const double area0 = op[LO::AREA0];
         {
             double gx[3], gy[3], b1[3];
@@ -2037,6 +2068,20 @@ hipError_t launch_limiter_t1(const LaunchCtx& c, const DevMesh& m, const void* u
                              const int32_t* list, const uint32_t* count, double* compact, uint32_t* status,
                              int max_cells);
 
+// the limiter's launch with the smoothness-indicator reading as a template
+// argument (the literal reading's extra registers stay out of the default)
+#define CSWDG_LIMITER_LAUNCH(QT)                                                                             \
+    do {                                                                                                     \
+        if (c.beta_lit)                                                                                      \
+            k_limiter<EQ, N, S, QT, true><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact,  \
+                                                                   status, c.gamma, c.eps, c.char_comp,      \
+                                                                   c.weights_linear);                        \
+        else                                                                                                 \
+            k_limiter<EQ, N, S, QT, false><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, \
+                                                                    status, c.gamma, c.eps, c.char_comp,     \
+                                                                    c.weights_linear);                       \
+    } while (0)
+
 hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, const double* ops,
                           const int32_t* list, const uint32_t* count, double* compact, uint32_t* status,
                           int max_cells) {
@@ -2053,30 +2098,24 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
         const int qt = N >= 2 ? c.qtop : kTopQuartic;
         if (N == 1)
-            k_limiter<EQ, N, S, kTopQuartic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
-                                                                       c.gamma, c.eps, c.char_comp, c.weights_linear);
+            CSWDG_LIMITER_LAUNCH(kTopQuartic);
         else if (qt == kTopQuadratic)
-            k_limiter<EQ, N, S, kTopQuadratic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
-                                                                         c.gamma, c.eps, c.char_comp, c.weights_linear);
+            CSWDG_LIMITER_LAUNCH(kTopQuadratic);
         else if (qt == kTopCubic)
-            k_limiter<EQ, N, S, kTopCubic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
-                                                                     c.gamma, c.eps, c.char_comp, c.weights_linear);
+            CSWDG_LIMITER_LAUNCH(kTopCubic);
         else if (qt == kTopCubicTel)
-            k_limiter<EQ, N, S, kTopCubicTel><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
-                                                                        c.gamma, c.eps, c.char_comp, c.weights_linear);
+            CSWDG_LIMITER_LAUNCH(kTopCubicTel);
         else if (qt == kTopSextic) {
             if constexpr (N == 3)
-                k_limiter<EQ, N, S, kTopSextic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact,
-                                                                          status, c.gamma, c.eps, c.char_comp,
-                                                                          c.weights_linear);
+                CSWDG_LIMITER_LAUNCH(kTopSextic);
             else
                 return hipErrorInvalidValue;
         } else
-            k_limiter<EQ, N, S, kTopQuartic><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
-                                                                       c.gamma, c.eps, c.char_comp, c.weights_linear);
+            CSWDG_LIMITER_LAUNCH(kTopQuartic);
     });
     return hipGetLastError();
 }
+#undef CSWDG_LIMITER_LAUNCH
 
 hipError_t launch_limiter_t1(const LaunchCtx& c, const DevMesh& m, const void* u, const double* ops,
                              const int32_t* list, const uint32_t* count, double* compact, uint32_t* status,

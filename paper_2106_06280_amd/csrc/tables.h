@@ -83,7 +83,8 @@ struct OpLayout {
     static constexpr int X3 = X2 + 2 * 3;                           // [5][9]   pinv, quadratic level
     static constexpr int X5 = X3 + 5 * 9;                           // [NT][NROW] pinv, top level on T4 or T5
     static constexpr int BP = X5 + NT * NROW;                       // packed upper triangle of the beta matrix
-    static constexpr int MINV = BP + NBP;                           // [3][2][2] inverse centroid-difference matrices
+    static constexpr int BPL = BP + NBP;                            // the same over derivative orders 1..N only
+    static constexpr int MINV = BPL + NBP;                          // [3][2][2] inverse centroid-difference matrices
     static constexpr int PM = MINV + 12;                            // [NP-1][NM] projection onto psi_1..
     static constexpr int GBASE = PM + (D::NP - 1) * NM;             // base b of the linear weights b^(l-1): 1/h0 or 10
     static constexpr int AREA0 = GBASE + 1;                         // area of Delta0

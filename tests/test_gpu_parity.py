@@ -520,3 +520,48 @@ def test_limiter_with_no_troubled_cell(torch, eq, N):
     Sn.ssprk3_step(un)
     assert Sk.troubled_count() == 0
     assert torch.equal(uk, un)
+
+
+@pytest.mark.parametrize("N,p2_top", [(1, 0), (2, 0), (2, 2), (2, 4), (3, 0), (3, 5)])
+@pytest.mark.parametrize("eq", [0, 1])
+def test_limiter_literal_smoothness_indicators(torch, eq, N, p2_top):
+    """beta_mode = 1: the smoothness indicators of the equivalent
+    polynomials p_l over derivative orders 1..N (eq. smoothnessIndicator as
+    printed) in place of those of q_l, with every cell limited and over three
+    KXRCF-limited steps, against the oracle's beta_literal reading (for the
+    default, the quartic and the printed cubic tops of N = 2 and the default
+    and sextic tops of N = 3)."""
+    b = _binding()
+    top = b.top_name(N, p2_top)
+    v, t = inputs.jittered_mesh(10, seed=181 + N)
+    M = Mesh(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    dg = DG(M, N, eq)
+    S = b.Solver(eq, N, p2_top=p2_top, beta_mode=1)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    u = _jump_state(dg, eq, seed=8)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    exp = csweno.limit(dg, u, np.ones(M.K, bool), top=top, beta_literal=True)
+    assert _relerr(S.to_host(out), exp) < TOL
+    # a different reading from the default one on the same data
+    assert np.abs(exp - csweno.limit(dg, u, np.ones(M.K, bool), top=top)).max() > 1e-8
+    ud = S.to_device(u)
+    lim = lambda w: csweno.limit(dg, w, kxrcf.indicator(dg, w)[1], top=top, beta_literal=True)
+    for _ in range(3):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    assert _relerr(S.to_host(ud), u) < steps_tol(3), _relerr(S.to_host(ud), u)
+
+
+def test_literal_smoothness_indicators_validation(torch):
+    b = _binding()
+    for bad in (-1, 2):
+        with pytest.raises(b.CswdgError):
+            b.Solver(1, 2, beta_mode=bad)
+    with pytest.raises(b.CswdgError):
+        b.Solver(1, 2, beta_mode=1, reconstruction=1)
+    v, t = inputs.jittered_mesh(4, seed=3)
+    S = b.Solver(1, 2, beta_mode=1)
+    S.mesh_upload(v, t, BC_PERIODIC, (1.0, 1.0))
+    u = S.project_fn(inputs.IsentropicVortex(beta=1.0, x0=0.5, y0=0.5, period_x=1.0, period_y=1.0))
+    with pytest.raises(b.CswdgError):
+        S.csweno_limit_vjp(u, u.clone())
