@@ -95,8 +95,16 @@ __global__ __launch_bounds__(256) void k_residual_vjp(DevMesh msh, const double*
     constexpr int M = Phys<EQ>::M, NP = D::NP, NE = D::NE, NQ = D::NQ;
     const int K = msh.K;
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
-    if (e >= K) return;
     const Tab<N>& T = tab<N>();
+    // the face-point tables in LDS: the neighbour's side reads them at the
+    // neighbour's own face (a per-lane index)
+    __shared__ double sPF[3 * NE * NP], sWPF[3 * NE * NP];
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += blockDim.x) {
+        sPF[i] = (&T.PF[0][0][0])[i];
+        sWPF[i] = (&T.wPF[0][0][0])[i];
+    }
+    __syncthreads();
+    if (e >= K) return;
     const double scale = dtp ? c_dt * (*dtp) : c_dt;
 
     double U[M][NP], Rb[M][NP], Ub[M][NP];
@@ -180,9 +188,9 @@ __global__ __launch_bounds__(256) void k_residual_vjp(DevMesh msh, const double*
 #pragma unroll
                 for (int n = 0; n < NP; ++n) {
                     s += T.PF[f][g][n] * U[c][n];
-                    t += T.PF[fp][NE - 1 - g][n] * Un[c][n];
+                    t += sPF[(fp * NE + NE - 1 - g) * NP + n] * Un[c][n];
                     fo += Rb[c][n] * T.wPF[f][g][n];
-                    fn += Rbn[c][n] * T.wPF[fp][NE - 1 - g][n];
+                    fn += Rbn[c][n] * sWPF[(fp * NE + NE - 1 - g) * NP + n];
                 }
                 um[c] = s;
                 up[c] = t;

@@ -332,9 +332,15 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
     const int K = msh.K;
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     if (cnt_reset != nullptr && blockIdx.x == 0 && threadIdx.x < kListSegs) cnt_reset[threadIdx.x * kCountStride] = 0u;
+    const auto& T = TabOf<N, R>::get();
+    // the face-point table in LDS: the neighbour's trace reads it at the
+    // neighbour's own face (a per-lane index), which from constant memory
+    // would be one vector-memory access per entry
+    __shared__ R sPF[3 * NE * NP];
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += blockDim.x) sPF[i] = (&T.PF[0][0][0])[i];
+    __syncthreads();
     if (e >= K) return;
     const double ag = lf_global(msh, e);  // < 0: local Lax-Friedrichs
-    const auto& T = TabOf<N, R>::get();
     const R gm = (R)gamma;
 
     R U[M][NP];
@@ -405,7 +411,7 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
 #pragma unroll
                 for (int n = 0; n < NP; ++n) {
                     a += T.PF[f][g][n] * U[c][n];
-                    b += T.PF[fp][gr - g][n] * u[(size_t)(c * NP + n) * K + nb];
+                    b += sPF[(fp * NE + gr - g) * NP + n] * u[(size_t)(c * NP + n) * K + nb];
                 }
                 um[c] = a;
                 upg[c] = bnd ? a : b;
@@ -975,6 +981,11 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
     const int K = msh.K;
     const int e = xcd_block(blockIdx.x, gridDim.x, msh.xcd_tiles) * blockDim.x + threadIdx.x;
     bool tr = false;
+    // the face-point table in LDS (the neighbour's trace reads it at the
+    // neighbour's own face: a per-lane index)
+    __shared__ double sPF[3 * NE * NP];
+    for (int i = threadIdx.x; i < 3 * NE * NP; i += blockDim.x) sPF[i] = (&tab<N>().PF[0][0][0])[i];
+    __syncthreads();
     if (e < K) {
         const Tab<N>& T = tab<N>();
         double U0[NP], U1[NP], U2[NP];
@@ -1016,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
                         mu += T.PF[f][g][n] * U1[n];
                         mv += T.PF[f][g][n] * U2[n];
                     }
-                    upv += T.PF[fp][NE - 1 - g][n] * Un[n];
+                    upv += sPF[(fp * NE + NE - 1 - g) * NP + n] * Un[n];
                 }
                 double vx, vy;
                 if constexpr (EQ == 1) {
