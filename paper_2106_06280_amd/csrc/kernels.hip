@@ -383,6 +383,13 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
     }
 
     const uint32_t info4 = msh.info[e];
+    // 1 / J with 2 J = area: the surface scale L_f / (2 J) per face
+    double iJf;
+    {
+        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
+        iJf = 1.0 / (0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)));
+    }
 #pragma unroll 1
     for (int f = 0; f < 3; ++f) {
         const int f1 = (f == 2) ? 0 : f + 1;
@@ -392,11 +399,7 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
         const double L = sqrt(ex * ex + ey * ey);
         const double iL = 1.0 / L;
         const R nx = (R)(ey * iL), ny = (R)(-ex * iL);
-        // L_f / (2 J) with 2 J = area; recomputed from the vertices
-        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
-        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
-        const double J = 0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
-        const R sf = (R)(0.5 * L / J);
+        const R sf = (R)(0.5 * L * iJf);
         const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
         const bool bnd = (inf & 0x40u) != 0u;
         const int fp = bnd ? 0 : (int)(inf & 3u);
