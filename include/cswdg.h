@@ -163,8 +163,15 @@ typedef struct cswdg_params {
      * of Delta0 exact, combined with weights lambda_k / (1e-14 + beta_k)^4
      * (lambda 1e5 central, 1 sectors; beta of eq. smoothnessIndicator);
      * the boundary ghosts are those of the hierarchical one (the mirror image
-     * and the boundary kinds, ghost_mode 0).  N = 3, ghost_mode 1 or the
-     * adjoint calls with 1: CSWDG_EINVAL. */
+     * and the boundary kinds, ghost_mode 0); 2 a type-II WENO reconstruction
+     * (N = 2 only): linear least-squares fits on the three single-neighbour
+     * stencils (each neighbour's three centroid subcells) and on the three
+     * sectors, combined at each of the 9 points of the degree-4 rule on
+     * Delta0 with linear weights of minimal distance to 1/6 that reproduce
+     * the quadratic fit on T3, negative weights split into two positive
+     * groups (Shi, Hu and Shu), nonlinear weights gamma_j / (1e-10 + beta_j)^2
+     * per group, then projected onto P2.  1 with N = 3, 2 with N != 2,
+     * ghost_mode 1, or the adjoint calls with 1 or 2: CSWDG_EINVAL. */
     int reconstruction;
     /* the smoothness indicators beta_l, l >= 2, of the hierarchical
      * reconstruction (Section 3.2, Step 3, eq. smoothnessIndicator):

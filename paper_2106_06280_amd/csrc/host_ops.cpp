@@ -685,6 +685,256 @@ int build_type1_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t&
     return CSWDG_EINVAL;
 }
 
+// The record of the type-II reconstruction (OpLayoutT2, N = 2): the
+// centroid-subcell geometry of the hierarchical one, linear least-squares
+// fits on the single-neighbour and sector stencils, and at the 9 points of
+// the degree-4 rule the linear weights of minimal distance to 1/6 that make
+// the six linear fits reproduce the quadratic fit on T3 (exact for
+// quadratic data: sum_j g_j = 1, sum_j g_j L_j[phi_k](x) = phi_k(x) for the
+// three quadratic scaled monomials).
+struct OpBuilderT2 {
+    using L = OpLayoutT2;
+    static constexpr int N = 2, NP = 6, NM = 5;
+    const HostMesh& m;
+    std::vector<double> C;
+    Rule2D rN, rTop, rQ;
+    std::vector<double> psiQ;  // [q][NP] at the reference points of rQ
+    MonoList mono{2};
+
+    explicit OpBuilderT2(const HostMesh& mm) : m(mm) {
+        basis_monomial_form(N, C);
+        rN = triangle_rule((N + 2) / 2);
+        rTop = triangle_rule((N + 2) / 2);
+        rQ = triangle_rule(3);  // degree 4: the points where R is evaluated
+        psiQ.resize(rQ.w.size() * NP);
+        for (size_t q = 0; q < rQ.w.size(); ++q) basis_eval(N, rQ.r[q], rQ.s[q], &psiQ[q * NP]);
+    }
+
+    P2d vert(int64_t e, int k) const { return {m.vx[k * m.K + e], m.vy[k * m.K + e]}; }
+
+    void psi_mono(double r, double s, double* psi) const {
+        double pw[NP];
+        int k = 0;
+        for (int d = 0; d <= N; ++d)
+            for (int bb = 0; bb <= d; ++bb) {
+                double v = 1.0;
+                for (int t = 0; t < d - bb; ++t) v *= r;
+                for (int t = 0; t < bb; ++t) v *= s;
+                pw[k++] = v;
+            }
+        for (int n = 0; n < NP; ++n) {
+            double acc = 0;
+            for (int kk = 0; kk < NP; ++kk) acc += C[n * NP + kk] * pw[kk];
+            psi[n] = acc;
+        }
+    }
+
+    void to_ref(int64_t src, P2d x, double& r, double& s) const {
+        P2d v0 = vert(src, 0), v1 = vert(src, 1), v2 = vert(src, 2);
+        double xr = 0.5 * (v1.x - v0.x), xs = 0.5 * (v2.x - v0.x);
+        double yr = 0.5 * (v1.y - v0.y), ys = 0.5 * (v2.y - v0.y);
+        double J = xr * ys - xs * yr;
+        double dx = x.x - v0.x, dy = x.y - v0.y;
+        r = -1.0 + (ys * dx - xs * dy) / J;
+        s = -1.0 + (-yr * dx + xr * dy) / J;
+    }
+
+    static P2d map_tri(const P2d* T, double r, double s) {
+        return T[0] + (0.5 * (1.0 + r)) * (T[1] - T[0]) + (0.5 * (1.0 + s)) * (T[2] - T[0]);
+    }
+
+    void mono_eval(P2d x, P2d c0, double h0, double* out) const {
+        double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
+        for (int j = 0; j < mono.n; ++j) {
+            double v = 1.0;
+            for (int t = 0; t < mono.a[j]; ++t) v *= xi;
+            for (int t = 0; t < mono.b[j]; ++t) v *= eta;
+            out[j] = v;
+        }
+    }
+
+    // solves the 4 x 4 system A x = b in place (partial pivoting)
+    static bool solve4(double A[4][4], double b[4]) {
+        for (int k = 0; k < 4; ++k) {
+            int piv = k;
+            for (int i = k + 1; i < 4; ++i)
+                if (std::fabs(A[i][k]) > std::fabs(A[piv][k])) piv = i;
+            if (!(std::fabs(A[piv][k]) > 0.0)) return false;
+            if (piv != k) {
+                for (int j = 0; j < 4; ++j) std::swap(A[k][j], A[piv][j]);
+                std::swap(b[k], b[piv]);
+            }
+            for (int i = k + 1; i < 4; ++i) {
+                const double f = A[i][k] / A[k][k];
+                for (int j = k; j < 4; ++j) A[i][j] -= f * A[k][j];
+                b[i] -= f * b[k];
+            }
+        }
+        for (int k = 3; k >= 0; --k) {
+            double t = b[k];
+            for (int j = k + 1; j < 4; ++j) t -= A[k][j] * b[j];
+            b[k] = t / A[k][k];
+        }
+        return true;
+    }
+
+    bool build(int64_t e, double* op) const {
+        for (int i = 0; i < L::LEN; ++i) op[i] = 0.0;
+        P2d V0[3] = {vert(e, 0), vert(e, 1), vert(e, 2)};
+        P2d c0 = (1.0 / 3.0) * (V0[0] + V0[1] + V0[2]);
+        double h0 = (std::sqrt(dot(V0[1] - V0[0], V0[1] - V0[0])) + std::sqrt(dot(V0[2] - V0[1], V0[2] - V0[1])) +
+                     std::sqrt(dot(V0[0] - V0[2], V0[0] - V0[2]))) / 3.0;
+        double area0 = tri_area(V0[0], V0[1], V0[2]);
+        double mavg0[NM] = {0}, tmp[NM];
+        {
+            double wsum = 0;
+            for (size_t q = 0; q < rTop.w.size(); ++q) {
+                mono_eval(map_tri(V0, rTop.r[q], rTop.s[q]), c0, h0, tmp);
+                for (int j = 0; j < NM; ++j) mavg0[j] += rTop.w[q] * tmp[j];
+                wsum += rTop.w[q];
+            }
+            for (int j = 0; j < NM; ++j) mavg0[j] /= wsum;
+        }
+        double mavg[3][3][NM];  // [face][piece][monomial], minus the mean over e
+        for (int f = 0; f < 3; ++f) {
+            uint8_t inf = m.info[3 * e + f];
+            bool mirror = false;
+            P2d shift{0.0, 0.0}, P{0, 0}, Q{0, 0}, W[3];
+            int fp;
+            int64_t src;
+            if (inf & 0x40) {
+                mirror = true;
+                P = V0[f];
+                Q = V0[(f + 1) % 3];
+                P2d d = Q - P;
+                P2d X = V0[(f + 2) % 3];
+                P2d F = P + (dot(X - P, d) / dot(d, d)) * d;
+                W[0] = Q;
+                W[1] = P;
+                W[2] = 2.0 * F - X;
+                fp = 0;
+                src = e;
+            } else {
+                int cx = (inf >> 2) & 3, cy = (inf >> 4) & 3;
+                shift = {cx == 1 ? m.px : (cx == 2 ? -m.px : 0.0), cy == 1 ? m.py : (cy == 2 ? -m.py : 0.0)};
+                src = m.nbr[3 * e + f];
+                for (int k = 0; k < 3; ++k) W[k] = vert(src, k) + shift;
+                fp = inf & 3;
+            }
+            auto back = [&](P2d x) {
+                if (!mirror) return x - shift;
+                P2d d = Q - P;
+                P2d F = P + (dot(x - P, d) / dot(d, d)) * d;
+                return 2.0 * F - x;
+            };
+            P2d G = (1.0 / 3.0) * (W[0] + W[1] + W[2]);
+            P2d wa = W[fp], wb = W[(fp + 1) % 3], wc = W[(fp + 2) % 3];
+            P2d pcs[3][3] = {{G, wa, wb}, {G, wb, wc}, {G, wc, wa}};
+            for (int p = 0; p < 3; ++p) {
+                double acc[NP] = {0}, psi[NP], wsum = 0;
+                for (size_t q = 0; q < rN.w.size(); ++q) {
+                    double r, s;
+                    to_ref(src, back(map_tri(pcs[p], rN.r[q], rN.s[q])), r, s);
+                    psi_mono(r, s, psi);
+                    for (int n = 0; n < NP; ++n) acc[n] += rN.w[q] * psi[n];
+                    wsum += rN.w[q];
+                }
+                for (int n = 0; n < NP; ++n) op[L::AVG + (f * 3 + p) * NP + n] = acc[n] / wsum;
+                double ma[NM] = {0};
+                wsum = 0;
+                for (size_t q = 0; q < rTop.w.size(); ++q) {
+                    mono_eval(map_tri(pcs[p], rTop.r[q], rTop.s[q]), c0, h0, tmp);
+                    for (int j = 0; j < NM; ++j) ma[j] += rTop.w[q] * tmp[j];
+                    wsum += rTop.w[q];
+                }
+                for (int j = 0; j < NM; ++j) mavg[f][p][j] = ma[j] / wsum - mavg0[j];
+            }
+        }
+        bool valid = true;
+        // the six linear fits: pseudo-inverses, and the fits of the three
+        // quadratic monomials' averages, Lq[j][k][c]
+        double Lq[6][3][2];
+        for (int j = 0; j < 6; ++j) {
+            const bool sector = j >= 3;
+            const int fa = sector ? j - 3 : j, fb = (fa + 1) % 3;
+            const int nr = sector ? 6 : 3;
+            double A[6 * 2], X[2 * 6];
+            for (int p = 0; p < 3; ++p)
+                for (int i = 0; i < (sector ? 2 : 1); ++i) {
+                    const int row = sector ? p * 2 + i : p, f = i == 0 ? fa : fb;
+                    for (int c = 0; c < 2; ++c) A[row * 2 + c] = mavg[f][p][c];
+                }
+            valid &= pinv(nr, 2, A, X);
+            double* dst = sector ? op + L::XS + (j - 3) * 12 : op + L::XF + j * 6;
+            for (int i = 0; i < 2 * nr; ++i) dst[i] = X[i];
+            for (int k = 0; k < 3; ++k)
+                for (int c = 0; c < 2; ++c) {
+                    double t = 0.0;
+                    for (int p = 0; p < 3; ++p)
+                        for (int i = 0; i < (sector ? 2 : 1); ++i) {
+                            const int row = sector ? p * 2 + i : p, f = i == 0 ? fa : fb;
+                            t += X[c * nr + row] * mavg[f][p][2 + k];
+                        }
+                    Lq[j][k][c] = t;
+                }
+        }
+        // the points of the degree-4 rule: linear weights, linear monomials,
+        // projection weights
+        for (size_t q = 0; q < rQ.w.size(); ++q) {
+            double ph[NM];
+            mono_eval(map_tri(V0, rQ.r[q], rQ.s[q]), c0, h0, ph);
+            for (int j = 0; j < NM; ++j) ph[j] -= mavg0[j];
+            op[L::PHI + q * 2 + 0] = ph[0];
+            op[L::PHI + q * 2 + 1] = ph[1];
+            double Am[4][6], b[4] = {1.0, ph[2], ph[3], ph[4]};
+            for (int j = 0; j < 6; ++j) {
+                Am[0][j] = 1.0;
+                for (int k = 0; k < 3; ++k) Am[1 + k][j] = ph[0] * Lq[j][k][0] + ph[1] * Lq[j][k][1];
+            }
+            // g = 1/6 + A^T (A A^T)^{-1} (b - A g0)
+            double r4[4], AAt[4][4];
+            for (int i = 0; i < 4; ++i) {
+                double t = b[i];
+                for (int j = 0; j < 6; ++j) t -= Am[i][j] / 6.0;
+                r4[i] = t;
+                for (int k = 0; k < 4; ++k) {
+                    double a = 0.0;
+                    for (int j = 0; j < 6; ++j) a += Am[i][j] * Am[k][j];
+                    AAt[i][k] = a;
+                }
+            }
+            valid &= solve4(AAt, r4);
+            for (int j = 0; j < 6; ++j) {
+                double g = 1.0 / 6.0;
+                for (int i = 0; i < 4; ++i) g += Am[i][j] * r4[i];
+                op[L::GAM + q * 6 + j] = g;
+            }
+            for (int i = 1; i < NP; ++i) op[L::PMQ + (i - 1) * L::NQ + q] = rQ.w[q] * psiQ[q * NP + i];
+        }
+        op[L::BSC] = area0 / (h0 * h0);
+        op[L::VALID] = valid ? 1.0 : 0.0;
+        return valid;
+    }
+};
+
+int build_type2_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank) {
+    using L = OpLayoutT2;
+    OpBuilderT2 b(m);
+    ops.assign((size_t)m.K * L::LEN, 0.0);
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<int64_t> rank(nt, 0);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int64_t e = t; e < m.K; e += nt)
+                if (!b.build(e, &ops[(size_t)e * L::LEN])) ++rank[t];
+        });
+    for (auto& x : th) x.join();
+    n_rank = 0;
+    for (unsigned t = 0; t < nt; ++t) n_rank += rank[t];
+    return CSWDG_OK;
+}
+
 // TVB minmod indicator (Cockburn and Shu's limiter for triangles): for each
 // element (centroid b0) and face midpoint m_i, coefficients A[3 i + f] with
 // m_i - b0 = sum_f A[3 i + f] (b_f - b0), b_f the centroid of the neighbour

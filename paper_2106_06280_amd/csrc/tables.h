@@ -114,4 +114,26 @@ struct OpLayoutT1 {
     static constexpr int LEN = (RAW + 7) / 8 * 8;
 };
 
+// Layout of the per-element record of the type-II reconstruction (N = 2):
+// the centroid-subcell average functionals, the pseudo-inverses of the
+// linear fits on the three single-neighbour stencils (rows: the neighbour's
+// three pieces) and on the three sectors (faces k, k+1; rows piece-major,
+// then the two faces), and at the 9 points of the degree-4 rule on Delta0
+// the six linear weights, the two mean-free scaled linear monomials and the
+// projection weights w_q psi_i(x_q); BSC = |Delta0| / h0^2 (the smoothness
+// indicator of a linear fit is BSC |c|^2 in its scaled coefficients).
+struct OpLayoutT2 {
+    static constexpr int NP = 6, NQ = 9, NJ = 6;
+    static constexpr int AVG = 0;                 // [3][3][NP]
+    static constexpr int XF = AVG + 9 * NP;       // [3][2][3]
+    static constexpr int XS = XF + 3 * 2 * 3;     // [3][2][6]
+    static constexpr int GAM = XS + 3 * 2 * 6;    // [NQ][NJ]
+    static constexpr int PHI = GAM + NQ * NJ;     // [NQ][2]
+    static constexpr int PMQ = PHI + NQ * 2;      // [NP-1][NQ]
+    static constexpr int BSC = PMQ + (NP - 1) * NQ;
+    static constexpr int VALID = BSC + 1;
+    static constexpr int RAW = VALID + 1;
+    static constexpr int LEN = (RAW + 7) / 8 * 8;
+};
+
 }  // namespace cswdg
