@@ -591,10 +591,54 @@ def adjoint_ratio(S, u, fwd_ms_per_step, reps=5):
         times.append(ev0.elapsed_time(ev1))
     t = sorted(times)[len(times) // 2]
     ok = bool(torch.isfinite(ubar).all())
+    # per-kernel times of one more VJP, and the residual VJP against the HBM
+    # roofline: per element it reads u and the incoming adjoint and writes
+    # the outgoing one (3 S), plus the geometry (neighbour reads are the
+    # same arrays)
+    S.profile(True)
+    S.ssprk3_step_vjp(tape, ybar, ubar)
+    kt = S.kernel_times()
+    S.profile(False)
     del tape
-    return {"ratio": round(t / fwd_ms_per_step, 3), "vjp_ms_per_step": round(t, 3),
-            "fwd_ms_per_step": round(fwd_ms_per_step, 3), "finite": ok,
-            "what": "step VJP (3 x limiter VJP with frozen troubled set + residual/RK VJP) / forward step"}
+    out = {"ratio": round(t / fwd_ms_per_step, 3), "vjp_ms_per_step": round(t, 3),
+           "fwd_ms_per_step": round(fwd_ms_per_step, 3), "finite": ok,
+           "what": "step VJP (3 x limiter VJP with frozen troubled set + residual/RK VJP) / forward step",
+           "kernel_ms_per_step": {k: round(a, 4) for k, (a, b) in kt.items() if b}}
+    if "residual_vjp" in kt and kt["residual_vjp"][1]:
+        avg = kt["residual_vjp"][0] / kt["residual_vjp"][1] / 1000.0
+        Sb = 8 * S.Np * S.m
+        b = S.K * (3 * Sb + 64)
+        out["residual_vjp_roofline"] = {"bound": "hbm", "achieved": round(b / avg / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": round(b / avg / 1e9 / HBM_PEAK_GBS, 4),
+                                        "avg_launch_us": round(avg * 1e6, 2), "algorithmic_bytes_per_launch": int(b)}
+    return out
+
+
+def matrix_schedule_us(S, u, reps=5):
+    """Microseconds per residual launch (mode 0) of the compact schedule and
+    of the matrix-core one on the same state (P2 FP64 only), the schedule
+    restored afterwards."""
+    import torch
+    if S.degree != 2 or S.precision != 0:
+        return None
+    saved = S.get_schedule()
+    res = {}
+    for name, var in (("compact", 3), ("matrix", 4)):
+        S.set_schedule(var, 128, 1)
+        S.dg_residual(u)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            S.dg_residual(u)
+        ev1.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = round(1000.0 * ev0.elapsed_time(ev1) / reps, 2)
+    S.set_schedule(*saved)
+    res["what"] = ("residual launch (mode 0) of the compact VALU schedule and of the matrix-core schedule "
+                   "(v_mfma_f64_16x16x4 evaluations and projections), same state")
+    return res
 
 
 def measured_traffic(workload):
@@ -899,6 +943,7 @@ def main():
         roof["stage_bytes_per_dof"] = round(b_elem / (Np * m), 2)
     adjoint_ok = precision == 0 and opts["indicator"] == 0 and opts["gamma_mode"] == 0
     adj = None if (args.no_adjoint or not adjoint_ok) else adjoint_ratio(S, u, secs * 1e3 / args.steps)
+    sched = None if args.no_profile else matrix_schedule_us(S, u)
     out = {
         "metric": METRICS[args.workload],
         "value": value,
@@ -922,6 +967,7 @@ def main():
         "roofline": roof,
         "us_per_stage": {"plain": round(secs * 1e6 / stages, 2), "graph": round(secs_graph * 1e6 / stages, 2)},
         "adjoint": adj,
+        "residual_schedules": sched,
         "kernel_ms_per_step": {k: round(a / 3, 4) for k, (a, b) in breakdown.items() if b},
         "status_bits": status,
     }
