@@ -169,8 +169,9 @@ typedef struct cswdg_params {
      * sectors, combined at each of the 9 points of the degree-4 rule on
      * Delta0 with linear weights of minimal distance to 1/6 that reproduce
      * the quadratic fit on T3, negative weights split into two positive
-     * groups (Shi, Hu and Shu), nonlinear weights gamma_j / (1e-10 + beta_j)^2
-     * per group, then projected onto P2.  1 with N = 3, 2 with N != 2,
+     * groups (Shi, Hu and Shu), nonlinear weights of the WENO-Z form
+     * gamma_j (1 + (tau / (1e-10 + beta_j))^2) per group (tau = max beta -
+     * min beta), then projected onto P2.  1 with N = 3, 2 with N != 2,
      * ghost_mode 1, or the adjoint calls with 1 or 2: CSWDG_EINVAL. */
     int reconstruction;
     /* the smoothness indicators beta_l, l >= 2, of the hierarchical

@@ -20,9 +20,14 @@ paper gives no type-II details; the readings:
   Q(x) for all data);
 * negative weights by the splitting of Shi, Hu and Shu (J. Comput. Phys.
   175, 2002): gamma+ = (gamma + 3 |gamma|) / 2, gamma- = gamma+ - gamma,
-  sigma+- = sum gamma+-, nonlinear weights
-  omega+-_j = (gamma+-_j / sigma+-) / (EPS2 + beta_j)^2 normalised, and
-  R(x) = sigma+ sum_j omega+_j L_j(x) - sigma- sum_j omega-_j L_j(x);
+  sigma+- = sum gamma+-, nonlinear weights of the WENO-Z form
+  omega+-_j = (gamma+-_j / sigma+-) (1 + (tau / (EPS2 + beta_j))^2)
+  normalised, tau = max_j beta_j - min_j beta_j, and
+  R(x) = sigma+ sum_j omega+_j L_j(x) - sigma- sum_j omega-_j L_j(x)
+  (away from extrema the beta_j differ at O(h) relative and omega moves
+  off gamma at O(h^2); the classical form gamma_j / (EPS2 + beta_j)^2
+  moves at O(h): one application measured 2.66, 2.82, 2.93 against 2.46,
+  2.57, 2.67 on 16-128 squares);
 * beta_j = |Delta0| |grad L_j|^2 (eq. smoothnessIndicator of a linear
   function);
 * R is evaluated at the points of the degree-4 rule on Delta0 and
@@ -171,8 +176,10 @@ def reconstruct_type2(dg: DG, u, elems, return_info=False, characteristic=True, 
             continue
         gp, gm, sp, sm = split(g)
         B = np.stack(beta, axis=1)  # [T, J, F]
-        wp = (gp / sp[:, None])[..., None] / (EPS2 + B) ** 2
-        wm = (gm / sm[:, None])[..., None] / (EPS2 + B) ** 2
+        tau = B.max(axis=1, keepdims=True) - B.min(axis=1, keepdims=True)
+        z = 1.0 + (tau / (EPS2 + B)) ** 2
+        wp = (gp / sp[:, None])[..., None] * z
+        wm = (gm / sm[:, None])[..., None] * z
         wp = wp / wp.sum(axis=1, keepdims=True)
         wm = wm / wm.sum(axis=1, keepdims=True)
         Rq[:, q] = sp[:, None] * np.sum(wp * Lx, axis=1) - sm[:, None] * np.sum(wm * Lx, axis=1)

@@ -1758,8 +1758,9 @@ __global__ __launch_bounds__(64, 3) void k_limiter_t1(DevMesh msh, const S* __re
 // stencils and the three sectors, their smoothness indicators, and at the
 // nine points of the degree-4 rule the stored linear weights split into two
 // positive groups (gamma+- of Shi, Hu and Shu), nonlinear weights
-// (gamma+-_j / sigma+-) / (1e-10 + beta_j)^2 per group, R(x_q) =
-// sigma+ R+ - sigma- R-, and the projection sum_q w_q R(x_q) psi_i(x_q).
+// (gamma+-_j / sigma+-) (1 + (tau / (1e-10 + beta_j))^2) per group with tau
+// = max beta - min beta, R(x_q) = sigma+ R+ - sigma- R-, and the projection
+// sum_q w_q R(x_q) psi_i(x_q).
 template <int EQ, typename S>
 __global__ __launch_bounds__(64, 3) void k_limiter_t2(DevMesh msh, const S* __restrict__ u,
                                                 const double* __restrict__ ops,
@@ -1908,11 +1909,21 @@ __global__ __launch_bounds__(64, 3) void k_limiter_t2(DevMesh msh, const S* __re
                 cl[3 + sk][jj] = s;
             }
         }
+        // WENO-Z form: iw_j = 1 + (tau / (EPS2 + beta_j))^2, tau = max beta - min beta
         const double bsc = op[LO::BSC];
+        double bmax = 0.0, bmin = 0.0;
 #pragma unroll
         for (int jj = 0; jj < 6; ++jj) {
-            const double b = EPS2 + bsc * (cl[jj][0] * cl[jj][0] + cl[jj][1] * cl[jj][1]);
-            iw[jj] = 1.0 / (b * b);
+            const double b = bsc * (cl[jj][0] * cl[jj][0] + cl[jj][1] * cl[jj][1]);
+            iw[jj] = b;
+            bmax = (jj == 0) ? b : fmax(bmax, b);
+            bmin = (jj == 0) ? b : fmin(bmin, b);
+        }
+        const double tau = bmax - bmin;
+#pragma unroll
+        for (int jj = 0; jj < 6; ++jj) {
+            const double r = tau / (EPS2 + iw[jj]);
+            iw[jj] = 1.0 + r * r;
         }
         // at each point: the split linear weights, the nonlinear weights of
         // each group, R(x_q), and its contribution to the moments

@@ -17,12 +17,15 @@ from paper_2106_06280_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-# With every cell limited at every stage the type-II reconstruction's
-# weights (gamma_j / (eps + beta_j)^2 per group) move off the linear weights
-# at O(h) on smooth data, so each application leaves an O(h^3) change that
-# the ~1/h applications accumulate to second order: measured 2.14 (Burgers)
-# and 2.02 (entropy wave) on 80 -> 160 squares, against the hierarchical
-# reconstruction's 3.0.
+# With every cell limited at every stage the type-II reconstruction
+# converges at second order: its linear weights are O(1) (some negative), so
+# near the data's extrema, where the smoothness indicators are all small and
+# their spread tau is of their own size, the nonlinear weights leave the
+# linear ones by O(1) and R leaves the T3 quadratic by O(h^2) on a band of
+# O(h) width, every stage (measured: 2.16 for Burgers on 80 -> 160 squares
+# with the Z-type weights, 2.14 with the classical ones; the hierarchical
+# reconstruction's h-dependent linear weights keep its top member's weight
+# at 1 - O(h) and reach 3.0).
 MIN_ORDER = 1.8
 ORDERS = oracle_runs.load_orders()
 
