@@ -641,18 +641,32 @@ def matrix_schedule_us(S, u, reps=5):
     return res
 
 
+def residual_kernel_fingerprint():
+    """sha256 of the source the default residual kernel is compiled from: the
+    text of residual_body_compact and k_residual_compact_d in kernels.hip,
+    and the headers it includes (device_common.h, tables.h)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2106_06280_amd", "csrc")
+    k = open(os.path.join(csrc, "kernels.hip")).read()
+    i0 = k.index("__device__ __forceinline__ void residual_body_compact(")
+    i1 = k.index("residual_body_compact<EQ, N, MODE, double>(msh, u, un, out, dtp, gamma, cnt_reset);", i0)
+    i1 = k.index("}", i1) + 1
+    h = hashlib.sha256(k[i0:i1].encode())
+    for name in ("device_common.h", "tables.h"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload):
     """Per-launch HBM bytes of the residual kernel from the committed counter
     summary, or None when that summary was taken on a different kernel
-    source or workload."""
-    import hashlib
+    source (residual_kernel_fingerprint) or workload."""
     path = os.path.join(ROOT, "profiles", f"{workload}_residual_traffic.json")
-    src = os.path.join(ROOT, "paper_2106_06280_amd", "csrc", "kernels.hip")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if d.get("source_sha256") != sha or os.environ.get("CSWDG_RESIDUAL_VARIANT", "3") != "3":
+    if d.get("kernel_source_sha256") != residual_kernel_fingerprint() or \
+            os.environ.get("CSWDG_RESIDUAL_VARIANT", "3") != "3":
         return None
     return int(d["read_bytes_per_launch"] + d["write_bytes_per_launch"])
 
