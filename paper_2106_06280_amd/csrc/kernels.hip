@@ -2427,6 +2427,7 @@ hipError_t launch_positivity(const LaunchCtx& c, const DevMesh& m, void* u, uint
     if (m.K == 0) return hipSuccess;
     const unsigned g = grid_for(m.K, 256);
     CSWDG_DISPATCH_ENP(1, c.N, c.precision, {
+        (void)EQ;
         k_positivity<N, S><<<g, 256, 0, c.stream>>>(m.K, (S*)u, c.gamma, status);
     });
     return hipGetLastError();
@@ -2445,6 +2446,7 @@ hipError_t launch_project(const LaunchCtx& c, const DevMesh& m, const double* va
     const unsigned g = grid_for(m.K, 256);
     const int mv = c.eq == 0 ? 1 : 4;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
+        (void)EQ;
         k_project<N, S><<<g, 256, 0, c.stream>>>(m.K, mv, vals, (S*)u);
     });
     return hipGetLastError();
