@@ -256,14 +256,21 @@ def limiter_options(args, degree, default_p2_top=0):
     from paper_2106_06280_amd import binding
     p2_top = default_p2_top if args.p2_top is None else args.p2_top
     return {"gamma_mode": args.gamma_mode, "tvb_m": args.tvb_m, "p2_top": p2_top if degree >= 2 else 0,
-            "indicator": binding.INDICATOR_TVB if args.indicator == "tvb" else binding.INDICATOR_KXRCF}
+            "indicator": binding.INDICATOR_TVB if args.indicator == "tvb" else binding.INDICATOR_KXRCF,
+            "reconstruction": args.reconstruction, "beta_mode": args.beta_mode}
 
 
 def limiter_config(opts, degree):
     from paper_2106_06280_amd import binding
-    return {"indicator": "tvb" if opts["indicator"] == 1 else "kxrcf", "tvb_m": opts["tvb_m"],
-            "linear_weights": "10^(l-1)" if opts["gamma_mode"] == 1 else "(1/h)^(l-1)",
-            "top_member": binding.top_name(degree, opts["p2_top"])}
+    cfg = {"indicator": "tvb" if opts["indicator"] == 1 else "kxrcf", "tvb_m": opts["tvb_m"],
+           "linear_weights": "10^(l-1)" if opts["gamma_mode"] == 1 else "(1/h)^(l-1)",
+           "top_member": binding.top_name(degree, opts["p2_top"])}
+    if opts.get("reconstruction", 0):
+        cfg["reconstruction"] = {1: "type-I WENO", 2: "type-II WENO"}[opts["reconstruction"]]
+        cfg.pop("top_member")
+    if opts.get("beta_mode", 0):
+        cfg["smoothness_indicators"] = "p_l over orders 1..N (as printed)"
+    return cfg
 
 
 def ffstep_solver(args, degree=2):
@@ -808,9 +815,14 @@ def main():
     ap.add_argument("--indicator", default="kxrcf", choices=("kxrcf", "tvb"),
                     help="troubled-cell indicator; not the batch")
     ap.add_argument("--tvb-m", type=float, default=0.0, help="TVB constant M of --indicator tvb")
-    ap.add_argument("--p2-top", type=int, default=None, choices=(0, 1, 2, 3, 4),
+    ap.add_argument("--p2-top", type=int, default=None, choices=(0, 1, 2, 3, 4, 5),
                     help="top member of the N >= 2 hierarchy: 0 the default reading (quadratic for P2, quartic "
-                         "for P3), 1 quadratic, 2 quartic, 3 telescoping cubic, 4 the printed cubic p_4")
+                         "for P3), 1 quadratic, 2 quartic, 3 telescoping cubic, 4 the printed cubic p_4, "
+                         "5 the sextic on T5 (P3)")
+    ap.add_argument("--reconstruction", type=int, default=0, choices=(0, 1, 2),
+                    help="0 the paper's hierarchical reconstruction, 1 type-I WENO (P1, P2), 2 type-II WENO (P2)")
+    ap.add_argument("--beta-mode", type=int, default=0, choices=(0, 1),
+                    help="smoothness indicators of q_l (0) or, as printed, of p_l over orders 1..N (1)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -955,7 +967,8 @@ def main():
         roof["stage_frac"] = round(stage_ach / HBM_PEAK_GBS, 4)
         roof["stage_achieved"] = round(stage_ach, 1)
         roof["stage_bytes_per_dof"] = round(b_elem / (Np * m), 2)
-    adjoint_ok = precision == 0 and opts["indicator"] == 0 and opts["gamma_mode"] == 0
+    adjoint_ok = (precision == 0 and opts["indicator"] == 0 and opts["gamma_mode"] == 0
+                  and opts["reconstruction"] == 0 and opts["beta_mode"] == 0 and opts["p2_top"] != 5)
     adj = None if (args.no_adjoint or not adjoint_ok) else adjoint_ratio(S, u, secs * 1e3 / args.steps)
     sched = None if args.no_profile else matrix_schedule_us(S, u)
     out = {
