@@ -354,9 +354,10 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
     for (int c = 0; c < M; ++c)
 #pragma unroll
         for (int n = 0; n < NP; ++n) acc[c][n] = R(0);
+    // the vertices, kept for the faces (one load each)
+    const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
+    const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
     {
-        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
-        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
         const double xr = 0.5 * (x1 - x0), xs = 0.5 * (x2 - x0);
         const double yr = 0.5 * (y1 - y0), ys = 0.5 * (y2 - y0);
         const double iJ = 1.0 / (xr * ys - xs * yr);
@@ -384,17 +385,26 @@ __device__ __forceinline__ void residual_body_compact(DevMesh msh, const R* __re
 
     const uint32_t info4 = msh.info[e];
     // 1 / J with 2 J = area: the surface scale L_f / (2 J) per face
-    double iJf;
-    {
-        const double x0 = msh.vx[e], x1 = msh.vx[K + e], x2 = msh.vx[2 * K + e];
-        const double y0 = msh.vy[e], y1 = msh.vy[K + e], y2 = msh.vy[2 * K + e];
-        iJf = 1.0 / (0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)));
-    }
+    const double iJf = 1.0 / (0.25 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)));
+    // FP64 P1/P2 keep the vertices in registers for the faces (fewer
+    // vector-memory instructions; the registers are there at two waves per
+    // SIMD); the others reload them (P3 and FP32-bulk would lose occupancy)
+    constexpr bool hold = sizeof(R) == 8 && N <= 2;
 #pragma unroll 1
     for (int f = 0; f < 3; ++f) {
         const int f1 = (f == 2) ? 0 : f + 1;
-        const double xa = msh.vx[f * K + e], ya = msh.vy[f * K + e];
-        const double xb = msh.vx[f1 * K + e], yb = msh.vy[f1 * K + e];
+        double xa, ya, xb, yb;
+        if constexpr (hold) {
+            xa = (f == 0) ? x0 : ((f == 1) ? x1 : x2);
+            ya = (f == 0) ? y0 : ((f == 1) ? y1 : y2);
+            xb = (f == 0) ? x1 : ((f == 1) ? x2 : x0);
+            yb = (f == 0) ? y1 : ((f == 1) ? y2 : y0);
+        } else {
+            xa = msh.vx[f * K + e];
+            ya = msh.vy[f * K + e];
+            xb = msh.vx[f1 * K + e];
+            yb = msh.vy[f1 * K + e];
+        }
         const double ex = xb - xa, ey = yb - ya;
         const double L = sqrt(ex * ex + ey * ey);
         const double iL = 1.0 / L;
