@@ -23,10 +23,10 @@ def torch():
     return t
 
 
-def _solver(eq, N, n, bc, seed):
+def _solver(eq, N, n, bc, seed, **kw):
     from paper_2106_06280_amd import binding
     v, t = inputs.jittered_mesh(n, seed=seed)
-    S = binding.Solver(eq, N)
+    S = binding.Solver(eq, N, **kw)
     S.mesh_upload(v, t, bc, (1.0, 1.0))
     dg = DG(Mesh(v, t, bc, (1.0, 1.0)), N, eq)
     if eq == 0:
@@ -43,6 +43,18 @@ def _both(torch, S, u, mask=None):
     flags = torch.empty(S.K, dtype=torch.uint8, device="cuda")
     out, flags = S.csweno_limit_noalloc(u, out, flags, mask=mask)
     return ref, fref, out, flags
+
+
+@pytest.mark.parametrize("N,kw", [(2, {"reconstruction": 1}), (2, {"reconstruction": 2}), (3, {"p2_top": 5}),
+                                  (2, {"beta_mode": 1})])
+def test_noalloc_limiter_other_readings(torch, N, kw):
+    """The entry point runs the solver's own reconstruction: type-I,
+    type-II, the sextic top, the printed smoothness indicators."""
+    for n, seed in ((12, 43), (7, 44)):
+        S, u = _solver(1, N, n, BC_TRANSMISSIVE, seed, **kw)
+        ref, fref, out, flags = _both(torch, S, u)
+        assert int(fref.sum()) > 0
+        assert torch.equal(flags, fref) and torch.equal(out, ref)
 
 
 @pytest.mark.parametrize("eq,N,bc", [(1, 2, BC_TRANSMISSIVE), (0, 1, BC_PERIODIC), (1, 3, BC_PERIODIC)])
