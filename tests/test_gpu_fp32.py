@@ -171,6 +171,35 @@ def test_fp32_limiter(torch, eq, N, bc):
     assert _relerr(got, csweno.limit(dg, u, fo)) < TOL_LIM
 
 
+@pytest.mark.parametrize("eq", [0, 1])
+@pytest.mark.parametrize("N,kw", [(2, {"reconstruction": 1}), (2, {"reconstruction": 2}), (3, {"p2_top": 5}),
+                                  (2, {"beta_mode": 1})])
+def test_fp32_limiter_other_readings(torch, eq, N, kw):
+    """The other reconstructions and readings read the float state and
+    compute in FP64 too: every cell limited against the oracle on the
+    float-rounded input, one rounding to float apart."""
+    from oracle import weno_type1, weno_type2
+    from paper_2106_06280_amd import binding
+    v, t = inputs.jittered_mesh(10, seed=83)
+    M = Mesh(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    dg = DG(M, N, eq)
+    S = binding.Solver(eq, N, precision=1, **kw)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    u = _jump_state(dg, eq, seed=10)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    allm = np.ones(M.K, bool)
+    if kw.get("reconstruction") == 1:
+        exp = weno_type1.limit_type1(dg, u, allm)
+    elif kw.get("reconstruction") == 2:
+        exp = weno_type2.limit_type2(dg, u, allm)
+    else:
+        exp = csweno.limit(dg, u, allm, top=binding.top_name(N, kw.get("p2_top", 0)),
+                           beta_literal=bool(kw.get("beta_mode", 0)))
+    got = S.to_host(out)
+    assert np.array_equal(got[:, :, 0], u[:, :, 0])
+    assert _relerr(got, exp) < TOL_LIM
+
+
 @pytest.mark.parametrize("eq,N", [(0, 2), (1, 2)])
 def test_fp32_step_all_troubled(torch, eq, N):
     """One SSP-RK3 step with every cell limited (no flag decisions): the
