@@ -81,16 +81,15 @@ def split(gamma):
     return gp, gm, gp.sum(axis=-1), gm.sum(axis=-1)
 
 
-def reconstruct_type2(dg: DG, u, elems, return_info=False, characteristic=True, linear_only=False):
-    """New coefficients [T, m, Np] of the troubled cells elems (mode 0
-    copied) by the type-II reconstruction (N = 2)."""
+def small_stencil_fits(dg: DG, u, E, characteristic=True):
+    """What the type-II and the mixed reconstructions share for the troubled
+    cells E (N = 2): Delta0's frame (centroid, mean side, area), the piece
+    averages of the three neighbours with the boundary ghosts, the fields
+    (characteristic in x and in y for Euler), the mean-free scaled monomial
+    averages of the pieces, and the six linear least-squares fits L_j (mean
+    of Delta0 exact) with their pseudo-inverses."""
     M = dg.mesh
-    E = np.asarray(elems, dtype=np.int64)
-    T, N, m, Np = len(E), dg.N, dg.m, dg.Np
-    if N != 2:
-        raise ValueError("the type-II reconstruction is defined for N = 2")
-    if T == 0:
-        return np.zeros((0, m, Np))
+    T, m = len(E), dg.m
     V0 = M.V[E]
     x0 = V0[:, :, 0].mean(axis=1)
     y0 = V0[:, :, 1].mean(axis=1)
@@ -126,30 +125,54 @@ def reconstruct_type2(dg: DG, u, elems, return_info=False, characteristic=True, 
     favg = {nm: to_fields(avg[nm]) for nm in NAMES}
     fbar0 = to_fields(ubar0[:, None, :])[:, 0, :]
 
-    mono2 = monomials(2)  # x, y, x^2, xy, y^2 (scaled, mean-free below)
     mavg0 = monomial_average(V0, x0, y0, h0, 2)
     mavg = {nm: monomial_average(pcs[nm], x0, y0, h0, 2) - mavg0[:, None, :] for nm in NAMES}  # [T, 3 faces, 5]
 
     def fit(faces, ncol):
-        A = np.concatenate([mavg[nm][:, list(faces)][..., :ncol] for nm in NAMES], axis=1)
-        return A
+        return np.concatenate([mavg[nm][:, list(faces)][..., :ncol] for nm in NAMES], axis=1)
 
-    # small linear fits: operators X_j [T, 2, rows] and their data rows
-    Xs, rows = [], []
+    def data(faces):
+        return np.concatenate([favg[nm][:, list(faces)] for nm in NAMES], axis=1) - fbar0[:, None, :]
+
+    # small linear fits: pseudo-inverses X_j [T, 2, rows] and coefficients
+    # cL_j [T, 2, F] per field
+    Xs, cL = [], []
     for faces in SMALL:
-        A = fit(faces, 2)
-        Q, Rr = np.linalg.qr(A)
-        Xs.append(np.linalg.solve(Rr, Q.transpose(0, 2, 1)))  # pseudo-inverse [T, 2, r]
-        rows.append(faces)
+        Q, Rr = np.linalg.qr(fit(faces, 2))
+        Xs.append(np.linalg.solve(Rr, Q.transpose(0, 2, 1)))
+        cL.append(np.einsum("tcr,trf->tcf", Xs[-1], data(faces)))
+    return dict(V0=V0, x0=x0, y0=y0, h0=h0, area0=area0, Ls=Ls, Rs=Rs, ND=ND, favg=favg, fbar0=fbar0,
+                mavg0=mavg0, mavg=mavg, fit=fit, data=data, Xs=Xs, cL=cL)
+
+
+def back_to_conserved(mom, Rs, m):
+    """Moments [T, ND*m, n] of the fields back to conserved variables,
+    averaged over the ND directions."""
+    ND = len(Rs)
+    out = 0.0
+    for d in range(ND):
+        out = out + np.einsum("tij,tjn->tin", Rs[d], mom[:, d * m:(d + 1) * m, :]) / ND
+    return out
+
+
+def reconstruct_type2(dg: DG, u, elems, return_info=False, characteristic=True, linear_only=False):
+    """New coefficients [T, m, Np] of the troubled cells elems (mode 0
+    copied) by the type-II reconstruction (N = 2)."""
+    E = np.asarray(elems, dtype=np.int64)
+    T, N, m, Np = len(E), dg.N, dg.m, dg.Np
+    if N != 2:
+        raise ValueError("the type-II reconstruction is defined for N = 2")
+    if T == 0:
+        return np.zeros((0, m, Np))
+    S = small_stencil_fits(dg, u, E, characteristic)
+    V0, x0, y0, h0, area0 = S["V0"], S["x0"], S["y0"], S["h0"], S["area0"]
+    ND, fbar0, mavg0, Xs, cL = S["ND"], S["fbar0"], S["mavg0"], S["Xs"], S["cL"]
+    mono2 = monomials(2)  # x, y, x^2, xy, y^2 (scaled, mean-free below)
     J = len(SMALL)
-    cL = []  # linear coefficients of each small fit per field [T, 2, F]
-    for j, faces in enumerate(SMALL):
-        b = np.concatenate([favg[nm][:, list(faces)] for nm in NAMES], axis=1) - fbar0[:, None, :]
-        cL.append(np.einsum("tcr,trf->tcf", Xs[j], b))
     # the quadratic monomials' data through the small fits: L_j[phi_k] coefficients [T, 2] per k
     Lphi = []
     for j, faces in enumerate(SMALL):
-        bq = fit(faces, 5)[..., 2:]  # [T, r, 3]: piece averages of phi_k minus Delta0's mean
+        bq = S["fit"](faces, 5)[..., 2:]  # [T, r, 3]: piece averages of phi_k minus Delta0's mean
         Lphi.append(np.einsum("tcr,trk->tck", Xs[j], bq))  # [T, 2, 3]
     beta = [area0[:, None] * np.sum(c * c, axis=1) / h0[:, None] ** 2 for c in cL]  # |grad L|^2 in physical units
 
@@ -184,13 +207,11 @@ def reconstruct_type2(dg: DG, u, elems, return_info=False, characteristic=True, 
         wm = wm / wm.sum(axis=1, keepdims=True)
         Rq[:, q] = sp[:, None] * np.sum(wp * Lx, axis=1) - sm[:, None] * np.sum(wm * Lx, axis=1)
     mom = np.einsum("q,tqf,qi->tfi", w, Rq, Vh)
-    out = np.zeros((T, m, Np))
-    for d in range(ND):
-        out += np.einsum("tij,tjn->tin", Rs[d], mom[:, d * m:(d + 1) * m, :]) / ND
+    out = back_to_conserved(mom, S["Rs"], m)
     out[:, :, 0] = u[E, :, 0]
     if return_info:
-        return out, dict(cL=cL, Lphi=Lphi, beta=beta, gammas=gammas, phi=phi, fbar0=fbar0, favg=favg,
-                         mavg=mavg, mavg0=mavg0, x0=x0, y0=y0, h0=h0, area0=area0, Xs=Xs, rule=(r, s, w))
+        return out, dict(cL=cL, Lphi=Lphi, beta=beta, gammas=gammas, phi=phi, fbar0=fbar0, favg=S["favg"],
+                         mavg=S["mavg"], mavg0=mavg0, x0=x0, y0=y0, h0=h0, area0=area0, Xs=Xs, rule=(r, s, w))
     return out
 
 
