@@ -266,7 +266,7 @@ def limiter_config(opts, degree):
            "linear_weights": "10^(l-1)" if opts["gamma_mode"] == 1 else "(1/h)^(l-1)",
            "top_member": binding.top_name(degree, opts["p2_top"])}
     if opts.get("reconstruction", 0):
-        cfg["reconstruction"] = {1: "type-I WENO", 2: "type-II WENO"}[opts["reconstruction"]]
+        cfg["reconstruction"] = {1: "type-I WENO", 2: "type-II WENO", 3: "mixed WENO"}[opts["reconstruction"]]
         cfg.pop("top_member")
     if opts.get("beta_mode", 0):
         cfg["smoothness_indicators"] = "p_l over orders 1..N (as printed)"
@@ -819,8 +819,9 @@ def main():
                     help="top member of the N >= 2 hierarchy: 0 the default reading (quadratic for P2, quartic "
                          "for P3), 1 quadratic, 2 quartic, 3 telescoping cubic, 4 the printed cubic p_4, "
                          "5 the sextic on T5 (P3)")
-    ap.add_argument("--reconstruction", type=int, default=0, choices=(0, 1, 2),
-                    help="0 the paper's hierarchical reconstruction, 1 type-I WENO (P1, P2), 2 type-II WENO (P2)")
+    ap.add_argument("--reconstruction", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="0 the paper's hierarchical reconstruction, 1 type-I WENO (P1, P2), 2 type-II WENO (P2), "
+                         "3 mixed WENO (P2)")
     ap.add_argument("--beta-mode", type=int, default=0, choices=(0, 1),
                     help="smoothness indicators of q_l (0) or, as printed, of p_l over orders 1..N (1)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")

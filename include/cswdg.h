@@ -171,8 +171,15 @@ typedef struct cswdg_params {
      * the quadratic fit on T3, negative weights split into two positive
      * groups (Shi, Hu and Shu), nonlinear weights of the WENO-Z form
      * gamma_j (1 + (tau / (1e-10 + beta_j))^2) per group (tau = max beta -
-     * min beta), then projected onto P2.  1 with N = 3, 2 with N != 2,
-     * ghost_mode 1, or the adjoint calls with 1 or 2: CSWDG_EINVAL. */
+     * min beta), then projected onto P2; 3 a mixed WENO reconstruction
+     * (N = 2 only): the quadratic fit Q on T3 and the six linear fits L_j
+     * of reconstruction 2, combined with constant positive linear weights
+     * through p_0 = (Q - 0.025 sum_j L_j) / 0.85 (so that 0.85 p_0 +
+     * 0.025 sum_j L_j = Q), nonlinear weights gamma_j / (1e-6 + beta_j)^2
+     * (beta of eq. smoothnessIndicator: orders 1 and 2 for p_0), R =
+     * omega_0 p_0 + sum_j omega_j L_j projected onto P2.  1 with N = 3, 2
+     * or 3 with N != 2, ghost_mode 1 with 1, 2 or 3, or the adjoint calls
+     * with any but 0: CSWDG_EINVAL. */
     int reconstruction;
     /* the smoothness indicators beta_l, l >= 2, of the hierarchical
      * reconstruction (Section 3.2, Step 3, eq. smoothnessIndicator):
@@ -180,8 +187,8 @@ typedef struct cswdg_params {
      * (the default: only then are linear data reproduced, every beta being
      * |Delta0| |grad u|^2); 1 as the equation is printed, of the equivalent
      * polynomials p_l over derivative orders 1..N.  beta_1 (eqs. sigmaEqn,
-     * smoothnessIndicatorT1) is the same in both.  1 with reconstruction 1
-     * or in the adjoint calls: CSWDG_EINVAL. */
+     * smoothnessIndicatorT1) is the same in both.  1 with reconstruction
+     * other than 0 or in the adjoint calls: CSWDG_EINVAL. */
     int beta_mode;
 } cswdg_params;
 

@@ -150,8 +150,9 @@ def host_tvb_decomposition(vxy, tri, bc, period=(0.0, 0.0)):
 # p2_top values (Section 3.2, Steps 1-2 for P2: the fourth member of the
 # N >= 2 hierarchy) and the oracle's name of each reading
 TOP_DEFAULT, TOP_QUADRATIC, TOP_QUARTIC, TOP_CUBIC_TEL, TOP_CUBIC, TOP_SEXTIC = 0, 1, 2, 3, 4, 5
-# reconstruction values: the paper's hierarchical WENO, type-I or type-II WENO
-RECON_HIERARCHICAL, RECON_TYPE1, RECON_TYPE2 = 0, 1, 2
+# reconstruction values: the paper's hierarchical WENO, type-I, type-II or
+# mixed WENO
+RECON_HIERARCHICAL, RECON_TYPE1, RECON_TYPE2, RECON_MIXED = 0, 1, 2, 3
 TOP_NAMES = {TOP_QUADRATIC: "quadratic", TOP_QUARTIC: "quartic", TOP_CUBIC_TEL: "cubic_tel", TOP_CUBIC: "cubic",
              TOP_SEXTIC: "sextic"}
 

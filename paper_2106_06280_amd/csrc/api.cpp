@@ -347,9 +347,11 @@ int cswdg_create(const cswdg_params* params, void* hip_stream, cswdg_solver** ou
         return fail(nullptr, CSWDG_EINVAL, "tvb_m must be finite and >= 0");
     if (p.gamma_mode < 0 || p.gamma_mode > 1) return fail(nullptr, CSWDG_EINVAL, "gamma_mode must be 0 or 1");
     if (p.ghost_mode < 0 || p.ghost_mode > 1) return fail(nullptr, CSWDG_EINVAL, "ghost_mode must be 0 or 1");
-    if (p.reconstruction < 0 || p.reconstruction > 2) return fail(nullptr, CSWDG_EINVAL, "reconstruction must be 0, 1 or 2");
+    if (p.reconstruction < 0 || p.reconstruction > 3) return fail(nullptr, CSWDG_EINVAL, "reconstruction must be 0, 1, 2 or 3");
     if (p.reconstruction == 2 && (p.degree != 2 || p.ghost_mode != 0))
         return fail(nullptr, CSWDG_EINVAL, "the type-II reconstruction takes N = 2 and the mirror ghost (ghost_mode = 0)");
+    if (p.reconstruction == 3 && (p.degree != 2 || p.ghost_mode != 0))
+        return fail(nullptr, CSWDG_EINVAL, "the mixed reconstruction takes N = 2 and the mirror ghost (ghost_mode = 0)");
     if (p.beta_mode < 0 || p.beta_mode > 1) return fail(nullptr, CSWDG_EINVAL, "beta_mode must be 0 or 1");
     if (p.beta_mode == 1 && p.reconstruction != 0)
         return fail(nullptr, CSWDG_EINVAL, "beta_mode = 1 is a reading of the hierarchical reconstruction (reconstruction = 0)");
@@ -1162,6 +1164,7 @@ int upload_mesh(cswdg_solver* s) {
     std::vector<double> ops;
     rc = s->p.reconstruction == 1   ? build_type1_ops(s->mesh, s->p.degree, ops, s->n_rank)
          : s->p.reconstruction == 2 ? build_type2_ops(s->mesh, ops, s->n_rank)
+         : s->p.reconstruction == 3 ? build_mixed_ops(s->mesh, ops, s->n_rank)
                                     : build_limiter_ops(s->mesh, s->p.degree, s->ctx.qtop, s->p.gamma_mode == 1,
                                                         s->p.ghost_mode == 1, ops, s->n_rank, s->n_foot);
     if (rc != CSWDG_OK) return fail(s, rc, "limiter operator build failed");

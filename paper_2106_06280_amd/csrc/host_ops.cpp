@@ -450,6 +450,55 @@ int build_ops_n(const HostMesh& m, bool constant_gamma, bool ghost_extrapolate, 
     return CSWDG_OK;
 }
 
+// The smoothness-indicator matrix of eq. smoothnessIndicator over the
+// derivative orders 1..nd for q = sum_j c_j phi_j in the scaled monomials of
+// mono on triangle V0 (centroid c0, mean side h0, area area0): c^T B c =
+// sum_{1<=|alpha|<=nd} area0^{|alpha|-1} int (D^alpha q)^2, physical
+// derivatives, by the rule rBeta; the packed upper triangle is written.
+void smoothness_matrix_packed(int nd, const P2d V0[3], P2d c0, double h0, double area0, const Rule2D& rBeta,
+                              const MonoList& mono, double* packed) {
+    const int NM = mono.n;
+    double B[5][5] = {{0}};
+    double ihp[3], ap[3];
+    ihp[0] = 1.0;
+    ap[0] = 1.0 / area0;
+    for (int sd = 1; sd <= nd; ++sd) {
+        ihp[sd] = ihp[sd - 1] / h0;
+        ap[sd] = ap[sd - 1] * area0;
+    }
+    const double J0 = 0.5 * area0;
+    for (size_t q = 0; q < rBeta.w.size(); ++q) {
+        const P2d x = V0[0] + (0.5 * (1.0 + rBeta.r[q])) * (V0[1] - V0[0]) + (0.5 * (1.0 + rBeta.s[q])) * (V0[2] - V0[0]);
+        const double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
+        const double wq = J0 * rBeta.w[q];
+        for (int sd = 1; sd <= nd; ++sd)
+            for (int a1 = 0; a1 <= sd; ++a1) {
+                const int a2 = sd - a1;
+                double Dv[5];
+                for (int j = 0; j < NM; ++j) {
+                    const int a = mono.a[j], b = mono.b[j];
+                    if (a < a1 || b < a2) {
+                        Dv[j] = 0;
+                        continue;
+                    }
+                    double coef = 1.0;
+                    for (int t = 0; t < a1; ++t) coef *= (a - t);
+                    for (int t = 0; t < a2; ++t) coef *= (b - t);
+                    double v = coef * ihp[sd];
+                    for (int t = 0; t < a - a1; ++t) v *= xi;
+                    for (int t = 0; t < b - a2; ++t) v *= eta;
+                    Dv[j] = v;
+                }
+                const double sc = ap[sd] * wq;
+                for (int i = 0; i < NM; ++i)
+                    for (int j = 0; j < NM; ++j) B[i][j] += sc * Dv[i] * Dv[j];
+            }
+    }
+    int k = 0;
+    for (int i = 0; i < NM; ++i)
+        for (int j = i; j < NM; ++j) packed[k++] = B[i][j];
+}
+
 // The record of the type-I reconstruction (OpLayoutT1): the same stencil
 // geometry as the hierarchical one (centroid subcells only), least-squares
 // pseudo-inverses of degree N on the central stencil and the three sectors.
@@ -607,46 +656,7 @@ struct OpBuilderT1 {
             valid &= pinv(6, NM, A, op + L::XS + k * NM * 6);
         }
         // smoothness matrix over derivative orders 1..N
-        {
-            double B[5][5] = {{0}};
-            double ihp[N + 1], ap[N + 1];
-            ihp[0] = 1.0;
-            ap[0] = 1.0 / area0;
-            for (int sd = 1; sd <= N; ++sd) {
-                ihp[sd] = ihp[sd - 1] / h0;
-                ap[sd] = ap[sd - 1] * area0;
-            }
-            for (size_t q = 0; q < rBeta.w.size(); ++q) {
-                P2d x = map_tri(V0, rBeta.r[q], rBeta.s[q]);
-                double xi = (x.x - c0.x) / h0, eta = (x.y - c0.y) / h0;
-                double wq = J0 * rBeta.w[q];
-                for (int sd = 1; sd <= N; ++sd)
-                    for (int a1 = 0; a1 <= sd; ++a1) {
-                        int a2 = sd - a1;
-                        double Dv[5];
-                        for (int j = 0; j < NM; ++j) {
-                            int a = mono.a[j], b = mono.b[j];
-                            if (a < a1 || b < a2) {
-                                Dv[j] = 0;
-                                continue;
-                            }
-                            double coef = 1.0;
-                            for (int t = 0; t < a1; ++t) coef *= (a - t);
-                            for (int t = 0; t < a2; ++t) coef *= (b - t);
-                            double v = coef * ihp[sd];
-                            for (int t = 0; t < a - a1; ++t) v *= xi;
-                            for (int t = 0; t < b - a2; ++t) v *= eta;
-                            Dv[j] = v;
-                        }
-                        double sc = ap[sd] * wq;
-                        for (int i = 0; i < NM; ++i)
-                            for (int j = 0; j < NM; ++j) B[i][j] += sc * Dv[i] * Dv[j];
-                    }
-            }
-            int k = 0;
-            for (int i = 0; i < NM; ++i)
-                for (int j = i; j < NM; ++j) op[L::BP + k++] = B[i][j];
-        }
+        smoothness_matrix_packed(N, V0, c0, h0, area0, rBeta, mono, op + L::BP);
         for (size_t q = 0; q < rProj.w.size(); ++q) {
             mono_eval(map_tri(V0, rProj.r[q], rProj.s[q]), c0, h0, tmp);
             for (int i = 1; i < D::NP; ++i)
@@ -692,12 +702,18 @@ int build_type1_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t&
 // the six linear fits reproduce the quadratic fit on T3 (exact for
 // quadratic data: sum_j g_j = 1, sum_j g_j L_j[phi_k](x) = phi_k(x) for the
 // three quadratic scaled monomials).
+//
+// The record of the mixed reconstruction (OpLayoutMX) shares the piece
+// geometry and the linear fits; in place of the point-wise weights it holds
+// the quadratic fit on the nine pieces, the smoothness matrix of a quadratic
+// and the projection of the scaled monomials.
+template <class L>
 struct OpBuilderT2 {
-    using L = OpLayoutT2;
+    static constexpr bool MIXED = std::is_same<L, OpLayoutMX>::value;
     static constexpr int N = 2, NP = 6, NM = 5;
     const HostMesh& m;
     std::vector<double> C;
-    Rule2D rN, rTop, rQ;
+    Rule2D rN, rTop, rQ, rBeta;
     std::vector<double> psiQ;  // [q][NP] at the reference points of rQ
     MonoList mono{2};
 
@@ -706,6 +722,7 @@ struct OpBuilderT2 {
         rN = triangle_rule((N + 2) / 2);
         rTop = triangle_rule((N + 2) / 2);
         rQ = triangle_rule(3);  // degree 4: the points where R is evaluated
+        rBeta = triangle_rule(2);
         psiQ.resize(rQ.w.size() * NP);
         for (size_t q = 0; q < rQ.w.size(); ++q) basis_eval(N, rQ.r[q], rQ.s[q], &psiQ[q * NP]);
     }
@@ -878,8 +895,30 @@ struct OpBuilderT2 {
                     Lq[j][k][c] = t;
                 }
         }
-        // the points of the degree-4 rule: linear weights, linear monomials,
-        // projection weights
+        if constexpr (MIXED) {
+            double A[9 * NM];
+            for (int p = 0; p < 3; ++p)
+                for (int f = 0; f < 3; ++f)
+                    for (int j = 0; j < NM; ++j) A[(p * 3 + f) * NM + j] = mavg[f][p][j];
+            valid &= pinv(9, NM, A, op + L::X3);
+            smoothness_matrix_packed(2, V0, c0, h0, area0, rBeta, mono, op + L::BP);
+            for (size_t q = 0; q < rQ.w.size(); ++q) {
+                mono_eval(map_tri(V0, rQ.r[q], rQ.s[q]), c0, h0, tmp);
+                for (int i = 1; i < NP; ++i)
+                    for (int j = 0; j < NM; ++j) op[L::PM + (i - 1) * NM + j] += rQ.w[q] * tmp[j] * psiQ[q * NP + i];
+            }
+        } else {
+            point_weights(V0, c0, h0, mavg0, Lq, op, valid);
+        }
+        op[L::BSC] = area0 / (h0 * h0);
+        op[L::VALID] = valid ? 1.0 : 0.0;
+        return valid;
+    }
+
+    // the points of the degree-4 rule: linear weights, linear monomials,
+    // projection weights (type-II record)
+    void point_weights(const P2d V0[3], P2d c0, double h0, const double mavg0[NM], const double Lq[6][3][2],
+                       double* op, bool& valid) const {
         for (size_t q = 0; q < rQ.w.size(); ++q) {
             double ph[NM];
             mono_eval(map_tri(V0, rQ.r[q], rQ.s[q]), c0, h0, ph);
@@ -911,15 +950,12 @@ struct OpBuilderT2 {
             }
             for (int i = 1; i < NP; ++i) op[L::PMQ + (i - 1) * L::NQ + q] = rQ.w[q] * psiQ[q * NP + i];
         }
-        op[L::BSC] = area0 / (h0 * h0);
-        op[L::VALID] = valid ? 1.0 : 0.0;
-        return valid;
     }
 };
 
-int build_type2_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank) {
-    using L = OpLayoutT2;
-    OpBuilderT2 b(m);
+template <class L>
+int build_small_stencil_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank) {
+    OpBuilderT2<L> b(m);
     ops.assign((size_t)m.K * L::LEN, 0.0);
     unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
     std::vector<int64_t> rank(nt, 0);
@@ -933,6 +969,14 @@ int build_type2_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank
     n_rank = 0;
     for (unsigned t = 0; t < nt; ++t) n_rank += rank[t];
     return CSWDG_OK;
+}
+
+int build_type2_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank) {
+    return build_small_stencil_ops<OpLayoutT2>(m, ops, n_rank);
+}
+
+int build_mixed_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank) {
+    return build_small_stencil_ops<OpLayoutMX>(m, ops, n_rank);
 }
 
 // TVB minmod indicator (Cockburn and Shu's limiter for triangles): for each

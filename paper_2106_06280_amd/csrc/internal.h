@@ -81,6 +81,7 @@ inline int top_for(int N, int p2_top) {
 int build_type1_ops(const HostMesh& m, int N, std::vector<double>& ops, int64_t& n_rank);
 // the per-element record of the type-II reconstruction (OpLayoutT2, N = 2)
 int build_type2_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank);
+int build_mixed_ops(const HostMesh& m, std::vector<double>& ops, int64_t& n_rank);
 
 int build_limiter_ops(const HostMesh& m, int N, int qtop, bool constant_gamma, bool ghost_extrapolate, std::vector<double>& ops,
                       int64_t& n_rank, int64_t& n_foot);
@@ -122,7 +123,7 @@ struct LaunchCtx {
     int char_comp;         // Euler limiting on the conserved variables
     int weights_linear;    // limiter weights omega = gamma
     int qtop;  // N >= 2: top member of the hierarchy (kTop* below)
-    int recon; // 0 the hierarchical reconstruction, 1 type-I WENO, 2 type-II WENO
+    int recon; // 0 the hierarchical reconstruction, 1 type-I WENO, 2 type-II WENO, 3 mixed WENO
     int beta_lit;  // 1: smoothness indicators of p_l over orders 1..N (eq. smoothnessIndicator as printed)
     int indicator;         // troubled-cell indicator: 0 KXRCF, 1 TVB minmod
     double tvb_m;          // TVB constant M

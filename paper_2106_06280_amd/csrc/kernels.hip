@@ -20,6 +20,9 @@
 //               projection; a lane butterfly recombines the conserved
 //               moments; results to a compact buffer (every cell reads the
 //               pre-limit field).
+//   k_limiter_t1, k_limiter_t2, k_limiter_mx  the same lanes with the
+//               type-I, type-II and mixed WENO reconstructions on the
+//               subcell stencils (params.reconstruction = 1, 2, 3).
 //   k_scatter   compact results -> state (modes >= 1).
 //   k_positivity  optional, not in the paper: Zhang-Shu positivity scaling
 //               of every Euler cell at the residual's evaluation points.
@@ -1762,12 +1765,188 @@ __global__ __launch_bounds__(64, 3) void k_limiter_t1(DevMesh msh, const S* __re
     }
 }
 
+// What the type-II and the mixed reconstructions share (N = 2), for the
+// lane (direction d, field k) of troubled cell e: column k of R_d at the
+// mean of Delta0 (Rc), the field's mean w0 on Delta0, its averages w over
+// the three pieces of each neighbour (boundary ghosts included) and the six
+// linear least-squares fits cl on the single-neighbour stencils (rows: the
+// three pieces) and on the sectors (faces k, k+1; rows piece-major, then the
+// two faces); the lanes and the characteristic fields as in k_limiter.
+template <int EQ, typename S, class LO>
+__device__ __forceinline__ void small_stencil_fits(const DevMesh& msh, const S* __restrict__ u,
+                                                   const double* __restrict__ op, int e, int d, int k,
+                                                   double gamma, int comp, double (&Rc)[Phys<EQ>::M],
+                                                   double& w0, double (&w)[3][3], double (&cl)[6][2]) {
+    constexpr int M = Phys<EQ>::M, NP = 6, NPC = 3;
+    const int K = msh.K;
+    double ub0[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) ub0[c] = u[(size_t)(c * NP) * K + e] * kPsi0;
+    // row k of L_d and column k of R_d at the mean of Delta0
+    double Lr[M];
+    if constexpr (EQ == 1) {
+        double Lm[4][4], Rm[4][4];
+        euler_eigen(ub0, d == 0 ? 1.0 : 0.0, d == 0 ? 0.0 : 1.0, gamma, Lm, Rm);
+        if (comp) {
+            // conserved variables: both "directions" use the identity
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) Lm[a][b] = Rm[a][b] = (a == b) ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double a = Lm[0][c], b = Rm[c][0];
+#pragma unroll
+            for (int kk = 1; kk < 4; ++kk) {
+                a = (k == kk) ? Lm[kk][c] : a;
+                b = (k == kk) ? Rm[c][kk] : b;
+            }
+            Lr[c] = a;
+            Rc[c] = b;
+        }
+    } else {
+        Lr[0] = 1.0;
+        Rc[0] = 1.0;
+    }
+    w0 = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) w0 += Lr[c] * ub0[c];
+
+    // field-k averages over the pieces of the three neighbours
+    const uint32_t info4 = msh.info[e];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
+        const bool bnd = (inf & 0x40u) != 0u;
+        const uint32_t kind = bnd ? (inf & 3u) : 0u;
+        const int src = bnd ? e : msh.nbr[f * K + e];
+        // row of the field for this face's source: a wall's mirror ghost
+        // carries the reflected momentum, so its averages map through the
+        // reflection (row Lr times the symmetric reflection matrix)
+        double Lf[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) Lf[c] = Lr[c];
+        if constexpr (EQ == 1) {
+            if (kind == 1u) {
+                const int f1 = (f == 2) ? 0 : f + 1;
+                const double ex = msh.vx[f1 * K + e] - msh.vx[f * K + e];
+                const double ey = msh.vy[f1 * K + e] - msh.vy[f * K + e];
+                const double iL = 1.0 / sqrt(ex * ex + ey * ey);
+                const double nx = ey * iL, ny = -ex * iL;
+                Lf[1] = Lr[1] * (1.0 - 2.0 * nx * nx) - Lr[2] * (2.0 * nx * ny);
+                Lf[2] = -Lr[1] * (2.0 * nx * ny) + Lr[2] * (1.0 - 2.0 * ny * ny);
+            }
+        }
+        if (kind == 2u || kind == 3u) {
+            // inflow ghost: the prescribed state on every piece; moving
+            // shock: its state at the face midpoint and the step's start
+            const double* st = msh.inflow;
+            if (kind == 3u) {
+                const int f1 = (f == 2) ? 0 : f + 1;
+                const double xm = 0.5 * (msh.vx[f * K + e] + msh.vx[f1 * K + e]);
+                const double ym = 0.5 * (msh.vy[f * K + e] + msh.vy[f1 * K + e]);
+                st = msh.shock + shock_state_at(msh.shock, xm, ym, msh.time[inst_of(msh, e)]);
+            }
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) s += Lr[c] * st[c];
+#pragma unroll
+            for (int p = 0; p < NPC; ++p) w[f][p] = s;
+            continue;
+        }
+        double ws[NP];
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) s += Lf[c] * u[(size_t)(c * NP + n) * K + src];
+            ws[n] = s;
+        }
+#pragma unroll
+        for (int p = 0; p < NPC; ++p) {
+            const double* a = op + LO::AVG + (f * NPC + p) * NP;
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < NP; ++n) s += a[n] * ws[n];
+            w[f][p] = s;
+        }
+    }
+    // linear fits on the single-neighbour stencils (rows: the three
+    // pieces) and on the sectors (faces k, k+1; rows piece-major, then
+    // the two faces)
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) s += op[LO::XF + (f * 2 + jj) * 3 + p] * (w[f][p] - w0);
+            cl[f][jj] = s;
+        }
+#pragma unroll
+    for (int sk = 0; sk < 3; ++sk) {
+        const int fa = sk, fb = (sk == 2) ? 0 : sk + 1;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const double* x = op + LO::XS + (sk * 2 + jj) * 6;
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) s += x[p * 2] * (w[fa][p] - w0) + x[p * 2 + 1] * (w[fb][p] - w0);
+            cl[3 + sk][jj] = s;
+        }
+    }
+}
+
+// The limited moments of one lane back to conserved variables (the sum over
+// the cell's lanes of R_d[c][k] mom_dk / ND) and the store of the cell's
+// compact row: the mean copied, the new moments where the record is valid,
+// the old ones (and the rank status bit) where it is not.
+template <int EQ, typename S>
+__device__ __forceinline__ void store_small_stencil(const S* __restrict__ u, int K, int e, uint32_t t, bool active,
+                                                    bool valid, int j, const double (&Rc)[Phys<EQ>::M],
+                                                    const double (&mom)[5], double* __restrict__ compact,
+                                                    uint32_t* __restrict__ status) {
+    constexpr int M = Phys<EQ>::M, NP = 6;
+    constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
+    // back to conserved variables: sum over (d, k) of R_d[c][k] mom_dk / ND
+    double res[M][NP - 1];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int i = 0; i < NP - 1; ++i) res[c][i] = (1.0 / ND) * Rc[c] * mom[i];
+#pragma unroll
+    for (int o = 1; o < LPC; o <<= 1)
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int i = 0; i < NP - 1; ++i) res[c][i] += __shfl_xor(res[c][i], o, LPC);
+    if (active && j < M) {
+        double* outp = compact + (size_t)t * (M * NP) + j * NP;
+        double sel[NP - 1];
+#pragma unroll
+        for (int i = 0; i < NP - 1; ++i) {
+            double v = res[0][i];
+#pragma unroll
+            for (int c = 1; c < M; ++c) v = (j == c) ? res[c][i] : v;
+            sel[i] = v;
+        }
+        outp[0] = u[(size_t)(j * NP) * K + e];
+        if (valid) {
+#pragma unroll
+            for (int i = 1; i < NP; ++i) outp[i] = sel[i - 1];
+        } else {
+#pragma unroll
+            for (int i = 1; i < NP; ++i) outp[i] = u[(size_t)(j * NP + i) * K + e];
+        }
+    }
+    if (active && !valid && j == 0) atomicOr(status, CSWDG_STATUS_RANK);
+}
+
 // Type-II WENO on the same subcell stencils (params.reconstruction = 2; N
-// = 2): the lanes, the characteristic fields and the piece averages as in
-// k_limiter; linear least-squares fits on the three single-neighbour
-// stencils and the three sectors, their smoothness indicators, and at the
-// nine points of the degree-4 rule the stored linear weights split into two
-// positive groups (gamma+- of Shi, Hu and Shu), nonlinear weights
+// = 2): the small-stencil fits above, their smoothness indicators, and at
+// the nine points of the degree-4 rule the stored linear weights split into
+// two positive groups (gamma+- of Shi, Hu and Shu), nonlinear weights
 // (gamma+-_j / sigma+-) (1 + (tau / (1e-10 + beta_j))^2) per group with tau
 // = max beta - min beta, R(x_q) = sigma+ R+ - sigma- R-, and the projection
 // sum_q w_q R(x_q) psi_i(x_q).
@@ -1782,9 +1961,9 @@ __global__ __launch_bounds__(64, 3) void k_limiter_t2(DevMesh msh, const S* __re
     constexpr int N = 2;
     using D = Dims<N>;
     using LO = OpLayoutT2;
-    constexpr int M = Phys<EQ>::M, NP = D::NP, NPC = 3, NQ = LO::NQ;
+    constexpr int M = Phys<EQ>::M, NP = D::NP, NQ = LO::NQ;
     constexpr double EPS2 = 1e-10;
-    constexpr int ND = LimLanes<EQ>::ND, LPC = LimLanes<EQ>::LPC;
+    constexpr int LPC = LimLanes<EQ>::LPC;
     constexpr int CPB = 64 / LPC;  // cells per block
     const int K = msh.K;
     uint32_t pre[kListSegs + 1];
@@ -1799,126 +1978,8 @@ __global__ __launch_bounds__(64, 3) void k_limiter_t2(DevMesh msh, const S* __re
         const int e = active ? seg_elem(list, pre, K, t) : 0;
         const double* __restrict__ op = ops + (size_t)e * LO::LEN;
         const bool valid = active && op[LO::VALID] != 0.0;
-
-        double ub0[M];
-#pragma unroll
-        for (int c = 0; c < M; ++c) ub0[c] = u[(size_t)(c * NP) * K + e] * kPsi0;
-        // row k of L_d and column k of R_d at the mean of Delta0
-        double Lr[M], Rc[M];
-        if constexpr (EQ == 1) {
-            double Lm[4][4], Rm[4][4];
-            euler_eigen(ub0, d == 0 ? 1.0 : 0.0, d == 0 ? 0.0 : 1.0, gamma, Lm, Rm);
-            if (comp) {
-                // conserved variables: both "directions" use the identity
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) Lm[a][b] = Rm[a][b] = (a == b) ? 1.0 : 0.0;
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                double a = Lm[0][c], b = Rm[c][0];
-#pragma unroll
-                for (int kk = 1; kk < 4; ++kk) {
-                    a = (k == kk) ? Lm[kk][c] : a;
-                    b = (k == kk) ? Rm[c][kk] : b;
-                }
-                Lr[c] = a;
-                Rc[c] = b;
-            }
-        } else {
-            Lr[0] = 1.0;
-            Rc[0] = 1.0;
-        }
-        double w0 = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c) w0 += Lr[c] * ub0[c];
-
-        // field-k averages over the pieces of the three neighbours
-        const uint32_t info4 = msh.info[e];
-        double w[3][NPC];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
-            const bool bnd = (inf & 0x40u) != 0u;
-            const uint32_t kind = bnd ? (inf & 3u) : 0u;
-            const int src = bnd ? e : msh.nbr[f * K + e];
-            // row of the field for this face's source: a wall's mirror ghost
-            // carries the reflected momentum, so its averages map through the
-            // reflection (row Lr times the symmetric reflection matrix)
-            double Lf[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) Lf[c] = Lr[c];
-            if constexpr (EQ == 1) {
-                if (kind == 1u) {
-                    const int f1 = (f == 2) ? 0 : f + 1;
-                    const double ex = msh.vx[f1 * K + e] - msh.vx[f * K + e];
-                    const double ey = msh.vy[f1 * K + e] - msh.vy[f * K + e];
-                    const double iL = 1.0 / sqrt(ex * ex + ey * ey);
-                    const double nx = ey * iL, ny = -ex * iL;
-                    Lf[1] = Lr[1] * (1.0 - 2.0 * nx * nx) - Lr[2] * (2.0 * nx * ny);
-                    Lf[2] = -Lr[1] * (2.0 * nx * ny) + Lr[2] * (1.0 - 2.0 * ny * ny);
-                }
-            }
-            if (kind == 2u || kind == 3u) {
-                // inflow ghost: the prescribed state on every piece; moving
-                // shock: its state at the face midpoint and the step's start
-                const double* st = msh.inflow;
-                if (kind == 3u) {
-                    const int f1 = (f == 2) ? 0 : f + 1;
-                    const double xm = 0.5 * (msh.vx[f * K + e] + msh.vx[f1 * K + e]);
-                    const double ym = 0.5 * (msh.vy[f * K + e] + msh.vy[f1 * K + e]);
-                    st = msh.shock + shock_state_at(msh.shock, xm, ym, msh.time[inst_of(msh, e)]);
-                }
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < M; ++c) s += Lr[c] * st[c];
-#pragma unroll
-                for (int p = 0; p < NPC; ++p) w[f][p] = s;
-                continue;
-            }
-            double ws[NP];
-#pragma unroll
-            for (int n = 0; n < NP; ++n) {
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < M; ++c) s += Lf[c] * u[(size_t)(c * NP + n) * K + src];
-                ws[n] = s;
-            }
-#pragma unroll
-            for (int p = 0; p < NPC; ++p) {
-                const double* a = op + LO::AVG + (f * NPC + p) * NP;
-                double s = 0.0;
-#pragma unroll
-                for (int n = 0; n < NP; ++n) s += a[n] * ws[n];
-                w[f][p] = s;
-            }
-        }
-        // linear fits on the single-neighbour stencils (rows: the three
-        // pieces) and on the sectors (faces k, k+1; rows piece-major, then
-        // the two faces), their smoothness indicators BSC |c|^2
-        double cl[6][2], iw[6];
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
-                double s = 0.0;
-#pragma unroll
-                for (int p = 0; p < 3; ++p) s += op[LO::XF + (f * 2 + jj) * 3 + p] * (w[f][p] - w0);
-                cl[f][jj] = s;
-            }
-#pragma unroll
-        for (int sk = 0; sk < 3; ++sk) {
-            const int fa = sk, fb = (sk == 2) ? 0 : sk + 1;
-#pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
-                const double* x = op + LO::XS + (sk * 2 + jj) * 6;
-                double s = 0.0;
-#pragma unroll
-                for (int p = 0; p < 3; ++p) s += x[p * 2] * (w[fa][p] - w0) + x[p * 2 + 1] * (w[fb][p] - w0);
-                cl[3 + sk][jj] = s;
-            }
-        }
+        double Rc[M], w0, w[3][3], cl[6][2], iw[6];
+        small_stencil_fits<EQ, S, LO>(msh, u, op, e, d, k, gamma, comp, Rc, w0, w, cl);
         // WENO-Z form: iw_j = 1 + (tau / (EPS2 + beta_j))^2, tau = max beta - min beta
         const double bsc = op[LO::BSC];
         double bmax = 0.0, bmin = 0.0;
@@ -1966,38 +2027,102 @@ __global__ __launch_bounds__(64, 3) void k_limiter_t2(DevMesh msh, const S* __re
 #pragma unroll
             for (int i = 0; i < NP - 1; ++i) mom[i] += op[LO::PMQ + i * NQ + q] * R;
         }
-        // back to conserved variables: sum over (d, k) of R_d[c][k] mom_dk / ND
-        double res[M][NP - 1];
+        store_small_stencil<EQ, S>(u, K, e, t, active, valid, j, Rc, mom, compact, status);
+    }
+}
+
+// Mixed WENO on the same subcell stencils (params.reconstruction = 3; N =
+// 2): the small-stencil fits above, the quadratic fit Q on the nine pieces,
+// p_0 = (Q - gamma_s sum_j L_j) / gamma_0 with gamma_0 = 0.85 and gamma_s =
+// 0.025, the smoothness indicators (of p_0 by the stored matrix over the
+// derivative orders 1 and 2, of L_j as BSC |c_j|^2), the weights
+// gamma_j / (1e-6 + beta_j)^2 normalised, R = omega_0 p_0 + sum_j omega_j L_j
+// in the scaled monomials, and its moments by the stored projection.
+template <int EQ, typename S>
+__global__ __launch_bounds__(64, 3) void k_limiter_mx(DevMesh msh, const S* __restrict__ u,
+                                                const double* __restrict__ ops,
+                                                const int32_t* __restrict__ list,
+                                                const uint32_t* __restrict__ count,
+                                                double* __restrict__ compact,
+                                                uint32_t* __restrict__ status, double gamma,
+                                                int comp) {
+    using LO = OpLayoutMX;
+    constexpr int M = Phys<EQ>::M, NM = LO::NM;
+    constexpr double G0 = 0.85, GS = 0.025, EPS = 1e-6;
+    constexpr int LPC = LimLanes<EQ>::LPC;
+    constexpr int CPB = 64 / LPC;  // cells per block
+    const int K = msh.K;
+    uint32_t pre[kListSegs + 1];
+    seg_prefix(count, K, pre);
+    const uint32_t ncell = pre[kListSegs];
+    const int j = threadIdx.x % LPC;  // lane within the cell
+    const int d = j / M;              // characteristic direction
+    const int k = j % M;              // characteristic field
+    for (uint32_t base = blockIdx.x * CPB; base < ncell; base += gridDim.x * CPB) {
+        const uint32_t t = base + threadIdx.x / LPC;
+        const bool active = t < ncell;
+        const int e = active ? seg_elem(list, pre, K, t) : 0;
+        const double* __restrict__ op = ops + (size_t)e * LO::LEN;
+        const bool valid = active && op[LO::VALID] != 0.0;
+        double Rc[M], w0, w[3][3], cl[6][2];
+        small_stencil_fits<EQ, S, LO>(msh, u, op, e, d, k, gamma, comp, Rc, w0, w, cl);
+        // Q on the nine pieces (row 3 p + f), then p_0
+        double c0[NM];
 #pragma unroll
-        for (int c = 0; c < M; ++c)
+        for (int i = 0; i < NM; ++i) {
+            double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < NP - 1; ++i) res[c][i] = (1.0 / ND) * Rc[c] * mom[i];
+            for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int o = 1; o < LPC; o <<= 1)
-#pragma unroll
-            for (int c = 0; c < M; ++c)
-#pragma unroll
-                for (int i = 0; i < NP - 1; ++i) res[c][i] += __shfl_xor(res[c][i], o, LPC);
-        if (active && j < M) {
-            double* outp = compact + (size_t)t * (M * NP) + j * NP;
-            double sel[NP - 1];
-#pragma unroll
-            for (int i = 0; i < NP - 1; ++i) {
-                double v = res[0][i];
-#pragma unroll
-                for (int c = 1; c < M; ++c) v = (j == c) ? res[c][i] : v;
-                sel[i] = v;
-            }
-            outp[0] = u[(size_t)(j * NP) * K + e];
-            if (valid) {
-#pragma unroll
-                for (int i = 1; i < NP; ++i) outp[i] = sel[i - 1];
-            } else {
-#pragma unroll
-                for (int i = 1; i < NP; ++i) outp[i] = u[(size_t)(j * NP + i) * K + e];
-            }
+                for (int f = 0; f < 3; ++f) s += op[LO::X3 + i * 9 + p * 3 + f] * (w[f][p] - w0);
+            c0[i] = s;
         }
-        if (active && !valid && j == 0) atomicOr(status, CSWDG_STATUS_RANK);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < 6; ++jj) s += cl[jj][i];
+            c0[i] -= GS * s;
+        }
+#pragma unroll
+        for (int i = 0; i < NM; ++i) c0[i] /= G0;
+        // smoothness indicators and the nonlinear weights
+        double b0 = 0.0;
+        {
+            int q = 0;
+#pragma unroll
+            for (int a = 0; a < NM; ++a)
+#pragma unroll
+                for (int b = a; b < NM; ++b, ++q) b0 += (a == b ? 1.0 : 2.0) * op[LO::BP + q] * c0[a] * c0[b];
+        }
+        const double bsc = op[LO::BSC];
+        double om[7];
+        om[0] = G0 / ((EPS + b0) * (EPS + b0));
+        double osum = om[0];
+#pragma unroll
+        for (int jj = 0; jj < 6; ++jj) {
+            const double b = bsc * (cl[jj][0] * cl[jj][0] + cl[jj][1] * cl[jj][1]);
+            om[1 + jj] = GS / ((EPS + b) * (EPS + b));
+            osum += om[1 + jj];
+        }
+        // R = omega_0 p_0 + sum_j omega_j L_j, then its moments
+        double cr[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) cr[i] = (om[0] / osum) * c0[i];
+#pragma unroll
+        for (int jj = 0; jj < 6; ++jj) {
+            cr[0] += (om[1 + jj] / osum) * cl[jj][0];
+            cr[1] += (om[1 + jj] / osum) * cl[jj][1];
+        }
+        double mom[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < NM; ++kk) s += op[LO::PM + i * NM + kk] * cr[kk];
+            mom[i] = s;
+        }
+        store_small_stencil<EQ, S>(u, K, e, t, active, valid, j, Rc, mom, compact, status);
     }
 }
 
@@ -2352,7 +2477,7 @@ hipError_t launch_limiter(const LaunchCtx& c, const DevMesh& m, const void* u, c
                           const int32_t* list, const uint32_t* count, double* compact, uint32_t* status,
                           int max_cells) {
     if (c.recon == 1) return launch_limiter_t1(c, m, u, ops, list, count, compact, status, max_cells);
-    if (c.recon == 2) return launch_limiter_t2(c, m, u, ops, list, count, compact, status, max_cells);
+    if (c.recon == 2 || c.recon == 3) return launch_limiter_t2(c, m, u, ops, list, count, compact, status, max_cells);
     const unsigned bs = 64;
     const int lpc = c.eq == 1 ? LimLanes<1>::LPC : LimLanes<0>::LPC;
     // at four waves per SIMD, 4,096 one-wave blocks are resident at once;
@@ -2413,9 +2538,14 @@ hipError_t launch_limiter_t2(const LaunchCtx& c, const DevMesh& m, const void* u
     if (g == 0) g = 1;
     if (c.N != 2) return hipErrorInvalidValue;
     CSWDG_DISPATCH_ENP(c.eq, c.N, c.precision, {
-        if constexpr (N == 2)
-            k_limiter_t2<EQ, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status, c.gamma,
-                                                       c.char_comp);
+        if constexpr (N == 2) {
+            if (c.recon == 3)
+                k_limiter_mx<EQ, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                           c.gamma, c.char_comp);
+            else
+                k_limiter_t2<EQ, S><<<g, bs, 0, c.stream>>>(m, (const S*)u, ops, list, count, compact, status,
+                                                           c.gamma, c.char_comp);
+        }
     });
     return hipGetLastError();
 }

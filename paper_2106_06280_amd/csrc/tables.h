@@ -136,4 +136,27 @@ struct OpLayoutT2 {
     static constexpr int LEN = (RAW + 7) / 8 * 8;
 };
 
+// Layout of the per-element record of the mixed reconstruction (N = 2):
+// the centroid-subcell average functionals and the linear fits of the
+// type-II record, the pseudo-inverse of the quadratic fit on the nine
+// pieces (rows piece-major: piece p of face f is row 3 p + f), the packed
+// upper triangle of the smoothness matrix of a quadratic (derivative
+// orders 1 and 2), the projection PM[i-1][j] = sum_q w_q phi_j(x_q)
+// psi_i(x_q) of the scaled monomials onto psi_1..psi_5 (degree-4 rule of the
+// reference triangle, where the basis is orthonormal), and BSC = |Delta0| /
+// h0^2.
+struct OpLayoutMX {
+    static constexpr int NP = 6, NM = 5;
+    static constexpr int AVG = 0;               // [3][3][NP]
+    static constexpr int XF = AVG + 9 * NP;     // [3][2][3]
+    static constexpr int XS = XF + 3 * 2 * 3;   // [3][2][6]
+    static constexpr int X3 = XS + 3 * 2 * 6;   // [NM][9]
+    static constexpr int BP = X3 + NM * 9;      // [NM (NM + 1) / 2]
+    static constexpr int PM = BP + NM * (NM + 1) / 2;  // [NP-1][NM]
+    static constexpr int BSC = PM + (NP - 1) * NM;
+    static constexpr int VALID = BSC + 1;
+    static constexpr int RAW = VALID + 1;
+    static constexpr int LEN = (RAW + 7) / 8 * 8;
+};
+
 }  // namespace cswdg

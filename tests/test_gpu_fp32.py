@@ -172,13 +172,13 @@ def test_fp32_limiter(torch, eq, N, bc):
 
 
 @pytest.mark.parametrize("eq", [0, 1])
-@pytest.mark.parametrize("N,kw", [(2, {"reconstruction": 1}), (2, {"reconstruction": 2}), (3, {"p2_top": 5}),
-                                  (2, {"beta_mode": 1})])
+@pytest.mark.parametrize("N,kw", [(2, {"reconstruction": 1}), (2, {"reconstruction": 2}), (2, {"reconstruction": 3}),
+                                  (3, {"p2_top": 5}), (2, {"beta_mode": 1})])
 def test_fp32_limiter_other_readings(torch, eq, N, kw):
     """The other reconstructions and readings read the float state and
     compute in FP64 too: every cell limited against the oracle on the
     float-rounded input, one rounding to float apart."""
-    from oracle import weno_type1, weno_type2
+    from oracle import weno_mixed, weno_type1, weno_type2
     from paper_2106_06280_amd import binding
     v, t = inputs.jittered_mesh(10, seed=83)
     M = Mesh(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
@@ -192,6 +192,8 @@ def test_fp32_limiter_other_readings(torch, eq, N, kw):
         exp = weno_type1.limit_type1(dg, u, allm)
     elif kw.get("reconstruction") == 2:
         exp = weno_type2.limit_type2(dg, u, allm)
+    elif kw.get("reconstruction") == 3:
+        exp = weno_mixed.limit_mixed(dg, u, allm)
     else:
         exp = csweno.limit(dg, u, allm, top=binding.top_name(N, kw.get("p2_top", 0)),
                            beta_literal=bool(kw.get("beta_mode", 0)))

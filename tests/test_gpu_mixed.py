@@ -1,0 +1,156 @@
+"""GPU parity of the mixed WENO reconstruction on the subcell stencils
+(params.reconstruction = 3, N = 2) against oracle/weno_mixed.py, and its
+accuracy with every cell limited (the paper's claim that the stencils work
+with any WENO reconstruction, Sections 1 and 5)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle_runs
+from oracle import kxrcf
+from oracle import weno_mixed as wm
+from oracle.dg import DG
+from oracle.mesh import BC_PERIODIC, BC_TRANSMISSIVE, Mesh
+from paper_2106_06280_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+# With every cell limited at every stage the order depends on the size of
+# the smoothness indicators against EPS = 1e-6: while they exceed it (coarse
+# meshes), the weights leave the constant linear ones by O(1) near the
+# data's extrema and R leaves Q by O(h^2) there, second order as for the
+# type-II reconstruction (measured 2.14, 2.23 for Burgers on 20 -> 40 -> 80
+# squares, 2.11 for the entropy wave on 20 -> 40); once they fall below it,
+# omega -> gamma and R -> Q, the T3 quadratic (3.16 for Burgers on 80 ->
+# 160, 3.38 and 4.21 for the entropy wave on 40 -> 80 -> 160, the last pair
+# passing from one regime to the other).  The finest pair is held to the
+# design order within 0.35.
+MIN_ORDER = 2.65
+ORDERS = oracle_runs.load_orders()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _relerr(gpu, ref):
+    return max(np.abs(gpu[:, c] - ref[:, c]).max() / max(np.abs(ref[:, c]).max(), 1e-300) for c in range(ref.shape[1]))
+
+
+def _state(dg, eq, seed, smooth=False):
+    if eq == 0:
+        f = (lambda x, y: 0.4 + 0.5 * np.sin(2 * math.pi * x) * np.cos(2 * math.pi * y)) if smooth else \
+            (lambda x, y: 0.3 + 0.5 * np.sin(2 * math.pi * (x + y)) + np.where(x + 0.3 * y > 0.55, 0.8, 0.0))
+        return dg.project(f)
+    if smooth:
+        return dg.project(inputs.IsentropicVortex(beta=2.0, x0=0.5, y0=0.5, period_x=1.0, period_y=1.0))
+    return dg.project(inputs.FourQuadrant(seed=seed, xc=0.47, yc=0.53, rho_range=(0.6, 1.4), p_range=(0.6, 1.4),
+                                          vel_range=(-0.5, 0.5)))
+
+
+@pytest.mark.parametrize("bc", [BC_PERIODIC, BC_TRANSMISSIVE])
+@pytest.mark.parametrize("eq,N", [(0, 2), (1, 2)])
+def test_mixed_limiter_and_steps(torch, eq, N, bc):
+    from paper_2106_06280_amd import binding
+    v, t = inputs.jittered_mesh(12, seed=181)
+    M = Mesh(v, t, bc, (1.0, 1.0))
+    dg = DG(M, N, eq)
+    S = binding.Solver(eq, N, reconstruction=binding.RECON_MIXED)
+    S.mesh_upload(v, t, bc, (1.0, 1.0))
+    for u in (_state(dg, eq, 4), _state(dg, eq, 5, smooth=True)):
+        out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+        exp = wm.limit_mixed(dg, u, np.ones(M.K, bool))
+        assert _relerr(S.to_host(out), exp) < TOL
+        assert np.array_equal(S.to_host(out)[:, :, 0], u[:, :, 0])
+    u = _state(dg, eq, 6)
+    ud = S.to_device(u)
+    out, flags = S.csweno_limit(ud)
+    fo = kxrcf.indicator(dg, u)[1]
+    assert np.array_equal(flags.cpu().numpy().astype(bool), fo) and fo.any()
+    assert _relerr(S.to_host(out), wm.limit_mixed(dg, u, fo)) < TOL
+    lim = lambda w: wm.limit_mixed(dg, w, kxrcf.indicator(dg, w)[1])
+    for _ in range(3):
+        u = dg.ssprk3_step(u, dg.max_dt(u), lim)
+        S.ssprk3_step(ud)
+    # three free-running steps: nine stages of the per-stage bar
+    assert _relerr(S.to_host(ud), u) < 9 * TOL
+
+
+def test_mixed_with_walls_and_inflow(torch):
+    """Euler P2 in a box with reflective walls below and above, inflow on the
+    left and outflow on the right: the ghosts' piece averages (mirror image,
+    wall reflection, inflow state) as in the hierarchical reconstruction."""
+    from paper_2106_06280_amd import binding
+    v, t = inputs.jittered_mesh(10, seed=191)
+    M = Mesh(v, t, BC_TRANSMISSIVE)
+    kinds = np.zeros((M.K, 3), dtype=np.int64)
+    for f in range(3):
+        mid = 0.5 * (M.V[:, f] + M.V[:, (f + 1) % 3])
+        kinds[:, f] = np.where(mid[:, 0] < 1e-12, 2, np.where((mid[:, 1] < 1e-12) | (mid[:, 1] > 1 - 1e-12), 1, 0))
+    M.set_boundary_kinds(kinds)
+    dg = DG(M, 2, 1)
+    dg.inflow = inputs.UniformFlow(1.2, 0.4, 0.0, 1.1).state
+    S = binding.Solver(1, 2, reconstruction=binding.RECON_MIXED)
+    S.mesh_upload(v, t, BC_TRANSMISSIVE, (1.0, 1.0))
+    S.set_boundary(kinds.astype(np.uint8), dg.inflow)
+    u = _state(dg, 1, 7)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    assert _relerr(S.to_host(out), wm.limit_mixed(dg, u, np.ones(M.K, bool))) < TOL
+
+
+def test_mixed_switch_rejections(torch):
+    from paper_2106_06280_amd import binding
+    for N in (1, 3):
+        with pytest.raises(binding.CswdgError):
+            binding.Solver(1, N, reconstruction=binding.RECON_MIXED)
+    with pytest.raises(binding.CswdgError):
+        binding.Solver(1, 2, reconstruction=binding.RECON_MIXED, ghost_mode=1)
+    with pytest.raises(binding.CswdgError):
+        binding.Solver(1, 2, reconstruction=binding.RECON_MIXED, beta_mode=1)
+    S = binding.Solver(1, 2, reconstruction=binding.RECON_MIXED)
+    v, t = inputs.jittered_mesh(4, seed=1)
+    S.mesh_upload(v, t, BC_PERIODIC, (1.0, 1.0))
+    u = S.to_device(np.ones((S.K, 4, 6)))
+    with pytest.raises(binding.CswdgError):
+        S.dg_residual_vjp(u, u.clone())
+
+
+def _run(torch, problem, N, n):
+    from paper_2106_06280_amd import binding
+    if problem == "burgers":
+        v, t = inputs.jittered_mesh(n, -2, 2, -2, 2, seed=7)
+        per, ic, eq, t_end = (4.0, 4.0), inputs.BurgersSine(), 0, 0.5 / math.pi
+    else:
+        v, t = inputs.jittered_mesh(n, 0, 2, 0, 2, seed=7)
+        per, ic, eq, t_end = (2.0, 2.0), inputs.EntropyWave(), 1, 0.2
+    S = binding.Solver(eq, N, limiter_mode=binding.LIMIT_ALL, reconstruction=binding.RECON_MIXED)
+    S.mesh_upload(v, t, BC_PERIODIC, per)
+    u = S.project_fn(ic)
+    nsteps = int(math.ceil(t_end / S.max_dt(u).item()))
+    dt = torch.tensor([t_end / nsteps], dtype=torch.float64, device="cuda")
+    out, _ = S.csweno_limit(u, mask=torch.ones(S.K, dtype=torch.uint8, device="cuda"))
+    u.copy_(out)
+    for _ in range(nsteps):
+        S.ssprk3_step(u, dt)
+    assert S.status() & 0x3 == 0
+    dg = DG(Mesh(v, t, BC_PERIODIC, per), N, eq)
+    return dg.errors(S.to_host(u), lambda x, y: ic.exact(x, y, t_end))[0]
+
+
+@pytest.mark.parametrize("problem,table,N", [("burgers", 1, 2), ("entropy", 2, 2)])
+def test_mixed_convergence_with_every_cell_limited(torch, problem, table, N):
+    """Tables 1-2 'with limiter' setups (every cell limited) with the mixed
+    reconstruction: errors fall under refinement at an order of at least
+    MIN_ORDER on the finest pair (40 -> 80 -> 160 squares)."""
+    errs = [_run(torch, problem, N, n) for n in (20, 40, 80, 160)]
+    orders = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(3)]
+    print(f"mixed {problem} P{N}, every cell limited: errors {errs}, orders {orders} "
+          f"(paper's hierarchical {ORDERS[(table, N)][1]})", flush=True)
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert orders[-1] >= MIN_ORDER

@@ -45,11 +45,11 @@ def _both(torch, S, u, mask=None):
     return ref, fref, out, flags
 
 
-@pytest.mark.parametrize("N,kw", [(2, {"reconstruction": 1}), (2, {"reconstruction": 2}), (3, {"p2_top": 5}),
-                                  (2, {"beta_mode": 1})])
+@pytest.mark.parametrize("N,kw", [(2, {"reconstruction": 1}), (2, {"reconstruction": 2}), (2, {"reconstruction": 3}),
+                                  (3, {"p2_top": 5}), (2, {"beta_mode": 1})])
 def test_noalloc_limiter_other_readings(torch, N, kw):
     """The entry point runs the solver's own reconstruction: type-I,
-    type-II, the sextic top, the printed smoothness indicators."""
+    type-II, mixed, the sextic top, the printed smoothness indicators."""
     for n, seed in ((12, 43), (7, 44)):
         S, u = _solver(1, N, n, BC_TRANSMISSIVE, seed, **kw)
         ref, fref, out, flags = _both(torch, S, u)
