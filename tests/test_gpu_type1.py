@@ -100,7 +100,7 @@ def test_type1_switch_rejections(torch):
     with pytest.raises(binding.CswdgError):
         binding.Solver(1, 2, reconstruction=binding.RECON_TYPE1, ghost_mode=1)
     with pytest.raises(binding.CswdgError):
-        binding.Solver(1, 2, reconstruction=3)
+        binding.Solver(1, 2, reconstruction=4)
     S = binding.Solver(1, 2, reconstruction=binding.RECON_TYPE1)
     v, t = inputs.jittered_mesh(4, seed=1)
     S.mesh_upload(v, t, BC_PERIODIC, (1.0, 1.0))
