@@ -30,7 +30,12 @@ namespace cswdg {
 
 namespace {
 
-// ubar += (d(F.n)/dU)^T xb
+// ubar += (d(F.n)/dU)^T xb, as the gradient of phi(U) = xb . F.n(U): with
+// u_n the normal velocity, H the total enthalpy and p the pressure,
+// phi = u_n (xb . (rho, m, l, E + p)) + p (xb_1 n_x + xb_2 n_y), so
+// grad phi = s (-u_n, n_x, n_y, 0) + u_n xb + w (gamma - 1) (q^2/2, -u, -v, 1)
+// with s = xb_0 + xb_1 u + xb_2 v + xb_3 H and w = u_n xb_3 + xb_1 n_x +
+// xb_2 n_y (the transposed Jacobian applied without forming it).
 template <int EQ>
 __device__ __forceinline__ void flux_jacT(const double* U, double nx, double ny, double g, const double* xb,
                                           double* ub) {
@@ -45,14 +50,12 @@ __device__ __forceinline__ void flux_jacT(const double* U, double nx, double ny,
         const double p = gm * (E - 0.5 * rho * q2);
         const double H = (E + p) * ir;
         const double un = u * nx + v * ny;
-        // rows of d(F.n)/dU
-        const double A10 = -u * un + nx * gm * 0.5 * q2, A11 = un + u * nx - gm * u * nx, A12 = u * ny - gm * v * nx, A13 = gm * nx;
-        const double A20 = -v * un + ny * gm * 0.5 * q2, A21 = v * nx - gm * u * ny, A22 = un + v * ny - gm * v * ny, A23 = gm * ny;
-        const double A30 = un * (gm * 0.5 * q2 - H), A31 = H * nx - gm * u * un, A32 = H * ny - gm * v * un, A33 = g * un;
-        ub[0] += A10 * xb[1] + A20 * xb[2] + A30 * xb[3];
-        ub[1] += nx * xb[0] + A11 * xb[1] + A21 * xb[2] + A31 * xb[3];
-        ub[2] += ny * xb[0] + A12 * xb[1] + A22 * xb[2] + A32 * xb[3];
-        ub[3] += A13 * xb[1] + A23 * xb[2] + A33 * xb[3];
+        const double sv = xb[0] + xb[1] * u + xb[2] * v + xb[3] * H;
+        const double wg = gm * (un * xb[3] + xb[1] * nx + xb[2] * ny);
+        ub[0] += -sv * un + un * xb[0] + wg * (0.5 * q2);
+        ub[1] += sv * nx + un * xb[1] - wg * u;
+        ub[2] += sv * ny + un * xb[2] - wg * v;
+        ub[3] += un * xb[3] + wg;
     }
 }
 
