@@ -52,13 +52,16 @@ def indicator(dg: DG, u, elems=None, c_k=1.0, norm="l2"):
             xg, yg = M.physical_points(*quadrature.face_reference_points(f, dg.et), elems=E)
             Ub = np.where((kind == 3)[:, None], moving_shock_state(dg.shock, xg, yg, dg.time)[..., 0], Ub)
         Up = np.where(isb[:, None], Ub, up)
+        # inflow points, v.n < 0, as the sign of rho (rho v).(L n) with L n =
+        # (ey, -ex) for the edge vector (ex, ey) of face f (L > 0 and rho^2 > 0
+        # leave the sign of v.n unchanged; no division); Burgers: v = (u, u)
+        ed = M.V[E, (f + 1) % 3] - M.V[E, f]
+        ex, ey = ed[:, 0][:, None], ed[:, 1][:, None]
         if dg.eq == EQ_BURGERS:
-            vx = vy = Um
+            sn = Um * (ey - ex)
         else:
-            vx = um[..., 1] / um[..., 0]
-            vy = um[..., 2] / um[..., 0]
-        vn = vx * M.nx[E, f][:, None] + vy * M.ny[E, f][:, None]
-        inflow = vn < 0.0
+            sn = (um[..., 1] * ey - um[..., 2] * ex) * um[..., 0]
+        inflow = sn < 0.0
         ds = 0.5 * M.L[E, f][:, None] * dg.ew[None, :]
         num += np.sum(np.where(inflow, ds * (Um - Up), 0.0), axis=1)
         length += np.sum(np.where(inflow, ds, 0.0), axis=1)

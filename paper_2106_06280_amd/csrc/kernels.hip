@@ -1025,7 +1025,6 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
             const double ex = X[f1] - X[f], ey = Y[f1] - Y[f];
             const double L = sqrt(ex * ex + ey * ey);
             Ls[f] = L;
-            const double nx = ey / L, ny = -ex / L;
             const uint32_t inf = (info4 >> (8 * f)) & 0xffu;
             const bool bnd = (inf & 0x40u) != 0u;
             const int fp = bnd ? 0 : (int)(inf & 3u);
@@ -1045,16 +1044,16 @@ __global__ __launch_bounds__(256) void k_kxrcf(DevMesh msh, const S* __restrict_
                     }
                     upv += sPF[(fp * NE + NE - 1 - g) * NP + n] * Un[n];
                 }
-                double vx, vy;
+                // inflow point: v.n < 0, tested as the sign of rho (rho v).(L n)
+                // with L n = (ey, -ex) (L > 0, rho^2 > 0: the same points,
+                // no division); Burgers: v = (u, u)
+                double sn;
                 if constexpr (EQ == 1) {
-                    vx = mu / um;
-                    vy = mv / um;
+                    sn = (mu * ey - mv * ex) * um;
                 } else {
-                    vx = um;
-                    vy = um;
+                    sn = um * (ey - ex);
                 }
-                const double vn = vx * nx + vy * ny;
-                if (vn < 0.0) {
+                if (sn < 0.0) {
                     // boundary faces: the interior trace (outflow, wall), the
                     // inflow state's indicator variable (inflow), the moving
                     // shock's at the point and the step's start (moving shock)
