@@ -43,7 +43,7 @@ __device__ __forceinline__ void flux_jacT(const double* U, double nx, double ny,
         ub[0] += U[0] * (nx + ny) * xb[0];
     } else {
         const double rho = U[0], m = U[1], l = U[2], E = U[3];
-        const double ir = 1.0 / rho;
+        const double ir = rcp_nr(rho);
         const double u = m * ir, v = l * ir;
         const double q2 = u * u + v * v;
         const double gm = g - 1.0;
@@ -68,15 +68,15 @@ __device__ __forceinline__ double speed_grad(const double* U, double nx, double 
         return fabs(s);
     } else {
         const double rho = U[0], m = U[1], l = U[2], E = U[3];
-        const double ir = 1.0 / rho;
+        const double ir = rcp_nr(rho);
         const double u = m * ir, v = l * ir;
         const double q2 = u * u + v * v;
         const double gm = g - 1.0;
         const double p = gm * (E - 0.5 * rho * q2);
-        const double c = sqrt(g * p * ir);
+        const double c = sqrt_nr(g * p * ir);
         const double un = u * nx + v * ny;
         const double sg = un > 0.0 ? 1.0 : (un < 0.0 ? -1.0 : 0.0);
-        const double k = g / (2.0 * c);
+        const double k = g * rcp_nr(2.0 * c);
         // d(p/rho)
         const double dp0 = gm * (-E * ir * ir + q2 * ir), dp1 = -gm * u * ir, dp2 = -gm * v * ir, dp3 = gm * ir;
         dl[0] = sg * (-un * ir) + k * dp0;
