@@ -26,13 +26,20 @@ def _hipcc():
     return "hipcc"
 
 
+def _rocm_include():
+    h = _hipcc()
+    root = os.path.dirname(os.path.dirname(h)) if os.path.isabs(h) else "/opt/rocm"
+    return os.path.join(root, "include")
+
+
 def _compile(src: str, verbose: bool):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [_hipcc()] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE_FLAGS + ["-x", "hip"]
     else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
+        # host-only C++ (no device pass): the HIP runtime API headers only
+        cmd += ["-D__HIP_PLATFORM_AMD__", "-I" + _rocm_include(), "-x", "c++"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

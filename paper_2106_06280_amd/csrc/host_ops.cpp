@@ -573,7 +573,6 @@ struct OpBuilderT1 {
         double h0 = (std::sqrt(dot(V0[1] - V0[0], V0[1] - V0[0])) + std::sqrt(dot(V0[2] - V0[1], V0[2] - V0[1])) +
                      std::sqrt(dot(V0[0] - V0[2], V0[0] - V0[2]))) / 3.0;
         double area0 = tri_area(V0[0], V0[1], V0[2]);
-        double J0 = 0.5 * area0;
         double mavg0[5] = {0}, tmp[5];
         {
             double wsum = 0;
