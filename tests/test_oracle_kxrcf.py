@@ -63,3 +63,35 @@ def test_smooth_data_unflagged_and_jump_flagged_for_euler():
     c = M.centroid
     near = (np.abs(c[:, 0] - 0.5) < 2.5 / 16) | (np.abs(c[:, 1] - 0.5) < 2.5 / 16)
     assert tr.sum() > 0 and np.all(near[tr])
+
+
+def test_inflow_points_of_euler_by_velocity_and_normal():
+    """The inflow test as the sign of rho (rho v).(L n) selects the points
+    where the interior velocity has v.n < 0: an Euler state whose traces
+    have a uniform velocity (a, b) (density and energy varying) has R equal
+    to a plain loop that takes a face's points as inflow when a n_x + b n_y <
+    0 (the velocity is exact here, so no point is a rounding tie)."""
+    v, t = inputs.jittered_mesh(5, seed=9)
+    M = Mesh(v, t, BC_PERIODIC, (1.0, 1.0))
+    d = DG(M, 1, 1)
+    a, b = 0.3, -0.7
+    rho = lambda x, y: 1.0 + 0.4 * np.where(x + 0.2 * y > 0.5, 1.0, 0.0) + 0.1 * np.sin(2 * math.pi * y)
+    U = d.project(lambda x, y: np.stack([rho(x, y), a * rho(x, y), b * rho(x, y), 2.5 + 0.0 * x], -1))
+    R, _ = kxrcf.indicator(d, U)
+    ue = U[:, 0, :]
+    for e in range(M.K):
+        num = ln = 0.0
+        for f in range(3):
+            if a * M.nx[e, f] + b * M.ny[e, f] >= 0.0:
+                continue
+            nb = M.nbr[e, f]
+            fp = M.neighbour_face()[e, f]
+            for g in range(len(d.ew)):
+                um = d.PF[f, g] @ ue[e]
+                up = d.PF[fp, len(d.ew) - 1 - g] @ ue[nb]
+                ds = 0.5 * M.L[e, f] * d.ew[g]
+                num += ds * (um - up)
+                ln += ds
+        nrm = math.sqrt(M.J[e] * np.sum(ue[e] ** 2))
+        exp = abs(num) / (M.circumradius[e] ** 1.0 * ln * nrm) if ln > 0 else 0.0
+        assert abs(R[e] - exp) <= 1e-12 * max(1.0, exp), (e, R[e], exp)
