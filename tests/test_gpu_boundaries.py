@@ -331,7 +331,7 @@ def test_example4_shock_position_p1(torch):
     assert abs(xs - exp) < 1.0 / n
 
 
-def _dmr_case(N, s, seed, positivity=0):
+def _dmr_case(N, s, seed, positivity=0, reconstruction=0):
     from paper_2106_06280_amd import binding
     D = inputs.DoubleMachReflection
     v, t = inputs.dmr_mesh(s, seed=seed)
@@ -342,7 +342,7 @@ def _dmr_case(N, s, seed, positivity=0):
     sh = D.shock()
     dg.shock = sh
     dg.inflow = np.asarray(sh["post"])
-    S = binding.Solver(1, N, positivity=positivity)
+    S = binding.Solver(1, N, positivity=positivity, reconstruction=reconstruction)
     S.mesh_upload(v, t, BC_TRANSMISSIVE, (0.0, 0.0))
     S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
     S.set_boundary(kinds.astype(np.uint8), sh["post"])
@@ -384,6 +384,24 @@ def test_moving_shock_operators(torch, N):
     mid = 0.5 * (M.V + np.roll(M.V, -1, axis=1))[top] @ np.array(dg.shock["n"])
     behind = mid < dg.shock["d0"] + dg.shock["w"] * T
     assert behind.any() and (~behind).any()
+
+
+@pytest.mark.parametrize("recon,N", [(1, 1), (1, 2), (2, 2), (3, 2)])
+def test_moving_shock_other_reconstructions(torch, recon, N):
+    """The other reconstructions' ghosts at Example 5's boundaries (inflow,
+    wall, outflow and the moving shock's state at the face midpoint and the
+    step's start): type-I, type-II and mixed WENO with every cell troubled
+    at time 0.03 against their oracles."""
+    from oracle import weno_mixed, weno_type1, weno_type2
+    M, dg, S = _dmr_case(N, 6, seed=37, reconstruction=recon)
+    T = 0.03
+    dg.time = T
+    S.set_time(T)
+    u = _dmr_state(M, dg, T)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    allm = np.ones(M.K, bool)
+    exp = {1: weno_type1.limit_type1, 2: weno_type2.limit_type2, 3: weno_mixed.limit_mixed}[recon](dg, u, allm)
+    assert _relerr(S.to_host(out), exp) < TOL
 
 
 @pytest.mark.parametrize("N", [1, 2])
