@@ -30,20 +30,20 @@ def _instances(eq, ns, seed):
     return out
 
 
-def _singles(torch, eq, N, inst, limiter_mode=0):
+def _singles(torch, eq, N, inst, limiter_mode=0, **kw):
     from paper_2106_06280_amd import binding
     sol, us = [], []
     for vxy, tri, bc, ic in inst:
-        S = binding.Solver(eq, N, limiter_mode=limiter_mode)
+        S = binding.Solver(eq, N, limiter_mode=limiter_mode, **kw)
         S.mesh_upload(vxy, tri, bc, (1.0, 1.0))
         sol.append(S)
         us.append(S.project_fn(ic))
     return sol, us
 
 
-def _batch(torch, eq, N, inst, us, limiter_mode=0):
+def _batch(torch, eq, N, inst, us, limiter_mode=0, **kw):
     from paper_2106_06280_amd import binding
-    B = binding.Solver(eq, N, limiter_mode=limiter_mode)
+    B = binding.Solver(eq, N, limiter_mode=limiter_mode, **kw)
     B.mesh_upload_batch([(v, t) for v, t, _, _ in inst], [bc for _, _, bc, _ in inst], (1.0, 1.0))
     return B, torch.cat(us, dim=2).contiguous()
 
@@ -69,6 +69,25 @@ def test_batch_equals_single_instances(torch, eq, N, ns):
         for i, u in enumerate(us):
             assert torch.equal(ub[:, :, off[i]:off[i + 1]], u), (step, i)
     # troubled cells were exercised
+    assert B.troubled_stats()[0] > 0
+    assert B.status() & 3 == 0
+
+
+@pytest.mark.parametrize("eq,recon", [(0, 1), (1, 1), (1, 2), (0, 3), (1, 3)])
+def test_batch_other_reconstructions(torch, eq, recon):
+    """The type-I, type-II and mixed reconstructions on a disjoint-union
+    batch (P2): every instance of the batch equals its own solver, bit for
+    bit, over three steps."""
+    inst = _instances(eq, [6, 9, 4], seed=41 + recon)
+    sol, us = _singles(torch, eq, 2, inst, reconstruction=recon)
+    B, ub = _batch(torch, eq, 2, inst, us, reconstruction=recon)
+    off = B.instances()
+    for step in range(3):
+        B.ssprk3_step(ub)
+        for S, u in zip(sol, us):
+            S.ssprk3_step(u)
+        for i, u in enumerate(us):
+            assert torch.equal(ub[:, :, off[i]:off[i + 1]], u), (step, i)
     assert B.troubled_stats()[0] > 0
     assert B.status() & 3 == 0
 
