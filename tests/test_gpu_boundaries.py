@@ -331,7 +331,7 @@ def test_example4_shock_position_p1(torch):
     assert abs(xs - exp) < 1.0 / n
 
 
-def _dmr_case(N, s, seed, positivity=0, reconstruction=0):
+def _dmr_case(N, s, seed, positivity=0, **kw):
     from paper_2106_06280_amd import binding
     D = inputs.DoubleMachReflection
     v, t = inputs.dmr_mesh(s, seed=seed)
@@ -342,7 +342,7 @@ def _dmr_case(N, s, seed, positivity=0, reconstruction=0):
     sh = D.shock()
     dg.shock = sh
     dg.inflow = np.asarray(sh["post"])
-    S = binding.Solver(1, N, positivity=positivity, reconstruction=reconstruction)
+    S = binding.Solver(1, N, positivity=positivity, **kw)
     S.mesh_upload(v, t, BC_TRANSMISSIVE, (0.0, 0.0))
     S.set_moving_shock(sh["post"], sh["pre"], sh["n"], sh["d0"], sh["w"])
     S.set_boundary(kinds.astype(np.uint8), sh["post"])
@@ -401,6 +401,25 @@ def test_moving_shock_other_reconstructions(torch, recon, N):
     out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
     allm = np.ones(M.K, bool)
     exp = {1: weno_type1.limit_type1, 2: weno_type2.limit_type2, 3: weno_mixed.limit_mixed}[recon](dg, u, allm)
+    assert _relerr(S.to_host(out), exp) < TOL
+
+
+@pytest.mark.parametrize("N,kw", [(2, {"p2_top": 2}), (2, {"p2_top": 3}), (2, {"p2_top": 4}),
+                                  (2, {"beta_mode": 1}), (3, {"p2_top": 1}), (3, {"p2_top": 5})])
+def test_moving_shock_other_readings(torch, N, kw):
+    """The readings of the N >= 2 hierarchy (the quartic, telescoping-cubic
+    and printed-cubic tops, the printed smoothness indicators, the sextic
+    P3 top on T5) with Example 5's ghosts, every cell troubled at time 0.03,
+    against the oracle with the same reading."""
+    from paper_2106_06280_amd import binding
+    M, dg, S = _dmr_case(N, 6, seed=43, **kw)
+    T = 0.03
+    dg.time = T
+    S.set_time(T)
+    u = _dmr_state(M, dg, T)
+    out, _ = S.csweno_limit(S.to_device(u), mask=torch.ones(M.K, dtype=torch.uint8))
+    exp = csweno.limit(dg, u, np.ones(M.K, bool), top=binding.top_name(N, kw.get("p2_top", 0)),
+                       beta_literal=bool(kw.get("beta_mode", 0)))
     assert _relerr(S.to_host(out), exp) < TOL
 
 
