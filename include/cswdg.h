@@ -208,7 +208,9 @@ const char* cswdg_last_error(const cswdg_solver* s);
  * unpaired boundary edges become boundary faces (outflow until
  * cswdg_set_boundary says otherwise), as Example 4's sides.  Builds the
  * connectivity on the host, the element geometry and the per-element
- * stencil operators of the limiter on the device.  Synchronous. */
+ * stencil operators of the limiter on the device.  At most 715,827,882
+ * triangles (the kernels index [3][K] arrays with 32-bit integers; a batch
+ * counts all its instances): CSWDG_EINVAL beyond.  Synchronous. */
 int cswdg_mesh_upload(cswdg_solver* s, int64_t nv, const double* vxy, int64_t nt,
                       const int32_t* tri, int bc, double period_x, double period_y);
 

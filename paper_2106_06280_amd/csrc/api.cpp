@@ -481,6 +481,8 @@ int cswdg_mesh_upload_batch(cswdg_solver* s, int32_t n_inst, const int64_t* nv, 
         if (rc != CSWDG_OK) return fail(s, rc, "instance " + std::to_string(i) + ": " + msg);
         vo += nv[i];
         to += nt[i];
+        if (to > kMaxTriangles)
+            return fail(s, CSWDG_EINVAL, "batch: more than 715,827,882 triangles in all (32-bit element indices)");
     }
     int rc = concat_meshes(parts, s->mesh, s->inst_off, s->inst_hmin, msg);
     if (rc != CSWDG_OK) return fail(s, rc, msg);

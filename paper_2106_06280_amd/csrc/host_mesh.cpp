@@ -32,8 +32,9 @@ int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri_in,
         msg = "mesh: unknown boundary condition";
         return CSWDG_EINVAL;
     }
-    if (nt > (int64_t)0x3fffffff) {
-        msg = "mesh: too many triangles for int32 ids";
+    if (nt > kMaxTriangles) {
+        msg = "mesh: more than 715,827,882 triangles (the kernels index the [3][K] vertex and neighbour arrays "
+              "with 32-bit integers)";
         return CSWDG_EINVAL;
     }
     const int64_t K = nt;

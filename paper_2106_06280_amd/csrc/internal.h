@@ -50,6 +50,9 @@ struct HostMesh {
     double hmin = 0;            // min over elements of 2 * inradius
 };
 
+// largest mesh: the last index of a [3][K] array, 3 K - 1, fits a 32-bit
+// signed integer (the kernels' element indices)
+constexpr int64_t kMaxTriangles = 715827882;
 // returns CSWDG_OK or an error code with msg filled
 int build_mesh(int64_t nv, const double* vxy, int64_t nt, const int32_t* tri, int bc, double px,
                double py, HostMesh& m, std::string& msg);

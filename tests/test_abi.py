@@ -40,6 +40,20 @@ def test_host_connectivity_bit_exact(n, seed, bc, period):
     assert np.array_equal(info, oinfo)
 
 
+def test_mesh_size_limit():
+    """More triangles than 32-bit [3][K] indices allow are rejected before
+    any array is read (the arrays passed are tiny)."""
+    vxy = np.zeros((3, 2))
+    tri = np.zeros((1, 3), np.int32)
+    out = np.zeros((1, 3), np.int32)
+    info = np.zeros((1, 3), np.uint8)
+    lim = binding.lib()
+    rc = lim.cswdg_host_connectivity(3, vxy.ctypes.data, 715827883, tri.ctypes.data, 1, 0.0, 0.0, out.ctypes.data,
+                                     out.ctypes.data, info.ctypes.data)
+    assert rc == -1
+    assert b"715,827,882" in lim.cswdg_last_error(None)
+
+
 def test_host_connectivity_errors():
     v, t = inputs.jittered_mesh(3, seed=1)
     bad = t.copy()
